@@ -1,0 +1,784 @@
+/*
+ * oracle.c -- plain, slow FP64 reference of the spiking-network hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file.  It exists so that tests, the smoke check and the
+ * CPU-baseline leg of the benchmark can compare the HIP implementation with
+ * an implementation that follows the paper step by step.  It shares no code,
+ * header, table or constant with the HIP library.
+ *
+ * Paper: Pastorelli et al., "Gaussian and exponential lateral connectivity on
+ * distributed spiking neural network simulation" (PDP 2018).
+ *
+ * What is computed, and where it comes from:
+ *   - a 2-D grid of cortical modules of excitatory and inhibitory point
+ *     neurons (Sec. III.B);
+ *   - distance-dependent connection probabilities from the Gaussian law
+ *     B*exp(-r^2/2 sigma^2) and the exponential law A*exp(-r/lambda), where
+ *     the prefactor fixes the total number of connections (Sec. I, Sec. III.B);
+ *   - per-neuron synapse projections with individual target, delay and weight
+ *     (Sec. II.B), weights Gaussian for excitatory sources, delays uniform;
+ *   - external (thalamo-cortical) drive as a Poisson process (Sec. III.A);
+ *   - leaky integrate-and-fire neurons with spike-frequency adaptation,
+ *     Eq. (1) and Eq. (2), threshold, reset and absolute refractory period
+ *     (Sec. III.A), instantaneous (delta) synapses;
+ *   - the 1 ms time-driven step: find spikers, send spikes, queue them by
+ *     delay, inject charge at arrival, integrate (Sec. II.A);
+ *   - counting of recurrent and external synaptic events (Sec. III.D).
+ *
+ * Readings of points where the paper is silent or ambiguous are listed in the
+ * design document; the ones that change arithmetic are repeated next to the
+ * code below.  Floating point is FP64 throughout; integer work (connectivity,
+ * fixed-point charge, delivery) is exact.
+ *
+ * Parity pins: Philox4x32-10 is checked against an independent library
+ * implementation; tables against closed forms and library distributions;
+ * the neuron map against closed-form interspike intervals; connectivity
+ * against its expected in-degree and distance statistics; delivery against
+ * a dense brute-force simulation and exact charge conservation.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_E_INVAL (-1)
+#define OR_E_NOMEM (-2)
+#define OR_E_OVERFLOW (-5)
+
+#define OR_GAUSS 0
+#define OR_EXP 1
+#define OR_REC_F32 0
+#define OR_REC_CODE8 1
+#define OR_EXT_POISSON 0
+#define OR_EXT_CONST 1
+
+#define RING 32            /* delay ring slots: must exceed the largest delay */
+#define POIS_MAX 64        /* longest Poisson CDF threshold table            */
+
+/* Philox stream identifiers (third counter word). */
+#define ST_CONN 1u
+#define ST_ATTR 2u
+#define ST_EXT 3u
+#define ST_INIT 4u
+
+/* Flat description of one network.  Times in ms, potentials in mV. */
+typedef struct {
+    uint32_t gx, gy, n_exc, n_inh;
+    uint32_t periodic;
+    double tau_m, v_th, v_reset, e_rest, t_ref, alpha_w, tau_w;
+    uint32_t sfa_on_inh;
+    uint64_t seed;
+    uint32_t kernel;          /* OR_GAUSS / OR_EXP                            */
+    double range;             /* sigma or lambda, in module spacings          */
+    double k_in;              /* expected number of recurrent synapses/neuron */
+    uint32_t d_min, d_max;    /* integer delays in ms                         */
+    double w_exc, w_exc_sd, w_inh;
+    uint32_t record;          /* OR_REC_F32 / OR_REC_CODE8                    */
+    uint32_t ext_mode;        /* OR_EXT_POISSON / OR_EXT_CONST                */
+    double ext_n, ext_rate_hz, ext_w;
+    int32_t ext_const_q;      /* charge per step in const mode (2^-16 mV)    */
+    uint32_t pad_;
+} or_cfg;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10, the counter-based generator of Salmon, Moraes, Dror and   */
+/* Shaw (SC'11): ten rounds of two 32x32->64 multiplications, with the      */
+/* key advanced by the Weyl constants between rounds.                       */
+/* ------------------------------------------------------------------------ */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; round++) {
+        uint64_t p0 = (uint64_t)M0 * c0;
+        uint64_t p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void philox_draw(uint64_t seed, uint32_t a, uint32_t b, uint32_t stream, uint32_t out[4])
+{
+    uint32_t ctr[4] = {a, b, stream, 0u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    or_philox(ctr, key, out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Standard normal helpers (used only to build the weight tables).          */
+/* ------------------------------------------------------------------------ */
+static double norm_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+/* 2.5066282746310002 is sqrt(2 pi) rounded to double */
+static double norm_pdf(double x) { return exp(-0.5 * x * x) / 2.5066282746310002; }
+
+/* Inverse normal CDF by plain bisection on norm_cdf. */
+static double norm_quantile(double u)
+{
+    if (u <= 0.0) return -INFINITY;
+    if (u >= 1.0) return INFINITY;
+    double lo = -40.0, hi = 40.0;
+    for (int it = 0; it < 400; it++) {
+        double mid = 0.5 * (lo + hi);
+        if (mid == lo || mid == hi) break;
+        if (norm_cdf(mid) < u) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* Mean of Z ~ N(0,1) restricted to the quantile interval [ua, ub):
+ * (phi(a) - phi(b)) / (ub - ua). */
+static double norm_bin_mean(double ua, double ub)
+{
+    double a = norm_quantile(ua), b = norm_quantile(ub);
+    double pa = isinf(a) ? 0.0 : norm_pdf(a);
+    double pb = isinf(b) ? 0.0 : norm_pdf(b);
+    return (pa - pb) / (ub - ua);
+}
+
+static int32_t fixq(double mv) { return (int32_t)nearbyint(mv * 65536.0); }
+
+/* ------------------------------------------------------------------------ */
+/* Tables                                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t *T;            /* [gy*gx] connection thresholds per torus offset */
+    int32_t wtab[65536];    /* excitatory weight by top 16 bits of the draw   */
+    int32_t cb[256];        /* 8-bit weight codebook                          */
+    uint32_t poisc[POIS_MAX];
+    uint32_t npois;
+    double dm, dw, kappa;   /* one-step propagator constants                  */
+    uint32_t nref;          /* refractory steps                               */
+    int32_t jext_q, winh_q;
+} or_tables;
+
+static uint32_t module_size(const or_cfg *c) { return c->n_exc + c->n_inh; }
+
+/* Signed torus offset of a raw difference in [0, g): mapped to (-g/2, g/2]. */
+static int torus_off(int raw, int g) { return (2 * raw <= g) ? raw : raw - g; }
+
+/* Distance law, Sec. I and Sec. III.B: Gaussian exp(-r^2 / 2 sigma^2) or
+ * exponential exp(-r / lambda), r in module spacings. */
+static double law(const or_cfg *c, int r2)
+{
+    if (c->kernel == OR_GAUSS) return exp(-(double)r2 / (2.0 * c->range * c->range));
+    return exp(-sqrt((double)r2) / c->range);
+}
+
+/* Connection thresholds.  The prefactor B fixes the expected number of
+ * recurrent synapses per neuron to k_in (Sec. I: "fixes the total"):
+ * B = k_in / sum_off n(off) f(r_off), with n = module size for a remote
+ * offset and module size - 1 for the own module (no self-connection).
+ * The pair probability p = B f(r) is stored as round(p * 2^32). */
+static int make_thresholds(const or_cfg *c, uint32_t *T)
+{
+    int gx = (int)c->gx, gy = (int)c->gy;
+    double M = (double)module_size(c);
+    double s = 0.0;
+    for (int dyr = 0; dyr < gy; dyr++)
+        for (int dxr = 0; dxr < gx; dxr++) {
+            int dx = torus_off(dxr, gx), dy = torus_off(dyr, gy);
+            double n = (dxr == 0 && dyr == 0) ? M - 1.0 : M;
+            s += n * law(c, dx * dx + dy * dy);
+        }
+    double B = (c->k_in > 0.0) ? c->k_in / s : 0.0;
+    for (int dyr = 0; dyr < gy; dyr++)
+        for (int dxr = 0; dxr < gx; dxr++) {
+            int dx = torus_off(dxr, gx), dy = torus_off(dyr, gy);
+            double p = B * law(c, dx * dx + dy * dy);
+            double q = nearbyint(p * 4294967296.0);
+            if (!(q < 4294967296.0)) return OR_E_INVAL;
+            T[dyr * gx + dxr] = (uint32_t)q;
+        }
+    return OR_OK;
+}
+
+/* Excitatory weights: Gaussian efficacies (Sec. II.B), realised as the
+ * conditional mean of each of 65536 equiprobable bins of N(mu, sd^2),
+ * in fixed point with 2^-16 mV resolution. */
+static void make_wtab(const or_cfg *c, int32_t *wtab)
+{
+    for (int k = 0; k < 65536; k++) {
+        double e = norm_bin_mean((double)k / 65536.0, (double)(k + 1) / 65536.0);
+        wtab[k] = fixq(c->w_exc + c->w_exc_sd * e);
+    }
+}
+
+/* 8-bit codebook: codes 0..254 are the conditional means of the bins
+ * selected by floor(u * 255 / 2^32) of the same draw; code 255 is the
+ * inhibitory weight. */
+static void make_codebook(const or_cfg *c, int32_t *cb)
+{
+    for (int k = 0; k < 255; k++) {
+        /* smallest u with floor(u*255/2^32) == k is ceil(k * 2^32 / 255) */
+        uint64_t e0 = ((uint64_t)k * 4294967296ull + 254u) / 255u;
+        uint64_t e1 = ((uint64_t)(k + 1) * 4294967296ull + 254u) / 255u;
+        double e = norm_bin_mean((double)e0 / 4294967296.0, (double)e1 / 4294967296.0);
+        cb[k] = fixq(c->w_exc + c->w_exc_sd * e);
+    }
+    cb[255] = fixq(c->w_inh);
+}
+
+/* External Poisson drive (Sec. III.A): mean count per 1 ms step is
+ * ext_n * rate * 1e-3.  CDF thresholds round(2^32 F(k)) are kept while
+ * below 2^32; the count is the number of thresholds not above the draw. */
+static int make_poisson(const or_cfg *c, uint32_t *poisc, uint32_t *npois)
+{
+    double m = c->ext_n * c->ext_rate_hz * 1e-3;
+    double term = exp(-m), F = term;
+    uint32_t n = 0;
+    for (int k = 0; k < POIS_MAX; k++) {
+        if (k > 0) { term *= m / (double)k; F += term; }
+        double q = nearbyint(F * 4294967296.0);
+        if (!(q < 4294967296.0)) { *npois = n; return OR_OK; }
+        poisc[n++] = (uint32_t)q;
+    }
+    return OR_E_INVAL; /* distribution not exhausted within the table */
+}
+
+static int make_tables(const or_cfg *c, or_tables *tb)
+{
+    if (c->gx == 0 || c->gy == 0 || module_size(c) == 0) return OR_E_INVAL;
+    if (!c->periodic) return OR_E_INVAL;
+    if (c->d_min < 1 || c->d_max < c->d_min || c->d_max >= RING) return OR_E_INVAL;
+    if (!(c->range > 0.0) || c->k_in < 0.0) return OR_E_INVAL;
+    if (!(c->tau_m > 0.0) || !(c->tau_w > 0.0) || c->t_ref < 0.0) return OR_E_INVAL;
+    tb->T = (uint32_t *)calloc((size_t)c->gx * c->gy, sizeof(uint32_t));
+    if (!tb->T) return OR_E_NOMEM;
+    int st = make_thresholds(c, tb->T);
+    if (st) return st;
+    make_wtab(c, tb->wtab);
+    make_codebook(c, tb->cb);
+    tb->npois = 0;
+    if (c->ext_mode == OR_EXT_POISSON) {
+        st = make_poisson(c, tb->poisc, &tb->npois);
+        if (st) return st;
+    }
+    /* Exact one-step solution of du/dt = -(u + w)/tau_m, dw/dt = -w/tau_w
+     * (Eq. (1)-(2) with the leak restoring towards E and the fatigue term
+     * g_c c / C_m read as w / tau_m, w in mV), step 1 ms. */
+    const double h = 1.0;
+    tb->dm = -expm1(-h / c->tau_m);
+    tb->dw = -expm1(-h / c->tau_w);
+    if (c->tau_w != c->tau_m)
+        tb->kappa = c->tau_w / (c->tau_w - c->tau_m) * (exp(-h / c->tau_w) - exp(-h / c->tau_m));
+    else
+        tb->kappa = (h / c->tau_m) * exp(-h / c->tau_m);
+    tb->nref = (uint32_t)llround(c->t_ref / h);
+    tb->jext_q = fixq(c->ext_w);
+    tb->winh_q = fixq(c->w_inh);
+    return OR_OK;
+}
+
+/* Exported for the table pins. */
+int or_make_tables(const or_cfg *c, uint32_t *T, int32_t *wtab, int32_t *cb,
+                   uint32_t *poisc, uint32_t *npois, double *consts, int32_t *iconsts)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    if (st == OR_OK) {
+        if (T) memcpy(T, tb->T, sizeof(uint32_t) * c->gx * c->gy);
+        if (wtab) memcpy(wtab, tb->wtab, sizeof(tb->wtab));
+        if (cb) memcpy(cb, tb->cb, sizeof(tb->cb));
+        if (poisc) memcpy(poisc, tb->poisc, sizeof(uint32_t) * tb->npois);
+        if (npois) *npois = tb->npois;
+        if (consts) { consts[0] = tb->dm; consts[1] = tb->dw; consts[2] = tb->kappa; }
+        if (iconsts) { iconsts[0] = (int32_t)tb->nref; iconsts[1] = tb->jext_q; iconsts[2] = tb->winh_q; }
+    }
+    free(tb->T);
+    free(tb);
+    return st;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Connectivity (Sec. II.B, Sec. III.B)                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Threshold of the ordered pair (i -> j) from the torus offset of their modules. */
+static uint32_t pair_threshold(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t j)
+{
+    uint32_t M = module_size(c);
+    uint32_t mi = i / M, mj = j / M;
+    uint32_t xi = mi % c->gx, yi = mi / c->gx, xj = mj % c->gx, yj = mj / c->gx;
+    uint32_t dxr = (xj + c->gx - xi) % c->gx, dyr = (yj + c->gy - yi) % c->gy;
+    return tb->T[dyr * c->gx + dxr];
+}
+
+/* Does neuron i project a synapse onto neuron j?  One Bernoulli trial per
+ * ordered pair, no self-connections, at most one synapse per pair. */
+static int connects(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t j)
+{
+    if (i == j) return 0;
+    uint32_t r[4];
+    philox_draw(c->seed, i, j >> 2, ST_CONN, r);
+    return r[j & 3u] < pair_threshold(c, tb, i, j);
+}
+
+/* Delay and fixed-point weight of the synapse i -> j (Sec. II.B: individual
+ * delay, uniform; individual weight, Gaussian for excitatory sources). */
+static void attributes(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t j,
+                       uint32_t *delay, int32_t *wq, uint32_t *code)
+{
+    uint32_t a[4];
+    philox_draw(c->seed, i, j, ST_ATTR, a);
+    uint32_t span = c->d_max - c->d_min + 1;
+    *delay = c->d_min + (uint32_t)(((uint64_t)a[0] * span) >> 32);
+    int exc = (i % module_size(c)) < c->n_exc;
+    if (c->record == OR_REC_CODE8) {
+        uint32_t k = exc ? (uint32_t)(((uint64_t)a[1] * 255u) >> 32) : 255u;
+        *code = k;
+        *wq = tb->cb[k];
+    } else {
+        *code = 0;
+        *wq = exc ? tb->wtab[a[1] >> 16] : tb->winh_q;
+    }
+}
+
+/* Uncompressed FP64 weight of the same draw, for precision statements. */
+static double attributes_fp64_weight(const or_cfg *c, uint32_t i, uint32_t j)
+{
+    uint32_t a[4];
+    philox_draw(c->seed, i, j, ST_ATTR, a);
+    int exc = (i % module_size(c)) < c->n_exc;
+    if (!exc) return c->w_inh;
+    return c->w_exc + c->w_exc_sd * norm_quantile(((double)a[1] + 0.5) / 4294967296.0);
+}
+
+/* One synapse as stored: target, delay, weight (fixed point and FP64). */
+typedef struct {
+    uint32_t tgt, delay, code;
+    int32_t wq;
+    double wf;
+} or_syn;
+
+/* The projection of neuron i: every j with connects(i, j), ordered by
+ * (delay, target).  Returns the count; *out is malloc'ed. */
+static int64_t build_row(const or_cfg *c, const or_tables *tb, uint32_t i, or_syn **out, int want_fp64)
+{
+    uint32_t N = c->gx * c->gy * module_size(c);
+    uint32_t D = c->d_max - c->d_min + 1;
+    size_t cap = 1024, n = 0;
+    or_syn *hits = (or_syn *)malloc(cap * sizeof(or_syn));
+    if (!hits) return OR_E_NOMEM;
+    for (uint32_t j = 0; j < N; j++) {
+        if (!connects(c, tb, i, j)) continue;
+        if (n == cap) {
+            cap *= 2;
+            or_syn *nh = (or_syn *)realloc(hits, cap * sizeof(or_syn));
+            if (!nh) { free(hits); return OR_E_NOMEM; }
+            hits = nh;
+        }
+        or_syn s;
+        s.tgt = j;
+        attributes(c, tb, i, j, &s.delay, &s.wq, &s.code);
+        s.wf = want_fp64 ? attributes_fp64_weight(c, i, j) : 0.0;
+        hits[n++] = s;
+    }
+    /* stable counting sort by delay: targets stay ascending within a delay */
+    or_syn *sorted = (or_syn *)malloc((n ? n : 1) * sizeof(or_syn));
+    if (!sorted) { free(hits); return OR_E_NOMEM; }
+    size_t k = 0;
+    for (uint32_t d = 0; d < D; d++)
+        for (size_t h = 0; h < n; h++)
+            if (hits[h].delay == c->d_min + d) sorted[k++] = hits[h];
+    free(hits);
+    *out = sorted;
+    return (int64_t)n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Network                                                                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    or_cfg c;
+    or_tables tb;
+    uint32_t N, D;
+    /* CSR of outgoing synapses, rows ordered by (delay, target) */
+    uint64_t *row_ptr;      /* [N+1] */
+    uint16_t *bend;         /* [N][D] end of each delay bucket, row-relative */
+    or_syn *syn;            /* [nnz] */
+    uint64_t nnz;
+    int built;
+    int fp64_weights;       /* deliver FP64 weights instead of fixed point  */
+    /* state */
+    double *V, *w;
+    int32_t *ref;
+    int32_t *ring;          /* [RING][N] fixed-point charge, int32 wrap-add */
+    int64_t *ring64;        /* [RING][N] exact shadow                        */
+    double *ringf;          /* [RING][N] FP64 charge when fp64_weights       */
+    uint8_t *flag;
+    uint32_t t;
+    /* spike history (AER: time step, neuron id), Sec. II.C */
+    uint32_t *hist;
+    size_t hist_n, hist_cap;
+    uint64_t n_spikes, rec_events, ext_events;
+    int overflow;
+} or_net;
+
+void or_net_free(void *h)
+{
+    or_net *n = (or_net *)h;
+    if (!n) return;
+    free(n->tb.T); free(n->row_ptr); free(n->bend); free(n->syn);
+    free(n->V); free(n->w); free(n->ref); free(n->ring); free(n->ring64); free(n->ringf);
+    free(n->flag); free(n->hist);
+    free(n);
+}
+
+/* Initial state: V uniform in [E, V_th) from the INIT stream, no fatigue,
+ * not refractory, empty delay queues. */
+void *or_net_create(const or_cfg *c, int fp64_weights)
+{
+    or_net *n = (or_net *)calloc(1, sizeof(or_net));
+    if (!n) return NULL;
+    n->c = *c;
+    if (make_tables(c, &n->tb) != OR_OK) { or_net_free(n); return NULL; }
+    n->N = c->gx * c->gy * module_size(c);
+    n->D = c->d_max - c->d_min + 1;
+    n->fp64_weights = fp64_weights;
+    n->V = (double *)calloc(n->N, sizeof(double));
+    n->w = (double *)calloc(n->N, sizeof(double));
+    n->ref = (int32_t *)calloc(n->N, sizeof(int32_t));
+    n->ring = (int32_t *)calloc((size_t)RING * n->N, sizeof(int32_t));
+    n->ring64 = (int64_t *)calloc((size_t)RING * n->N, sizeof(int64_t));
+    n->ringf = (double *)calloc((size_t)RING * n->N, sizeof(double));
+    n->flag = (uint8_t *)calloc(n->N, 1);
+    n->hist_cap = 1024;
+    n->hist = (uint32_t *)malloc(2 * n->hist_cap * sizeof(uint32_t));
+    if (!n->V || !n->w || !n->ref || !n->ring || !n->ring64 || !n->ringf || !n->flag || !n->hist) {
+        or_net_free(n);
+        return NULL;
+    }
+    for (uint32_t g = 0; g < n->N; g++) {
+        uint32_t r[4];
+        philox_draw(c->seed, g >> 2, 0u, ST_INIT, r);
+        double u = (double)(r[g & 3u] >> 8) * (1.0 / 16777216.0);
+        n->V[g] = c->e_rest + (c->v_th - c->e_rest) * u;
+    }
+    return n;
+}
+
+/* Build every projection (Sec. II.B). */
+int or_net_build(void *h)
+{
+    or_net *n = (or_net *)h;
+    n->row_ptr = (uint64_t *)calloc((size_t)n->N + 1, sizeof(uint64_t));
+    n->bend = (uint16_t *)calloc((size_t)n->N * n->D, sizeof(uint16_t));
+    if (!n->row_ptr || !n->bend) return OR_E_NOMEM;
+    size_t cap = 1024;
+    n->syn = (or_syn *)malloc(cap * sizeof(or_syn));
+    if (!n->syn) return OR_E_NOMEM;
+    uint64_t nnz = 0;
+    for (uint32_t i = 0; i < n->N; i++) {
+        or_syn *row = NULL;
+        int64_t len = build_row(&n->c, &n->tb, i, &row, n->fp64_weights);
+        if (len < 0) return (int)len;
+        if (len > 65535) { free(row); return OR_E_OVERFLOW; }
+        while (nnz + (uint64_t)len > cap) {
+            cap *= 2;
+            or_syn *ns = (or_syn *)realloc(n->syn, cap * sizeof(or_syn));
+            if (!ns) { free(row); return OR_E_NOMEM; }
+            n->syn = ns;
+        }
+        memcpy(n->syn + nnz, row, (size_t)len * sizeof(or_syn));
+        n->row_ptr[i] = nnz;
+        for (uint32_t d = 0; d < n->D; d++) {
+            uint32_t e = 0;
+            for (int64_t k = 0; k < len; k++)
+                if (row[k].delay <= n->c.d_min + d) e = (uint32_t)(k + 1);
+            n->bend[(size_t)i * n->D + d] = (uint16_t)e;
+        }
+        nnz += (uint64_t)len;
+        free(row);
+    }
+    n->row_ptr[n->N] = nnz;
+    n->nnz = nnz;
+    n->built = 1;
+    return OR_OK;
+}
+
+/* Serialise projections in the library's record layout: for F32 records
+ * 8 bytes {u32 target, f32 weight in mV}; for CODE8 records one u32
+ * (target << 8 | code).  Buckets end offsets are row-relative u16. */
+static void put_record(const or_cfg *c, const or_syn *s, uint8_t *dst)
+{
+    if (c->record == OR_REC_CODE8) {
+        uint32_t v = (s->tgt << 8) | s->code;
+        memcpy(dst, &v, 4);
+    } else {
+        float wf = (float)((double)s->wq / 65536.0);
+        memcpy(dst, &s->tgt, 4);
+        memcpy(dst + 4, &wf, 4);
+    }
+}
+
+static size_t record_bytes(const or_cfg *c) { return c->record == OR_REC_CODE8 ? 4 : 8; }
+
+/* Rows pre0 .. pre0+cnt-1 of the projection table, built one by one. */
+int or_build_rows(const or_cfg *c, uint32_t pre0, uint32_t cnt, uint64_t *row_len,
+                  uint16_t *bend, void *recs, uint64_t rec_cap, uint64_t *n_out)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    uint32_t D = c->d_max - c->d_min + 1;
+    uint64_t total = 0;
+    size_t rb = record_bytes(c);
+    for (uint32_t r = 0; st == OR_OK && r < cnt; r++) {
+        or_syn *row = NULL;
+        int64_t len = build_row(c, tb, pre0 + r, &row, 0);
+        if (len < 0) { st = (int)len; break; }
+        row_len[r] = (uint64_t)len;
+        for (uint32_t d = 0; d < D; d++) {
+            uint32_t e = 0;
+            for (int64_t k = 0; k < len; k++)
+                if (row[k].delay <= c->d_min + d) e = (uint32_t)(k + 1);
+            bend[(size_t)r * D + d] = (uint16_t)e;
+        }
+        for (int64_t k = 0; k < len; k++)
+            if (total + (uint64_t)k < rec_cap)
+                put_record(c, &row[k], (uint8_t *)recs + (size_t)(total + (uint64_t)k) * rb);
+        total += (uint64_t)len;
+        free(row);
+    }
+    *n_out = total;
+    free(tb->T);
+    free(tb);
+    if (st == OR_OK && total > rec_cap) return OR_E_OVERFLOW;
+    return st;
+}
+
+/* Charge that the presynaptic neurons pres[0..np) deliver to neuron j, by
+ * delay bucket: sum of fixed-point weights of the synapses pres -> j. */
+int or_col_input(const or_cfg *c, uint32_t j, const uint32_t *pres, uint64_t np, int64_t *per_delay)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    uint32_t D = c->d_max - c->d_min + 1;
+    for (uint32_t d = 0; d < D; d++) per_delay[d] = 0;
+    for (uint64_t k = 0; st == OR_OK && k < np; k++) {
+        uint32_t i = pres[k];
+        if (!connects(c, tb, i, j)) continue;
+        uint32_t delay, code;
+        int32_t wq;
+        attributes(c, tb, i, j, &delay, &wq, &code);
+        per_delay[delay - c->d_min] += wq;
+    }
+    free(tb->T);
+    free(tb);
+    return st;
+}
+
+int or_net_csr(void *h, uint64_t *row_ptr, uint16_t *bend, void *recs, uint64_t rec_cap)
+{
+    or_net *n = (or_net *)h;
+    if (!n->built) return OR_E_INVAL;
+    if (row_ptr) memcpy(row_ptr, n->row_ptr, ((size_t)n->N + 1) * sizeof(uint64_t));
+    if (bend) memcpy(bend, n->bend, (size_t)n->N * n->D * sizeof(uint16_t));
+    if (recs) {
+        if (rec_cap < n->nnz) return OR_E_OVERFLOW;
+        size_t rb = record_bytes(&n->c);
+        for (uint64_t k = 0; k < n->nnz; k++) put_record(&n->c, &n->syn[k], (uint8_t *)recs + k * rb);
+    }
+    return OR_OK;
+}
+
+uint64_t or_net_nnz(void *h) { return ((or_net *)h)->nnz; }
+
+/* Use a caller-supplied projection table (rows in the library's record
+ * layout, F32 records only): lets a brute-force or hand-made network be
+ * simulated by the same step code. */
+int or_net_set_csr(void *h, const uint64_t *row_ptr, const uint16_t *bend, const uint32_t *tgt,
+                   const uint32_t *delay, const int32_t *wq)
+{
+    or_net *n = (or_net *)h;
+    uint64_t nnz = row_ptr[n->N];
+    free(n->row_ptr); free(n->bend); free(n->syn);
+    n->row_ptr = (uint64_t *)malloc(((size_t)n->N + 1) * sizeof(uint64_t));
+    n->bend = (uint16_t *)malloc((size_t)n->N * n->D * sizeof(uint16_t));
+    n->syn = (or_syn *)malloc((nnz ? nnz : 1) * sizeof(or_syn));
+    if (!n->row_ptr || !n->bend || !n->syn) return OR_E_NOMEM;
+    memcpy(n->row_ptr, row_ptr, ((size_t)n->N + 1) * sizeof(uint64_t));
+    memcpy(n->bend, bend, (size_t)n->N * n->D * sizeof(uint16_t));
+    for (uint64_t k = 0; k < nnz; k++) {
+        n->syn[k].tgt = tgt[k];
+        n->syn[k].delay = delay[k];
+        n->syn[k].wq = wq[k];
+        n->syn[k].code = 0;
+        n->syn[k].wf = (double)wq[k] / 65536.0;
+    }
+    n->nnz = nnz;
+    n->built = 1;
+    return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Simulation (Sec. II.A, Sec. III.A)                                       */
+/* ------------------------------------------------------------------------ */
+
+/* External Poisson count of neuron g in step t. */
+static uint32_t ext_count(const or_net *n, uint32_t g, uint32_t t)
+{
+    uint32_t r[4];
+    philox_draw(n->c.seed, g >> 2, t, ST_EXT, r);
+    uint32_t u = r[g & 3u], k = 0;
+    for (uint32_t q = 0; q < n->tb.npois; q++)
+        if (n->tb.poisc[q] <= u) k++;
+    return k;
+}
+
+static void hist_push(or_net *n, uint32_t t, uint32_t g)
+{
+    if (n->hist_n == n->hist_cap) {
+        size_t nc = n->hist_cap * 2;
+        uint32_t *nh = (uint32_t *)realloc(n->hist, 2 * nc * sizeof(uint32_t));
+        if (!nh) { n->overflow = 1; return; }
+        n->hist = nh;
+        n->hist_cap = nc;
+    }
+    n->hist[2 * n->hist_n] = t;
+    n->hist[2 * n->hist_n + 1] = g;
+    n->hist_n++;
+}
+
+/* One 1 ms step.  Every neuron first takes the charge queued for this step
+ * (recurrent, from the delay queue, plus external), then integrates
+ * Eq. (1)-(2); the spikers, in ascending id, are recorded and their
+ * projections enqueue charge at step t + delay.
+ * When forced is non-NULL the spike set is forced[] instead of the
+ * threshold test (lock-step mode): forced neurons that are not refractory
+ * are reset as spikers, every other neuron integrates. */
+static int step_once(or_net *n, const uint8_t *forced)
+{
+    const or_cfg *c = &n->c;
+    uint32_t t = n->t, slot = t % RING, N = n->N;
+    for (uint32_t j = 0; j < N; j++) {
+        size_t s = (size_t)slot * N + j;
+        int64_t in64 = n->ring64[s];
+        double inf = n->ringf[s];
+        if (in64 > INT32_MAX || in64 < INT32_MIN) n->overflow = 1;
+        int32_t iq = n->ring[s];
+        n->ring[s] = 0;
+        n->ring64[s] = 0;
+        n->ringf[s] = 0.0;
+        int32_t eq;
+        if (c->ext_mode == OR_EXT_CONST) {
+            eq = c->ext_const_q;
+        } else {
+            uint32_t k = ext_count(n, j, t);
+            n->ext_events += k;
+            eq = (int32_t)k * n->tb.jext_q;
+        }
+        double J = n->fp64_weights ? inf + (double)eq / 65536.0 : (double)(iq + eq) / 65536.0;
+        int exc = (j % module_size(c)) < c->n_exc;
+        n->flag[j] = 0;
+        if (n->ref[j] > 0) {
+            /* absolute refractory period: held at reset, input ignored */
+            n->ref[j] -= 1;
+            n->V[j] = c->v_reset;
+        } else {
+            double V = n->V[j] + J;
+            int spike = forced ? (forced[j] != 0) : (V > c->v_th);
+            if (spike) {
+                n->flag[j] = 1;
+                V = c->v_reset;
+                n->ref[j] = (int32_t)n->tb.nref;
+                if (exc || c->sfa_on_inh) n->w[j] += c->alpha_w;
+            } else {
+                double u = V - c->e_rest;
+                u = u - u * n->tb.dm - n->tb.kappa * n->w[j];
+                V = c->e_rest + u;
+            }
+            n->V[j] = V;
+        }
+        n->w[j] = n->w[j] - n->w[j] * n->tb.dw;
+    }
+    for (uint32_t i = 0; i < N; i++) {
+        if (!n->flag[i]) continue;
+        hist_push(n, t, i);
+        n->n_spikes++;
+        if (!n->built) continue;
+        for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
+            const or_syn *s = &n->syn[k];
+            size_t a = (size_t)((t + s->delay) % RING) * N + s->tgt;
+            n->ring[a] = (int32_t)((uint32_t)n->ring[a] + (uint32_t)s->wq);
+            n->ring64[a] += s->wq;
+            n->ringf[a] += s->wf;
+            n->rec_events++;
+        }
+    }
+    n->t = t + 1;
+    return n->overflow ? OR_E_OVERFLOW : OR_OK;
+}
+
+int or_net_step(void *h, uint32_t steps)
+{
+    or_net *n = (or_net *)h;
+    for (uint32_t s = 0; s < steps; s++) {
+        int st = step_once(n, NULL);
+        if (st) return st;
+    }
+    return OR_OK;
+}
+
+/* One step with a given spike set (ids need not be sorted). */
+int or_net_step_forced(void *h, const uint32_t *gids, uint64_t cnt)
+{
+    or_net *n = (or_net *)h;
+    uint8_t *forced = (uint8_t *)calloc(n->N, 1);
+    if (!forced) return OR_E_NOMEM;
+    for (uint64_t k = 0; k < cnt; k++) {
+        if (gids[k] >= n->N) { free(forced); return OR_E_INVAL; }
+        forced[gids[k]] = 1;
+    }
+    int st = step_once(n, forced);
+    free(forced);
+    return st;
+}
+
+int or_net_state(void *h, double *V, double *w, int32_t *ref)
+{
+    or_net *n = (or_net *)h;
+    if (V) memcpy(V, n->V, n->N * sizeof(double));
+    if (w) memcpy(w, n->w, n->N * sizeof(double));
+    if (ref) memcpy(ref, n->ref, n->N * sizeof(int32_t));
+    return OR_OK;
+}
+
+int or_net_ring(void *h, int32_t *ring)
+{
+    or_net *n = (or_net *)h;
+    memcpy(ring, n->ring, (size_t)RING * n->N * sizeof(int32_t));
+    return OR_OK;
+}
+
+uint64_t or_net_hist(void *h, uint32_t *pairs, uint64_t cap)
+{
+    or_net *n = (or_net *)h;
+    uint64_t m = n->hist_n < cap ? n->hist_n : cap;
+    if (pairs) memcpy(pairs, n->hist, (size_t)m * 2 * sizeof(uint32_t));
+    return n->hist_n;
+}
+
+void or_net_stats(void *h, uint64_t *out)
+{
+    or_net *n = (or_net *)h;
+    out[0] = n->t;
+    out[1] = n->n_spikes;
+    out[2] = n->rec_events;
+    out[3] = n->ext_events;
+    out[4] = n->nnz;
+    out[5] = (uint64_t)n->overflow;
+}

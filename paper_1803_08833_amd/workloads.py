@@ -1,0 +1,88 @@
+"""Seeded synthetic workloads: network descriptions only, no arithmetic.
+
+Every workload is a plain dict of model parameters plus a seed.  Both the HIP
+library binding and the test-only oracle consume these dicts; all random
+numbers a network needs are drawn from its seed by each side's own
+counter-based generator, so nothing here computes any part of the method.
+
+Model (Sec. III.A-B of the paper): a 2-D torus of cortical modules, each of
+992 excitatory LIF neurons with spike-frequency adaptation and 248 inhibitory
+LIF neurons without it, at one module spacing per grid step.  Lateral
+connectivity follows a Gaussian or an exponential distance law whose
+prefactor fixes the expected number of recurrent synapses per neuron.  Each
+neuron also receives an external Poisson drive.  Parameter values the paper
+does not print are the workload definitions below.
+"""
+from __future__ import annotations
+
+import copy
+import random
+
+GAUSS = 0
+EXP = 1
+REC_F32 = 0
+REC_CODE8 = 1
+EXT_POISSON = 0
+EXT_CONST = 1
+
+NEURON = dict(
+    n_exc=992, n_inh=248, periodic=1,
+    tau_m=20.0, v_th=20.0, v_reset=15.0, e_rest=0.0, t_ref=2.0,
+    alpha_w=0.2, tau_w=500.0, sfa_on_inh=0,
+)
+
+SYNAPSE = dict(
+    d_min=1, d_max=20, w_exc=0.4, w_exc_sd=0.04, w_inh=-1.6,
+    record=REC_F32, ext_mode=EXT_POISSON, ext_n=800.0, ext_rate_hz=3.0, ext_w=0.4,
+    ext_const_q=0,
+)
+
+
+def make(gx, gy, kernel, rng, k_in, seed, **over):
+    """One network description (all keys both sides understand)."""
+    d = dict(NEURON)
+    d.update(SYNAPSE)
+    d.update(gx=gx, gy=gy, kernel=kernel, range=float(rng), k_in=float(k_in), seed=int(seed))
+    d.update(over)
+    return d
+
+
+# Named workloads.  "steps" is the biological duration in 1 ms steps.
+WORKLOADS = {
+    # 4x4 Gaussian, sigma 1 module: small enough for the oracle in seconds.
+    "grid4_gauss": dict(net=make(4, 4, GAUSS, 1.0, 1100, 1), steps=1000),
+    # 24x24 Gaussian, sigma 1.5 modules, 1100 synapses/neuron (~786 M synapses).
+    "grid24_gauss": dict(net=make(24, 24, GAUSS, 1.5, 1100, 2), steps=10000),
+    # 24x24 exponential, lambda 5 modules, 1100 synapses/neuron: the headline.
+    "grid24_exp": dict(net=make(24, 24, EXP, 5.0, 1100, 3), steps=10000),
+    # 96x96 exponential, lambda 8 modules, 2600 synapses/neuron, 8-bit codes.
+    "grid96_exp_code8": dict(net=make(96, 96, EXP, 8.0, 2600, 5, record=REC_CODE8), steps=2000),
+}
+
+
+def workload(name, **over):
+    w = copy.deepcopy(WORKLOADS[name])
+    w["net"].update(over)
+    return w
+
+
+def n_neurons(net):
+    return net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
+
+
+def serving_stream(n_jobs=512, seed=4):
+    """Job stream of the batched/served workload: grid sizes uniform over
+    {2,4,8,12,16}^2, exactly half Gaussian (sigma ~ U[1,2]) and half
+    exponential (lambda ~ U[2,6]) in shuffled order, durations uniform in
+    0.5-5 s of biological time, per-job seeds.  Arrival times are attached by
+    the server from its measured capacity."""
+    r = random.Random(seed)
+    kinds = [GAUSS] * (n_jobs // 2) + [EXP] * (n_jobs - n_jobs // 2)
+    r.shuffle(kinds)
+    jobs = []
+    for i, kind in enumerate(kinds):
+        g = r.choice([2, 4, 8, 12, 16])
+        rng = r.uniform(1.0, 2.0) if kind == GAUSS else r.uniform(2.0, 6.0)
+        dur = int(round(r.uniform(500.0, 5000.0)))
+        jobs.append(dict(net=make(g, g, kind, rng, 1100, 1_000_000 + i), steps=dur))
+    return jobs
