@@ -1,0 +1,210 @@
+/*
+ * snn.h -- C ABI of the MI355X (gfx950) spiking-network hot path.
+ *
+ * Method: Pastorelli et al., "Gaussian and exponential lateral connectivity
+ * on distributed spiking neural network simulation" (PDP 2018).  A 2-D grid
+ * of cortical modules of point neurons (Sec. III.B) is simulated in 1 ms
+ * time-driven steps (Sec. II.A): LIF neurons with spike-frequency adaptation
+ * (Sec. III.A, Eq. (1)-(2)) are integrated, spikers are identified, and each
+ * spike is fanned out through its neuron's projection (target, weight,
+ * delay; Sec. II.B) into per-target delay queues.  Projections are drawn from
+ * the Gaussian B*exp(-r^2/2 sigma^2) or exponential A*exp(-r/lambda) lateral
+ * laws (Sec. I, Sec. III.B).
+ *
+ * Conventions for every call:
+ *   - Status codes: SNN_OK (0) or a negative snn_status; no C++ exception
+ *     crosses the ABI.  snn_last_error() gives the text of the last error.
+ *   - Ownership: the library owns every device buffer it allocates (plain
+ *     hipMalloc) and frees it in snn_destroy().  Host buffers passed in are
+ *     owned by the caller and only read or written during the call.
+ *   - Streams: all device work of a network runs on the HIP stream given to
+ *     snn_build_grid (NULL = the default stream).  Calls that return host
+ *     data synchronise that stream; the others only enqueue work.
+ *   - Truncation: calls that fill a caller buffer of capacity `cap` return
+ *     SNN_E_TRUNC when it is too small and set *n_out to the size needed.
+ *   - Lifecycle: snn_step* before snn_build_synapses, or snn_build_synapses
+ *     twice, returns SNN_E_STATE.  A HIP runtime error returns SNN_E_HIP and
+ *     poisons the handle (every later call except destroy returns SNN_E_HIP).
+ *   - Threading: one network handle is used by one host thread at a time.
+ *
+ * Fixed-point charge: synaptic weights and external charge are integers in
+ * units of 2^-16 mV and are summed in int32 (two's-complement wrap-add, exact
+ * while the per-step total of a neuron fits in int32).
+ */
+#ifndef SNN_H
+#define SNN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SNN_OK = 0,
+    SNN_E_INVAL = -1,     /* invalid argument or description               */
+    SNN_E_NOMEM = -2,     /* device or host allocation failed / over budget */
+    SNN_E_HIP = -3,       /* HIP runtime error; handle is poisoned          */
+    SNN_E_STATE = -4,     /* call out of order                              */
+    SNN_E_OVERFLOW = -5,  /* a row longer than 65535 synapses, or similar   */
+    SNN_E_TRUNC = -6      /* caller buffer too small; *n_out = size needed  */
+} snn_status;
+
+enum { SNN_GAUSS = 0, SNN_EXP = 1 };
+enum { SNN_REC_F32 = 0, SNN_REC_CODE8 = 1 };
+enum { SNN_EXT_POISSON = 0, SNN_EXT_CONST = 1 };
+
+typedef struct snn_net snn_net;
+
+/* AER spike record (Sec. II.C): step index and neuron id.  Spike times are
+ * quantised to the 1 ms step.  History is ordered by (t_ms, gid). */
+typedef struct {
+    uint32_t t_ms;
+    uint32_t gid;
+} snn_spike;
+
+/* The grid of modules and its neurons (Sec. III.A-B).
+ * Neuron id: gid = module * (n_exc + n_inh) + local, module = y * gx + x;
+ * local < n_exc is excitatory.  Potentials in mV, times in ms. */
+typedef struct {
+    uint32_t gx, gy;          /* grid size in modules                           */
+    uint32_t n_exc, n_inh;    /* neurons per module                             */
+    uint32_t periodic;        /* must be 1: torus boundaries                    */
+    double tau_m;             /* membrane time constant                         */
+    double v_th;              /* threshold V_theta; a spike when V exceeds it   */
+    double v_reset;           /* reset potential V_r                            */
+    double e_rest;            /* resting potential E                            */
+    double t_ref;             /* absolute refractory period (whole steps)       */
+    double alpha_w;           /* fatigue increment per spike (mV)               */
+    double tau_w;             /* fatigue decay time                             */
+    uint32_t sfa_on_inh;      /* 0: inhibitory neurons have no adaptation       */
+    uint32_t pad0_;
+    uint64_t seed;            /* Philox4x32-10 key of every random draw         */
+    uint64_t hist_cap;        /* spike-history capacity in records (0 = 1<<24)  */
+} snn_grid_desc;
+
+/* Recurrent projections and external drive (Sec. II.B, Sec. III.A-B).
+ * Connection probability of a pair at torus distance r (module spacings):
+ * p = B f(r), f = exp(-r^2 / 2 range^2) (Gaussian) or exp(-r / range)
+ * (exponential), B chosen so that the expected number of recurrent synapses
+ * per neuron is k_in.  Delays are uniform integers in [d_min, d_max] ms;
+ * excitatory weights Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh. */
+typedef struct {
+    uint32_t kernel;          /* SNN_GAUSS or SNN_EXP                           */
+    uint32_t record;          /* SNN_REC_F32 (8 B) or SNN_REC_CODE8 (4 B)       */
+    double range;             /* sigma or lambda, in module spacings            */
+    double k_in;              /* expected recurrent in-degree (0 = none)        */
+    uint32_t d_min, d_max;    /* 1 <= d_min <= d_max <= 31                      */
+    double w_exc, w_exc_sd, w_inh;
+    uint32_t ext_mode;        /* SNN_EXT_POISSON or SNN_EXT_CONST              */
+    int32_t ext_const_q;      /* const mode: charge per neuron and step, 2^-16 mV */
+    double ext_n;             /* number of external synapses per neuron          */
+    double ext_rate_hz;       /* their Poisson rate                              */
+    double ext_w;             /* their weight (mV)                               */
+} snn_syn_desc;
+
+typedef struct {
+    uint64_t t;               /* steps simulated so far                          */
+    uint64_t spikes;          /* total spikes                                    */
+    uint64_t rec_events;      /* recurrent synaptic events delivered             */
+    uint64_t ext_events;      /* external (Poisson) events                       */
+    uint64_t nnz;             /* recurrent synapses                              */
+    uint64_t n_neurons;
+    uint64_t bytes_device;    /* device memory held by the network               */
+    uint64_t hist_n;          /* spikes recorded (may exceed hist_cap)           */
+    uint64_t disagree;        /* lock-step: own threshold test != forced set     */
+    double build_ms;          /* wall time of snn_build_synapses                 */
+} snn_stats_t;
+
+/* Per-kernel average durations in ms (HIP events on the network's stream). */
+typedef struct {
+    double update_ms;         /* fused neuron update                             */
+    double compact_ms;        /* ordered spike compaction                        */
+    double deliver_ms;        /* projection fan-out into the delay ring           */
+    double step_ms;           /* whole step, launched back to back               */
+    uint64_t steps;
+    uint64_t rec_events;      /* recurrent events delivered in the timed steps   */
+    uint64_t spikes;
+} snn_kernel_times;
+
+/* Tuning knobs (snn_set_option). */
+enum {
+    SNN_OPT_GRAPH_CHUNK = 1,     /* steps per captured HIP graph (0 = no graph)   */
+    SNN_OPT_DELIVER_WAVES = 2,   /* waves in the fan-out grid                      */
+    SNN_OPT_DELIVER_UNROLL = 3   /* records in flight per lane: 1, 2 or 4          */
+};
+
+/* Create the grid (Sec. III.B) and the initial neuron state: V uniform in
+ * [E, V_th) from the INIT stream, no fatigue, not refractory, empty delay
+ * queues, t = 0.  hip_stream: a hipStream_t owned by the caller, or NULL. */
+snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** out);
+
+/* Draw every projection on the device (Sec. II.B): for each ordered pair
+ * i != j one Bernoulli trial against the 32-bit threshold of their torus
+ * offset, then delay and weight from a second draw.  Rows are stored ordered
+ * by (delay, target).  Blocks until construction has finished. */
+snn_status snn_build_synapses(snn_net* net, const snn_syn_desc* s);
+
+/* Enqueue n_ms 1 ms steps (Sec. II.A) on the network's stream. */
+snn_status snn_step(snn_net* net, uint32_t n_ms);
+
+/* One step in lock-step mode: the spike set of this step is gids[0..n)
+ * (host array, any order) instead of each neuron's own threshold test; the
+ * threshold test is still evaluated and disagreements are counted. */
+snn_status snn_step_forced(snn_net* net, const uint32_t* gids, size_t n);
+
+/* Copy recorded spikes with t0_ms <= t_ms < t1_ms, ordered by (t_ms, gid),
+ * into host_buf.  Synchronises.  SNN_E_TRUNC when more than cap match, or
+ * when the history itself overflowed (then *n_out is what was kept). */
+snn_status snn_read_spikes(snn_net* net, uint64_t t0_ms, uint64_t t1_ms,
+                           snn_spike* host_buf, size_t cap, size_t* n_out);
+
+/* Copy the neuron state to host arrays of n_neurons entries each (any may be
+ * NULL): membrane potential, fatigue (mV), refractory steps left. */
+snn_status snn_read_state(snn_net* net, float* v, float* w, uint8_t* ref);
+
+/* Copy the delay ring, int32 [32][n_neurons], slot = arrival step mod 32. */
+snn_status snn_read_ring(snn_net* net, int32_t* host_ring);
+
+/* Copy rows pre0 .. pre0+n-1 of the projection table to host memory:
+ * row_len[n] (u64), bucket ends bend[n][d_max-d_min+1] (u16, row-relative end
+ * of each delay), and the records back to back in rec_buf (8 B
+ * {u32 target, f32 weight mV} for SNN_REC_F32; 4 B (target << 8 | code) for
+ * SNN_REC_CODE8).  rec_cap is in records; *n_out = records in the range. */
+snn_status snn_export_rows(snn_net* net, uint32_t pre0, uint32_t n, uint64_t* row_len,
+                           uint16_t* bend, void* rec_buf, size_t rec_cap, size_t* n_out);
+
+/* Counters (synchronises). */
+snn_status snn_stats(snn_net* net, snn_stats_t* out);
+
+/* Run n_ms steps launching each kernel separately between HIP events on the
+ * network's stream and report average kernel durations.  The steps are real
+ * simulation steps (state advances). */
+snn_status snn_time_kernels(snn_net* net, uint32_t n_ms, snn_kernel_times* out);
+
+/* Set a tuning knob (SNN_OPT_*).  Takes effect on the next step call. */
+snn_status snn_set_option(snn_net* net, int key, int64_t value);
+
+/* Host-only (no device work): the integer tables the library derives from a
+ * description, for inspection and tests.  T[gy*gx] connection thresholds
+ * round(B f(r) 2^32) indexed by torus offset (dy mod gy) * gx + (dx mod gx);
+ * wtab[65536] excitatory weights by the top 16 bits of the weight draw;
+ * cb[256] the 8-bit codebook; poisc[64] Poisson CDF thresholds (*npois
+ * used); consts[3] = {1 - exp(-1/tau_m), 1 - exp(-1/tau_w), kappa} of the
+ * one-step propagator.  Any output may be NULL. */
+snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32_t* T, int32_t* wtab,
+                           int32_t* cb, uint32_t* poisc, uint32_t* npois, double* consts);
+
+/* Free every device buffer of the network (synchronises its stream). */
+void snn_destroy(snn_net* net);
+
+/* Text of the last error of this handle (or of the last failed create when
+ * net is NULL).  Valid until the next call on the handle. */
+const char* snn_last_error(const snn_net* net);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SNN_H */

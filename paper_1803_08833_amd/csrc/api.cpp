@@ -1,0 +1,645 @@
+// api.cpp -- C ABI of the gfx950 spiking-network library (include/snn.h):
+// device memory, construction, step orchestration (HIP graphs of step
+// sequences), read-back and kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "snn.h"
+#include "snn_dev.h"
+#include "tables.h"
+
+using snn::Ctrl;
+using snn::StepArgs;
+
+struct snn_net {
+    snn_grid_desc g{};
+    snn_syn_desc s{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool built = false;
+    bool poisoned = false;
+    std::string err;
+    StepArgs a{};
+    std::vector<std::pair<void*, size_t>> allocs;
+    uint64_t bytes = 0;
+    uint32_t N = 0, M = 0, D = 0;
+    uint64_t nnz = 0;
+    uint32_t max_len = 0;
+    double build_ms = 0.0;
+    uint32_t* T = nullptr;
+    int32_t* wtab = nullptr;
+    uint8_t* forced = nullptr;
+    uint32_t* forced_ids = nullptr;
+    // options
+    uint32_t graph_chunk = 64;
+    uint32_t deliver_waves = 8192;
+    uint32_t unroll = 4;
+    std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+snn_status fail(snn_net* n, snn_status st, const std::string& msg)
+{
+    if (n) n->err = msg;
+    else g_create_err = msg;
+    return st;
+}
+
+snn_status fail_hip(snn_net* n, hipError_t e, const char* what)
+{
+    std::string m = std::string("HIP error in ") + what + ": " + hipGetErrorString(e);
+    if (n) n->poisoned = true;
+    return fail(n, SNN_E_HIP, m);
+}
+
+#define HIPCHK(net, x)                                      \
+    do {                                                    \
+        hipError_t e_ = (x);                                \
+        if (e_ != hipSuccess) return fail_hip(net, e_, #x); \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(snn_net* n, T** p, size_t count)
+{
+    void* q = nullptr;
+    const size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 16;
+    hipError_t e = hipMalloc(&q, b);
+    if (e != hipSuccess) return e;
+    n->allocs.push_back(std::make_pair(q, b));
+    n->bytes += b;
+    *p = (T*)q;
+    return hipSuccess;
+}
+
+void dfree(snn_net* n, void* p)
+{
+    if (!p) return;
+    for (size_t i = 0; i < n->allocs.size(); ++i) {
+        if (n->allocs[i].first == p) {
+            n->bytes -= n->allocs[i].second;
+            n->allocs.erase(n->allocs.begin() + (long)i);
+            break;
+        }
+    }
+    (void)hipFree(p);
+}
+
+void drop_graphs(snn_net* n)
+{
+    for (auto& kv : n->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    n->graphs.clear();
+}
+
+snn_status check_usable(snn_net* n)
+{
+    if (!n) return fail(nullptr, SNN_E_INVAL, "null network handle");
+    if (n->poisoned) return SNN_E_HIP;
+    return SNN_OK;
+}
+
+// Enqueue step k (0-based within the current chunk) of the plain path.
+hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
+{
+    hipError_t e = snn::launch_update(a, k, n->stream);
+    if (e != hipSuccess) return e;
+    e = snn::launch_compact(a, k, n->stream);
+    if (e != hipSuccess) return e;
+    return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
+}
+
+hipError_t get_graph(snn_net* n, uint32_t chunk, hipGraphExec_t* out)
+{
+    auto it = n->graphs.find(chunk);
+    if (it != n->graphs.end()) {
+        *out = it->second.second;
+        return hipSuccess;
+    }
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    for (uint32_t k = 0; k < chunk && le == hipSuccess; ++k) le = enqueue_step(n, n->a, k);
+    if (le == hipSuccess) le = snn::launch_advance(n->a.ctrl, chunk, n->stream);
+    e = hipStreamEndCapture(n->stream, &gr);
+    if (le != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return e;
+    }
+    n->graphs[chunk] = std::make_pair(gr, ex);
+    *out = ex;
+    return hipSuccess;
+}
+
+bool valid_grid(const snn_grid_desc* g, std::string& why)
+{
+    const uint64_t M = (uint64_t)g->n_exc + g->n_inh;
+    if (g->gx == 0 || g->gy == 0 || M == 0) return why = "empty grid", false;
+    if (M % 4 != 0) return why = "module size must be a multiple of 4", false;
+    if (!g->periodic) return why = "only torus (periodic) grids are supported", false;
+    const uint64_t N = (uint64_t)g->gx * g->gy * M;
+    if (N * snn::kRing >= (1ull << 32)) return why = "too many neurons for a 32-slot int32 ring", false;
+    if (!(g->tau_m > 0) || !(g->tau_w > 0) || !(g->t_ref >= 0)) return why = "bad time constants", false;
+    if (g->t_ref > 250.0) return why = "refractory period too long", false;
+    if (!(g->v_th > g->e_rest)) return why = "threshold must exceed the resting potential", false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* snn_last_error(const snn_net* net)
+{
+    return net ? net->err.c_str() : g_create_err.c_str();
+}
+
+snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** out)
+{
+    if (!g || !out) return fail(nullptr, SNN_E_INVAL, "null argument");
+    *out = nullptr;
+    std::string why;
+    if (!valid_grid(g, why)) return fail(nullptr, SNN_E_INVAL, why);
+    snn_net* n = new snn_net();
+    n->g = *g;
+    if (n->g.hist_cap == 0) n->g.hist_cap = 1ull << 24;
+    n->M = g->n_exc + g->n_inh;
+    n->N = g->gx * g->gy * n->M;
+    if (hip_stream) {
+        n->stream = (hipStream_t)hip_stream;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&n->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete n;
+            return fail_hip(nullptr, e, "hipStreamCreateWithFlags");
+        }
+        n->own_stream = true;
+    }
+    StepArgs& a = n->a;
+    a.N = n->N;
+    a.nq = n->N / 4;
+    a.M = n->M;
+    a.n_exc = g->n_exc;
+    a.sfa_on_inh = g->sfa_on_inh;
+    a.nblk = (n->N + snn::kNeuronsPerBlock - 1) / snn::kNeuronsPerBlock;
+    a.ngrp = (a.nblk + snn::kGroup - 1) / snn::kGroup;
+    a.key0 = (uint32_t)g->seed;
+    a.key1 = (uint32_t)(g->seed >> 32);
+    a.hist_cap = n->g.hist_cap;
+    a.v_th = (float)g->v_th;
+    a.v_reset = (float)g->v_reset;
+    a.e_rest = (float)g->e_rest;
+    a.alpha = (float)g->alpha_w;
+    hipError_t e = hipSuccess;
+#define ALLOC(p, cnt)                                       \
+    if (e == hipSuccess) e = dalloc(n, &(p), (size_t)(cnt))
+    ALLOC(a.V, n->N);
+    ALLOC(a.W, n->N);
+    ALLOC(a.ref, n->N);
+    ALLOC(a.ring, (size_t)snn::kRing * n->N);
+    ALLOC(a.blk_cnt, a.nblk);
+    ALLOC(a.blk_list, (size_t)a.nblk * snn::kNeuronsPerBlock);
+    ALLOC(a.grp_cnt, 2 * a.ngrp);
+    ALLOC(a.spk, n->N);
+    ALLOC(a.hist, n->g.hist_cap);
+    ALLOC(a.ctrl, 1);
+    ALLOC(n->forced, n->N);
+    ALLOC(n->forced_ids, n->N);
+#undef ALLOC
+    if (e != hipSuccess) {
+        snn_destroy(n);
+        return fail(nullptr, SNN_E_NOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
+    }
+    e = hipMemsetAsync(a.ring, 0, sizeof(int32_t) * (size_t)snn::kRing * n->N, n->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(a.grp_cnt, 0, sizeof(uint32_t) * 2 * a.ngrp, n->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(a.ctrl, 0, sizeof(Ctrl), n->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(n->forced, 0, n->N, n->stream);
+    if (e == hipSuccess) e = snn::launch_init(a, n->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    if (e != hipSuccess) {
+        snn_status st = fail_hip(nullptr, e, "grid initialisation");
+        snn_destroy(n);
+        return st;
+    }
+    *out = n;
+    return SNN_OK;
+}
+
+snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!s) return fail(n, SNN_E_INVAL, "null synapse description");
+    if (n->built) return fail(n, SNN_E_STATE, "synapses already built");
+    if (s->kernel > 1u) return fail(n, SNN_E_INVAL, "unknown lateral kernel");
+    if (s->record > 1u) return fail(n, SNN_E_INVAL, "unknown record format");
+    if (s->ext_mode > 1u) return fail(n, SNN_E_INVAL, "unknown external drive mode");
+    if (s->d_min < 1 || s->d_max < s->d_min || s->d_max > snn::kMaxD)
+        return fail(n, SNN_E_INVAL, "delays must satisfy 1 <= d_min <= d_max <= 31");
+    if (!(s->range > 0) || !(s->k_in >= 0)) return fail(n, SNN_E_INVAL, "bad range or in-degree");
+    if (s->record == SNN_REC_CODE8 && n->N > (1u << 24))
+        return fail(n, SNN_E_INVAL, "8-bit code records need fewer than 2^24 neurons");
+    if (s->ext_mode == SNN_EXT_POISSON && !(s->ext_n * s->ext_rate_hz >= 0))
+        return fail(n, SNN_E_INVAL, "bad external drive");
+    const auto t_start = std::chrono::steady_clock::now();
+    snn::TableParams tp{};
+    tp.gx = n->g.gx;
+    tp.gy = n->g.gy;
+    tp.M = n->M;
+    tp.kernel = s->kernel;
+    tp.range = s->range;
+    tp.k_in = s->k_in;
+    tp.w_exc = s->w_exc;
+    tp.w_exc_sd = s->w_exc_sd;
+    tp.w_inh = s->w_inh;
+    tp.ext_poisson = s->ext_mode == SNN_EXT_POISSON;
+    tp.ext_n = s->ext_n;
+    tp.ext_rate_hz = s->ext_rate_hz;
+    tp.ext_w = s->ext_w;
+    tp.tau_m = n->g.tau_m;
+    tp.tau_w = n->g.tau_w;
+    tp.t_ref = n->g.t_ref;
+    snn::HostTables tb;
+    std::string why = snn::build_tables(tp, tb);
+    if (!why.empty()) return fail(n, SNN_E_INVAL, why);
+    n->s = *s;
+    n->D = s->d_max - s->d_min + 1;
+    StepArgs& a = n->a;
+    a.D = n->D;
+    a.d_min = s->d_min;
+    a.record = s->record;
+    a.npois = (uint32_t)tb.poisc.size();
+    a.ext_const = s->ext_mode == SNN_EXT_CONST;
+    a.ext_const_q = s->ext_const_q;
+    a.jext_q = tb.jext_q;
+    a.dm = (float)tb.dm;
+    a.dw = (float)tb.dw;
+    a.kappa = (float)tb.kappa;
+    a.nref = tb.nref;
+
+    uint32_t* poisc = nullptr;
+    int32_t* cb = nullptr;
+    uint64_t* row_ptr = nullptr;
+    uint16_t* bend = nullptr;
+    uint32_t* rowlen = nullptr;
+    uint64_t* tsum = nullptr;
+    hipError_t e = dalloc(n, &n->T, tb.T.size());
+    if (e == hipSuccess) e = dalloc(n, &n->wtab, 65536);
+    if (e == hipSuccess) e = dalloc(n, &cb, 256);
+    if (e == hipSuccess) e = dalloc(n, &poisc, snn::kMaxPois);
+    if (e == hipSuccess) e = dalloc(n, &row_ptr, (size_t)n->N + 1);
+    if (e == hipSuccess) e = dalloc(n, &bend, (size_t)n->N * n->D);
+    if (e == hipSuccess) e = dalloc(n, &rowlen, n->N);
+    if (e == hipSuccess) e = dalloc(n, &tsum, snn::scan_tiles(n->N) + 1);
+    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (tables/offsets)");
+    HIPCHK(n, hipMemcpyAsync(n->T, tb.T.data(), tb.T.size() * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, hipMemcpyAsync(n->wtab, tb.wtab.data(), 65536 * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, hipMemcpyAsync(cb, tb.cb.data(), 256 * 4, hipMemcpyHostToDevice, n->stream));
+    if (!tb.poisc.empty())
+        HIPCHK(n, hipMemcpyAsync(poisc, tb.poisc.data(), tb.poisc.size() * 4, hipMemcpyHostToDevice, n->stream));
+    a.poisc = poisc;
+    a.cb = cb;
+    a.row_ptr = row_ptr;
+    a.bend = bend;
+
+    snn::BuildArgs b{};
+    b.N = n->N;
+    b.M = n->M;
+    b.n_exc = n->g.n_exc;
+    b.gx = n->g.gx;
+    b.gy = n->g.gy;
+    b.D = n->D;
+    b.d_min = s->d_min;
+    b.record = s->record;
+    b.key0 = a.key0;
+    b.key1 = a.key1;
+    b.winh_q = tb.winh_q;
+    b.T = n->T;
+    b.wtab = n->wtab;
+    b.bend = bend;
+    b.rowlen = rowlen;
+    b.row_ptr = row_ptr;
+    b.ctrl = a.ctrl;
+    // Rows are built in slices so that no single launch runs for long.
+    const uint32_t slice = 1u << 16;
+    for (uint32_t r0 = 0; r0 < n->N; r0 += slice) {
+        b.row0 = r0;
+        b.nrows = (n->N - r0) < slice ? (n->N - r0) : slice;
+        HIPCHK(n, snn::launch_syn_count(b, n->stream));
+    }
+    HIPCHK(n, snn::launch_scan_rows(rowlen, row_ptr, tsum, n->N, n->stream));
+    Ctrl hc{};
+    HIPCHK(n, hipMemcpyAsync(&hc, a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, n->stream));
+    uint64_t nnz = 0;
+    HIPCHK(n, hipMemcpyAsync(&nnz, row_ptr + n->N, 8, hipMemcpyDeviceToHost, n->stream));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    if (hc.err & 1u) return fail(n, SNN_E_OVERFLOW, "a projection row exceeds 65535 synapses");
+    n->nnz = nnz;
+    n->max_len = hc.max_len;
+    const size_t rb = s->record == SNN_REC_CODE8 ? 4 : 8;
+    void* recs = nullptr;
+    e = dalloc(n, (uint8_t**)&recs, (size_t)nnz * rb);
+    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (synapse records)");
+    b.recs = recs;
+    a.recs = recs;
+    for (uint32_t r0 = 0; r0 < n->N; r0 += slice) {
+        b.row0 = r0;
+        b.nrows = (n->N - r0) < slice ? (n->N - r0) : slice;
+        HIPCHK(n, snn::launch_syn_fill(b, n->stream));
+    }
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    dfree(n, rowlen);
+    dfree(n, tsum);
+    n->built = true;
+    n->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
+    return SNN_OK;
+}
+
+snn_status snn_step(snn_net* n, uint32_t n_ms)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    uint32_t left = n_ms;
+    if (n->graph_chunk > 0) {
+        while (left >= n->graph_chunk) {
+            hipGraphExec_t ex = nullptr;
+            HIPCHK(n, get_graph(n, n->graph_chunk, &ex));
+            HIPCHK(n, hipGraphLaunch(ex, n->stream));
+            left -= n->graph_chunk;
+        }
+    }
+    if (left) {
+        for (uint32_t k = 0; k < left; ++k) HIPCHK(n, enqueue_step(n, n->a, k));
+        HIPCHK(n, snn::launch_advance(n->a.ctrl, left, n->stream));
+    }
+    return SNN_OK;
+}
+
+snn_status snn_step_forced(snn_net* n, const uint32_t* gids, size_t cnt)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (cnt > n->N || (cnt && !gids)) return fail(n, SNN_E_INVAL, "bad forced spike set");
+    for (size_t i = 0; i < cnt; ++i)
+        if (gids[i] >= n->N) return fail(n, SNN_E_INVAL, "forced spike id out of range");
+    if (cnt) HIPCHK(n, hipMemcpyAsync(n->forced_ids, gids, cnt * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, snn::launch_set_flags(n->forced, n->forced_ids, (uint32_t)cnt, 1, n->stream));
+    StepArgs a = n->a;
+    a.forced = n->forced;
+    HIPCHK(n, enqueue_step(n, a, 0));
+    HIPCHK(n, snn::launch_advance(a.ctrl, 1, n->stream));
+    HIPCHK(n, snn::launch_set_flags(n->forced, n->forced_ids, (uint32_t)cnt, 0, n->stream));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    return SNN_OK;
+}
+
+snn_status snn_read_spikes(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, size_t cap,
+                           size_t* n_out)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n_out || (cap && !buf)) return fail(n, SNN_E_INVAL, "null output");
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    Ctrl hc{};
+    HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    const uint64_t kept = hc.hist_n < n->g.hist_cap ? hc.hist_n : n->g.hist_cap;
+    // history is sorted by time: binary-search the [t0, t1) range
+    auto time_at = [&](uint64_t i, uint32_t* t) -> hipError_t {
+        uint2 v;
+        hipError_t e = hipMemcpy(&v, n->a.hist + i, sizeof(uint2), hipMemcpyDeviceToHost);
+        *t = v.x;
+        return e;
+    };
+    auto lower = [&](uint64_t tv, uint64_t* pos) -> hipError_t {
+        uint64_t lo = 0, hi = kept;
+        while (lo < hi) {
+            const uint64_t mid = (lo + hi) / 2;
+            uint32_t tm = 0;
+            hipError_t e = time_at(mid, &tm);
+            if (e != hipSuccess) return e;
+            if ((uint64_t)tm < tv) lo = mid + 1;
+            else hi = mid;
+        }
+        *pos = lo;
+        return hipSuccess;
+    };
+    uint64_t p0 = 0, p1 = 0;
+    HIPCHK(n, lower(t0, &p0));
+    HIPCHK(n, lower(t1, &p1));
+    if (p1 < p0) p1 = p0;
+    const uint64_t m = p1 - p0;
+    *n_out = (size_t)m;
+    if (m > cap) return fail(n, SNN_E_TRUNC, "spike buffer too small");
+    if (m) HIPCHK(n, hipMemcpy(buf, n->a.hist + p0, m * sizeof(snn_spike), hipMemcpyDeviceToHost));
+    if (hc.hist_n > n->g.hist_cap) return fail(n, SNN_E_TRUNC, "spike history overflowed its capacity");
+    return SNN_OK;
+}
+
+snn_status snn_read_state(snn_net* n, float* v, float* w, uint8_t* ref)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    if (v) HIPCHK(n, hipMemcpy(v, n->a.V, (size_t)n->N * 4, hipMemcpyDeviceToHost));
+    if (w) HIPCHK(n, hipMemcpy(w, n->a.W, (size_t)n->N * 4, hipMemcpyDeviceToHost));
+    if (ref) HIPCHK(n, hipMemcpy(ref, n->a.ref, (size_t)n->N, hipMemcpyDeviceToHost));
+    return SNN_OK;
+}
+
+snn_status snn_read_ring(snn_net* n, int32_t* host_ring)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!host_ring) return fail(n, SNN_E_INVAL, "null output");
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    HIPCHK(n, hipMemcpy(host_ring, n->a.ring, (size_t)snn::kRing * n->N * 4, hipMemcpyDeviceToHost));
+    return SNN_OK;
+}
+
+snn_status snn_export_rows(snn_net* n, uint32_t pre0, uint32_t cnt, uint64_t* row_len,
+                           uint16_t* bend, void* rec_buf, size_t rec_cap, size_t* n_out)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "no synapses built");
+    if ((uint64_t)pre0 + cnt > n->N || !n_out) return fail(n, SNN_E_INVAL, "row range out of bounds");
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    std::vector<uint64_t> rp((size_t)cnt + 1);
+    HIPCHK(n, hipMemcpy(rp.data(), n->a.row_ptr + pre0, ((size_t)cnt + 1) * 8, hipMemcpyDeviceToHost));
+    if (row_len)
+        for (uint32_t i = 0; i < cnt; ++i) row_len[i] = rp[i + 1] - rp[i];
+    if (bend && cnt)
+        HIPCHK(n, hipMemcpy(bend, n->a.bend + (size_t)pre0 * n->D, (size_t)cnt * n->D * 2, hipMemcpyDeviceToHost));
+    const uint64_t m = rp[cnt] - rp[0];
+    *n_out = (size_t)m;
+    if (m > rec_cap) return fail(n, SNN_E_TRUNC, "record buffer too small");
+    const size_t rb = n->s.record == SNN_REC_CODE8 ? 4 : 8;
+    if (m && rec_buf)
+        HIPCHK(n, hipMemcpy(rec_buf, (const uint8_t*)n->a.recs + rp[0] * rb, m * rb, hipMemcpyDeviceToHost));
+    return SNN_OK;
+}
+
+snn_status snn_stats(snn_net* n, snn_stats_t* out)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!out) return fail(n, SNN_E_INVAL, "null output");
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    Ctrl hc{};
+    HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    out->t = hc.t0;
+    out->spikes = hc.spikes;
+    out->rec_events = hc.rec_events;
+    out->ext_events = hc.ext_events;
+    out->nnz = n->nnz;
+    out->n_neurons = n->N;
+    out->bytes_device = n->bytes;
+    out->hist_n = hc.hist_n;
+    out->disagree = hc.disagree;
+    out->build_ms = n->build_ms;
+    return SNN_OK;
+}
+
+snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (!out) return fail(n, SNN_E_INVAL, "null output");
+    std::memset(out, 0, sizeof(*out));
+    hipEvent_t ev[4];
+    for (auto& e : ev) HIPCHK(n, hipEventCreate(&e));
+    Ctrl c0{}, c1{};
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    HIPCHK(n, hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    double tu = 0, tc = 0, td = 0, ts = 0;
+    for (uint32_t k = 0; k < n_ms; ++k) {
+        HIPCHK(n, hipEventRecord(ev[0], n->stream));
+        HIPCHK(n, snn::launch_update(n->a, 0, n->stream));
+        HIPCHK(n, hipEventRecord(ev[1], n->stream));
+        HIPCHK(n, snn::launch_compact(n->a, 0, n->stream));
+        HIPCHK(n, hipEventRecord(ev[2], n->stream));
+        HIPCHK(n, snn::launch_deliver(n->a, 0, n->deliver_waves, n->unroll, n->max_len, n->stream));
+        HIPCHK(n, hipEventRecord(ev[3], n->stream));
+        HIPCHK(n, snn::launch_advance(n->a.ctrl, 1, n->stream));
+        HIPCHK(n, hipEventSynchronize(ev[3]));
+        float a = 0, b = 0, c = 0, d = 0;
+        HIPCHK(n, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIPCHK(n, hipEventElapsedTime(&b, ev[1], ev[2]));
+        HIPCHK(n, hipEventElapsedTime(&c, ev[2], ev[3]));
+        HIPCHK(n, hipEventElapsedTime(&d, ev[0], ev[3]));
+        tu += a;
+        tc += b;
+        td += c;
+        ts += d;
+    }
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    HIPCHK(n, hipMemcpy(&c1, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    const double k = n_ms ? (double)n_ms : 1.0;
+    out->update_ms = tu / k;
+    out->compact_ms = tc / k;
+    out->deliver_ms = td / k;
+    out->step_ms = ts / k;
+    out->steps = n_ms;
+    out->rec_events = c1.rec_events - c0.rec_events;
+    out->spikes = c1.spikes - c0.spikes;
+    return SNN_OK;
+}
+
+snn_status snn_set_option(snn_net* n, int key, int64_t value)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    switch (key) {
+    case SNN_OPT_GRAPH_CHUNK:
+        if (value < 0 || value > 4096) return fail(n, SNN_E_INVAL, "graph chunk out of range");
+        n->graph_chunk = (uint32_t)value;
+        break;
+    case SNN_OPT_DELIVER_WAVES:
+        if (value < 4 || value > (1 << 20)) return fail(n, SNN_E_INVAL, "wave count out of range");
+        n->deliver_waves = (uint32_t)value;
+        break;
+    case SNN_OPT_DELIVER_UNROLL:
+        if (value != 1 && value != 2 && value != 4) return fail(n, SNN_E_INVAL, "unroll must be 1, 2 or 4");
+        n->unroll = (uint32_t)value;
+        break;
+    default:
+        return fail(n, SNN_E_INVAL, "unknown option");
+    }
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    drop_graphs(n);
+    return SNN_OK;
+}
+
+snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32_t* T, int32_t* wtab,
+                           int32_t* cb, uint32_t* poisc, uint32_t* npois, double* consts)
+{
+    if (!g || !s) return fail(nullptr, SNN_E_INVAL, "null argument");
+    std::string why;
+    if (!valid_grid(g, why)) return fail(nullptr, SNN_E_INVAL, why);
+    snn::TableParams tp{};
+    tp.gx = g->gx;
+    tp.gy = g->gy;
+    tp.M = g->n_exc + g->n_inh;
+    tp.kernel = s->kernel;
+    tp.range = s->range;
+    tp.k_in = s->k_in;
+    tp.w_exc = s->w_exc;
+    tp.w_exc_sd = s->w_exc_sd;
+    tp.w_inh = s->w_inh;
+    tp.ext_poisson = s->ext_mode == SNN_EXT_POISSON;
+    tp.ext_n = s->ext_n;
+    tp.ext_rate_hz = s->ext_rate_hz;
+    tp.ext_w = s->ext_w;
+    tp.tau_m = g->tau_m;
+    tp.tau_w = g->tau_w;
+    tp.t_ref = g->t_ref;
+    snn::HostTables tb;
+    why = snn::build_tables(tp, tb);
+    if (!why.empty()) return fail(nullptr, SNN_E_INVAL, why);
+    if (T) std::memcpy(T, tb.T.data(), tb.T.size() * 4);
+    if (wtab) std::memcpy(wtab, tb.wtab.data(), 65536 * 4);
+    if (cb) std::memcpy(cb, tb.cb.data(), 256 * 4);
+    if (poisc && !tb.poisc.empty()) std::memcpy(poisc, tb.poisc.data(), tb.poisc.size() * 4);
+    if (npois) *npois = (uint32_t)tb.poisc.size();
+    if (consts) {
+        consts[0] = tb.dm;
+        consts[1] = tb.dw;
+        consts[2] = tb.kappa;
+    }
+    return SNN_OK;
+}
+
+void snn_destroy(snn_net* n)
+{
+    if (!n) return;
+    if (n->stream) (void)hipStreamSynchronize(n->stream);
+    drop_graphs(n);
+    for (auto& p : n->allocs) (void)hipFree(p.first);
+    n->allocs.clear();
+    if (n->own_stream && n->stream) (void)hipStreamDestroy(n->stream);
+    delete n;
+}
+
+}  // extern "C"

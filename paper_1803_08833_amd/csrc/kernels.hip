@@ -1,0 +1,635 @@
+// kernels.hip -- gfx950 kernels of the spiking-network hot path.
+//
+//   k_init        initial membrane potentials (INIT stream)
+//   k_syn<false>  projection count pass: per-pair Bernoulli trials, delay histogram per row
+//   k_scan_*      row offsets (exclusive scan of row lengths)
+//   k_syn<true>   projection fill pass: records ordered by (delay, target)
+//   k_update      fused neuron step: ring read+clear, Poisson drive, LIF+SFA, ordered
+//                 block-local spike compaction
+//   k_compact     ordered global spike list + AER history
+//   k_deliver     wave-per-row-segment fan-out into the delay ring (int32 atomics)
+//
+// Nothing here is a dense contraction: the path is bound by HBM/L2 traffic and
+// atomics (update, delivery) or by 32-bit integer multiplies (Philox), so no MFMA.
+#include "snn_dev.h"
+
+namespace snn {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds, each two
+// 32x32->64-bit products of the even counter words with the round
+// multipliers, the odd words and key XORed into the high halves; the key is
+// advanced by the golden-ratio and sqrt(3)-1 Weyl increments.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return make_uint4(c0, c1, c2, c3);
+}
+
+// ---- wave64 helpers ----
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ uint32_t popc(uint64_t m) { return (uint32_t)__popcll(m); }
+__device__ __forceinline__ uint32_t readlane(uint32_t v, uint32_t l)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+// inclusive prefix sum over the 64 lanes
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v, uint32_t lane)
+{
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T u = __shfl_up(v, o);
+        if (lane >= (uint32_t)o) v += u;
+    }
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Initial state: V uniform in [E, V_th) from the top 24 bits of the INIT draw.
+// One thread per quad of neurons (gid = 4q + s).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_init(StepArgs a)
+{
+    const uint32_t q = blockIdx.x * 256u + threadIdx.x;
+    if (q >= a.nq) return;
+    const uint4 r = philox(q, 0u, kStreamInit, 0u, a.key0, a.key1);
+    const float span = a.v_th - a.e_rest;
+    float4 v;
+    v.x = a.e_rest + span * ((float)(r.x >> 8) * 0x1p-24f);
+    v.y = a.e_rest + span * ((float)(r.y >> 8) * 0x1p-24f);
+    v.z = a.e_rest + span * ((float)(r.z >> 8) * 0x1p-24f);
+    v.w = a.e_rest + span * ((float)(r.w >> 8) * 0x1p-24f);
+    reinterpret_cast<float4*>(a.V)[q] = v;
+    reinterpret_cast<float4*>(a.W)[q] = make_float4(0.f, 0.f, 0.f, 0.f);
+    reinterpret_cast<uchar4*>(a.ref)[q] = make_uchar4(0, 0, 0, 0);
+}
+
+// ---------------------------------------------------------------------------
+// Projection construction.  One wave per presynaptic row.  The wave walks the
+// target modules in ascending index (so targets come out ascending), and for
+// each module tests its candidates 256 at a time: lane l draws Philox CONN at
+// (row, j/4) and compares the four words with the module's threshold.  Hits
+// are appended in target order to a per-wave LDS queue; full queues are
+// flushed 64 hits at a time: each lane draws the ATTR word of one hit (delay
+// bucket, weight), and per-bucket ballots give each hit its rank among the
+// same-delay hits before it, so records land in (delay, target) order.
+// Count pass: per-bucket counts -> bucket ends and row length.
+// Fill pass: lane b holds the next free offset of bucket b.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kQCap = 512;
+
+template <bool FILL>
+__device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q, uint32_t n,
+                                          uint32_t row, bool exc, uint32_t lane, uint32_t& pos,
+                                          uint64_t rbase)
+{
+    wave_sync();
+    for (uint32_t base = 0; base < n; base += 64u) {
+        const uint32_t e = base + lane;
+        const bool valid = e < n;
+        uint32_t j = 0, b = 0xFFFFFFFFu, wsel = 0;
+        if (valid) {
+            j = q[e];
+            const uint4 r = philox(row, j, kStreamAttr, 0u, a.key0, a.key1);
+            b = __umulhi(r.x, a.D);
+            wsel = r.y;
+        }
+        for (uint32_t bb = 0; bb < a.D; ++bb) {
+            const uint64_t mb = __ballot(b == bb);
+            if (mb == 0) continue;
+            if (FILL) {
+                const uint32_t p0 = readlane(pos, bb);
+                if (b == bb) {
+                    const uint64_t at = rbase + p0 + mbcnt(mb);
+                    if (a.record == 1u) {
+                        const uint32_t code = exc ? __umulhi(wsel, 255u) : 255u;
+                        reinterpret_cast<uint32_t*>(a.recs)[at] = (j << 8) | code;
+                    } else {
+                        const int32_t wq = exc ? a.wtab[wsel >> 16] : a.winh_q;
+                        Rec8 r8;
+                        r8.tgt = j;
+                        r8.w = (float)wq * 0x1p-16f;
+                        reinterpret_cast<Rec8*>(a.recs)[at] = r8;
+                    }
+                }
+            }
+            if (lane == bb) pos += popc(mb);
+        }
+    }
+    wave_sync();
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_syn(BuildArgs a)
+{
+    __shared__ uint32_t qs[4][kQCap];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t rl = blockIdx.x * 4u + wv;
+    if (rl >= a.nrows) return;
+    const uint32_t row = a.row0 + rl;
+    uint32_t* q = qs[wv];
+    const uint32_t M = a.M, gx = a.gx, gy = a.gy;
+    const uint32_t mi = row / M, xi = mi % gx, yi = mi / gx;
+    const bool exc = (row - mi * M) < a.n_exc;
+    uint32_t pos = 0;
+    uint64_t rbase = 0;
+    if (FILL) {
+        rbase = a.row_ptr[row];
+        pos = (lane >= 1u && lane < a.D) ? (uint32_t)a.bend[(size_t)row * a.D + lane - 1u] : 0u;
+    }
+    uint32_t qn = 0;
+    for (uint32_t yj = 0; yj < gy; ++yj) {
+        const uint32_t dyr = yj >= yi ? yj - yi : yj + gy - yi;
+        const uint32_t* Trow = a.T + dyr * gx;
+        for (uint32_t xj = 0; xj < gx; ++xj) {
+            const uint32_t dxr = xj >= xi ? xj - xi : xj + gx - xi;
+            const uint32_t T = Trow[dxr];
+            if (T == 0u) continue;
+            const uint32_t jb = (yj * gx + xj) * M;
+            for (uint32_t c = 0; c < M; c += 256u) {
+                const uint32_t jo = c + 4u * lane;
+                uint32_t h = 0;
+                if (jo < M) {
+                    const uint32_t j0 = jb + jo;
+                    const uint4 r = philox(row, j0 >> 2, kStreamConn, 0u, a.key0, a.key1);
+                    h = (uint32_t)(r.x < T) | ((uint32_t)(r.y < T) << 1) |
+                        ((uint32_t)(r.z < T) << 2) | ((uint32_t)(r.w < T) << 3);
+                    const uint32_t self = row - j0;      // no self-connection
+                    if (self < 4u) h &= ~(1u << self);
+                }
+                const uint64_t m0 = __ballot(h & 1u), m1 = __ballot(h & 2u);
+                const uint64_t m2 = __ballot(h & 4u), m3 = __ballot(h & 8u);
+                const uint32_t tot = popc(m0) + popc(m1) + popc(m2) + popc(m3);
+                if (tot) {
+                    uint32_t o = qn + mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
+                    const uint32_t j0 = jb + jo;
+                    if (h & 1u) q[o++] = j0;
+                    if (h & 2u) q[o++] = j0 + 1u;
+                    if (h & 4u) q[o++] = j0 + 2u;
+                    if (h & 8u) q[o++] = j0 + 3u;
+                    qn += tot;
+                    if (qn >= 256u) {
+                        syn_flush<FILL>(a, q, qn, row, exc, lane, pos, rbase);
+                        qn = 0;
+                    }
+                }
+            }
+        }
+    }
+    if (qn) syn_flush<FILL>(a, q, qn, row, exc, lane, pos, rbase);
+    if (!FILL) {
+        const uint32_t v = wave_incl_scan<uint32_t>(lane < a.D ? pos : 0u, lane);
+        if (lane < a.D) a.bend[(size_t)row * a.D + lane] = (uint16_t)(v > 65535u ? 65535u : v);
+        const uint32_t len = readlane(v, a.D - 1u);
+        if (lane == 0) {
+            a.rowlen[row] = len;
+            atomicMax(&a.ctrl->max_len, len);
+            if (len > 65535u) atomicOr(&a.ctrl->err, 1u);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row offsets: exclusive scan of u32 row lengths into u64 offsets, 1024 rows
+// per tile (256 threads x 4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t block_excl_scan(uint64_t v, uint64_t* wsum, uint64_t& total)
+{
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint64_t inc = wave_incl_scan<uint64_t>(v, lane);
+    if (lane == 63u) wsum[wv] = inc;
+    __syncthreads();
+    uint64_t off = 0;
+    total = 0;
+    for (uint32_t i = 0; i < 4u; ++i) {
+        if (i < wv) off += wsum[i];
+        total += wsum[i];
+    }
+    __syncthreads();
+    return off + inc - v;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* x, uint64_t* tsum, uint32_t N)
+{
+    __shared__ uint64_t ws[4];
+    const uint32_t i0 = blockIdx.x * 1024u + threadIdx.x * 4u;
+    uint64_t s = 0;
+    for (uint32_t u = 0; u < 4u; ++u)
+        if (i0 + u < N) s += x[i0 + u];
+    uint64_t tot;
+    block_excl_scan(s, ws, tot);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(256) void k_scan_tiles(uint64_t* tsum, uint32_t nt)
+{
+    __shared__ uint64_t ws[4];
+    uint64_t carry = 0;
+    for (uint32_t b = 0; b < nt; b += 256u) {
+        const uint32_t i = b + threadIdx.x;
+        const uint64_t v = i < nt ? tsum[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_excl_scan(v, ws, tot);
+        if (i < nt) tsum[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* x, const uint64_t* toff,
+                                                    uint64_t* out, uint32_t N)
+{
+    __shared__ uint64_t ws[4];
+    const uint32_t i0 = blockIdx.x * 1024u + threadIdx.x * 4u;
+    uint32_t v[4];
+    uint64_t s = 0;
+    for (uint32_t u = 0; u < 4u; ++u) {
+        v[u] = (i0 + u < N) ? x[i0 + u] : 0u;
+        s += v[u];
+    }
+    uint64_t tot;
+    uint64_t o = toff[blockIdx.x] + block_excl_scan(s, ws, tot);
+    for (uint32_t u = 0; u < 4u; ++u) {
+        if (i0 + u < N) out[i0 + u] = o;
+        o += v[u];
+    }
+    if (blockIdx.x == gridDim.x - 1u && threadIdx.x == 0) out[N] = toff[blockIdx.x] + tot;
+}
+
+// ---------------------------------------------------------------------------
+// Fused neuron step (one thread per quad of neurons, 1024 neurons per block):
+// take the charge queued for step t and clear its ring slot, draw the external
+// Poisson count (one Philox EXT call per quad), integrate the LIF+SFA exact
+// one-step map in fp32, and compact the block's spikers in ascending id.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool neuron_step(const StepArgs& a, uint32_t gid, bool exc, int32_t iq,
+                                            float& V, float& W, uint8_t& R, uint32_t& dis)
+{
+    const float J = (float)iq * 0x1p-16f;
+    bool spike = false;
+    if (R > 0) {
+        R = (uint8_t)(R - 1);
+        V = a.v_reset;
+    } else {
+        const float Vn = V + J;
+        const bool own = Vn > a.v_th;
+        if (a.forced) {
+            spike = a.forced[gid] != 0;
+            dis += (spike != own) ? 1u : 0u;
+        } else {
+            spike = own;
+        }
+        if (spike) {
+            V = a.v_reset;
+            R = (uint8_t)a.nref;
+            if (exc || a.sfa_on_inh) W += a.alpha;
+        } else {
+            float u = Vn - a.e_rest;
+            u = u - u * a.dm - a.kappa * W;
+            V = a.e_rest + u;
+        }
+    }
+    W = W - W * a.dw;
+    return spike;
+}
+
+__global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
+{
+    __shared__ uint32_t wtot[4];
+    __shared__ unsigned long long wext[4];
+    __shared__ uint32_t wdis[4];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t q = blockIdx.x * 256u + tid;
+    const uint32_t t = a.ctrl->t0 + k;
+    uint32_t flags = 0, ext_tot = 0, dis = 0;
+    if (q < a.nq) {
+        int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
+        const int4 in = *rp;
+        *rp = make_int4(0, 0, 0, 0);
+        float4 V = reinterpret_cast<const float4*>(a.V)[q];
+        float4 W = reinterpret_cast<const float4*>(a.W)[q];
+        uchar4 R = reinterpret_cast<const uchar4*>(a.ref)[q];
+        int32_t e0, e1, e2, e3;
+        if (a.ext_const) {
+            e0 = e1 = e2 = e3 = a.ext_const_q;
+        } else {
+            const uint4 u = philox(q, t, kStreamExt, 0u, a.key0, a.key1);
+            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+            for (uint32_t i = 0; i < a.npois; ++i) {
+                const uint32_t th = a.poisc[i];
+                c0 += (th <= u.x) ? 1u : 0u;
+                c1 += (th <= u.y) ? 1u : 0u;
+                c2 += (th <= u.z) ? 1u : 0u;
+                c3 += (th <= u.w) ? 1u : 0u;
+            }
+            ext_tot = c0 + c1 + c2 + c3;
+            e0 = (int32_t)c0 * a.jext_q;
+            e1 = (int32_t)c1 * a.jext_q;
+            e2 = (int32_t)c2 * a.jext_q;
+            e3 = (int32_t)c3 * a.jext_q;
+        }
+        const uint32_t g0 = 4u * q;
+        const uint32_t loc = g0 % a.M;   // the quad lies in one module (M % 4 == 0)
+        const auto add = [](int32_t x, int32_t y) { return (int32_t)((uint32_t)x + (uint32_t)y); };
+        flags |= neuron_step(a, g0, loc < a.n_exc, add(in.x, e0), V.x, W.x, R.x, dis) ? 1u : 0u;
+        flags |= neuron_step(a, g0 + 1u, loc + 1u < a.n_exc, add(in.y, e1), V.y, W.y, R.y, dis) ? 2u : 0u;
+        flags |= neuron_step(a, g0 + 2u, loc + 2u < a.n_exc, add(in.z, e2), V.z, W.z, R.z, dis) ? 4u : 0u;
+        flags |= neuron_step(a, g0 + 3u, loc + 3u < a.n_exc, add(in.w, e3), V.w, W.w, R.w, dis) ? 8u : 0u;
+        reinterpret_cast<float4*>(a.V)[q] = V;
+        reinterpret_cast<float4*>(a.W)[q] = W;
+        reinterpret_cast<uchar4*>(a.ref)[q] = R;
+    }
+    // ordered block-local compaction: ids ascend with (lane, bit)
+    const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
+    const uint64_t m2 = __ballot(flags & 4u), m3 = __ballot(flags & 8u);
+    const uint32_t pre = mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
+    const uint32_t wt = popc(m0) + popc(m1) + popc(m2) + popc(m3);
+    const unsigned long long we = wave_sum<unsigned long long>(ext_tot);
+    const uint32_t wd = wave_sum<uint32_t>(dis);
+    if (lane == 0) {
+        wtot[wv] = wt;
+        wext[wv] = we;
+        wdis[wv] = wd;
+    }
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+    for (uint32_t i = 0; i < 4u; ++i) {
+        if (i < wv) woff += wtot[i];
+        btot += wtot[i];
+    }
+    if (flags) {
+        uint32_t* dst = a.blk_list + (size_t)blockIdx.x * kNeuronsPerBlock + woff + pre;
+        const uint32_t g0 = 4u * q;
+        if (flags & 1u) *dst++ = g0;
+        if (flags & 2u) *dst++ = g0 + 1u;
+        if (flags & 4u) *dst++ = g0 + 2u;
+        if (flags & 8u) *dst++ = g0 + 3u;
+    }
+    if (tid == 0) {
+        a.blk_cnt[blockIdx.x] = btot;
+        if (btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blockIdx.x / kGroup], btot);
+        const unsigned long long be = wext[0] + wext[1] + wext[2] + wext[3];
+        if (be) atomicAdd((unsigned long long*)&a.ctrl->ext_events, be);
+        const uint32_t bd = wdis[0] + wdis[1] + wdis[2] + wdis[3];
+        if (bd) atomicAdd((unsigned long long*)&a.ctrl->disagree, (unsigned long long)bd);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Ordered global compaction: block g owns update blocks [64g, 64g+64); its
+// base offset is the sum of the group counts before it (this step's parity
+// buffer).  Writes the step's spike list and the AER history, counts the
+// recurrent events of the step, and clears its entry of the other parity
+// buffer for the next step.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
+{
+    __shared__ uint32_t red[4];
+    __shared__ uint32_t boff[kGroup + 1];
+    __shared__ unsigned long long wev[4];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t t = a.ctrl->t0 + k, par = t & 1u;
+    const uint32_t* gc = a.grp_cnt + par * a.ngrp;
+    uint32_t s = 0;
+    for (uint32_t i = tid; i < g; i += 256u) s += gc[i];
+    s = wave_sum<uint32_t>(s);
+    if (lane == 0) red[wv] = s;
+    const uint32_t b0 = g * kGroup;
+    const uint32_t nb = (a.nblk - b0) < kGroup ? (a.nblk - b0) : kGroup;
+    if (wv == 0) {
+        const uint32_t c = lane < nb ? a.blk_cnt[b0 + lane] : 0u;
+        const uint32_t v = wave_incl_scan<uint32_t>(c, lane);
+        boff[lane + 1u] = v;
+        if (lane == 0) boff[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t base = red[0] + red[1] + red[2] + red[3];
+    const uint32_t gtot = boff[nb];
+    const uint64_t h0 = a.ctrl->hist_n;
+    unsigned long long ev = 0;
+    for (uint32_t b = 0; b < nb; ++b) {
+        const uint32_t cnt = boff[b + 1] - boff[b];
+        const uint32_t* src = a.blk_list + (size_t)(b0 + b) * kNeuronsPerBlock;
+        for (uint32_t i = tid; i < cnt; i += 256u) {
+            const uint32_t gid = src[i];
+            const uint32_t p = base + boff[b] + i;
+            a.spk[p] = gid;
+            const uint64_t hp = h0 + p;
+            if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, gid);
+            ev += a.row_ptr[gid + 1] - a.row_ptr[gid];
+        }
+    }
+    ev = wave_sum<unsigned long long>(ev);
+    if (lane == 0) wev[wv] = ev;
+    __syncthreads();
+    if (tid == 0) {
+        a.grp_cnt[(par ^ 1u) * a.ngrp + g] = 0u;
+        const unsigned long long be = wev[0] + wev[1] + wev[2] + wev[3];
+        if (be) atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+        if (g == a.ngrp - 1u) {
+            a.ctrl->nspk = base + gtot;
+            a.ctrl->spikes += base + gtot;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Delivery.  Work item = (spike, segment of 64*U records of its row); one wave
+// per item.  Each lane loads U records (coalesced), finds its delay bucket
+// from the row's bucket ends (held one per lane: a ballot gives the bucket of
+// the first record of each 64-record chunk, and only the few ends falling
+// inside the chunk are walked), and adds the fixed-point weight into
+// ring[(t + delay) mod 32][target] with a non-returning device-scope atomic.
+// ---------------------------------------------------------------------------
+template <int U, bool CODE8>
+__global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_t smax)
+{
+    __shared__ int32_t cb_s[256];
+    if (CODE8) {
+        cb_s[threadIdx.x] = a.cb[threadIdx.x];
+        __syncthreads();
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nw = (gridDim.x * 256u) >> 6;
+    const uint32_t t = a.ctrl->t0 + k;
+    const uint32_t n = a.ctrl->nspk;
+    if (wave == 0 && lane == 0) a.ctrl->hist_n += n;
+    constexpr uint32_t SEG = 64u * U;
+    const uint64_t items = (uint64_t)n * smax;
+    for (uint64_t it = wave; it < items; it += nw) {
+        const uint32_t si = (uint32_t)(it / smax);
+        const uint32_t seg = (uint32_t)(it - (uint64_t)si * smax);
+        const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.spk[si]);
+        const uint64_t rb = a.row_ptr[pre];
+        const uint32_t len = (uint32_t)(a.row_ptr[pre + 1] - rb);
+        const uint32_t c0 = seg * SEG;
+        if (c0 >= len) continue;
+        const uint32_t be = lane < a.D ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
+        uint32_t tg[U];
+        int32_t wq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t kk = c0 + 64u * u + lane;
+            tg[u] = 0;
+            wq[u] = 0;
+            if (kk < len) {
+                if (CODE8) {
+                    const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
+                    tg[u] = v >> 8;
+                    wq[u] = (int32_t)(v & 255u);
+                } else {
+                    const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
+                    tg[u] = r.tgt;
+                    wq[u] = __float2int_rn(r.w * 65536.0f);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const uint32_t c = c0 + 64u * u;
+            if (c >= len) break;
+            const uint32_t kk = c + lane;
+            uint32_t bl = popc(__ballot(be <= c));
+            uint64_t inm = __ballot(be > c && be < c + 64u);
+            while (inm) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+                inm &= inm - 1u;
+                bl += (kk >= readlane(be, l)) ? 1u : 0u;
+            }
+            if (kk < len) {
+                const int32_t w = CODE8 ? cb_s[wq[u]] : wq[u];
+                const uint32_t slot = (t + a.d_min + bl) & (kRing - 1u);
+                __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tg[u], w, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+    }
+}
+
+__global__ void k_advance(Ctrl* c, uint32_t n)
+{
+    if (threadIdx.x == 0) c->t0 += n;
+}
+
+__global__ __launch_bounds__(256) void k_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n,
+                                                   uint8_t v)
+{
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < n) flags[ids[i]] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static inline uint32_t cdiv(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
+
+hipError_t launch_init(const StepArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_init, dim3(cdiv(a.nq, 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_syn_count(const BuildArgs& a, hipStream_t s)
+{
+    if (a.nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_syn<false>, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_syn_fill(const BuildArgs& a, hipStream_t s)
+{
+    if (a.nrows == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_syn<true>, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+uint32_t scan_tiles(uint32_t N) { return cdiv(N, 1024); }
+
+hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
+                            uint32_t N, hipStream_t s)
+{
+    const uint32_t nt = scan_tiles(N);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(256), 0, s, rowlen, tile_sums, N);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(256), 0, s, tile_sums, nt);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, s, rowlen, tile_sums, row_ptr, N);
+    return hipGetLastError();
+}
+
+hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update, dim3(a.nblk), dim3(256), 0, s, a, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_compact, dim3(a.ngrp), dim3(256), 0, s, a, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_t unroll,
+                          uint32_t max_len, hipStream_t s)
+{
+    const uint32_t blocks = cdiv(waves < 4u ? 4u : waves, 4);
+    const uint32_t seg = 64u * unroll;
+    const uint32_t smax = max_len ? cdiv(max_len, seg) : 1u;
+    const bool c8 = a.record == 1u;
+#define SNN_DELIVER(U)                                                                          \
+    if (c8) hipLaunchKernelGGL((k_deliver<U, true>), dim3(blocks), dim3(256), 0, s, a, k, smax); \
+    else hipLaunchKernelGGL((k_deliver<U, false>), dim3(blocks), dim3(256), 0, s, a, k, smax)
+    if (unroll == 1u) {
+        SNN_DELIVER(1);
+    } else if (unroll == 2u) {
+        SNN_DELIVER(2);
+    } else {
+        SNN_DELIVER(4);
+    }
+#undef SNN_DELIVER
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_flags, dim3(cdiv(n, 256)), dim3(256), 0, s, flags, ids, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace snn

@@ -1,0 +1,96 @@
+// snn_dev.h -- device-side data layout, kernel arguments and launchers of the
+// gfx950 spiking-network library.  Included by the kernels and by the host
+// runtime; contains no host-only code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace snn {
+
+constexpr uint32_t kRing = 32;      // delay-ring slots (more than the largest delay)
+constexpr uint32_t kQuadsPerBlock = 256;
+constexpr uint32_t kNeuronsPerBlock = 4 * kQuadsPerBlock;  // one update block: 1024 neurons
+constexpr uint32_t kGroup = 64;     // update blocks per compaction group
+constexpr uint32_t kMaxPois = 64;   // Poisson CDF thresholds
+constexpr uint32_t kMaxD = 31;      // delay buckets per row
+
+// Philox stream identifiers (third counter word).
+constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
+
+struct Rec8 {        // 8-byte record: target and weight in mV (an exact multiple of 2^-16)
+    uint32_t tgt;
+    float w;
+};
+
+// Device-side control block, one per network.
+struct Ctrl {
+    uint32_t t0;            // first step of the chunk being executed
+    uint32_t nspk;          // spikes of the step in flight (written by compaction)
+    uint64_t hist_n;        // spikes recorded so far
+    uint64_t rec_events;    // recurrent events delivered
+    uint64_t ext_events;    // external Poisson events
+    uint64_t spikes;        // total spikes
+    uint64_t disagree;      // lock-step threshold disagreements
+    uint32_t err;           // construction error flags (bit 0: row longer than 65535)
+    uint32_t max_len;       // longest projection row
+};
+
+// Everything the step kernels read, passed by value.
+struct StepArgs {
+    uint32_t N, nq, M, n_exc, sfa_on_inh;
+    uint32_t nblk, ngrp, D, d_min;
+    uint32_t npois, ext_const, record;
+    int32_t ext_const_q, jext_q;
+    uint32_t key0, key1;
+    uint64_t hist_cap;
+    float v_th, v_reset, e_rest, alpha, dm, dw, kappa;
+    uint32_t nref;
+    float* V;
+    float* W;
+    uint8_t* ref;
+    int32_t* ring;          // [kRing][N]
+    uint32_t* blk_cnt;      // [nblk]
+    uint32_t* blk_list;     // [nblk * kNeuronsPerBlock]
+    uint32_t* grp_cnt;      // [2][ngrp]
+    uint32_t* spk;          // [N] spike ids of the step in flight
+    uint2* hist;            // [hist_cap] (t, gid)
+    Ctrl* ctrl;
+    const uint64_t* row_ptr;  // [N+1]
+    const uint16_t* bend;     // [N][D]
+    const void* recs;
+    const uint32_t* poisc;    // [npois]
+    const int32_t* cb;        // [256] codebook (CODE8 records)
+    const uint8_t* forced;    // lock-step flags or nullptr
+};
+
+// Arguments of the projection builder.
+struct BuildArgs {
+    uint32_t N, M, n_exc, gx, gy, D, d_min, record;
+    uint32_t key0, key1;
+    int32_t winh_q;
+    uint32_t row0, nrows;      // rows built by this launch
+    const uint32_t* T;         // [gy][gx] thresholds per torus offset
+    const int32_t* wtab;       // [65536]
+    uint16_t* bend;            // [N][D]
+    uint32_t* rowlen;          // [N]
+    const uint64_t* row_ptr;   // [N+1] (fill pass)
+    void* recs;
+    Ctrl* ctrl;
+};
+
+// ---- launchers (kernels.hip) ----
+hipError_t launch_init(const StepArgs& a, hipStream_t s);
+hipError_t launch_syn_count(const BuildArgs& a, hipStream_t s);
+hipError_t launch_syn_fill(const BuildArgs& a, hipStream_t s);
+hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
+                            uint32_t N, hipStream_t s);
+hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s);
+hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s);
+hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_t unroll,
+                          uint32_t max_len, hipStream_t s);
+hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s);
+hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v,
+                            hipStream_t s);
+uint32_t scan_tiles(uint32_t N);
+
+}  // namespace snn

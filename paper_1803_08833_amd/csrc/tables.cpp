@@ -1,0 +1,146 @@
+// tables.cpp -- FP64 host tables that turn the model's real-valued laws into the
+// integer tables the kernels use.
+//
+//   * connection thresholds: p(offset) = B f(r) with f the Gaussian
+//     exp(-r^2/2 sigma^2) or exponential exp(-r/lambda) lateral law (Sec. I,
+//     Sec. III.B); B makes the expected recurrent in-degree equal to k_in
+//     ("fixes the total"); stored as round(p * 2^32);
+//   * excitatory weights: Gaussian efficacies (Sec. II.B) as the conditional
+//     means of 65536 equiprobable bins (and of 255 bins for the 8-bit codebook);
+//   * external drive: Poisson count per 1 ms step (Sec. III.A) by integer CDF
+//     thresholds;
+//   * neuron propagator: exact one-step solution of Eq. (1)-(2).
+//
+// Rounding is round-half-even everywhere; sums are taken in a fixed order
+// (offset rows outer, columns inner; Poisson terms in increasing k) so that the
+// integer tables are a deterministic function of the description.
+#include "tables.h"
+
+#include <cmath>
+
+namespace snn {
+
+namespace {
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kInvSqrt2 = 0.70710678118654752440;
+constexpr double kInvSqrt2Pi = 0.39894228040143267794;
+
+double phi(double x) { return kInvSqrt2Pi * std::exp(-0.5 * x * x); }
+double Phi(double x) { return 0.5 * std::erfc(-x * kInvSqrt2); }
+
+// Lower-tail quantile (0 < u <= 0.5): the rational start of Abramowitz and
+// Stegun 26.2.23 (|error| < 4.5e-4), then Newton steps on Phi.
+double inv_lower(double u)
+{
+    const double t = std::sqrt(-2.0 * std::log(u));
+    double x = -(t - (2.515517 + 0.802853 * t + 0.010328 * t * t) /
+                         (1.0 + 1.432788 * t + 0.189269 * t * t + 0.001308 * t * t * t));
+    for (int it = 0; it < 60; ++it) {
+        const double dx = (Phi(x) - u) / phi(x);
+        x -= dx;
+        if (std::fabs(dx) <= 1e-17 * std::fmax(1.0, std::fabs(x))) break;
+    }
+    return x;
+}
+
+int32_t to_fixed(double mv) { return (int32_t)std::nearbyint(mv * 65536.0); }
+
+// Mean of a standard normal restricted to the probability interval [u0, u1).
+double bin_mean(double u0, double u1)
+{
+    const double a = inv_norm_cdf(u0), b = inv_norm_cdf(u1);
+    const double pa = std::isinf(a) ? 0.0 : phi(a);
+    const double pb = std::isinf(b) ? 0.0 : phi(b);
+    return (pa - pb) / (u1 - u0);
+}
+
+int signed_offset(int raw, int g) { return 2 * raw <= g ? raw : raw - g; }
+
+double lateral_law(uint32_t kernel, double range, int r2)
+{
+    if (kernel == 0) return std::exp(-(double)r2 / (2.0 * range * range));
+    return std::exp(-std::sqrt((double)r2) / range);
+}
+
+}  // namespace
+
+double inv_norm_cdf(double u)
+{
+    if (u <= 0.0) return -INFINITY;
+    if (u >= 1.0) return INFINITY;
+    if (u == 0.5) return 0.0;
+    if (u > 0.5) return -inv_lower(1.0 - u);
+    return inv_lower(u);
+}
+
+std::string build_tables(const TableParams& p, HostTables& out)
+{
+    const int gx = (int)p.gx, gy = (int)p.gy;
+    // --- connection thresholds -------------------------------------------
+    double total = 0.0;
+    for (int ry = 0; ry < gy; ++ry) {
+        for (int rx = 0; rx < gx; ++rx) {
+            const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
+            const double cand = (rx == 0 && ry == 0) ? (double)p.M - 1.0 : (double)p.M;
+            total += cand * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
+        }
+    }
+    out.B = p.k_in > 0.0 ? p.k_in / total : 0.0;
+    out.T.assign((size_t)gx * gy, 0u);
+    for (int ry = 0; ry < gy; ++ry) {
+        for (int rx = 0; rx < gx; ++rx) {
+            const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
+            const double prob = out.B * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
+            const double thr = std::nearbyint(prob * kTwo32);
+            if (!(thr < kTwo32)) return "connection probability reaches 1: k_in too large for this grid";
+            out.T[(size_t)ry * gx + rx] = (uint32_t)thr;
+        }
+    }
+    // --- weights -----------------------------------------------------------
+    out.wtab.resize(65536);
+    for (int k = 0; k < 65536; ++k)
+        out.wtab[k] = to_fixed(p.w_exc + p.w_exc_sd * bin_mean(k / 65536.0, (k + 1) / 65536.0));
+    out.cb.resize(256);
+    for (int k = 0; k < 255; ++k) {
+        // draws u with floor(u * 255 / 2^32) == k start at ceil(k 2^32 / 255)
+        const uint64_t lo = ((uint64_t)k << 32) / 255u + ((((uint64_t)k << 32) % 255u) ? 1u : 0u);
+        const uint64_t hi = ((uint64_t)(k + 1) << 32) / 255u + ((((uint64_t)(k + 1) << 32) % 255u) ? 1u : 0u);
+        out.cb[k] = to_fixed(p.w_exc + p.w_exc_sd * bin_mean((double)lo / kTwo32, (double)hi / kTwo32));
+    }
+    out.winh_q = to_fixed(p.w_inh);
+    out.cb[255] = out.winh_q;
+    // --- external drive ----------------------------------------------------
+    out.poisc.clear();
+    if (p.ext_poisson) {
+        const double mean = p.ext_n * p.ext_rate_hz * 1e-3;
+        double term = std::exp(-mean), cdf = term;
+        bool done = false;
+        for (int k = 0; k < 64; ++k) {
+            if (k > 0) {
+                term *= mean / (double)k;
+                cdf += term;
+            }
+            const double thr = std::nearbyint(cdf * kTwo32);
+            if (!(thr < kTwo32)) {
+                done = true;
+                break;
+            }
+            out.poisc.push_back((uint32_t)thr);
+        }
+        if (!done) return "external Poisson mean too large for a 64-entry CDF table";
+    }
+    out.jext_q = to_fixed(p.ext_w);
+    // --- propagator (step h = 1 ms) ---------------------------------------
+    const double h = 1.0;
+    out.dm = -std::expm1(-h / p.tau_m);
+    out.dw = -std::expm1(-h / p.tau_w);
+    if (p.tau_w != p.tau_m)
+        out.kappa = p.tau_w / (p.tau_w - p.tau_m) * (out.dm - out.dw);
+    else
+        out.kappa = (h / p.tau_m) * std::exp(-h / p.tau_m);
+    out.nref = (uint32_t)std::llround(p.t_ref / h);
+    return std::string();
+}
+
+}  // namespace snn

@@ -1,0 +1,248 @@
+"""Thin ctypes binding of the gfx950 library (include/snn.h).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+libsnn.so.  PyTorch is imported first so that the process uses one HIP runtime
+(torch's) and so that callers can hand in a torch stream; the library owns its
+device memory.  There is no CPU fallback: if libsnn.so is missing this module
+raises on import of the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsnn.so")
+
+SNN_OK, SNN_E_INVAL, SNN_E_NOMEM, SNN_E_HIP, SNN_E_STATE, SNN_E_OVERFLOW, SNN_E_TRUNC = 0, -1, -2, -3, -4, -5, -6
+OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL = 1, 2, 3
+RING = 32
+
+EXPORTS = [
+    "snn_build_grid", "snn_build_synapses", "snn_step", "snn_step_forced", "snn_read_spikes",
+    "snn_read_state", "snn_read_ring", "snn_export_rows", "snn_stats", "snn_time_kernels",
+    "snn_set_option", "snn_host_tables", "snn_destroy", "snn_last_error",
+]
+
+
+class GridDesc(C.Structure):
+    _fields_ = [
+        ("gx", C.c_uint32), ("gy", C.c_uint32), ("n_exc", C.c_uint32), ("n_inh", C.c_uint32),
+        ("periodic", C.c_uint32),
+        ("tau_m", C.c_double), ("v_th", C.c_double), ("v_reset", C.c_double), ("e_rest", C.c_double),
+        ("t_ref", C.c_double), ("alpha_w", C.c_double), ("tau_w", C.c_double),
+        ("sfa_on_inh", C.c_uint32), ("pad0_", C.c_uint32),
+        ("seed", C.c_uint64), ("hist_cap", C.c_uint64),
+    ]
+
+
+class SynDesc(C.Structure):
+    _fields_ = [
+        ("kernel", C.c_uint32), ("record", C.c_uint32),
+        ("range", C.c_double), ("k_in", C.c_double),
+        ("d_min", C.c_uint32), ("d_max", C.c_uint32),
+        ("w_exc", C.c_double), ("w_exc_sd", C.c_double), ("w_inh", C.c_double),
+        ("ext_mode", C.c_uint32), ("ext_const_q", C.c_int32),
+        ("ext_n", C.c_double), ("ext_rate_hz", C.c_double), ("ext_w", C.c_double),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("t", C.c_uint64), ("spikes", C.c_uint64), ("rec_events", C.c_uint64),
+        ("ext_events", C.c_uint64), ("nnz", C.c_uint64), ("n_neurons", C.c_uint64),
+        ("bytes_device", C.c_uint64), ("hist_n", C.c_uint64), ("disagree", C.c_uint64),
+        ("build_ms", C.c_double),
+    ]
+
+
+class KernelTimes(C.Structure):
+    _fields_ = [
+        ("update_ms", C.c_double), ("compact_ms", C.c_double), ("deliver_ms", C.c_double),
+        ("step_ms", C.c_double), ("steps", C.c_uint64), ("rec_events", C.c_uint64),
+        ("spikes", C.c_uint64),
+    ]
+
+
+class SNNError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"snn status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libsnn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_1803_08833_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        P, U32, U64, SZ = C.c_void_p, C.c_uint32, C.c_uint64, C.c_size_t
+        sig = {
+            "snn_build_grid": ([C.POINTER(GridDesc), P, C.POINTER(P)], C.c_int),
+            "snn_build_synapses": ([P, C.POINTER(SynDesc)], C.c_int),
+            "snn_step": ([P, U32], C.c_int),
+            "snn_step_forced": ([P, P, SZ], C.c_int),
+            "snn_read_spikes": ([P, U64, U64, P, SZ, C.POINTER(SZ)], C.c_int),
+            "snn_read_state": ([P, P, P, P], C.c_int),
+            "snn_read_ring": ([P, P], C.c_int),
+            "snn_export_rows": ([P, U32, U32, P, P, P, SZ, C.POINTER(SZ)], C.c_int),
+            "snn_stats": ([P, C.POINTER(Stats)], C.c_int),
+            "snn_time_kernels": ([P, U32, C.POINTER(KernelTimes)], C.c_int),
+            "snn_set_option": ([P, C.c_int, C.c_int64], C.c_int),
+            "snn_host_tables": ([C.POINTER(GridDesc), C.POINTER(SynDesc), P, P, P, P, P, P], C.c_int),
+            "snn_destroy": ([P], None),
+            "snn_last_error": ([P], C.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def grid_desc(net: dict, hist_cap: int = 0) -> GridDesc:
+    g = GridDesc()
+    for k in ("gx", "gy", "n_exc", "n_inh", "periodic", "tau_m", "v_th", "v_reset", "e_rest",
+              "t_ref", "alpha_w", "tau_w", "sfa_on_inh", "seed"):
+        setattr(g, k, net[k])
+    g.hist_cap = hist_cap
+    return g
+
+
+def syn_desc(net: dict) -> SynDesc:
+    s = SynDesc()
+    for k in ("kernel", "record", "range", "k_in", "d_min", "d_max", "w_exc", "w_exc_sd", "w_inh",
+              "ext_mode", "ext_const_q", "ext_n", "ext_rate_hz", "ext_w"):
+        setattr(s, k, net[k])
+    return s
+
+
+def current_stream_handle():
+    """The torch current HIP stream as a raw handle (None without a GPU)."""
+    if torch.cuda.is_available():
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return None
+
+
+def host_tables(net: dict) -> dict:
+    """The library's own integer tables for a description (host computation)."""
+    g, s = grid_desc(net), syn_desc(net)
+    T = np.zeros(net["gx"] * net["gy"], dtype=np.uint32)
+    wtab = np.zeros(65536, dtype=np.int32)
+    cb = np.zeros(256, dtype=np.int32)
+    poisc = np.zeros(64, dtype=np.uint32)
+    npois = np.zeros(1, dtype=np.uint32)
+    consts = np.zeros(3, dtype=np.float64)
+    st = lib().snn_host_tables(C.byref(g), C.byref(s), _p(T), _p(wtab), _p(cb), _p(poisc), _p(npois),
+                               _p(consts))
+    if st != SNN_OK:
+        raise SNNError(st, lib().snn_last_error(None).decode())
+    return dict(T=T.reshape(net["gy"], net["gx"]), wtab=wtab, cb=cb, poisc=poisc[: int(npois[0])].copy(),
+                dm=consts[0], dw=consts[1], kappa=consts[2])
+
+
+class Net:
+    """One network on the GPU: build_grid at construction, then
+    build_synapses, step, read_spikes ...  (names follow the C ABI)."""
+
+    def __init__(self, net: dict, hist_cap: int = 0, stream=None):
+        self.net = dict(net)
+        self.N = net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
+        self.D = net["d_max"] - net["d_min"] + 1
+        self._g = grid_desc(net, hist_cap)
+        h = C.c_void_p()
+        st = lib().snn_build_grid(C.byref(self._g), stream, C.byref(h))
+        if st != SNN_OK:
+            raise SNNError(st, lib().snn_last_error(None).decode())
+        self.h = h
+
+    def _check(self, st):
+        if st != SNN_OK:
+            raise SNNError(st, lib().snn_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().snn_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- the ABI calls ----
+    def build_synapses(self):
+        self._s = syn_desc(self.net)
+        self._check(lib().snn_build_synapses(self.h, C.byref(self._s)))
+        return self
+
+    def step(self, n_ms: int):
+        self._check(lib().snn_step(self.h, n_ms))
+
+    def step_forced(self, gids):
+        g = np.ascontiguousarray(gids, dtype=np.uint32)
+        self._check(lib().snn_step_forced(self.h, _p(g), g.size))
+
+    def read_spikes(self, t0=0, t1=2**63):
+        n = C.c_size_t(0)
+        st = lib().snn_read_spikes(self.h, t0, t1, None, 0, C.byref(n))
+        if st not in (SNN_OK, SNN_E_TRUNC):
+            self._check(st)
+        out = np.zeros((max(n.value, 1), 2), dtype=np.uint32)
+        self._check(lib().snn_read_spikes(self.h, t0, t1, _p(out), n.value, C.byref(n)))
+        return out[: n.value]
+
+    def read_state(self):
+        V = np.zeros(self.N, dtype=np.float32)
+        W = np.zeros(self.N, dtype=np.float32)
+        R = np.zeros(self.N, dtype=np.uint8)
+        self._check(lib().snn_read_state(self.h, _p(V), _p(W), _p(R)))
+        return V, W, R
+
+    def read_ring(self):
+        r = np.zeros((RING, self.N), dtype=np.int32)
+        self._check(lib().snn_read_ring(self.h, _p(r)))
+        return r
+
+    def export_rows(self, pre0: int, n: int):
+        """(row_len u64[n], bend u16[n, D], record bytes) of rows pre0..pre0+n-1."""
+        rb = 4 if self.net["record"] == 1 else 8
+        row_len = np.zeros(n, dtype=np.uint64)
+        bend = np.zeros((n, self.D), dtype=np.uint16)
+        m = C.c_size_t(0)
+        st = lib().snn_export_rows(self.h, pre0, n, _p(row_len), _p(bend), None, 0, C.byref(m))
+        if st not in (SNN_OK, SNN_E_TRUNC):
+            self._check(st)
+        recs = np.zeros(max(m.value, 1) * rb, dtype=np.uint8)
+        self._check(lib().snn_export_rows(self.h, pre0, n, _p(row_len), _p(bend), _p(recs), m.value,
+                                          C.byref(m)))
+        return row_len, bend, recs[: m.value * rb]
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(lib().snn_stats(self.h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def time_kernels(self, n_ms: int) -> dict:
+        kt = KernelTimes()
+        self._check(lib().snn_time_kernels(self.h, n_ms, C.byref(kt)))
+        return {k: getattr(kt, k) for k, _ in KernelTimes._fields_}
+
+    def set_option(self, key: int, value: int):
+        self._check(lib().snn_set_option(self.h, key, value))
