@@ -38,6 +38,7 @@ def parse():
     p.add_argument("--ext-rate", type=float, default=None, help="override external Poisson rate (Hz)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--kernel-steps", type=int, default=200, help="steps timed per kernel with HIP events")
+    p.add_argument("--deliver-mode", type=int, default=None, help="0 direct atomics, 1 tile-binned")
     return p.parse_args()
 
 
@@ -130,6 +131,8 @@ def main():
     g.build_synapses()
     torch.cuda.synchronize()
     build_s = time.perf_counter() - tb
+    if args.deliver_mode is not None:
+        g.set_option(snn.OPT_DELIVER_MODE, args.deliver_mode)
     st0 = g.stats()
     print(f"# built {args.workload}: {N} neurons, {st0['nnz']} synapses in {build_s:.2f} s", file=sys.stderr,
           flush=True)
@@ -153,6 +156,7 @@ def main():
           file=sys.stderr, flush=True)
 
     kt = g.time_kernels(args.kernel_steps)
+    stf = g.stats()
     per_launch_events = kt["rec_events"] / max(1, kt["steps"])
     bpe = BYTES_PER_EVENT[net["record"]]
     deliver_bytes = per_launch_events * bpe
@@ -165,10 +169,12 @@ def main():
     dom = "deliver" if kt["deliver_ms"] >= kt["update_ms"] else "update"
     dom_bytes = kern[dom]["bytes"]
     achieved = dom_bytes / (kern[dom]["ms"] * 1e-3) / 1e9 if kern[dom]["ms"] > 0 else 0.0
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+    mode = "tile-binned (k_scatter + k_tile)" if stf["deliver_mode"] == 1 else "direct atomics (k_deliver)"
+    roofline = {"bound": "hbm", "kernel": dom if dom == "update" else f"deliver: {mode}",
+                "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": round(dom_bytes, 1),
-                "avg_launch_ms": round(kern[dom]["ms"], 5)}
+                "bytes_per_launch": round(dom_bytes, 1), "avg_launch_ms": round(kern[dom]["ms"], 5),
+                "events_per_launch": round(per_launch_events, 1)}
     result = {
         "metric": "synaptic events/s (24x24 exp grid)",
         "value": rec / wall,
@@ -192,7 +198,11 @@ def main():
         "total_equiv_events_per_s": (rec + ext) / wall,
         "mean_rate_hz": rate_hz,
         "build_s": build_s,
-        "kernels_ms": {k: round(v["ms"], 5) for k, v in kern.items()},
+        "kernels_ms": {"update": round(kt["update_ms"], 5), "compact": round(kt["compact_ms"], 5),
+                       "deliver": round(kt["deliver_ms"], 5), "scatter": round(kt["scatter_ms"], 5),
+                       "tile": round(kt["tile_ms"], 5)},
+        "deliver_mode": stf["deliver_mode"],
+        "bin_overflow_events": stf["bin_overflow"],
         "roofline": roofline,
         "cpu_baseline": None,
     }

@@ -114,6 +114,9 @@ typedef struct {
     uint64_t bytes_device;    /* device memory held by the network               */
     uint64_t hist_n;          /* spikes recorded (may exceed hist_cap)           */
     uint64_t disagree;        /* lock-step: own threshold test != forced set     */
+    uint64_t bin_overflow;    /* binned delivery: events that took the fallback  */
+    uint32_t deliver_mode;    /* delivery schedule in use (SNN_OPT_DELIVER_MODE) */
+    uint32_t binned_ok;       /* 1 if the network supports binned delivery       */
     double build_ms;          /* wall time of snn_build_synapses                 */
 } snn_stats_t;
 
@@ -121,7 +124,9 @@ typedef struct {
 typedef struct {
     double update_ms;         /* fused neuron update                             */
     double compact_ms;        /* ordered spike compaction                        */
-    double deliver_ms;        /* projection fan-out into the delay ring           */
+    double deliver_ms;        /* projection fan-out into the delay ring (all phases) */
+    double scatter_ms;        /* binned delivery: events binned by target tile   */
+    double tile_ms;           /* binned delivery: per-tile LDS accumulation      */
     double step_ms;           /* whole step, launched back to back               */
     uint64_t steps;
     uint64_t rec_events;      /* recurrent events delivered in the timed steps   */
@@ -132,7 +137,13 @@ typedef struct {
 enum {
     SNN_OPT_GRAPH_CHUNK = 1,     /* steps per captured HIP graph (0 = no graph)   */
     SNN_OPT_DELIVER_WAVES = 2,   /* waves in the fan-out grid                      */
-    SNN_OPT_DELIVER_UNROLL = 3   /* records in flight per lane: 1, 2 or 4          */
+    SNN_OPT_DELIVER_UNROLL = 3,  /* direct delivery: records in flight per lane: 1, 2, 4 */
+    SNN_OPT_DELIVER_MODE = 4,    /* 0: direct ring atomics; 1: tile-binned (default
+                                    when the network allows it, see snn_stats)      */
+    SNN_OPT_SCATTER_BLOCKS = 5,  /* workgroups of the binned scatter phase          */
+    SNN_OPT_BIN_FRAC_PPM = 6     /* before snn_build_synapses: bin capacity per tile
+                                    as a fraction (ppm) of its expected in-synapses;
+                                    events beyond it take the direct path           */
 };
 
 /* Create the grid (Sec. III.B) and the initial neuron state: V uniform in

@@ -3,7 +3,9 @@
 // sequences), read-back and kernel timing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -40,6 +42,10 @@ struct snn_net {
     uint32_t graph_chunk = 64;
     uint32_t deliver_waves = 8192;
     uint32_t unroll = 4;
+    uint32_t mode = 0;          // 0 direct atomics, 1 tile-binned
+    bool binned_ok = false;
+    uint32_t scatter_blocks = 256;
+    double bin_frac = 0.5;      // bin capacity as a fraction of the tile's in-synapses
     std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
@@ -110,13 +116,26 @@ snn_status check_usable(snn_net* n)
 }
 
 // Enqueue step k (0-based within the current chunk) of the plain path.
+hipError_t enqueue_deliver(snn_net* n, const StepArgs& a, uint32_t k)
+{
+    if (n->mode == 1) {
+        hipError_t e = snn::launch_scatter(a, k, n->max_len, n->scatter_blocks, n->stream);
+        if (e != hipSuccess) return e;
+        return snn::launch_tile(a, k, n->stream);
+    }
+    return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
+}
+
 hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
 {
+    const uint64_t seg = 64ull * (n->mode == 1 ? 4 : n->unroll);
+    const uint64_t smax = n->max_len ? (n->max_len + seg - 1) / seg : 1;
+    if ((uint64_t)n->N * smax >= (1ull << 32)) return hipErrorInvalidValue;
     hipError_t e = snn::launch_update(a, k, n->stream);
     if (e != hipSuccess) return e;
     e = snn::launch_compact(a, k, n->stream);
     if (e != hipSuccess) return e;
-    return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
+    return enqueue_deliver(n, a, k);
 }
 
 hipError_t get_graph(snn_net* n, uint32_t chunk, hipGraphExec_t* out)
@@ -368,6 +387,41 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     HIPCHK(n, hipStreamSynchronize(n->stream));
     dfree(n, rowlen);
     dfree(n, tsum);
+    // Tile-binned delivery: possible when the tiles fit the LDS tables and
+    // every weight has a 17-bit event field (code, or w_q + 65536 in range).
+    a.ntiles = (n->N + snn::kTile - 1) / snn::kTile;
+    a.winh_q = tb.winh_q;
+    bool ok = a.ntiles <= snn::kMaxTiles;
+    if (s->record != SNN_REC_CODE8)
+        for (int32_t w : tb.wtab)
+            if (w != tb.winh_q && (w < -65536 || w > 65534)) ok = false;
+    n->binned_ok = ok;
+    if (ok) {
+        HIPCHK(n, snn::setup_kernels());
+        std::vector<uint64_t> base(a.ntiles);
+        std::vector<uint32_t> cap(a.ntiles);
+        uint64_t tot = 0;
+        for (uint32_t i = 0; i < a.ntiles; ++i) {
+            const uint32_t nn = (n->N - i * snn::kTile) < snn::kTile ? n->N - i * snn::kTile : snn::kTile;
+            const double c = n->bin_frac * (double)nn * (s->k_in + 6.0 * std::sqrt(s->k_in + 1.0)) + 4096.0;
+            cap[i] = (uint32_t)std::min(c, 4.0e9);
+            base[i] = tot;
+            tot += cap[i];
+        }
+        uint64_t* dbase = nullptr;
+        uint32_t* dcap = nullptr;
+        e = dalloc(n, &a.bin_fill, a.ntiles);
+        if (e == hipSuccess) e = dalloc(n, &dbase, a.ntiles);
+        if (e == hipSuccess) e = dalloc(n, &dcap, a.ntiles);
+        if (e == hipSuccess) e = dalloc(n, &a.bins, tot);
+        if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
+        HIPCHK(n, hipMemcpy(dbase, base.data(), 8 * base.size(), hipMemcpyHostToDevice));
+        HIPCHK(n, hipMemcpy(dcap, cap.data(), 4 * cap.size(), hipMemcpyHostToDevice));
+        HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles));
+        a.bin_base = dbase;
+        a.bin_cap = dcap;
+        n->mode = 1;
+    }
     n->built = true;
     n->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SNN_OK;
@@ -516,6 +570,9 @@ snn_status snn_stats(snn_net* n, snn_stats_t* out)
     out->bytes_device = n->bytes;
     out->hist_n = hc.hist_n;
     out->disagree = hc.disagree;
+    out->bin_overflow = hc.bin_overflow;
+    out->deliver_mode = n->mode;
+    out->binned_ok = n->binned_ok ? 1u : 0u;
     out->build_ms = n->build_ms;
     return SNN_OK;
 }
@@ -527,30 +584,40 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
     if (!out) return fail(n, SNN_E_INVAL, "null output");
     std::memset(out, 0, sizeof(*out));
-    hipEvent_t ev[4];
+    hipEvent_t ev[5];
     for (auto& e : ev) HIPCHK(n, hipEventCreate(&e));
     Ctrl c0{}, c1{};
     HIPCHK(n, hipStreamSynchronize(n->stream));
     HIPCHK(n, hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    double tu = 0, tc = 0, td = 0, ts = 0;
+    double tu = 0, tc = 0, td = 0, ts = 0, ta = 0, tb = 0;
     for (uint32_t k = 0; k < n_ms; ++k) {
         HIPCHK(n, hipEventRecord(ev[0], n->stream));
         HIPCHK(n, snn::launch_update(n->a, 0, n->stream));
         HIPCHK(n, hipEventRecord(ev[1], n->stream));
         HIPCHK(n, snn::launch_compact(n->a, 0, n->stream));
         HIPCHK(n, hipEventRecord(ev[2], n->stream));
-        HIPCHK(n, snn::launch_deliver(n->a, 0, n->deliver_waves, n->unroll, n->max_len, n->stream));
-        HIPCHK(n, hipEventRecord(ev[3], n->stream));
+        if (n->mode == 1) {
+            HIPCHK(n, snn::launch_scatter(n->a, 0, n->max_len, n->scatter_blocks, n->stream));
+            HIPCHK(n, hipEventRecord(ev[3], n->stream));
+            HIPCHK(n, snn::launch_tile(n->a, 0, n->stream));
+        } else {
+            HIPCHK(n, snn::launch_deliver(n->a, 0, n->deliver_waves, n->unroll, n->max_len, n->stream));
+            HIPCHK(n, hipEventRecord(ev[3], n->stream));
+        }
+        HIPCHK(n, hipEventRecord(ev[4], n->stream));
         HIPCHK(n, snn::launch_advance(n->a.ctrl, 1, n->stream));
-        HIPCHK(n, hipEventSynchronize(ev[3]));
-        float a = 0, b = 0, c = 0, d = 0;
+        HIPCHK(n, hipEventSynchronize(ev[4]));
+        float a = 0, b = 0, c = 0, d = 0, f = 0;
         HIPCHK(n, hipEventElapsedTime(&a, ev[0], ev[1]));
         HIPCHK(n, hipEventElapsedTime(&b, ev[1], ev[2]));
         HIPCHK(n, hipEventElapsedTime(&c, ev[2], ev[3]));
-        HIPCHK(n, hipEventElapsedTime(&d, ev[0], ev[3]));
+        HIPCHK(n, hipEventElapsedTime(&f, ev[3], ev[4]));
+        HIPCHK(n, hipEventElapsedTime(&d, ev[0], ev[4]));
         tu += a;
         tc += b;
-        td += c;
+        ta += c;
+        tb += f;
+        td += c + f;
         ts += d;
     }
     HIPCHK(n, hipStreamSynchronize(n->stream));
@@ -560,6 +627,8 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     out->update_ms = tu / k;
     out->compact_ms = tc / k;
     out->deliver_ms = td / k;
+    out->scatter_ms = ta / k;
+    out->tile_ms = tb / k;
     out->step_ms = ts / k;
     out->steps = n_ms;
     out->rec_events = c1.rec_events - c0.rec_events;
@@ -579,6 +648,20 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
     case SNN_OPT_DELIVER_WAVES:
         if (value < 4 || value > (1 << 20)) return fail(n, SNN_E_INVAL, "wave count out of range");
         n->deliver_waves = (uint32_t)value;
+        break;
+    case SNN_OPT_DELIVER_MODE:
+        if (value != 0 && value != 1) return fail(n, SNN_E_INVAL, "delivery mode must be 0 or 1");
+        if (value == 1 && !n->binned_ok) return fail(n, SNN_E_INVAL, "this network cannot use binned delivery");
+        n->mode = (uint32_t)value;
+        break;
+    case SNN_OPT_BIN_FRAC_PPM:
+        if (n->built) return fail(n, SNN_E_STATE, "bin capacity is fixed once synapses are built");
+        if (value < 1 || value > 4000000) return fail(n, SNN_E_INVAL, "bin fraction out of range");
+        n->bin_frac = (double)value * 1e-6;
+        return SNN_OK;
+    case SNN_OPT_SCATTER_BLOCKS:
+        if (value < 1 || value > 65536) return fail(n, SNN_E_INVAL, "scatter blocks out of range");
+        n->scatter_blocks = (uint32_t)value;
         break;
     case SNN_OPT_DELIVER_UNROLL:
         if (value != 1 && value != 2 && value != 4) return fail(n, SNN_E_INVAL, "unroll must be 1, 2 or 4");

@@ -8,6 +8,8 @@
 //                 block-local spike compaction
 //   k_compact     ordered global spike list + AER history
 //   k_deliver     wave-per-row-segment fan-out into the delay ring (int32 atomics)
+//   k_scatter     tile-binned delivery, phase A: events binned by target tile
+//   k_tile        tile-binned delivery, phase B: LDS accumulation, ring write-back
 //
 // Nothing here is a dense contraction: the path is bound by HBM/L2 traffic and
 // atomics (update, delivery) or by 32-bit integer multiplies (Philox), so no MFMA.
@@ -328,7 +330,10 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
     __shared__ uint32_t wtot[4];
     __shared__ unsigned long long wext[4];
     __shared__ uint32_t wdis[4];
+    __shared__ uint32_t pois_s[kMaxPois];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    if (tid < a.npois) pois_s[tid] = a.poisc[tid];
+    __syncthreads();
     const uint32_t q = blockIdx.x * 256u + tid;
     const uint32_t t = a.ctrl->t0 + k;
     uint32_t flags = 0, ext_tot = 0, dis = 0;
@@ -346,7 +351,7 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
             const uint4 u = philox(q, t, kStreamExt, 0u, a.key0, a.key1);
             uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
             for (uint32_t i = 0; i < a.npois; ++i) {
-                const uint32_t th = a.poisc[i];
+                const uint32_t th = pois_s[i];
                 c0 += (th <= u.x) ? 1u : 0u;
                 c1 += (th <= u.y) ? 1u : 0u;
                 c2 += (th <= u.z) ? 1u : 0u;
@@ -408,9 +413,11 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
 // ---------------------------------------------------------------------------
 // Ordered global compaction: block g owns update blocks [64g, 64g+64); its
 // base offset is the sum of the group counts before it (this step's parity
-// buffer).  Writes the step's spike list and the AER history, counts the
-// recurrent events of the step, and clears its entry of the other parity
-// buffer for the next step.
+// buffer).  Each thread places one spike: it finds the spike's update block by
+// binary search over the group's block offsets, then writes the step's spike
+// record {gid, row length, row start} and the AER history entry.  Also counts
+// the step's recurrent events and clears this group's entry of the other
+// parity buffer for the next step.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
 {
@@ -437,17 +444,21 @@ __global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
     const uint32_t gtot = boff[nb];
     const uint64_t h0 = a.ctrl->hist_n;
     unsigned long long ev = 0;
-    for (uint32_t b = 0; b < nb; ++b) {
-        const uint32_t cnt = boff[b + 1] - boff[b];
-        const uint32_t* src = a.blk_list + (size_t)(b0 + b) * kNeuronsPerBlock;
-        for (uint32_t i = tid; i < cnt; i += 256u) {
-            const uint32_t gid = src[i];
-            const uint32_t p = base + boff[b] + i;
-            a.spk[p] = gid;
-            const uint64_t hp = h0 + p;
-            if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, gid);
-            ev += a.row_ptr[gid + 1] - a.row_ptr[gid];
+    for (uint32_t i = tid; i < gtot; i += 256u) {
+        uint32_t lo = 0, hi = nb;   // boff[lo] <= i < boff[hi]
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (boff[mid] <= i) lo = mid;
+            else hi = mid;
         }
+        const uint32_t gid = a.blk_list[(size_t)(b0 + lo) * kNeuronsPerBlock + (i - boff[lo])];
+        const uint32_t p = base + i;
+        const uint64_t rb = a.row_ptr[gid];
+        const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
+        a.spk[p] = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+        const uint64_t hp = h0 + p;
+        if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, gid);
+        ev += len;
     }
     ev = wave_sum<unsigned long long>(ev);
     if (lane == 0) wev[wv] = ev;
@@ -486,33 +497,37 @@ __global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_
     const uint32_t n = a.ctrl->nspk;
     if (wave == 0 && lane == 0) a.ctrl->hist_n += n;
     constexpr uint32_t SEG = 64u * U;
-    const uint64_t items = (uint64_t)n * smax;
-    for (uint64_t it = wave; it < items; it += nw) {
-        const uint32_t si = (uint32_t)(it / smax);
-        const uint32_t seg = (uint32_t)(it - (uint64_t)si * smax);
-        const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.spk[si]);
-        const uint64_t rb = a.row_ptr[pre];
-        const uint32_t len = (uint32_t)(a.row_ptr[pre + 1] - rb);
+    const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
+    uint32_t it = wave;
+    uint4 nxt = make_uint4(0, 0, 0, 0);
+    if (it < items) nxt = a.spk[it / smax];
+    while (it < items) {
+        const uint4 info = nxt;
+        const uint32_t seg = it % smax;
+        const uint32_t itn = it + nw;
+        if (itn < items) nxt = a.spk[itn / smax];     // prefetch the next item's spike record
+        it = itn;
+        const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
+        const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.y);
+        const uint64_t rb = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.z) |
+                            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
         const uint32_t c0 = seg * SEG;
         if (c0 >= len) continue;
         const uint32_t be = lane < a.D ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
         uint32_t tg[U];
         int32_t wq[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t kk = c0 + 64u * u + lane;
-            tg[u] = 0;
-            wq[u] = 0;
-            if (kk < len) {
-                if (CODE8) {
-                    const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
-                    tg[u] = v >> 8;
-                    wq[u] = (int32_t)(v & 255u);
-                } else {
-                    const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
-                    tg[u] = r.tgt;
-                    wq[u] = __float2int_rn(r.w * 65536.0f);
-                }
+        for (int u = 0; u < U; ++u) {   // all loads issued before any use
+            uint32_t kk = c0 + 64u * u + lane;
+            kk = kk < len ? kk : len - 1u;
+            if (CODE8) {
+                const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
+                tg[u] = v >> 8;
+                wq[u] = (int32_t)(v & 255u);
+            } else {
+                const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
+                tg[u] = r.tgt;
+                wq[u] = __float2int_rn(r.w * 65536.0f);
             }
         }
 #pragma unroll
@@ -535,6 +550,259 @@ __global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_
             }
         }
     }
+}
+
+
+// ---------------------------------------------------------------------------
+// Tile-binned delivery, phase A (scatter).  Scattered global atomics are
+// limited to a few tens of G/s on this GPU, so events are first grouped by
+// target tile (1024 targets).  A workgroup takes a chunk of row segments and
+//   1. counts the chunk's events per tile in LDS,
+//   2. reserves room in each tile's bin with one global atomic per tile,
+//   3. re-reads the records, encodes each event in 32 bits
+//      (target & 1023 | delay bucket << 10 | weight field << 15) and stages
+//      it in LDS sorted by tile,
+//   4. writes each tile's run contiguously into the tile's bin.
+// Events that do not fit in a bin fall back to a direct ring atomic.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int32_t decode_weight(uint32_t field, bool code8, const int32_t* cb, int32_t winh)
+{
+    if (code8) return cb[field];
+    return field == kWInhField ? winh : (int32_t)field - 65536;
+}
+
+// One row segment (256 records) of the scatter phase: the spike record, the
+// four records of this lane, and the bucket ends of the row (one per lane).
+struct SegLoad {
+    uint32_t pre, len, s0, be;
+    uint32_t tg[4], wf[4];
+};
+
+template <bool CODE8, bool FULL>
+__device__ __forceinline__ SegLoad seg_load(const StepArgs& a, uint32_t it, uint32_t smax, uint32_t lane)
+{
+    SegLoad L;
+    const uint4 info = a.spk[it / smax];
+    L.pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
+    L.len = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.y);
+    const uint64_t rb = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.z) |
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
+    L.s0 = (it % smax) * 256u;
+    L.be = 0xFFFFFFFFu;
+    if (L.s0 >= L.len) return L;
+    if (FULL && lane < a.D) L.be = (uint32_t)a.bend[(size_t)L.pre * a.D + lane];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        uint32_t kk = L.s0 + 64u * u + lane;
+        kk = kk < L.len ? kk : L.len - 1u;
+        if (CODE8) {
+            const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
+            L.tg[u] = v >> 8;
+            L.wf[u] = v & 255u;
+        } else {
+            const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
+            L.tg[u] = r.tgt;
+            if (FULL) {
+                const int32_t wq = __float2int_rn(r.w * 65536.0f);
+                L.wf[u] = wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536);
+            } else {
+                L.wf[u] = 0;
+            }
+        }
+    }
+    return L;
+}
+
+__device__ __forceinline__ void seg_count(const SegLoad& L, uint32_t lane, uint32_t* tcnt)
+{
+    if (L.s0 >= L.len) return;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+        if (L.s0 + 64u * u + lane < L.len) atomicAdd(&tcnt[L.tg[u] >> kTileBits], 1u);
+}
+
+__device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint32_t* tcnt, uint32_t* stage)
+{
+    if (L.s0 >= L.len) return;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const uint32_t c = L.s0 + 64u * u;
+        if (c >= L.len) break;
+        const uint32_t kk = c + lane;
+        uint32_t bl = popc(__ballot(L.be <= c));
+        uint64_t inm = __ballot(L.be > c && L.be < c + 64u);
+        while (inm) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+            inm &= inm - 1u;
+            bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
+        }
+        if (kk < L.len) {
+            const uint32_t p = atomicAdd(&tcnt[L.tg[u] >> kTileBits], 1u);
+            stage[p] = (L.tg[u] & (kTile - 1u)) | (bl << kTileBits) | (L.wf[u] << 15);
+        }
+    }
+}
+
+constexpr uint32_t kScatterThreads = 1024;
+constexpr uint32_t kScatterWaves = kScatterThreads / 64;
+
+template <bool CODE8>
+__global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
+{
+    __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t tcnt[kMaxTiles];   // counts, then fill cursor
+    __shared__ uint32_t toff[kMaxTiles];   // start of each tile's run in `stage`
+    __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the tile's bin
+    __shared__ int32_t cb_s[256];
+    __shared__ uint32_t wsum[kScatterWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    if (CODE8 && tid < 256u) cb_s[tid] = a.cb[tid];
+    const uint32_t t = a.ctrl->t0 + k;
+    const uint32_t n = a.ctrl->nspk;
+    if (blockIdx.x == 0 && tid == 0) a.ctrl->hist_n += n;
+    const uint32_t items = n * smax;
+    const uint32_t nt = a.ntiles;
+    // chunk size: large chunks bin better, but every workgroup should get work
+    uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
+    per = per < 2u * kScatterWaves ? 2u * kScatterWaves : (per > kChunkItems ? kChunkItems : per);
+    unsigned long long spill = 0;
+    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += gridDim.x * per) {
+        const uint32_t c1 = (items - c0) < per ? items : c0 + per;
+        for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
+        __syncthreads();
+        // 1. histogram of targets by tile (two row segments in flight per wave)
+        for (uint32_t it = c0 + wv; it < c1; it += 2u * kScatterWaves) {
+            const uint32_t it2 = it + kScatterWaves;
+            const SegLoad A = seg_load<CODE8, false>(a, it, smax, lane);
+            SegLoad B;
+            B.s0 = 1u;
+            B.len = 0u;
+            if (it2 < c1) B = seg_load<CODE8, false>(a, it2, smax, lane);
+            seg_count(A, lane, tcnt);
+            seg_count(B, lane, tcnt);
+        }
+        __syncthreads();
+        // 2. exclusive scan of the counts (2 tiles per thread) and bin reservation
+        {
+            uint32_t v0 = 2u * tid < nt ? tcnt[2u * tid] : 0u;
+            uint32_t v1 = 2u * tid + 1u < nt ? tcnt[2u * tid + 1u] : 0u;
+            const uint32_t sum = v0 + v1;
+            const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
+            if (lane == 63u) wsum[wv] = inc;
+            __syncthreads();
+            uint32_t off = inc - sum;
+            for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
+            if (2u * tid < nt) {
+                toff[2u * tid] = off;
+                tcnt[2u * tid] = off;
+                tres[2u * tid] = v0 ? atomicAdd(&a.bin_fill[2u * tid], v0) : 0u;
+            }
+            if (2u * tid + 1u < nt) {
+                toff[2u * tid + 1u] = off + v0;
+                tcnt[2u * tid + 1u] = off + v0;
+                tres[2u * tid + 1u] = v1 ? atomicAdd(&a.bin_fill[2u * tid + 1u], v1) : 0u;
+            }
+        }
+        __syncthreads();
+        // 3. encode and stage sorted by tile
+        for (uint32_t it = c0 + wv; it < c1; it += 2u * kScatterWaves) {
+            const uint32_t it2 = it + kScatterWaves;
+            const SegLoad A = seg_load<CODE8, true>(a, it, smax, lane);
+            SegLoad B;
+            B.s0 = 1u;
+            B.len = 0u;
+            if (it2 < c1) B = seg_load<CODE8, true>(a, it2, smax, lane);
+            seg_stage(A, lane, tcnt, stage);
+            seg_stage(B, lane, tcnt, stage);
+        }
+        __syncthreads();
+        // 4. contiguous runs into the bins (one wave per tile)
+        for (uint32_t tt = wv; tt < nt; tt += kScatterWaves) {
+            const uint32_t o0 = toff[tt];
+            const uint32_t cnt = tcnt[tt] - o0;
+            if (cnt == 0) continue;
+            const uint32_t r0 = tres[tt];
+            const uint32_t cap = a.bin_cap[tt];
+            uint32_t* dst = a.bins + a.bin_base[tt];
+            for (uint32_t e = lane; e < cnt; e += 64u) {
+                const uint32_t code = stage[o0 + e];
+                const uint32_t pos = r0 + e;
+                if (pos < cap) {
+                    dst[pos] = code;
+                } else {
+                    const uint32_t tgt = (tt << kTileBits) | (code & (kTile - 1u));
+                    const uint32_t b = (code >> kTileBits) & 31u;
+                    const int32_t w = decode_weight(code >> 15, CODE8, cb_s, a.winh_q);
+                    const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                    __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, w, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    spill += 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    spill = wave_sum<unsigned long long>(spill);
+    if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
+}
+
+// ---------------------------------------------------------------------------
+// Tile-binned delivery, phase B: one workgroup per tile of 1024 targets.  The
+// tile's D future ring rows are loaded into LDS, the tile's binned events are
+// added with LDS atomics, and the rows are written back (coalesced 16-byte
+// accesses); the bin is emptied for the next step.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kTileThreads = 1024;
+
+template <bool CODE8>
+__global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
+{
+    extern __shared__ int32_t acc[];      // [D][1024]
+    const uint32_t tid = threadIdx.x, tt = blockIdx.x;
+    const uint32_t g0 = tt << kTileBits;
+    const uint32_t nn = (a.N - g0) < kTile ? (a.N - g0) : kTile;
+    const uint32_t t = a.ctrl->t0 + k;
+    const uint32_t D = a.D;
+    for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
+        const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
+        int4 v = make_int4(0, 0, 0, 0);
+        if (4u * q < nn) {
+            const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+            v = reinterpret_cast<const int4*>(a.ring + (size_t)slot * a.N + g0)[q];
+        }
+        reinterpret_cast<int4*>(acc)[idx] = v;
+    }
+    __syncthreads();
+    const uint32_t fill = a.bin_fill[tt];
+    const uint32_t cap = a.bin_cap[tt];
+    const uint32_t n = fill < cap ? fill : cap;
+    const uint32_t* ev = a.bins + a.bin_base[tt];
+    constexpr uint32_t U = 8;
+    for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
+        uint32_t code[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t e = e0 + u * kTileThreads + tid;
+            code[u] = e < n ? ev[e] : 0xFFFFFFFFu;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            if (code[u] != 0xFFFFFFFFu) {
+                const uint32_t b = (code[u] >> kTileBits) & 31u;
+                atomicAdd(&acc[b * kTile + (code[u] & (kTile - 1u))],
+                          decode_weight(code[u] >> 15, CODE8, a.cb, a.winh_q));
+            }
+        }
+    }
+    __syncthreads();
+    for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
+        const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
+        if (4u * q < nn) {
+            const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+            reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[q] = reinterpret_cast<const int4*>(acc)[idx];
+        }
+    }
+    if (tid == 0) a.bin_fill[tt] = 0u;
 }
 
 __global__ void k_advance(Ctrl* c, uint32_t n)
@@ -616,6 +884,32 @@ hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_
         SNN_DELIVER(4);
     }
 #undef SNN_DELIVER
+    return hipGetLastError();
+}
+
+hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
+                          hipStream_t s)
+{
+    const uint32_t smax = max_len ? cdiv(max_len, 256) : 1u;
+    if (a.record == 1u) hipLaunchKernelGGL((k_scatter<true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    else hipLaunchKernelGGL((k_scatter<false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    return hipGetLastError();
+}
+
+hipError_t setup_kernels()
+{
+    // phase B keeps D rows of 1024 int32 in LDS (up to 124 KB of the 160 KB per CU)
+    const int lds = (int)(kMaxD * kTile * sizeof(int32_t));
+    hipError_t e = hipFuncSetAttribute((const void*)k_tile<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void*)k_tile<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+}
+
+hipError_t launch_tile(const StepArgs& a, uint32_t k, hipStream_t s)
+{
+    const size_t lds = (size_t)a.D * kTile * sizeof(int32_t);
+    if (a.record == 1u) hipLaunchKernelGGL((k_tile<true>), dim3(a.ntiles), dim3(kTileThreads), lds, s, a, k);
+    else hipLaunchKernelGGL((k_tile<false>), dim3(a.ntiles), dim3(kTileThreads), lds, s, a, k);
     return hipGetLastError();
 }
 

@@ -13,6 +13,14 @@ constexpr uint32_t kNeuronsPerBlock = 4 * kQuadsPerBlock;  // one update block: 
 constexpr uint32_t kGroup = 64;     // update blocks per compaction group
 constexpr uint32_t kMaxPois = 64;   // Poisson CDF thresholds
 constexpr uint32_t kMaxD = 31;      // delay buckets per row
+// Tile-binned delivery: targets are grouped in tiles of 1024; each step's
+// events are binned per tile, then accumulated in LDS tile by tile.
+constexpr uint32_t kTileBits = 10;
+constexpr uint32_t kTile = 1u << kTileBits;
+constexpr uint32_t kMaxTiles = 2048;          // binned delivery needs N <= 2M neurons
+constexpr uint32_t kChunkItems = 128;         // row segments (256 records) per scatter chunk
+constexpr uint32_t kStage = kChunkItems * 256;
+constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for the inhibitory weight
 
 // Philox stream identifiers (third counter word).
 constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
@@ -33,6 +41,7 @@ struct Ctrl {
     uint64_t disagree;      // lock-step threshold disagreements
     uint32_t err;           // construction error flags (bit 0: row longer than 65535)
     uint32_t max_len;       // longest projection row
+    uint64_t bin_overflow;  // events delivered by the direct fallback (bin full)
 };
 
 // Everything the step kernels read, passed by value.
@@ -52,7 +61,7 @@ struct StepArgs {
     uint32_t* blk_cnt;      // [nblk]
     uint32_t* blk_list;     // [nblk * kNeuronsPerBlock]
     uint32_t* grp_cnt;      // [2][ngrp]
-    uint32_t* spk;          // [N] spike ids of the step in flight
+    uint4* spk;             // [N] spikes of the step in flight: {gid, row length, row start lo, hi}
     uint2* hist;            // [hist_cap] (t, gid)
     Ctrl* ctrl;
     const uint64_t* row_ptr;  // [N+1]
@@ -61,6 +70,13 @@ struct StepArgs {
     const uint32_t* poisc;    // [npois]
     const int32_t* cb;        // [256] codebook (CODE8 records)
     const uint8_t* forced;    // lock-step flags or nullptr
+    // tile-binned delivery
+    uint32_t ntiles;
+    int32_t winh_q;
+    uint32_t* bin_fill;       // [ntiles] events binned this step
+    const uint64_t* bin_base; // [ntiles] start of each tile's bin
+    const uint32_t* bin_cap;  // [ntiles]
+    uint32_t* bins;           // event codes: target & 1023 | bucket << 10 | weight field << 15
 };
 
 // Arguments of the projection builder.
@@ -88,6 +104,10 @@ hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s);
 hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s);
 hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_t unroll,
                           uint32_t max_len, hipStream_t s);
+hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
+                          hipStream_t s);
+hipError_t launch_tile(const StepArgs& a, uint32_t k, hipStream_t s);
+hipError_t setup_kernels();
 hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s);
 hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v,
                             hipStream_t s);

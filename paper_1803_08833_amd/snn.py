@@ -18,7 +18,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libsnn.so")
 
 SNN_OK, SNN_E_INVAL, SNN_E_NOMEM, SNN_E_HIP, SNN_E_STATE, SNN_E_OVERFLOW, SNN_E_TRUNC = 0, -1, -2, -3, -4, -5, -6
-OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL = 1, 2, 3
+OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL, OPT_DELIVER_MODE, OPT_SCATTER_BLOCKS = 1, 2, 3, 4, 5
+OPT_BIN_FRAC_PPM = 6
 RING = 32
 
 EXPORTS = [
@@ -55,6 +56,7 @@ class Stats(C.Structure):
         ("t", C.c_uint64), ("spikes", C.c_uint64), ("rec_events", C.c_uint64),
         ("ext_events", C.c_uint64), ("nnz", C.c_uint64), ("n_neurons", C.c_uint64),
         ("bytes_device", C.c_uint64), ("hist_n", C.c_uint64), ("disagree", C.c_uint64),
+        ("bin_overflow", C.c_uint64), ("deliver_mode", C.c_uint32), ("binned_ok", C.c_uint32),
         ("build_ms", C.c_double),
     ]
 
@@ -62,7 +64,7 @@ class Stats(C.Structure):
 class KernelTimes(C.Structure):
     _fields_ = [
         ("update_ms", C.c_double), ("compact_ms", C.c_double), ("deliver_ms", C.c_double),
-        ("step_ms", C.c_double), ("steps", C.c_uint64), ("rec_events", C.c_uint64),
+        ("scatter_ms", C.c_double), ("tile_ms", C.c_double), ("step_ms", C.c_double), ("steps", C.c_uint64), ("rec_events", C.c_uint64),
         ("spikes", C.c_uint64),
     ]
 

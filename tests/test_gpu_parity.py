@@ -210,20 +210,44 @@ def test_free_running_rate_small(snn, oracle_mod):
 
 def test_determinism_and_schedules(snn):
     net = W.workload("grid4_gauss", seed=31)["net"]
-    say("case: determinism across runs, graph chunking and unroll")
+    say("case: determinism across runs, delivery schedules, graph chunking and unroll")
     rings, spikes = [], []
-    for chunk, unroll, waves in ((64, 4, 8192), (0, 1, 64), (7, 2, 1000)):
+    variants = ((1, 64, 4, 8192, 256), (0, 64, 4, 8192, 256), (0, 0, 1, 64, 256), (0, 7, 2, 1000, 256),
+                (1, 0, 4, 8192, 3), (1, 13, 4, 8192, 1024))
+    for mode, chunk, unroll, waves, sblocks in variants:
         with snn.Net(net) as g:
             g.build_synapses()
+            assert g.stats()["binned_ok"] == 1
+            g.set_option(snn.OPT_DELIVER_MODE, mode)
             g.set_option(snn.OPT_GRAPH_CHUNK, chunk)
             g.set_option(snn.OPT_DELIVER_UNROLL, unroll)
             g.set_option(snn.OPT_DELIVER_WAVES, waves)
+            g.set_option(snn.OPT_SCATTER_BLOCKS, sblocks)
             g.step(300)
             rings.append(g.read_ring())
             spikes.append(g.read_spikes())
+            assert g.stats()["deliver_mode"] == mode
     for r, s in zip(rings[1:], spikes[1:]):
         np.testing.assert_array_equal(r, rings[0])
         np.testing.assert_array_equal(s, spikes[0])
+
+
+def test_bin_overflow_fallback_is_exact(snn):
+    """Bins far too small: most events take the direct fallback, the ring and
+    raster must still equal the direct schedule's."""
+    net = W.workload("grid4_gauss", seed=32)["net"]
+    say("case: binned delivery with tiny bins (fallback path)")
+    out = []
+    for mode, ppm in ((0, 500000), (1, 1)):
+        with snn.Net(net) as g:
+            g.set_option(snn.OPT_BIN_FRAC_PPM, ppm)
+            g.build_synapses()
+            g.set_option(snn.OPT_DELIVER_MODE, mode)
+            g.step(200)
+            out.append((g.read_ring(), g.read_spikes(), g.stats()))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[1][2]["bin_overflow"] > 0
 
 
 def test_errors_and_lifecycle(snn):
