@@ -398,28 +398,12 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     n->binned_ok = ok;
     if (ok) {
         HIPCHK(n, snn::setup_kernels());
-        std::vector<uint64_t> base(a.ntiles);
-        std::vector<uint32_t> cap(a.ntiles);
-        uint64_t tot = 0;
-        for (uint32_t i = 0; i < a.ntiles; ++i) {
-            const uint32_t nn = (n->N - i * snn::kTile) < snn::kTile ? n->N - i * snn::kTile : snn::kTile;
-            const double c = n->bin_frac * (double)nn * (s->k_in + 6.0 * std::sqrt(s->k_in + 1.0)) + 4096.0;
-            cap[i] = (uint32_t)std::min(c, 4.0e9);
-            base[i] = tot;
-            tot += cap[i];
-        }
-        uint64_t* dbase = nullptr;
-        uint32_t* dcap = nullptr;
+        const double c = n->bin_frac * (double)snn::kTile * (s->k_in + 6.0 * std::sqrt(s->k_in + 1.0)) + 4096.0;
+        a.bin_cap_tile = (uint32_t)std::min(c, 1.0e9);
         e = dalloc(n, &a.bin_fill, a.ntiles);
-        if (e == hipSuccess) e = dalloc(n, &dbase, a.ntiles);
-        if (e == hipSuccess) e = dalloc(n, &dcap, a.ntiles);
-        if (e == hipSuccess) e = dalloc(n, &a.bins, tot);
+        if (e == hipSuccess) e = dalloc(n, &a.bins, (size_t)a.ntiles * a.bin_cap_tile);
         if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
-        HIPCHK(n, hipMemcpy(dbase, base.data(), 8 * base.size(), hipMemcpyHostToDevice));
-        HIPCHK(n, hipMemcpy(dcap, cap.data(), 4 * cap.size(), hipMemcpyHostToDevice));
         HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles));
-        a.bin_base = dbase;
-        a.bin_cap = dcap;
         n->mode = 1;
     }
     n->built = true;

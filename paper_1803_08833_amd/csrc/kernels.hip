@@ -571,26 +571,25 @@ __device__ __forceinline__ int32_t decode_weight(uint32_t field, bool code8, con
     return field == kWInhField ? winh : (int32_t)field - 65536;
 }
 
-// One row segment (256 records) of the scatter phase: the spike record, the
-// four records of this lane, and the bucket ends of the row (one per lane).
+// One row segment (256 records) of the scatter phase, held in registers from
+// the counting pass to the staging pass: this lane's four records (target,
+// weight field) and the row's bucket ends (one per lane).
 struct SegLoad {
-    uint32_t pre, len, s0, be;
+    uint32_t len, s0, be;
     uint32_t tg[4], wf[4];
 };
 
-template <bool CODE8, bool FULL>
-__device__ __forceinline__ SegLoad seg_load(const StepArgs& a, uint32_t it, uint32_t smax, uint32_t lane)
+template <bool CODE8>
+__device__ __forceinline__ void seg_load(const StepArgs& a, uint4 info, uint32_t seg, uint32_t lane, SegLoad& L)
 {
-    SegLoad L;
-    const uint4 info = a.spk[it / smax];
-    L.pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
+    const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
     L.len = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.y);
     const uint64_t rb = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.z) |
                         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
-    L.s0 = (it % smax) * 256u;
+    L.s0 = seg * 256u;
     L.be = 0xFFFFFFFFu;
-    if (L.s0 >= L.len) return L;
-    if (FULL && lane < a.D) L.be = (uint32_t)a.bend[(size_t)L.pre * a.D + lane];
+    if (L.s0 >= L.len) return;
+    if (lane < a.D) L.be = (uint32_t)a.bend[(size_t)pre * a.D + lane];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         uint32_t kk = L.s0 + 64u * u + lane;
@@ -602,15 +601,10 @@ __device__ __forceinline__ SegLoad seg_load(const StepArgs& a, uint32_t it, uint
         } else {
             const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
             L.tg[u] = r.tgt;
-            if (FULL) {
-                const int32_t wq = __float2int_rn(r.w * 65536.0f);
-                L.wf[u] = wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536);
-            } else {
-                L.wf[u] = 0;
-            }
+            const int32_t wq = __float2int_rn(r.w * 65536.0f);
+            L.wf[u] = wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536);
         }
     }
-    return L;
 }
 
 __device__ __forceinline__ void seg_count(const SegLoad& L, uint32_t lane, uint32_t* tcnt)
@@ -645,6 +639,7 @@ __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint3
 
 constexpr uint32_t kScatterThreads = 1024;
 constexpr uint32_t kScatterWaves = kScatterThreads / 64;
+constexpr uint32_t kSegPerWave = kChunkItems / kScatterWaves;   // 7 row segments per wave
 
 template <bool CODE8>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
@@ -662,59 +657,58 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     if (blockIdx.x == 0 && tid == 0) a.ctrl->hist_n += n;
     const uint32_t items = n * smax;
     const uint32_t nt = a.ntiles;
+    const uint32_t cap = a.bin_cap_tile;
     // chunk size: large chunks bin better, but every workgroup should get work
     uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
-    per = per < 2u * kScatterWaves ? 2u * kScatterWaves : (per > kChunkItems ? kChunkItems : per);
+    per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
     unsigned long long spill = 0;
     for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += gridDim.x * per) {
         const uint32_t c1 = (items - c0) < per ? items : c0 + per;
         for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
-        __syncthreads();
-        // 1. histogram of targets by tile (two row segments in flight per wave)
-        for (uint32_t it = c0 + wv; it < c1; it += 2u * kScatterWaves) {
-            const uint32_t it2 = it + kScatterWaves;
-            const SegLoad A = seg_load<CODE8, false>(a, it, smax, lane);
-            SegLoad B;
-            B.s0 = 1u;
-            B.len = 0u;
-            if (it2 < c1) B = seg_load<CODE8, false>(a, it2, smax, lane);
-            seg_count(A, lane, tcnt);
-            seg_count(B, lane, tcnt);
+        // this wave's row segments: items c0 + wv + 16 j; all loads issued before use
+        uint4 info[kSegPerWave];
+#pragma unroll
+        for (uint32_t j = 0; j < kSegPerWave; ++j) {
+            const uint32_t it = c0 + wv + kScatterWaves * j;
+            info[j] = it < c1 ? a.spk[it / smax] : make_uint4(0, 0, 0, 0);
         }
+        SegLoad S[kSegPerWave];
+#pragma unroll
+        for (uint32_t j = 0; j < kSegPerWave; ++j) {
+            const uint32_t it = c0 + wv + kScatterWaves * j;
+            seg_load<CODE8>(a, info[j], it < c1 ? it % smax : 0u, lane, S[j]);
+        }
+        __syncthreads();
+        // 1. histogram of targets by tile
+#pragma unroll
+        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count(S[j], lane, tcnt);
         __syncthreads();
         // 2. exclusive scan of the counts (2 tiles per thread) and bin reservation
         {
-            uint32_t v0 = 2u * tid < nt ? tcnt[2u * tid] : 0u;
-            uint32_t v1 = 2u * tid + 1u < nt ? tcnt[2u * tid + 1u] : 0u;
+            const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
+            const uint32_t v0 = t0i < nt ? tcnt[t0i] : 0u;
+            const uint32_t v1 = t1i < nt ? tcnt[t1i] : 0u;
             const uint32_t sum = v0 + v1;
             const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
             if (lane == 63u) wsum[wv] = inc;
             __syncthreads();
             uint32_t off = inc - sum;
             for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
-            if (2u * tid < nt) {
-                toff[2u * tid] = off;
-                tcnt[2u * tid] = off;
-                tres[2u * tid] = v0 ? atomicAdd(&a.bin_fill[2u * tid], v0) : 0u;
+            if (t0i < nt) {
+                toff[t0i] = off;
+                tcnt[t0i] = off;
+                tres[t0i] = v0 ? atomicAdd(&a.bin_fill[t0i], v0) : 0u;
             }
-            if (2u * tid + 1u < nt) {
-                toff[2u * tid + 1u] = off + v0;
-                tcnt[2u * tid + 1u] = off + v0;
-                tres[2u * tid + 1u] = v1 ? atomicAdd(&a.bin_fill[2u * tid + 1u], v1) : 0u;
+            if (t1i < nt) {
+                toff[t1i] = off + v0;
+                tcnt[t1i] = off + v0;
+                tres[t1i] = v1 ? atomicAdd(&a.bin_fill[t1i], v1) : 0u;
             }
         }
         __syncthreads();
         // 3. encode and stage sorted by tile
-        for (uint32_t it = c0 + wv; it < c1; it += 2u * kScatterWaves) {
-            const uint32_t it2 = it + kScatterWaves;
-            const SegLoad A = seg_load<CODE8, true>(a, it, smax, lane);
-            SegLoad B;
-            B.s0 = 1u;
-            B.len = 0u;
-            if (it2 < c1) B = seg_load<CODE8, true>(a, it2, smax, lane);
-            seg_stage(A, lane, tcnt, stage);
-            seg_stage(B, lane, tcnt, stage);
-        }
+#pragma unroll
+        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage(S[j], lane, tcnt, stage);
         __syncthreads();
         // 4. contiguous runs into the bins (one wave per tile)
         for (uint32_t tt = wv; tt < nt; tt += kScatterWaves) {
@@ -722,8 +716,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             const uint32_t cnt = tcnt[tt] - o0;
             if (cnt == 0) continue;
             const uint32_t r0 = tres[tt];
-            const uint32_t cap = a.bin_cap[tt];
-            uint32_t* dst = a.bins + a.bin_base[tt];
+            uint32_t* dst = a.bins + (size_t)tt * cap;
             for (uint32_t e = lane; e < cnt; e += 64u) {
                 const uint32_t code = stage[o0 + e];
                 const uint32_t pos = r0 + e;
@@ -774,9 +767,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
     }
     __syncthreads();
     const uint32_t fill = a.bin_fill[tt];
-    const uint32_t cap = a.bin_cap[tt];
+    const uint32_t cap = a.bin_cap_tile;
     const uint32_t n = fill < cap ? fill : cap;
-    const uint32_t* ev = a.bins + a.bin_base[tt];
+    const uint32_t* ev = a.bins + (size_t)tt * cap;
     constexpr uint32_t U = 8;
     for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
         uint32_t code[U];

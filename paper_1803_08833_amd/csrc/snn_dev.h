@@ -18,7 +18,7 @@ constexpr uint32_t kMaxD = 31;      // delay buckets per row
 constexpr uint32_t kTileBits = 10;
 constexpr uint32_t kTile = 1u << kTileBits;
 constexpr uint32_t kMaxTiles = 2048;          // binned delivery needs N <= 2M neurons
-constexpr uint32_t kChunkItems = 128;         // row segments (256 records) per scatter chunk
+constexpr uint32_t kChunkItems = 112;       // row segments (256 records) per scatter chunk: 16 waves x 7
 constexpr uint32_t kStage = kChunkItems * 256;
 constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for the inhibitory weight
 
@@ -73,10 +73,10 @@ struct StepArgs {
     // tile-binned delivery
     uint32_t ntiles;
     int32_t winh_q;
+    uint32_t bin_cap_tile;    // capacity of every tile's bin (events)
     uint32_t* bin_fill;       // [ntiles] events binned this step
-    const uint64_t* bin_base; // [ntiles] start of each tile's bin
-    const uint32_t* bin_cap;  // [ntiles]
-    uint32_t* bins;           // event codes: target & 1023 | bucket << 10 | weight field << 15
+    uint32_t* bins;           // [ntiles][bin_cap_tile] event codes:
+                              //   target & 1023 | bucket << 10 | weight field << 15
 };
 
 // Arguments of the projection builder.
