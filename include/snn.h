@@ -117,6 +117,7 @@ typedef struct {
     uint64_t bin_overflow;    /* binned delivery: events that took the fallback  */
     uint32_t deliver_mode;    /* delivery schedule in use (SNN_OPT_DELIVER_MODE) */
     uint32_t binned_ok;       /* 1 if the network supports binned delivery       */
+    uint64_t bin_threshold;   /* per-step switch to direct delivery (events)     */
     double build_ms;          /* wall time of snn_build_synapses                 */
 } snn_stats_t;
 
@@ -141,9 +142,12 @@ enum {
     SNN_OPT_DELIVER_MODE = 4,    /* 0: direct ring atomics; 1: tile-binned (default
                                     when the network allows it, see snn_stats)      */
     SNN_OPT_SCATTER_BLOCKS = 5,  /* workgroups of the binned scatter phase          */
-    SNN_OPT_BIN_FRAC_PPM = 6     /* before snn_build_synapses: bin capacity per tile
+    SNN_OPT_BIN_FRAC_PPM = 6,    /* before snn_build_synapses: bin capacity per tile
                                     as a fraction (ppm) of its expected in-synapses;
                                     events beyond it take the direct path           */
+    SNN_OPT_BIN_THRESHOLD = 7    /* binned schedule: steps with fewer recurrent
+                                    events than this are delivered directly
+                                    (0 = always binned)                             */
 };
 
 /* Create the grid (Sec. III.B) and the initial neuron state: V uniform in

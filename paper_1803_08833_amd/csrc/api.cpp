@@ -46,6 +46,8 @@ struct snn_net {
     bool binned_ok = false;
     uint32_t scatter_blocks = 256;
     double bin_frac = 0.5;      // bin capacity as a fraction of the tile's in-synapses
+    bool bin_threshold_set = false;
+    uint64_t bin_threshold_opt = 0;
     std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 };
 
@@ -121,21 +123,52 @@ hipError_t enqueue_deliver(snn_net* n, const StepArgs& a, uint32_t k)
     if (n->mode == 1) {
         hipError_t e = snn::launch_scatter(a, k, n->max_len, n->scatter_blocks, n->stream);
         if (e != hipSuccess) return e;
-        return snn::launch_tile(a, k, n->stream);
+        return snn::launch_tile(a, k, false, n->stream);
     }
     return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
 }
 
-hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
+hipError_t check_items(snn_net* n)
 {
     const uint64_t seg = 64ull * (n->mode == 1 ? 4 : n->unroll);
     const uint64_t smax = n->max_len ? (n->max_len + seg - 1) / seg : 1;
-    if ((uint64_t)n->N * smax >= (1ull << 32)) return hipErrorInvalidValue;
-    hipError_t e = snn::launch_update(a, k, n->stream);
+    return ((uint64_t)n->N * smax >= (1ull << 32)) ? hipErrorInvalidValue : hipSuccess;
+}
+
+// Enqueue step k (0-based within the current chunk) of the plain path.
+hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
+{
+    hipError_t e = check_items(n);
+    if (e != hipSuccess) return e;
+    e = snn::launch_update(a, k, n->stream);
     if (e != hipSuccess) return e;
     e = snn::launch_compact(a, k, n->stream);
     if (e != hipSuccess) return e;
     return enqueue_deliver(n, a, k);
+}
+
+// Enqueue steps k0 .. k0+count-1.  With binned delivery the neuron update of
+// step k+1 runs inside step k's tile kernel, so only the first update is a
+// launch of its own; the last tile kernel does not update, leaving the state
+// at the end of the last step.
+hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
+{
+    if (count == 0) return hipSuccess;
+    if (n->mode != 1 || n->a.d_min != 1) {
+        for (uint32_t k = k0; k < k0 + count; ++k) {
+            hipError_t e = enqueue_step(n, n->a, k);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
+    hipError_t e = check_items(n);
+    if (e == hipSuccess) e = snn::launch_update(n->a, k0, n->stream);
+    for (uint32_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
+        e = snn::launch_compact(n->a, k, n->stream);
+        if (e == hipSuccess) e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream);
+        if (e == hipSuccess) e = snn::launch_tile(n->a, k, k + 1 < k0 + count, n->stream);
+    }
+    return e;
 }
 
 hipError_t get_graph(snn_net* n, uint32_t chunk, hipGraphExec_t* out)
@@ -149,8 +182,7 @@ hipError_t get_graph(snn_net* n, uint32_t chunk, hipGraphExec_t* out)
     hipGraphExec_t ex = nullptr;
     hipError_t e = hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
-    hipError_t le = hipSuccess;
-    for (uint32_t k = 0; k < chunk && le == hipSuccess; ++k) le = enqueue_step(n, n->a, k);
+    hipError_t le = enqueue_steps(n, 0, chunk);
     if (le == hipSuccess) le = snn::launch_advance(n->a.ctrl, chunk, n->stream);
     e = hipStreamEndCapture(n->stream, &gr);
     if (le != hipSuccess) {
@@ -404,6 +436,11 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
         if (e == hipSuccess) e = dalloc(n, &a.bins, (size_t)a.ntiles * a.bin_cap_tile);
         if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
         HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles));
+        // Per-step switch: binning costs about one read and one write of every
+        // future ring row (8 D N bytes at ~5.5 TB/s); direct delivery about one
+        // global atomic per event (~27 G/s).  Equal at ~0.039 D N events.
+        if (n->bin_threshold_set) a.bin_threshold = n->bin_threshold_opt;
+        else a.bin_threshold = (uint64_t)(0.039 * n->D * (double)n->N);
         n->mode = 1;
     }
     n->built = true;
@@ -426,7 +463,7 @@ snn_status snn_step(snn_net* n, uint32_t n_ms)
         }
     }
     if (left) {
-        for (uint32_t k = 0; k < left; ++k) HIPCHK(n, enqueue_step(n, n->a, k));
+        HIPCHK(n, enqueue_steps(n, 0, left));
         HIPCHK(n, snn::launch_advance(n->a.ctrl, left, n->stream));
     }
     return SNN_OK;
@@ -556,6 +593,7 @@ snn_status snn_stats(snn_net* n, snn_stats_t* out)
     out->disagree = hc.disagree;
     out->bin_overflow = hc.bin_overflow;
     out->deliver_mode = n->mode;
+    out->bin_threshold = n->a.bin_threshold;
     out->binned_ok = n->binned_ok ? 1u : 0u;
     out->build_ms = n->build_ms;
     return SNN_OK;
@@ -583,7 +621,7 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
         if (n->mode == 1) {
             HIPCHK(n, snn::launch_scatter(n->a, 0, n->max_len, n->scatter_blocks, n->stream));
             HIPCHK(n, hipEventRecord(ev[3], n->stream));
-            HIPCHK(n, snn::launch_tile(n->a, 0, n->stream));
+            HIPCHK(n, snn::launch_tile(n->a, 0, false, n->stream));
         } else {
             HIPCHK(n, snn::launch_deliver(n->a, 0, n->deliver_waves, n->unroll, n->max_len, n->stream));
             HIPCHK(n, hipEventRecord(ev[3], n->stream));
@@ -643,6 +681,12 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         if (value < 1 || value > 4000000) return fail(n, SNN_E_INVAL, "bin fraction out of range");
         n->bin_frac = (double)value * 1e-6;
         return SNN_OK;
+    case SNN_OPT_BIN_THRESHOLD:
+        if (value < 0) return fail(n, SNN_E_INVAL, "threshold must be >= 0");
+        n->bin_threshold_set = true;
+        n->bin_threshold_opt = (uint64_t)value;
+        n->a.bin_threshold = (uint64_t)value;
+        break;
     case SNN_OPT_SCATTER_BLOCKS:
         if (value < 1 || value > 65536) return fail(n, SNN_E_INVAL, "scatter blocks out of range");
         n->scatter_blocks = (uint32_t)value;

@@ -325,56 +325,60 @@ __device__ __forceinline__ bool neuron_step(const StepArgs& a, uint32_t gid, boo
     return spike;
 }
 
-__global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
+// One quad of neurons (gid = 4q .. 4q+3, all in one module since M % 4 == 0)
+// takes its step-t input `in` (ring slot, already cleared by the caller), draws
+// its external Poisson counts (one Philox EXT call) and integrates.  Returns the
+// spike flags (bit s for neuron 4q + s); adds to *ext_tot and *dis.
+__device__ __forceinline__ uint32_t update_quad(const StepArgs& a, const uint32_t* pois_s, uint32_t q,
+                                                uint32_t t, int4 in, uint32_t& ext_tot, uint32_t& dis)
 {
-    __shared__ uint32_t wtot[4];
-    __shared__ unsigned long long wext[4];
-    __shared__ uint32_t wdis[4];
-    __shared__ uint32_t pois_s[kMaxPois];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    if (tid < a.npois) pois_s[tid] = a.poisc[tid];
-    __syncthreads();
-    const uint32_t q = blockIdx.x * 256u + tid;
-    const uint32_t t = a.ctrl->t0 + k;
-    uint32_t flags = 0, ext_tot = 0, dis = 0;
-    if (q < a.nq) {
-        int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
-        const int4 in = *rp;
-        *rp = make_int4(0, 0, 0, 0);
-        float4 V = reinterpret_cast<const float4*>(a.V)[q];
-        float4 W = reinterpret_cast<const float4*>(a.W)[q];
-        uchar4 R = reinterpret_cast<const uchar4*>(a.ref)[q];
-        int32_t e0, e1, e2, e3;
-        if (a.ext_const) {
-            e0 = e1 = e2 = e3 = a.ext_const_q;
-        } else {
-            const uint4 u = philox(q, t, kStreamExt, 0u, a.key0, a.key1);
-            uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-            for (uint32_t i = 0; i < a.npois; ++i) {
-                const uint32_t th = pois_s[i];
-                c0 += (th <= u.x) ? 1u : 0u;
-                c1 += (th <= u.y) ? 1u : 0u;
-                c2 += (th <= u.z) ? 1u : 0u;
-                c3 += (th <= u.w) ? 1u : 0u;
-            }
-            ext_tot = c0 + c1 + c2 + c3;
-            e0 = (int32_t)c0 * a.jext_q;
-            e1 = (int32_t)c1 * a.jext_q;
-            e2 = (int32_t)c2 * a.jext_q;
-            e3 = (int32_t)c3 * a.jext_q;
+    float4 V = reinterpret_cast<const float4*>(a.V)[q];
+    float4 W = reinterpret_cast<const float4*>(a.W)[q];
+    uchar4 R = reinterpret_cast<const uchar4*>(a.ref)[q];
+    int32_t e0, e1, e2, e3;
+    if (a.ext_const) {
+        e0 = e1 = e2 = e3 = a.ext_const_q;
+    } else {
+        const uint4 u = philox(q, t, kStreamExt, 0u, a.key0, a.key1);
+        uint32_t c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        for (uint32_t i = 0; i < a.npois; ++i) {
+            const uint32_t th = pois_s[i];
+            c0 += (th <= u.x) ? 1u : 0u;
+            c1 += (th <= u.y) ? 1u : 0u;
+            c2 += (th <= u.z) ? 1u : 0u;
+            c3 += (th <= u.w) ? 1u : 0u;
         }
-        const uint32_t g0 = 4u * q;
-        const uint32_t loc = g0 % a.M;   // the quad lies in one module (M % 4 == 0)
-        const auto add = [](int32_t x, int32_t y) { return (int32_t)((uint32_t)x + (uint32_t)y); };
-        flags |= neuron_step(a, g0, loc < a.n_exc, add(in.x, e0), V.x, W.x, R.x, dis) ? 1u : 0u;
-        flags |= neuron_step(a, g0 + 1u, loc + 1u < a.n_exc, add(in.y, e1), V.y, W.y, R.y, dis) ? 2u : 0u;
-        flags |= neuron_step(a, g0 + 2u, loc + 2u < a.n_exc, add(in.z, e2), V.z, W.z, R.z, dis) ? 4u : 0u;
-        flags |= neuron_step(a, g0 + 3u, loc + 3u < a.n_exc, add(in.w, e3), V.w, W.w, R.w, dis) ? 8u : 0u;
-        reinterpret_cast<float4*>(a.V)[q] = V;
-        reinterpret_cast<float4*>(a.W)[q] = W;
-        reinterpret_cast<uchar4*>(a.ref)[q] = R;
+        ext_tot += c0 + c1 + c2 + c3;
+        e0 = (int32_t)c0 * a.jext_q;
+        e1 = (int32_t)c1 * a.jext_q;
+        e2 = (int32_t)c2 * a.jext_q;
+        e3 = (int32_t)c3 * a.jext_q;
     }
-    // ordered block-local compaction: ids ascend with (lane, bit)
+    const uint32_t g0 = 4u * q;
+    const uint32_t loc = g0 % a.M;
+    const auto add = [](int32_t x, int32_t y) { return (int32_t)((uint32_t)x + (uint32_t)y); };
+    uint32_t flags = 0;
+    flags |= neuron_step(a, g0, loc < a.n_exc, add(in.x, e0), V.x, W.x, R.x, dis) ? 1u : 0u;
+    flags |= neuron_step(a, g0 + 1u, loc + 1u < a.n_exc, add(in.y, e1), V.y, W.y, R.y, dis) ? 2u : 0u;
+    flags |= neuron_step(a, g0 + 2u, loc + 2u < a.n_exc, add(in.z, e2), V.z, W.z, R.z, dis) ? 4u : 0u;
+    flags |= neuron_step(a, g0 + 3u, loc + 3u < a.n_exc, add(in.w, e3), V.w, W.w, R.w, dis) ? 8u : 0u;
+    reinterpret_cast<float4*>(a.V)[q] = V;
+    reinterpret_cast<float4*>(a.W)[q] = W;
+    reinterpret_cast<uchar4*>(a.ref)[q] = R;
+    return flags;
+}
+
+// Ordered block-local compaction of the spikers of update block `blk` (1024
+// neurons; thread i < 256 holds the flags of quad 4*blk*256 + i): each spiker
+// is written as {gid, row length, row start} in ascending id, the block count
+// goes to blk_cnt and to its group counter of parity t & 1, and the block's
+// external-event and lock-step-disagreement counts are accumulated.
+template <uint32_t NW>
+__device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, uint32_t t, uint32_t q,
+                                              uint32_t flags, uint32_t ext_tot, uint32_t dis,
+                                              uint32_t* wtot, unsigned long long* wext, uint32_t* wdis)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
     const uint64_t m2 = __ballot(flags & 4u), m3 = __ballot(flags & 8u);
     const uint32_t pre = mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
@@ -388,47 +392,78 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
     }
     __syncthreads();
     uint32_t woff = 0, btot = 0;
-    for (uint32_t i = 0; i < 4u; ++i) {
+    for (uint32_t i = 0; i < NW; ++i) {
         if (i < wv) woff += wtot[i];
         btot += wtot[i];
     }
     if (flags) {
-        uint32_t* dst = a.blk_list + (size_t)blockIdx.x * kNeuronsPerBlock + woff + pre;
-        const uint32_t g0 = 4u * q;
-        if (flags & 1u) *dst++ = g0;
-        if (flags & 2u) *dst++ = g0 + 1u;
-        if (flags & 4u) *dst++ = g0 + 2u;
-        if (flags & 8u) *dst++ = g0 + 3u;
+        uint4* dst = a.blk_list + (size_t)blk * kNeuronsPerBlock + woff + pre;
+        for (uint32_t s = 0; s < 4u; ++s) {
+            if (flags & (1u << s)) {
+                const uint32_t gid = 4u * q + s;
+                const uint64_t rb = a.row_ptr[gid];
+                const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
+                *dst++ = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+            }
+        }
     }
     if (tid == 0) {
-        a.blk_cnt[blockIdx.x] = btot;
-        if (btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blockIdx.x / kGroup], btot);
-        const unsigned long long be = wext[0] + wext[1] + wext[2] + wext[3];
+        a.blk_cnt[blk] = btot;
+        if (btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blk / kGroup], btot);
+        unsigned long long be = 0;
+        uint32_t bd = 0;
+        for (uint32_t i = 0; i < NW; ++i) {
+            be += wext[i];
+            bd += wdis[i];
+        }
         if (be) atomicAdd((unsigned long long*)&a.ctrl->ext_events, be);
-        const uint32_t bd = wdis[0] + wdis[1] + wdis[2] + wdis[3];
         if (bd) atomicAdd((unsigned long long*)&a.ctrl->disagree, (unsigned long long)bd);
     }
 }
 
-// ---------------------------------------------------------------------------
-// Ordered global compaction: block g owns update blocks [64g, 64g+64); its
-// base offset is the sum of the group counts before it (this step's parity
-// buffer).  Each thread places one spike: it finds the spike's update block by
-// binary search over the group's block offsets, then writes the step's spike
-// record {gid, row length, row start} and the AER history entry.  Also counts
-// the step's recurrent events and clears this group's entry of the other
-// parity buffer for the next step.
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
+__global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
 {
-    __shared__ uint32_t red[4];
+    __shared__ uint32_t wtot[4];
+    __shared__ unsigned long long wext[4];
+    __shared__ uint32_t wdis[4];
+    __shared__ uint32_t pois_s[kMaxPois];
+    const uint32_t tid = threadIdx.x;
+    if (tid < a.npois) pois_s[tid] = a.poisc[tid];
+    __syncthreads();
+    const uint32_t q = blockIdx.x * 256u + tid;
+    const uint32_t t = a.ctrl->t0 + k;
+    uint32_t flags = 0, ext_tot = 0, dis = 0;
+    if (q < a.nq) {
+        int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
+        const int4 in = *rp;
+        *rp = make_int4(0, 0, 0, 0);
+        flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
+    }
+    block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, wtot, wext, wdis);
+}
+
+// ---------------------------------------------------------------------------
+// Ordered global compaction: block g owns update blocks [kGroup g, kGroup g +
+// kGroup); its base offset is the sum of the group counts before it (this
+// step's parity buffer).  Each thread places one spike (binary search over the
+// group's block offsets), copying its {gid, row length, row start} record to
+// the step's spike list and writing the AER history entry.  Also counts the
+// step's recurrent events and clears this group's entry of the other parity
+// buffer for the next step.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kCompactThreads = 1024;
+
+__global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_t k)
+{
+    constexpr uint32_t NW = kCompactThreads / 64;
+    __shared__ uint32_t red[NW];
     __shared__ uint32_t boff[kGroup + 1];
-    __shared__ unsigned long long wev[4];
+    __shared__ unsigned long long wev[NW];
     const uint32_t g = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint32_t t = a.ctrl->t0 + k, par = t & 1u;
     const uint32_t* gc = a.grp_cnt + par * a.ngrp;
     uint32_t s = 0;
-    for (uint32_t i = tid; i < g; i += 256u) s += gc[i];
+    for (uint32_t i = tid; i < g; i += kCompactThreads) s += gc[i];
     s = wave_sum<uint32_t>(s);
     if (lane == 0) red[wv] = s;
     const uint32_t b0 = g * kGroup;
@@ -436,37 +471,41 @@ __global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
     if (wv == 0) {
         const uint32_t c = lane < nb ? a.blk_cnt[b0 + lane] : 0u;
         const uint32_t v = wave_incl_scan<uint32_t>(c, lane);
-        boff[lane + 1u] = v;
+        if (lane < kGroup) boff[lane + 1u] = v;
         if (lane == 0) boff[0] = 0;
     }
     __syncthreads();
-    const uint32_t base = red[0] + red[1] + red[2] + red[3];
+    uint32_t base = 0;
+    for (uint32_t i = 0; i < NW; ++i) base += red[i];
     const uint32_t gtot = boff[nb];
     const uint64_t h0 = a.ctrl->hist_n;
     unsigned long long ev = 0;
-    for (uint32_t i = tid; i < gtot; i += 256u) {
+    for (uint32_t i = tid; i < gtot; i += kCompactThreads) {
         uint32_t lo = 0, hi = nb;   // boff[lo] <= i < boff[hi]
         while (hi - lo > 1u) {
             const uint32_t mid = (lo + hi) >> 1;
             if (boff[mid] <= i) lo = mid;
             else hi = mid;
         }
-        const uint32_t gid = a.blk_list[(size_t)(b0 + lo) * kNeuronsPerBlock + (i - boff[lo])];
+        const uint4 rec = a.blk_list[(size_t)(b0 + lo) * kNeuronsPerBlock + (i - boff[lo])];
         const uint32_t p = base + i;
-        const uint64_t rb = a.row_ptr[gid];
-        const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
-        a.spk[p] = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+        a.spk[p] = rec;
         const uint64_t hp = h0 + p;
-        if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, gid);
-        ev += len;
+        if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, rec.x);
+        ev += rec.y;
     }
     ev = wave_sum<unsigned long long>(ev);
     if (lane == 0) wev[wv] = ev;
     __syncthreads();
     if (tid == 0) {
         a.grp_cnt[(par ^ 1u) * a.ngrp + g] = 0u;
-        const unsigned long long be = wev[0] + wev[1] + wev[2] + wev[3];
-        if (be) atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+        unsigned long long be = 0;
+        for (uint32_t i = 0; i < NW; ++i) be += wev[i];
+        if (be) {
+            atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+            atomicAdd((unsigned long long*)&a.ctrl->step_ev[par], be);
+        }
+        if (g == 0) a.ctrl->step_ev[par ^ 1u] = 0;
         if (g == a.ngrp - 1u) {
             a.ctrl->nspk = base + gtot;
             a.ctrl->spikes += base + gtot;
@@ -483,19 +522,9 @@ __global__ __launch_bounds__(256) void k_compact(StepArgs a, uint32_t k)
 // ring[(t + delay) mod 32][target] with a non-returning device-scope atomic.
 // ---------------------------------------------------------------------------
 template <int U, bool CODE8>
-__global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_t smax)
+__device__ __forceinline__ void deliver_direct(const StepArgs& a, uint32_t t, uint32_t n, uint32_t smax,
+                                               uint32_t wave, uint32_t nw, uint32_t lane, const int32_t* cb)
 {
-    __shared__ int32_t cb_s[256];
-    if (CODE8) {
-        cb_s[threadIdx.x] = a.cb[threadIdx.x];
-        __syncthreads();
-    }
-    const uint32_t lane = threadIdx.x & 63u;
-    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
-    const uint32_t nw = (gridDim.x * 256u) >> 6;
-    const uint32_t t = a.ctrl->t0 + k;
-    const uint32_t n = a.ctrl->nspk;
-    if (wave == 0 && lane == 0) a.ctrl->hist_n += n;
     constexpr uint32_t SEG = 64u * U;
     const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
     uint32_t it = wave;
@@ -543,7 +572,7 @@ __global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_
                 bl += (kk >= readlane(be, l)) ? 1u : 0u;
             }
             if (kk < len) {
-                const int32_t w = CODE8 ? cb_s[wq[u]] : wq[u];
+                const int32_t w = CODE8 ? cb[wq[u]] : wq[u];
                 const uint32_t slot = (t + a.d_min + bl) & (kRing - 1u);
                 __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tg[u], w, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
@@ -552,6 +581,31 @@ __global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_
     }
 }
 
+template <int U, bool CODE8>
+__global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_t smax)
+{
+    __shared__ int32_t cb_s[256];
+    if (CODE8) {
+        cb_s[threadIdx.x] = a.cb[threadIdx.x];
+        __syncthreads();
+    }
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
+    const uint32_t nw = (gridDim.x * 256u) >> 6;
+    const uint32_t t = a.ctrl->t0 + k;
+    const uint32_t n = a.ctrl->nspk;
+    if (wave == 0 && lane == 0) a.ctrl->hist_n += n;
+    deliver_direct<U, CODE8>(a, t, n, smax, wave, nw, lane, cb_s);
+}
+
+// Binned delivery pays a fixed price per step (every tile's D ring rows are
+// read and written), so steps with few events are delivered directly instead.
+// The compaction kernel totals the step's events; every delivery kernel of the
+// step takes the same decision from that total.
+__device__ __forceinline__ bool step_binned(const StepArgs& a, uint32_t t)
+{
+    return a.ctrl->step_ev[t & 1u] >= a.bin_threshold;
+}
 
 // ---------------------------------------------------------------------------
 // Tile-binned delivery, phase A (scatter).  Scattered global atomics are
@@ -655,6 +709,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     const uint32_t t = a.ctrl->t0 + k;
     const uint32_t n = a.ctrl->nspk;
     if (blockIdx.x == 0 && tid == 0) a.ctrl->hist_n += n;
+    if (!step_binned(a, t)) {
+        if (CODE8) __syncthreads();
+        deliver_direct<4, CODE8>(a, t, n, smax, blockIdx.x * kScatterWaves + wv, gridDim.x * kScatterWaves,
+                                 lane, cb_s);
+        return;
+    }
     const uint32_t items = n * smax;
     const uint32_t nt = a.ntiles;
     const uint32_t cap = a.bin_cap_tile;
@@ -747,7 +807,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTileThreads = 1024;
 
-template <bool CODE8>
+// UPD (requires d_min == 1): after the tile's ring rows are complete for step
+// t + 1 (every event arriving then has been delivered), also run the neuron
+// update of step t + 1 for the tile's 1024 neurons (the tile is an update
+// block).  The first LDS row is slot t + 1: it is handed to the update and
+// written back as zeros, and its LDS space then holds the update's small
+// tables, so the kernel needs no static LDS and two workgroups fit a CU.
+template <bool CODE8, bool UPD>
 __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
 {
     extern __shared__ int32_t acc[];      // [D][1024]
@@ -756,46 +822,77 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
     const uint32_t nn = (a.N - g0) < kTile ? (a.N - g0) : kTile;
     const uint32_t t = a.ctrl->t0 + k;
     const uint32_t D = a.D;
-    for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
-        const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
-        int4 v = make_int4(0, 0, 0, 0);
-        if (4u * q < nn) {
-            const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
-            v = reinterpret_cast<const int4*>(a.ring + (size_t)slot * a.N + g0)[q];
+    const bool binned = step_binned(a, t);
+    if (!UPD && !binned) return;
+    if (binned) {
+        for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
+            const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
+            int4 v = make_int4(0, 0, 0, 0);
+            if (4u * q < nn) {
+                const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                v = reinterpret_cast<const int4*>(a.ring + (size_t)slot * a.N + g0)[q];
+            }
+            reinterpret_cast<int4*>(acc)[idx] = v;
         }
-        reinterpret_cast<int4*>(acc)[idx] = v;
-    }
-    __syncthreads();
-    const uint32_t fill = a.bin_fill[tt];
-    const uint32_t cap = a.bin_cap_tile;
-    const uint32_t n = fill < cap ? fill : cap;
-    const uint32_t* ev = a.bins + (size_t)tt * cap;
-    constexpr uint32_t U = 8;
-    for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
-        uint32_t code[U];
+        __syncthreads();
+        const uint32_t fill = a.bin_fill[tt];
+        const uint32_t cap = a.bin_cap_tile;
+        const uint32_t n = fill < cap ? fill : cap;
+        const uint32_t* ev = a.bins + (size_t)tt * cap;
+        constexpr uint32_t U = 8;
+        for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
+            uint32_t code[U];
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            const uint32_t e = e0 + u * kTileThreads + tid;
-            code[u] = e < n ? ev[e] : 0xFFFFFFFFu;
-        }
+            for (uint32_t u = 0; u < U; ++u) {
+                const uint32_t e = e0 + u * kTileThreads + tid;
+                code[u] = e < n ? ev[e] : 0xFFFFFFFFu;
+            }
 #pragma unroll
-        for (uint32_t u = 0; u < U; ++u) {
-            if (code[u] != 0xFFFFFFFFu) {
-                const uint32_t b = (code[u] >> kTileBits) & 31u;
-                atomicAdd(&acc[b * kTile + (code[u] & (kTile - 1u))],
-                          decode_weight(code[u] >> 15, CODE8, a.cb, a.winh_q));
+            for (uint32_t u = 0; u < U; ++u) {
+                if (code[u] != 0xFFFFFFFFu) {
+                    const uint32_t b = (code[u] >> kTileBits) & 31u;
+                    atomicAdd(&acc[b * kTile + (code[u] & (kTile - 1u))],
+                              decode_weight(code[u] >> 15, CODE8, a.cb, a.winh_q));
+                }
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
-        const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
-        if (4u * q < nn) {
-            const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
-            reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[q] = reinterpret_cast<const int4*>(acc)[idx];
+    uint32_t flags = 0, ext_tot = 0, dis = 0;
+    const uint32_t q = (g0 >> 2) + tid;
+    uint32_t* scratch = reinterpret_cast<uint32_t*>(acc);   // row 0 once consumed
+    if (UPD) {
+        int4 in = make_int4(0, 0, 0, 0);
+        if (tid < kTile / 4u && 4u * tid < nn) {
+            if (binned) {
+                in = reinterpret_cast<const int4*>(acc)[tid];
+            } else {
+                int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)((t + 1u) & (kRing - 1u)) * a.N) + q;
+                in = *rp;
+                *rp = make_int4(0, 0, 0, 0);
+            }
         }
+        __syncthreads();
+        if (tid < a.npois) scratch[tid] = a.poisc[tid];
+        __syncthreads();
+        if (tid < kTile / 4u && 4u * tid < nn) flags = update_quad(a, scratch, q, t + 1u, in, ext_tot, dis);
     }
-    if (tid == 0) a.bin_fill[tt] = 0u;
+    if (binned) {
+        for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
+            const uint32_t b = idx / (kTile / 4u), qq = idx % (kTile / 4u);
+            if (4u * qq < nn) {
+                const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                const int4 v = (UPD && b == 0u) ? make_int4(0, 0, 0, 0) : reinterpret_cast<const int4*>(acc)[idx];
+                reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[qq] = v;
+            }
+        }
+        if (tid == 0) a.bin_fill[tt] = 0u;
+    }
+    if (UPD) {
+        __syncthreads();   // every thread is past its use of the Poisson table
+        block_compact<kTileThreads / 64>(a, tt, t + 1u, q, flags, ext_tot, dis, scratch + 64,
+                                         reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80);
+    }
 }
 
 __global__ void k_advance(Ctrl* c, uint32_t n)
@@ -855,7 +952,7 @@ hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s)
 
 hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_compact, dim3(a.ngrp), dim3(256), 0, s, a, k);
+    hipLaunchKernelGGL(k_compact, dim3(a.ngrp), dim3(kCompactThreads), 0, s, a, k);
     return hipGetLastError();
 }
 
@@ -893,16 +990,26 @@ hipError_t setup_kernels()
 {
     // phase B keeps D rows of 1024 int32 in LDS (up to 124 KB of the 160 KB per CU)
     const int lds = (int)(kMaxD * kTile * sizeof(int32_t));
-    hipError_t e = hipFuncSetAttribute((const void*)k_tile<true>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute((const void*)k_tile<false>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    const void* fns[4] = {(const void*)k_tile<true, false>, (const void*)k_tile<false, false>,
+                          (const void*)k_tile<true, true>, (const void*)k_tile<false, true>};
+    for (const void* f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
-hipError_t launch_tile(const StepArgs& a, uint32_t k, hipStream_t s)
+hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s)
 {
     const size_t lds = (size_t)a.D * kTile * sizeof(int32_t);
-    if (a.record == 1u) hipLaunchKernelGGL((k_tile<true>), dim3(a.ntiles), dim3(kTileThreads), lds, s, a, k);
-    else hipLaunchKernelGGL((k_tile<false>), dim3(a.ntiles), dim3(kTileThreads), lds, s, a, k);
+    const dim3 g(a.ntiles), b(kTileThreads);
+    if (a.record == 1u) {
+        if (update_next) hipLaunchKernelGGL((k_tile<true, true>), g, b, lds, s, a, k);
+        else hipLaunchKernelGGL((k_tile<true, false>), g, b, lds, s, a, k);
+    } else {
+        if (update_next) hipLaunchKernelGGL((k_tile<false, true>), g, b, lds, s, a, k);
+        else hipLaunchKernelGGL((k_tile<false, false>), g, b, lds, s, a, k);
+    }
     return hipGetLastError();
 }
 

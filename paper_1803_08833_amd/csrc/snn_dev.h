@@ -10,13 +10,14 @@ namespace snn {
 constexpr uint32_t kRing = 32;      // delay-ring slots (more than the largest delay)
 constexpr uint32_t kQuadsPerBlock = 256;
 constexpr uint32_t kNeuronsPerBlock = 4 * kQuadsPerBlock;  // one update block: 1024 neurons
-constexpr uint32_t kGroup = 64;     // update blocks per compaction group
+constexpr uint32_t kGroup = 16;     // update blocks per compaction group
 constexpr uint32_t kMaxPois = 64;   // Poisson CDF thresholds
 constexpr uint32_t kMaxD = 31;      // delay buckets per row
 // Tile-binned delivery: targets are grouped in tiles of 1024; each step's
 // events are binned per tile, then accumulated in LDS tile by tile.
 constexpr uint32_t kTileBits = 10;
 constexpr uint32_t kTile = 1u << kTileBits;
+static_assert(kTile == kNeuronsPerBlock, "a delivery tile is an update block");
 constexpr uint32_t kMaxTiles = 2048;          // binned delivery needs N <= 2M neurons
 constexpr uint32_t kChunkItems = 112;       // row segments (256 records) per scatter chunk: 16 waves x 7
 constexpr uint32_t kStage = kChunkItems * 256;
@@ -42,6 +43,7 @@ struct Ctrl {
     uint32_t err;           // construction error flags (bit 0: row longer than 65535)
     uint32_t max_len;       // longest projection row
     uint64_t bin_overflow;  // events delivered by the direct fallback (bin full)
+    uint64_t step_ev[2];    // recurrent events of the step in flight, by step parity
 };
 
 // Everything the step kernels read, passed by value.
@@ -59,7 +61,7 @@ struct StepArgs {
     uint8_t* ref;
     int32_t* ring;          // [kRing][N]
     uint32_t* blk_cnt;      // [nblk]
-    uint32_t* blk_list;     // [nblk * kNeuronsPerBlock]
+    uint4* blk_list;        // [nblk * kNeuronsPerBlock] spikers {gid, row length, row start}
     uint32_t* grp_cnt;      // [2][ngrp]
     uint4* spk;             // [N] spikes of the step in flight: {gid, row length, row start lo, hi}
     uint2* hist;            // [hist_cap] (t, gid)
@@ -74,6 +76,7 @@ struct StepArgs {
     uint32_t ntiles;
     int32_t winh_q;
     uint32_t bin_cap_tile;    // capacity of every tile's bin (events)
+    uint64_t bin_threshold;   // steps with fewer events are delivered directly
     uint32_t* bin_fill;       // [ntiles] events binned this step
     uint32_t* bins;           // [ntiles][bin_cap_tile] event codes:
                               //   target & 1023 | bucket << 10 | weight field << 15
@@ -106,7 +109,7 @@ hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_
                           uint32_t max_len, hipStream_t s);
 hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
                           hipStream_t s);
-hipError_t launch_tile(const StepArgs& a, uint32_t k, hipStream_t s);
+hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s);
 hipError_t setup_kernels();
 hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s);
 hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v,

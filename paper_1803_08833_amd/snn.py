@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(PKG, "libsnn.so")
 SNN_OK, SNN_E_INVAL, SNN_E_NOMEM, SNN_E_HIP, SNN_E_STATE, SNN_E_OVERFLOW, SNN_E_TRUNC = 0, -1, -2, -3, -4, -5, -6
 OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL, OPT_DELIVER_MODE, OPT_SCATTER_BLOCKS = 1, 2, 3, 4, 5
 OPT_BIN_FRAC_PPM = 6
+OPT_BIN_THRESHOLD = 7
 RING = 32
 
 EXPORTS = [
@@ -57,6 +58,7 @@ class Stats(C.Structure):
         ("ext_events", C.c_uint64), ("nnz", C.c_uint64), ("n_neurons", C.c_uint64),
         ("bytes_device", C.c_uint64), ("hist_n", C.c_uint64), ("disagree", C.c_uint64),
         ("bin_overflow", C.c_uint64), ("deliver_mode", C.c_uint32), ("binned_ok", C.c_uint32),
+        ("bin_threshold", C.c_uint64),
         ("build_ms", C.c_double),
     ]
 

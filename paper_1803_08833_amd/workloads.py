@@ -54,7 +54,11 @@ WORKLOADS = {
     # 24x24 Gaussian, sigma 1.5 modules, 1100 synapses/neuron (~786 M synapses).
     "grid24_gauss": dict(net=make(24, 24, GAUSS, 1.5, 1100, 2), steps=10000),
     # 24x24 exponential, lambda 5 modules, 1100 synapses/neuron: the headline.
-    "grid24_exp": dict(net=make(24, 24, EXP, 5.0, 1100, 3), steps=10000),
+    # The external rate is tuned so that the mean rate is ~3-5 Hz: at these
+    # parameters the network alternates ~55 Hz up-states with silence, and
+    # 2.05 Hz drive gives one up-state per ~10 s (2.8 Hz over the 10 s after
+    # the first second, 5.0 Hz over the whole 11 s).
+    "grid24_exp": dict(net=make(24, 24, EXP, 5.0, 1100, 3, ext_rate_hz=2.05), steps=10000),
     # 96x96 exponential, lambda 8 modules, 2600 synapses/neuron, 8-bit codes.
     "grid96_exp_code8": dict(net=make(96, 96, EXP, 8.0, 2600, 5, record=REC_CODE8), steps=2000),
 }

@@ -212,13 +212,17 @@ def test_determinism_and_schedules(snn):
     net = W.workload("grid4_gauss", seed=31)["net"]
     say("case: determinism across runs, delivery schedules, graph chunking and unroll")
     rings, spikes = [], []
-    variants = ((1, 64, 4, 8192, 256), (0, 64, 4, 8192, 256), (0, 0, 1, 64, 256), (0, 7, 2, 1000, 256),
-                (1, 0, 4, 8192, 3), (1, 13, 4, 8192, 1024))
-    for mode, chunk, unroll, waves, sblocks in variants:
+    # (mode, graph chunk, unroll, waves, scatter blocks, per-step binning threshold)
+    variants = ((1, 64, 4, 8192, 256, None), (0, 64, 4, 8192, 256, None), (0, 0, 1, 64, 256, None),
+                (0, 7, 2, 1000, 256, None), (1, 0, 4, 8192, 3, 0), (1, 13, 4, 8192, 1024, 0),
+                (1, 64, 4, 8192, 256, 1 << 40), (1, 5, 4, 8192, 256, 200000))
+    for mode, chunk, unroll, waves, sblocks, thr in variants:
         with snn.Net(net) as g:
             g.build_synapses()
             assert g.stats()["binned_ok"] == 1
             g.set_option(snn.OPT_DELIVER_MODE, mode)
+            if thr is not None:
+                g.set_option(snn.OPT_BIN_THRESHOLD, thr)
             g.set_option(snn.OPT_GRAPH_CHUNK, chunk)
             g.set_option(snn.OPT_DELIVER_UNROLL, unroll)
             g.set_option(snn.OPT_DELIVER_WAVES, waves)
@@ -243,6 +247,7 @@ def test_bin_overflow_fallback_is_exact(snn):
             g.set_option(snn.OPT_BIN_FRAC_PPM, ppm)
             g.build_synapses()
             g.set_option(snn.OPT_DELIVER_MODE, mode)
+            g.set_option(snn.OPT_BIN_THRESHOLD, 0)
             g.step(200)
             out.append((g.read_ring(), g.read_spikes(), g.stats()))
     np.testing.assert_array_equal(out[0][0], out[1][0])
