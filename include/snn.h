@@ -145,9 +145,11 @@ enum {
     SNN_OPT_BIN_FRAC_PPM = 6,    /* before snn_build_synapses: bin capacity per tile
                                     as a fraction (ppm) of its expected in-synapses;
                                     events beyond it take the direct path           */
-    SNN_OPT_BIN_THRESHOLD = 7    /* binned schedule: steps with fewer recurrent
+    SNN_OPT_BIN_THRESHOLD = 7,   /* binned schedule: steps with fewer recurrent
                                     events than this are delivered directly
                                     (0 = always binned)                             */
+    SNN_OPT_EXT_RATE_UHZ = 8     /* after snn_build_synapses: external Poisson rate
+                                    in micro-hertz (rebuilds the CDF thresholds)    */
 };
 
 /* Create the grid (Sec. III.B) and the initial neuron state: V uniform in
@@ -197,6 +199,11 @@ snn_status snn_stats(snn_net* net, snn_stats_t* out);
  * network's stream and report average kernel durations.  The steps are real
  * simulation steps (state advances). */
 snn_status snn_time_kernels(snn_net* net, uint32_t n_ms, snn_kernel_times* out);
+
+/* Return the network to its initial state (as after snn_build_grid: V from the
+ * INIT stream, no fatigue, not refractory, empty ring, t = 0, empty history,
+ * zero counters); projections are kept.  Enqueued on the network's stream. */
+snn_status snn_reset(snn_net* net);
 
 /* Set a tuning knob (SNN_OPT_*).  Takes effect on the next step call. */
 snn_status snn_set_option(snn_net* net, int key, int64_t value);

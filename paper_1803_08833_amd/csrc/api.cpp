@@ -200,6 +200,28 @@ hipError_t get_graph(snn_net* n, uint32_t chunk, hipGraphExec_t* out)
     return hipSuccess;
 }
 
+snn::TableParams table_params(const snn_grid_desc& g, const snn_syn_desc& s)
+{
+    snn::TableParams tp{};
+    tp.gx = g.gx;
+    tp.gy = g.gy;
+    tp.M = g.n_exc + g.n_inh;
+    tp.kernel = s.kernel;
+    tp.range = s.range;
+    tp.k_in = s.k_in;
+    tp.w_exc = s.w_exc;
+    tp.w_exc_sd = s.w_exc_sd;
+    tp.w_inh = s.w_inh;
+    tp.ext_poisson = s.ext_mode == SNN_EXT_POISSON;
+    tp.ext_n = s.ext_n;
+    tp.ext_rate_hz = s.ext_rate_hz;
+    tp.ext_w = s.ext_w;
+    tp.tau_m = g.tau_m;
+    tp.tau_w = g.tau_w;
+    tp.t_ref = g.t_ref;
+    return tp;
+}
+
 bool valid_grid(const snn_grid_desc* g, std::string& why)
 {
     const uint64_t M = (uint64_t)g->n_exc + g->n_inh;
@@ -311,23 +333,7 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     if (s->ext_mode == SNN_EXT_POISSON && !(s->ext_n * s->ext_rate_hz >= 0))
         return fail(n, SNN_E_INVAL, "bad external drive");
     const auto t_start = std::chrono::steady_clock::now();
-    snn::TableParams tp{};
-    tp.gx = n->g.gx;
-    tp.gy = n->g.gy;
-    tp.M = n->M;
-    tp.kernel = s->kernel;
-    tp.range = s->range;
-    tp.k_in = s->k_in;
-    tp.w_exc = s->w_exc;
-    tp.w_exc_sd = s->w_exc_sd;
-    tp.w_inh = s->w_inh;
-    tp.ext_poisson = s->ext_mode == SNN_EXT_POISSON;
-    tp.ext_n = s->ext_n;
-    tp.ext_rate_hz = s->ext_rate_hz;
-    tp.ext_w = s->ext_w;
-    tp.tau_m = n->g.tau_m;
-    tp.tau_w = n->g.tau_w;
-    tp.t_ref = n->g.t_ref;
+    snn::TableParams tp = table_params(n->g, *s);
     snn::HostTables tb;
     std::string why = snn::build_tables(tp, tb);
     if (!why.empty()) return fail(n, SNN_E_INVAL, why);
@@ -658,6 +664,26 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     return SNN_OK;
 }
 
+snn_status snn_reset(snn_net* n)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    StepArgs& a = n->a;
+    HIPCHK(n, hipMemsetAsync(a.ring, 0, sizeof(int32_t) * (size_t)snn::kRing * n->N, n->stream));
+    HIPCHK(n, hipMemsetAsync(a.grp_cnt, 0, sizeof(uint32_t) * 2 * a.ngrp, n->stream));
+    HIPCHK(n, hipMemsetAsync(a.ctrl, 0, sizeof(Ctrl), n->stream));
+    if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles, n->stream));
+    HIPCHK(n, snn::launch_init(a, n->stream));
+    if (n->built) {
+        // the construction statistics live in the control block too
+        snn::Ctrl keep{};
+        keep.max_len = n->max_len;
+        HIPCHK(n, hipMemcpyAsync(a.ctrl, &keep, sizeof(Ctrl), hipMemcpyHostToDevice, n->stream));
+    }
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    return SNN_OK;
+}
+
 snn_status snn_set_option(snn_net* n, int key, int64_t value)
 {
     snn_status st = check_usable(n);
@@ -687,6 +713,21 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         n->bin_threshold_opt = (uint64_t)value;
         n->a.bin_threshold = (uint64_t)value;
         break;
+    case SNN_OPT_EXT_RATE_UHZ: {
+        if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before changing the drive");
+        if (value < 0) return fail(n, SNN_E_INVAL, "rate must be >= 0");
+        if (n->s.ext_mode != SNN_EXT_POISSON) return fail(n, SNN_E_INVAL, "network has no Poisson drive");
+        snn::TableParams tp = table_params(n->g, n->s);
+        tp.ext_rate_hz = (double)value * 1e-6;
+        snn::HostTables tb;
+        std::string why = snn::build_tables(tp, tb);
+        if (!why.empty()) return fail(n, SNN_E_INVAL, why);
+        HIPCHK(n, hipStreamSynchronize(n->stream));
+        HIPCHK(n, hipMemcpy((void*)n->a.poisc, tb.poisc.data(), tb.poisc.size() * 4, hipMemcpyHostToDevice));
+        n->a.npois = (uint32_t)tb.poisc.size();
+        n->s.ext_rate_hz = tp.ext_rate_hz;
+        break;
+    }
     case SNN_OPT_SCATTER_BLOCKS:
         if (value < 1 || value > 65536) return fail(n, SNN_E_INVAL, "scatter blocks out of range");
         n->scatter_blocks = (uint32_t)value;
@@ -709,23 +750,7 @@ snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32
     if (!g || !s) return fail(nullptr, SNN_E_INVAL, "null argument");
     std::string why;
     if (!valid_grid(g, why)) return fail(nullptr, SNN_E_INVAL, why);
-    snn::TableParams tp{};
-    tp.gx = g->gx;
-    tp.gy = g->gy;
-    tp.M = g->n_exc + g->n_inh;
-    tp.kernel = s->kernel;
-    tp.range = s->range;
-    tp.k_in = s->k_in;
-    tp.w_exc = s->w_exc;
-    tp.w_exc_sd = s->w_exc_sd;
-    tp.w_inh = s->w_inh;
-    tp.ext_poisson = s->ext_mode == SNN_EXT_POISSON;
-    tp.ext_n = s->ext_n;
-    tp.ext_rate_hz = s->ext_rate_hz;
-    tp.ext_w = s->ext_w;
-    tp.tau_m = g->tau_m;
-    tp.tau_w = g->tau_w;
-    tp.t_ref = g->t_ref;
+    snn::TableParams tp = table_params(*g, *s);
     snn::HostTables tb;
     why = snn::build_tables(tp, tb);
     if (!why.empty()) return fail(nullptr, SNN_E_INVAL, why);

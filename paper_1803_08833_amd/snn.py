@@ -21,12 +21,13 @@ SNN_OK, SNN_E_INVAL, SNN_E_NOMEM, SNN_E_HIP, SNN_E_STATE, SNN_E_OVERFLOW, SNN_E_
 OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL, OPT_DELIVER_MODE, OPT_SCATTER_BLOCKS = 1, 2, 3, 4, 5
 OPT_BIN_FRAC_PPM = 6
 OPT_BIN_THRESHOLD = 7
+OPT_EXT_RATE_UHZ = 8
 RING = 32
 
 EXPORTS = [
     "snn_build_grid", "snn_build_synapses", "snn_step", "snn_step_forced", "snn_read_spikes",
     "snn_read_state", "snn_read_ring", "snn_export_rows", "snn_stats", "snn_time_kernels",
-    "snn_set_option", "snn_host_tables", "snn_destroy", "snn_last_error",
+    "snn_set_option", "snn_host_tables", "snn_reset", "snn_destroy", "snn_last_error",
 ]
 
 
@@ -101,6 +102,7 @@ def lib():
             "snn_time_kernels": ([P, U32, C.POINTER(KernelTimes)], C.c_int),
             "snn_set_option": ([P, C.c_int, C.c_int64], C.c_int),
             "snn_host_tables": ([C.POINTER(GridDesc), C.POINTER(SynDesc), P, P, P, P, P, P], C.c_int),
+            "snn_reset": ([P], C.c_int),
             "snn_destroy": ([P], None),
             "snn_last_error": ([P], C.c_char_p),
         }
@@ -177,9 +179,9 @@ class Net:
             raise SNNError(st, lib().snn_last_error(self.h).decode())
 
     def close(self):
-        if getattr(self, "h", None):
-            lib().snn_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.snn_destroy(self.h)
+        self.h = None
 
     def __del__(self):
         self.close()
@@ -250,3 +252,10 @@ class Net:
 
     def set_option(self, key: int, value: int):
         self._check(lib().snn_set_option(self.h, key, value))
+
+    def reset(self):
+        self._check(lib().snn_reset(self.h))
+
+    def set_ext_rate(self, hz: float):
+        self.set_option(OPT_EXT_RATE_UHZ, int(round(hz * 1e6)))
+        self.net["ext_rate_hz"] = hz

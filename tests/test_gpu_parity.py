@@ -272,3 +272,25 @@ def test_errors_and_lifecycle(snn):
             g.set_option(snn.OPT_DELIVER_UNROLL, 3)
         g.step(5)
         assert g.stats()["t"] == 5
+
+
+def test_reset_and_drive_change_reproduce_fresh_networks(snn):
+    net = W.workload("grid4_gauss", seed=33)["net"]
+    say("case: reset and run-time drive change")
+    with snn.Net(net) as g:
+        g.build_synapses()
+        g.step(150)
+        first = (g.read_spikes(), g.read_ring())
+        g.reset()
+        assert g.stats()["t"] == 0
+        g.step(150)
+        np.testing.assert_array_equal(g.read_spikes(), first[0])
+        np.testing.assert_array_equal(g.read_ring(), first[1])
+        g.reset()
+        g.set_ext_rate(2.5)
+        g.step(150)
+        changed = g.read_spikes()
+    with snn.Net(dict(net, ext_rate_hz=2.5)) as h:
+        h.build_synapses()
+        h.step(150)
+        np.testing.assert_array_equal(changed, h.read_spikes())
