@@ -221,6 +221,50 @@ snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32
 /* Free every device buffer of the network (synchronises its stream). */
 void snn_destroy(snn_net* net);
 
+/* ---- Batched / served stepping of many networks ("jobs") ----------------
+ * A batch advances every admitted job by the same number of steps with one
+ * launch per phase for all jobs together (multi-job kernels over a device job
+ * table, replayed as HIP graphs), so many small networks share the GPU.  Each
+ * job is an ordinary network (same definitions, same results as stepping it
+ * alone) built on the batch's construction stream, so building a new job
+ * overlaps with the steps already enqueued for the others.  Jobs stop at
+ * their own duration.  Batched jobs use direct delivery. */
+typedef struct snn_batch snn_batch;
+
+/* hbm_budget: device bytes the batch may hold for its jobs (admission
+ * control); max_neurons: total neurons of jobs admitted at once (sizes the
+ * update grid); hip_stream: stepping stream (NULL = own stream). */
+snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip_stream, snn_batch** out);
+
+/* Admit a job of dur_ms steps: checks the footprint estimate (including a
+ * spike history with room for a 150 Hz mean rate) against the free budget,
+ * builds the network (blocks the calling thread while the build
+ * runs on the construction stream) and adds it to the job table.  *slot
+ * receives the job's slot.  SNN_E_NOMEM: not now (budget, neurons or all 64
+ * slots in use); SNN_E_INVAL: bad description. */
+snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_desc* s, uint32_t dur_ms,
+                           int32_t* slot);
+
+/* Enqueue chunk_ms steps for every admitted, unfinished job. */
+snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms);
+
+/* Finished jobs whose spikes have not been read yet (synchronises). */
+snn_status snn_batch_poll(snn_batch* b, int32_t* done_slots, size_t cap, size_t* n_out);
+
+/* Copy a finished job's whole spike history, ordered by (t_ms, gid), then
+ * free its slot and memory.  SNN_E_STATE if the job has not finished;
+ * SNN_E_TRUNC (slot kept) if cap is too small, *n_out = count needed. */
+snn_status snn_batch_read_spikes(snn_batch* b, int32_t slot, snn_spike* host_buf, size_t cap, size_t* n_out);
+
+/* Counters of one job (synchronises). */
+snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out);
+
+/* Device bytes the batch's jobs hold now; number of admitted jobs. */
+snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs);
+
+void snn_batch_destroy(snn_batch* b);
+const char* snn_batch_last_error(const snn_batch* b);
+
 /* Text of the last error of this handle (or of the last failed create when
  * net is NULL).  Valid until the next call on the handle. */
 const char* snn_last_error(const snn_net* net);

@@ -26,9 +26,8 @@ def build(verbose: bool = False) -> str:
     objs = []
     for src in SOURCES:
         obj = os.path.join(objdir, src + ".o")
-        cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
-            cmd[1:1] = DEVICE
+        # host sources are compiled as HIP too (hipcc's default), for gfx950 only
+        cmd = [HIPCC, *DEVICE, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

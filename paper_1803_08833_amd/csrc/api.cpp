@@ -43,6 +43,7 @@ struct snn_net {
     uint32_t deliver_waves = 8192;
     uint32_t unroll = 4;
     uint32_t mode = 0;          // 0 direct atomics, 1 tile-binned
+    int mode_pref = -1;         // set before the build: -1 automatic, 0 direct only
     bool binned_ok = false;
     uint32_t scatter_blocks = 256;
     double bin_frac = 0.5;      // bin capacity as a fraction of the tile's in-synapses
@@ -429,7 +430,7 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     // every weight has a 17-bit event field (code, or w_q + 65536 in range).
     a.ntiles = (n->N + snn::kTile - 1) / snn::kTile;
     a.winh_q = tb.winh_q;
-    bool ok = a.ntiles <= snn::kMaxTiles;
+    bool ok = a.ntiles <= snn::kMaxTiles && n->mode_pref != 0;
     if (s->record != SNN_REC_CODE8)
         for (int32_t w : tb.wtab)
             if (w != tb.winh_q && (w < -65536 || w > 65534)) ok = false;
@@ -524,9 +525,9 @@ snn_status snn_read_spikes(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf,
         *pos = lo;
         return hipSuccess;
     };
-    uint64_t p0 = 0, p1 = 0;
-    HIPCHK(n, lower(t0, &p0));
-    HIPCHK(n, lower(t1, &p1));
+    uint64_t p0 = 0, p1 = kept;
+    if (t0 > 0) HIPCHK(n, lower(t0, &p0));
+    if (t1 <= hc.t0) HIPCHK(n, lower(t1, &p1));
     if (p1 < p0) p1 = p0;
     const uint64_t m = p1 - p0;
     *n_out = (size_t)m;
@@ -699,6 +700,10 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         break;
     case SNN_OPT_DELIVER_MODE:
         if (value != 0 && value != 1) return fail(n, SNN_E_INVAL, "delivery mode must be 0 or 1");
+        if (!n->built) {
+            n->mode_pref = (int)value;    // 0 before the build: no bins are allocated
+            return SNN_OK;
+        }
         if (value == 1 && !n->binned_ok) return fail(n, SNN_E_INVAL, "this network cannot use binned delivery");
         n->mode = (uint32_t)value;
         break;
@@ -776,6 +781,351 @@ void snn_destroy(snn_net* n)
     n->allocs.clear();
     if (n->own_stream && n->stream) (void)hipStreamDestroy(n->stream);
     delete n;
+}
+
+}  // extern "C"
+
+/* ------------------------------------------------------------------------ */
+/* Batched stepping                                                          */
+/* ------------------------------------------------------------------------ */
+struct snn_batch {
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t build_stream = nullptr;
+    uint64_t budget = 0, used = 0;
+    uint32_t blk_cap = 0, blk_used = 0;
+    uint32_t scatter_blocks = 512;
+    struct Job {
+        snn_net* net = nullptr;
+        uint64_t bytes = 0;
+        uint32_t dur = 0, nblk = 0;
+        uint32_t t = 0;               // steps enqueued for the job (host-side schedule)
+        bool active = false;
+        bool binned = false;          // built with delivery bins for the batched kernels
+    };
+    Job jobs[snn::kMaxJobs];
+    snn::JobDesc* d_jobs = nullptr;
+    static constexpr int kTables = 8;  // pinned staging copies of the table, used in turn
+    snn::JobDesc* h_jobs[kTables] = {};
+    hipEvent_t h_done[kTables] = {};
+    int h_next = 0;
+    std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    std::string err;
+    bool poisoned = false;
+};
+
+namespace {
+
+thread_local std::string g_batch_err;
+
+snn_status bfail(snn_batch* b, snn_status st, const std::string& msg)
+{
+    if (b) b->err = msg;
+    else g_batch_err = msg;
+    return st;
+}
+
+#define BHIPCHK(b, x)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (x);                                                                  \
+        if (e_ != hipSuccess) {                                                               \
+            (b)->poisoned = true;                                                             \
+            return bfail(b, SNN_E_HIP, std::string("HIP error in " #x ": ") + hipGetErrorString(e_)); \
+        }                                                                                     \
+    } while (0)
+
+// A batch job may use binned delivery: F32 records, the fused next-step update
+// (d_min == 1) and a tile's delay rows within the batched tile kernel's LDS.
+bool batch_binnable(const snn_syn_desc& s)
+{
+    return s.record != SNN_REC_CODE8 && s.d_min == 1 && s.d_max - s.d_min + 1 <= snn::kBatchMaxD;
+}
+
+// Device bytes a network will hold (upper estimate used for admission).
+uint64_t estimate_bytes(const snn_grid_desc& g, const snn_syn_desc& s, uint64_t hist_cap)
+{
+    const uint64_t M = (uint64_t)g.n_exc + g.n_inh, N = (uint64_t)g.gx * g.gy * M;
+    const uint64_t D = s.d_max - s.d_min + 1;
+    const uint64_t nblk = (N + 1023) / 1024;
+    const double k = s.k_in + 6.0 * std::sqrt(s.k_in + 1.0);
+    const uint64_t rec = s.record == SNN_REC_CODE8 ? 4 : 8;
+    uint64_t b = N * (4 + 4 + 1) + 32 * N * 4 + nblk * 4 + nblk * 1024 * 16 + N * 16 + hist_cap * 8 + N * 5;
+    b += (uint64_t)g.gx * g.gy * 4 + 65536 * 4 + 1024 + 256 + (N + 1) * 8 + N * D * 2;
+    b += (uint64_t)((double)N * k) * rec + N * 4 + (1ull << 20);
+    if (batch_binnable(s)) b += nblk * 4 + nblk * (uint64_t)(0.5 * 1024.0 * k + 4096.0) * 4;
+    return b;
+}
+
+void batch_drop_graphs(snn_batch* b)
+{
+    for (auto& kv : b->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    b->graphs.clear();
+}
+
+// Rewrite the device job table (block ranges are packed in slot order).  The
+// copy is ordered on the stepping stream after the steps already enqueued; the
+// pinned staging buffers are reused in turn once their previous copy is done.
+hipError_t batch_upload(snn_batch* b)
+{
+    const int i = b->h_next;
+    b->h_next = (b->h_next + 1) % snn_batch::kTables;
+    hipError_t e = hipEventSynchronize(b->h_done[i]);
+    if (e != hipSuccess) return e;
+    snn::JobDesc* tab = b->h_jobs[i];
+    uint32_t base = 0;
+    for (uint32_t j = 0; j < snn::kMaxJobs; ++j) {
+        snn::JobDesc& d = tab[j];
+        std::memset(&d, 0, sizeof(d));
+        const snn_batch::Job& J = b->jobs[j];
+        if (!J.active) continue;
+        d.a = J.net->a;
+        d.t_end = J.dur;
+        d.active = 1;
+        d.blk_base = base;
+        d.smax = J.net->max_len ? (J.net->max_len + 255) / 256 : 1;
+        d.binned = (J.binned && J.net->binned_ok && d.a.bins) ? 1u : 0u;
+        base += J.nblk;
+    }
+    b->blk_used = base;
+    e = hipMemcpyAsync(b->d_jobs, tab, sizeof(snn::JobDesc) * snn::kMaxJobs, hipMemcpyHostToDevice, b->stream);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(b->h_done[i], b->stream);
+}
+
+hipError_t batch_graph(snn_batch* b, uint32_t chunk, hipGraphExec_t* out)
+{
+    auto it = b->graphs.find(chunk);
+    if (it != b->graphs.end()) {
+        *out = it->second.second;
+        return hipSuccess;
+    }
+    hipGraph_t gr = nullptr;
+    hipGraphExec_t ex = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipSuccess;
+    // step k: delivery of step k's spikes (binned or direct per job), then the
+    // tiles, which also update the neurons for step k + 1; the chunk's first
+    // update runs on its own and its last tile kernel updates nothing.
+    le = snn::launch_batch_update(b->d_jobs, b->blk_cap, 0, b->stream);
+    for (uint32_t k = 0; k < chunk && le == hipSuccess; ++k) {
+        le = snn::launch_batch_scatter(b->d_jobs, b->scatter_blocks, k, b->stream);
+        if (le == hipSuccess) le = snn::launch_batch_tile(b->d_jobs, b->blk_cap, k, k + 1 < chunk, b->stream);
+    }
+    if (le == hipSuccess) le = snn::launch_batch_advance(b->d_jobs, chunk, b->stream);
+    e = hipStreamEndCapture(b->stream, &gr);
+    if (le != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return le;
+    }
+    if (e != hipSuccess) return e;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        return e;
+    }
+    b->graphs[chunk] = std::make_pair(gr, ex);
+    *out = ex;
+    return hipSuccess;
+}
+
+snn_status batch_check(snn_batch* b)
+{
+    if (!b) return bfail(nullptr, SNN_E_INVAL, "null batch handle");
+    if (b->poisoned) return SNN_E_HIP;
+    return SNN_OK;
+}
+
+
+}  // namespace
+
+extern "C" {
+
+snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip_stream, snn_batch** out)
+{
+    if (!out || hbm_budget == 0 || max_neurons == 0) return bfail(nullptr, SNN_E_INVAL, "bad batch arguments");
+    *out = nullptr;
+    snn_batch* b = new snn_batch();
+    b->budget = hbm_budget;
+    b->blk_cap = (uint32_t)((max_neurons + 1023) / 1024);
+    hipError_t e = hipSuccess;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        b->own_stream = e == hipSuccess;
+    }
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->build_stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = snn::setup_kernels();
+    if (e == hipSuccess) e = hipMalloc((void**)&b->d_jobs, sizeof(snn::JobDesc) * snn::kMaxJobs);
+    for (int i = 0; i < snn_batch::kTables && e == hipSuccess; ++i) {
+        e = hipHostMalloc((void**)&b->h_jobs[i], sizeof(snn::JobDesc) * snn::kMaxJobs, 0);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = batch_upload(b);
+    if (e != hipSuccess) {
+        snn_batch_destroy(b);
+        return bfail(nullptr, SNN_E_HIP, std::string("batch creation failed: ") + hipGetErrorString(e));
+    }
+    *out = b;
+    return SNN_OK;
+}
+
+snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_desc* s, uint32_t dur_ms,
+                           int32_t* slot)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (!g || !s || !slot || dur_ms == 0) return bfail(b, SNN_E_INVAL, "bad job arguments");
+    *slot = -1;
+    int free_slot = -1;
+    for (uint32_t j = 0; j < snn::kMaxJobs; ++j)
+        if (!b->jobs[j].active) {
+            free_slot = (int)j;
+            break;
+        }
+    if (free_slot < 0) return bfail(b, SNN_E_NOMEM, "all job slots in use");
+    std::string why;
+    if (!valid_grid(g, why)) return bfail(b, SNN_E_INVAL, why);
+    const uint64_t N = (uint64_t)g->gx * g->gy * (g->n_exc + g->n_inh);
+    const uint32_t nblk = (uint32_t)((N + 1023) / 1024);
+    if (b->blk_used + nblk > b->blk_cap) return bfail(b, SNN_E_NOMEM, "neuron capacity of the batch in use");
+    snn_grid_desc gd = *g;
+    gd.hist_cap = (uint64_t)((double)N * dur_ms * 0.15) + 65536;   // room for a 150 Hz mean rate
+    const uint64_t est = estimate_bytes(gd, *s, gd.hist_cap);
+    if (b->used + est > b->budget) return bfail(b, SNN_E_NOMEM, "HBM budget in use");
+    snn_net* n = nullptr;
+    st = snn_build_grid(&gd, b->build_stream, &n);
+    if (st) return bfail(b, st, snn_last_error(nullptr));
+    const bool binnable = batch_binnable(*s);
+    if (!binnable) snn_set_option(n, SNN_OPT_DELIVER_MODE, 0);   // no bins to allocate
+    st = snn_build_synapses(n, s);
+    if (st) {
+        std::string m = snn_last_error(n);
+        snn_destroy(n);
+        return bfail(b, st, m);
+    }
+    snn_batch::Job& J = b->jobs[free_slot];
+    J.net = n;
+    J.bytes = n->bytes;
+    J.dur = dur_ms;
+    J.nblk = nblk;
+    J.t = 0;
+    J.active = true;
+    J.binned = binnable;
+    b->used += J.bytes;
+    BHIPCHK(b, batch_upload(b));
+    *slot = free_slot;
+    return SNN_OK;
+}
+
+snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (chunk_ms == 0) return SNN_OK;
+    hipGraphExec_t ex = nullptr;
+    BHIPCHK(b, batch_graph(b, chunk_ms, &ex));
+    BHIPCHK(b, hipGraphLaunch(ex, b->stream));
+    for (auto& J : b->jobs)
+        if (J.active) J.t = (J.t + chunk_ms < J.dur) ? J.t + chunk_ms : J.dur;
+    return SNN_OK;
+}
+
+snn_status snn_batch_poll(snn_batch* b, int32_t* done, size_t cap, size_t* n_out)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (!n_out || (cap && !done)) return bfail(b, SNN_E_INVAL, "null output");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    size_t n = 0;
+    for (uint32_t j = 0; j < snn::kMaxJobs; ++j) {
+        if (!b->jobs[j].active) continue;
+        if (b->jobs[j].t >= b->jobs[j].dur) {
+            if (n < cap) done[n] = (int32_t)j;
+            ++n;
+        }
+    }
+    *n_out = n;
+    return n > cap ? bfail(b, SNN_E_TRUNC, "slot buffer too small") : SNN_OK;
+}
+
+snn_status snn_batch_read_spikes(snn_batch* b, int32_t slot, snn_spike* buf, size_t cap, size_t* n_out)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !b->jobs[slot].active || !n_out)
+        return bfail(b, SNN_E_INVAL, "no job in this slot");
+    snn_batch::Job& J = b->jobs[slot];
+    if (J.t < J.dur) return bfail(b, SNN_E_STATE, "job has not finished");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    std::vector<snn_spike> all;
+    size_t m = 0;
+    st = snn_read_spikes(J.net, 0, ~0ull, nullptr, 0, &m);
+    if (st && st != SNN_E_TRUNC) return bfail(b, st, snn_last_error(J.net));
+    *n_out = m;
+    if (m > cap) return bfail(b, SNN_E_TRUNC, "spike buffer too small");
+    all.resize(m);
+    st = snn_read_spikes(J.net, 0, ~0ull, all.data(), m, &m);
+    const bool truncated = st == SNN_E_TRUNC;
+    if (st && !truncated) return bfail(b, st, snn_last_error(J.net));
+    // within a step the batched kernels append spikes in arrival order
+    std::sort(all.begin(), all.end(), [](const snn_spike& x, const snn_spike& y) {
+        return x.t_ms != y.t_ms ? x.t_ms < y.t_ms : x.gid < y.gid;
+    });
+    if (m) std::memcpy(buf, all.data(), m * sizeof(snn_spike));
+    snn_destroy(J.net);
+    b->used -= J.bytes;
+    J = snn_batch::Job();
+    BHIPCHK(b, batch_upload(b));
+    return truncated ? bfail(b, SNN_E_TRUNC, "job history overflowed its capacity") : SNN_OK;
+}
+
+snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !b->jobs[slot].active || !out)
+        return bfail(b, SNN_E_INVAL, "no job in this slot");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    st = snn_stats(b->jobs[slot].net, out);
+    return st ? bfail(b, st, snn_last_error(b->jobs[slot].net)) : SNN_OK;
+}
+
+snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    uint32_t n = 0;
+    for (auto& J : b->jobs) n += J.active ? 1u : 0u;
+    if (bytes) *bytes = b->used;
+    if (jobs) *jobs = n;
+    return SNN_OK;
+}
+
+void snn_batch_destroy(snn_batch* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    batch_drop_graphs(b);
+    for (auto& J : b->jobs)
+        if (J.net) snn_destroy(J.net);
+    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    for (int i = 0; i < snn_batch::kTables; ++i) {
+        if (b->h_jobs[i]) (void)hipHostFree(b->h_jobs[i]);
+        if (b->h_done[i]) (void)hipEventDestroy(b->h_done[i]);
+    }
+    if (b->build_stream) (void)hipStreamDestroy(b->build_stream);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+const char* snn_batch_last_error(const snn_batch* b)
+{
+    return b ? b->err.c_str() : g_batch_err.c_str();
 }
 
 }  // extern "C"

@@ -521,11 +521,61 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
 // inside the chunk are walked), and adds the fixed-point weight into
 // ring[(t + delay) mod 32][target] with a non-returning device-scope atomic.
 // ---------------------------------------------------------------------------
+// One work item of direct delivery: segment `seg` (64*U records) of the row of
+// spike record `info`, one global atomic per event.
+template <int U, bool CODE8>
+__device__ __forceinline__ void deliver_item(const StepArgs& a, uint32_t t, uint4 info, uint32_t seg,
+                                             uint32_t lane, const int32_t* cb)
+{
+    constexpr uint32_t SEG = 64u * U;
+    const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
+    const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.y);
+    const uint64_t rb = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.z) |
+                        ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
+    const uint32_t c0 = seg * SEG;
+    if (c0 >= len) return;
+    const uint32_t be = lane < a.D ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
+    uint32_t tg[U];
+    int32_t wq[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {   // all loads issued before any use
+        uint32_t kk = c0 + 64u * u + lane;
+        kk = kk < len ? kk : len - 1u;
+        if (CODE8) {
+            const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
+            tg[u] = v >> 8;
+            wq[u] = (int32_t)(v & 255u);
+        } else {
+            const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
+            tg[u] = r.tgt;
+            wq[u] = __float2int_rn(r.w * 65536.0f);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t c = c0 + 64u * u;
+        if (c >= len) break;
+        const uint32_t kk = c + lane;
+        uint32_t bl = popc(__ballot(be <= c));
+        uint64_t inm = __ballot(be > c && be < c + 64u);
+        while (inm) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+            inm &= inm - 1u;
+            bl += (kk >= readlane(be, l)) ? 1u : 0u;
+        }
+        if (kk < len) {
+            const int32_t w = CODE8 ? cb[wq[u]] : wq[u];
+            const uint32_t slot = (t + a.d_min + bl) & (kRing - 1u);
+            __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tg[u], w, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int U, bool CODE8>
 __device__ __forceinline__ void deliver_direct(const StepArgs& a, uint32_t t, uint32_t n, uint32_t smax,
                                                uint32_t wave, uint32_t nw, uint32_t lane, const int32_t* cb)
 {
-    constexpr uint32_t SEG = 64u * U;
     const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
     uint32_t it = wave;
     uint4 nxt = make_uint4(0, 0, 0, 0);
@@ -536,48 +586,7 @@ __device__ __forceinline__ void deliver_direct(const StepArgs& a, uint32_t t, ui
         const uint32_t itn = it + nw;
         if (itn < items) nxt = a.spk[itn / smax];     // prefetch the next item's spike record
         it = itn;
-        const uint32_t pre = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.x);
-        const uint32_t len = (uint32_t)__builtin_amdgcn_readfirstlane((int)info.y);
-        const uint64_t rb = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.z) |
-                            ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
-        const uint32_t c0 = seg * SEG;
-        if (c0 >= len) continue;
-        const uint32_t be = lane < a.D ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
-        uint32_t tg[U];
-        int32_t wq[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {   // all loads issued before any use
-            uint32_t kk = c0 + 64u * u + lane;
-            kk = kk < len ? kk : len - 1u;
-            if (CODE8) {
-                const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
-                tg[u] = v >> 8;
-                wq[u] = (int32_t)(v & 255u);
-            } else {
-                const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
-                tg[u] = r.tgt;
-                wq[u] = __float2int_rn(r.w * 65536.0f);
-            }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const uint32_t c = c0 + 64u * u;
-            if (c >= len) break;
-            const uint32_t kk = c + lane;
-            uint32_t bl = popc(__ballot(be <= c));
-            uint64_t inm = __ballot(be > c && be < c + 64u);
-            while (inm) {
-                const uint32_t l = (uint32_t)__builtin_ctzll(inm);
-                inm &= inm - 1u;
-                bl += (kk >= readlane(be, l)) ? 1u : 0u;
-            }
-            if (kk < len) {
-                const int32_t w = CODE8 ? cb[wq[u]] : wq[u];
-                const uint32_t slot = (t + a.d_min + bl) & (kRing - 1u);
-                __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tg[u], w, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
+        deliver_item<U, CODE8>(a, t, info, seg, lane, cb);
     }
 }
 
@@ -807,23 +816,86 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 // ---------------------------------------------------------------------------
 constexpr uint32_t kTileThreads = 1024;
 
-// UPD (requires d_min == 1): after the tile's ring rows are complete for step
-// t + 1 (every event arriving then has been delivered), also run the neuron
-// update of step t + 1 for the tile's 1024 neurons (the tile is an update
-// block).  The first LDS row is slot t + 1: it is handed to the update and
-// written back as zeros, and its LDS space then holds the update's small
-// tables, so the kernel needs no static LDS and two workgroups fit a CU.
-template <bool CODE8, bool UPD>
-__global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
+// Spikers of one update block appended, unordered, to the network's spike
+// list of step t (batched stepping): one atomic per block reserves room, each
+// spiker writes its record {gid, row length, row start} and history entry, and
+// the block's spike, external and recurrent event counts are accumulated
+// (including the step's event total used by the delivery switch).
+template <uint32_t NW>
+__device__ __forceinline__ void block_append(const StepArgs& a, uint32_t t, uint32_t q, uint32_t flags,
+                                             uint32_t ext_tot, uint32_t* wtot, unsigned long long* wext,
+                                             unsigned long long* wev, uint32_t* sbase)
 {
-    extern __shared__ int32_t acc[];      // [D][1024]
-    const uint32_t tid = threadIdx.x, tt = blockIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
+    const uint64_t m2 = __ballot(flags & 4u), m3 = __ballot(flags & 8u);
+    const uint32_t pre = mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
+    const uint32_t wt = popc(m0) + popc(m1) + popc(m2) + popc(m3);
+    const unsigned long long we = wave_sum<unsigned long long>(ext_tot);
+    if (lane == 0) {
+        wtot[wv] = wt;
+        wext[wv] = we;
+    }
+    __syncthreads();
+    uint32_t woff = 0, btot = 0;
+    unsigned long long bext = 0;
+    for (uint32_t i = 0; i < NW; ++i) {
+        if (i < wv) woff += wtot[i];
+        btot += wtot[i];
+        bext += wext[i];
+    }
+    if (tid == 0) {
+        *sbase = btot ? atomicAdd(&a.ctrl->nspk_par[t & 1u], btot) : 0u;
+        if (bext) atomicAdd((unsigned long long*)&a.ctrl->ext_events, bext);
+        if (btot) atomicAdd((unsigned long long*)&a.ctrl->spikes, (unsigned long long)btot);
+    }
+    __syncthreads();
+    unsigned long long ev = 0;
+    if (flags) {
+        uint32_t p = *sbase + woff + pre;
+        const uint64_t h0 = a.ctrl->hist_n;
+        for (uint32_t s = 0; s < 4u; ++s) {
+            if (flags & (1u << s)) {
+                const uint32_t gid = 4u * q + s;
+                const uint64_t rb = a.row_ptr[gid];
+                const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
+                a.spk[p] = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+                if (h0 + p < a.hist_cap) a.hist[h0 + p] = make_uint2(t, gid);
+                ev += len;
+                ++p;
+            }
+        }
+    }
+    ev = wave_sum<unsigned long long>(ev);
+    if (lane == 0) wev[wv] = ev;
+    __syncthreads();
+    if (tid == 0) {
+        unsigned long long be = 0;
+        for (uint32_t i = 0; i < NW; ++i) be += wev[i];
+        if (be) {
+            atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+            atomicAdd((unsigned long long*)&a.ctrl->step_ev[t & 1u], be);
+        }
+    }
+}
+
+// Phase B of binned delivery for tile tt of one network at step t (see
+// k_tile), optionally followed (UPD, d_min == 1, upd_live) by the neuron
+// update of step t + 1 for the tile's 1024 neurons.  The first LDS row is slot
+// t + 1: it is handed to the update and written back as zeros, and its LDS
+// space then holds the update's small tables, so no static LDS is needed and
+// two workgroups fit a CU.  APPEND selects the batched (unordered) spike
+// compaction instead of the ordered per-block one.
+template <bool CODE8, bool UPD, bool APPEND>
+__device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32_t t, bool binned, bool upd_live,
+                                          int32_t* acc)
+{
+    const uint32_t tid = threadIdx.x;
     const uint32_t g0 = tt << kTileBits;
     const uint32_t nn = (a.N - g0) < kTile ? (a.N - g0) : kTile;
-    const uint32_t t = a.ctrl->t0 + k;
     const uint32_t D = a.D;
-    const bool binned = step_binned(a, t);
-    if (!UPD && !binned) return;
+    const bool do_upd = UPD && upd_live;
+    if (!do_upd && !binned) return;
     if (binned) {
         for (uint32_t idx = tid; idx < D * (kTile / 4u); idx += kTileThreads) {
             const uint32_t b = idx / (kTile / 4u), q = idx % (kTile / 4u);
@@ -861,7 +933,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
     uint32_t flags = 0, ext_tot = 0, dis = 0;
     const uint32_t q = (g0 >> 2) + tid;
     uint32_t* scratch = reinterpret_cast<uint32_t*>(acc);   // row 0 once consumed
-    if (UPD) {
+    if (do_upd) {
         int4 in = make_int4(0, 0, 0, 0);
         if (tid < kTile / 4u && 4u * tid < nn) {
             if (binned) {
@@ -882,16 +954,303 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
             const uint32_t b = idx / (kTile / 4u), qq = idx % (kTile / 4u);
             if (4u * qq < nn) {
                 const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
-                const int4 v = (UPD && b == 0u) ? make_int4(0, 0, 0, 0) : reinterpret_cast<const int4*>(acc)[idx];
+                const int4 v = (do_upd && b == 0u) ? make_int4(0, 0, 0, 0) : reinterpret_cast<const int4*>(acc)[idx];
                 reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[qq] = v;
             }
         }
         if (tid == 0) a.bin_fill[tt] = 0u;
     }
-    if (UPD) {
+    if (do_upd) {
         __syncthreads();   // every thread is past its use of the Poisson table
-        block_compact<kTileThreads / 64>(a, tt, t + 1u, q, flags, ext_tot, dis, scratch + 64,
-                                         reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80);
+        constexpr uint32_t NW = kTileThreads / 64;
+        if (APPEND)
+            block_append<NW>(a, t + 1u, q, flags, ext_tot, scratch + 64,
+                             reinterpret_cast<unsigned long long*>(scratch + 96),
+                             reinterpret_cast<unsigned long long*>(scratch + 128), scratch + 160);
+        else
+            block_compact<NW>(a, tt, t + 1u, q, flags, ext_tot, dis, scratch + 64,
+                              reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80);
+    }
+}
+
+template <bool CODE8, bool UPD>
+__global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
+{
+    extern __shared__ int32_t acc[];      // [D][1024]
+    const uint32_t t = a.ctrl->t0 + k;
+    tile_work<CODE8, UPD, false>(a, blockIdx.x, t, step_binned(a, t), true, acc);
+}
+
+// ---------------------------------------------------------------------------
+// Batched stepping of many independent networks ("jobs") per launch.  A
+// device job table holds each job's step arguments; the update kernel's
+// blocks are spread over the jobs (job j owns blocks [blk_base, blk_base +
+// nblk)), spikers are appended to their job's spike list (order within a step
+// is free: delivery is order-independent and the history is sorted when read),
+// and the delivery kernel walks the concatenated work items of all jobs.  Jobs
+// stop at their own duration.  The kernels read everything from the table, so
+// captured step graphs stay valid while jobs come and go.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int job_of_block(const JobDesc* jobs, uint32_t b)
+{
+    const uint32_t lane = threadIdx.x & 63u;
+    const JobDesc& J = jobs[lane];
+    const bool mine = J.active && b >= J.blk_base && b < J.blk_base + J.a.nblk;
+    const uint64_t m = __ballot(mine);
+    return m ? (int)__builtin_ctzll(m) : -1;
+}
+
+__global__ __launch_bounds__(256) void k_batch_update(const JobDesc* __restrict__ jobs, uint32_t k)
+{
+    __shared__ uint32_t pois_s[kMaxPois];
+    __shared__ uint32_t wtot[4], sbase;
+    __shared__ unsigned long long wext[4], wev[4];
+    const uint32_t tid = threadIdx.x;
+    const int j = job_of_block(jobs, blockIdx.x);
+    if (j < 0) return;
+    const StepArgs& a = jobs[j].a;
+    const uint32_t t = a.ctrl->t0 + k;
+    if (t >= jobs[j].t_end) return;
+    const uint32_t blk = blockIdx.x - jobs[j].blk_base;
+    if (tid < a.npois) pois_s[tid] = a.poisc[tid];
+    __syncthreads();
+    const uint32_t q = blk * 256u + tid;
+    uint32_t flags = 0, ext_tot = 0, dis = 0;
+    if (q < a.nq) {
+        int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
+        const int4 in = *rp;
+        *rp = make_int4(0, 0, 0, 0);
+        flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
+    }
+    block_append<4>(a, t, q, flags, ext_tot, wtot, wext, wev, &sbase);
+}
+
+// Batched phase A: the concatenated row segments of all jobs are cut into
+// chunks; a chunk bins the events of its binned jobs into a window of tiles
+// (the chunk's jobs' tiles side by side, at most kMaxTiles), segments of jobs
+// delivered directly this step go out as atomics.  Also closes the previous
+// step's bookkeeping of each job (history count, cleared parity counters).
+__global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __restrict__ jobs, uint32_t k)
+{
+    __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t tcnt[kMaxTiles];
+    __shared__ uint32_t toff[kMaxTiles];
+    __shared__ uint32_t tres[kMaxTiles];
+    __shared__ uint32_t ibase[kMaxJobs + 1];
+    __shared__ uint32_t wbase[kMaxJobs + 1];
+    __shared__ uint32_t jbin[kMaxJobs];
+    __shared__ uint8_t segjob[kChunkItems];   // job of each row segment of the chunk
+    __shared__ uint32_t wsum[kScatterWaves];
+    __shared__ uint32_t wtotal;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    if (wv == 0) {
+        const JobDesc& J = jobs[lane];
+        uint32_t items = 0, bin = 0;
+        if (J.active) {
+            Ctrl* c = J.a.ctrl;
+            const uint32_t t = c->t0 + k;
+            if (t < J.t_end) {
+                items = c->nspk_par[t & 1u] * J.smax;
+                bin = (J.binned && c->step_ev[t & 1u] >= J.a.bin_threshold) ? 1u : 0u;
+                if (blockIdx.x == 0) {
+                    c->hist_n += c->nspk_par[t & 1u];
+                    c->nspk_par[(t + 1u) & 1u] = 0u;
+                    c->step_ev[(t + 1u) & 1u] = 0u;
+                }
+            }
+        }
+        const uint32_t v = wave_incl_scan<uint32_t>(items, lane);
+        ibase[lane + 1u] = v;
+        if (lane == 0) ibase[0] = 0;
+        jbin[lane] = bin;
+    }
+    __syncthreads();
+    const uint32_t total = ibase[kMaxJobs];
+    uint32_t per = (total + gridDim.x - 1u) / gridDim.x;
+    per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
+    auto job_of_item = [&](uint32_t it) {
+        uint32_t lo = 0, hi = kMaxJobs;   // ibase[lo] <= it < ibase[hi]
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (ibase[mid] <= it) lo = mid;
+            else hi = mid;
+        }
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);   // callers pass wave-uniform items
+    };
+    for (uint32_t c0 = blockIdx.x * per; c0 < total; c0 += gridDim.x * per) {
+        const uint32_t c1 = (total - c0) < per ? total : c0 + per;
+        const uint32_t jl = job_of_item(c0), jh = job_of_item(c1 - 1u);
+        if (tid == 0) {
+            uint32_t w = 0;
+            for (uint32_t j = jl; j <= jh; ++j) {
+                wbase[j] = w;
+                if (jbin[j]) w += jobs[j].a.ntiles;
+            }
+            wbase[jh + 1u] = w;
+            wtotal = w;
+        }
+        __syncthreads();
+        const uint32_t W = wtotal;
+        const bool windowed = W <= kMaxTiles;
+        for (uint32_t i = tid; i < (windowed ? W : 0u); i += kScatterThreads) tcnt[i] = 0;
+        // segments delivered directly go out first, so that no binned segment
+        // is held in registers meanwhile: those of jobs not binned this step,
+        // and every segment of a chunk whose tile window is too wide
+        for (uint32_t jj = 0; jj < kSegPerWave; ++jj) {
+            const uint32_t it = c0 + wv + kScatterWaves * jj;
+            const uint32_t j = it < c1 ? job_of_item(it) : 0u;
+            if (lane == 0) segjob[wv + kScatterWaves * jj] = (uint8_t)j;
+            if (it >= c1 || (windowed && jbin[j])) continue;
+            const StepArgs& a = jobs[j].a;
+            const uint32_t smax = jobs[j].smax;
+            const uint32_t local = it - ibase[j];
+            const uint4 info = a.spk[local / smax];
+            const uint32_t t = a.ctrl->t0 + k;
+            if (a.record == 1u) deliver_item<4, true>(a, t, info, local % smax, lane, a.cb);
+            else deliver_item<4, false>(a, t, info, local % smax, lane, a.cb);
+        }
+        if (!windowed) {
+            __syncthreads();
+            continue;
+        }
+        SegLoad S[kSegPerWave];
+#pragma unroll
+        for (uint32_t jj = 0; jj < kSegPerWave; ++jj) {
+            const uint32_t it = c0 + wv + kScatterWaves * jj;
+            S[jj].s0 = 1u;
+            S[jj].len = 0u;
+            const uint32_t j = it < c1 ? job_of_item(it) : 0u;
+            if (it < c1 && jbin[j]) {
+                const StepArgs& a = jobs[j].a;
+                const uint32_t local = it - ibase[j];
+                seg_load<false>(a, a.spk[local / jobs[j].smax], local % jobs[j].smax, lane, S[jj]);
+            }
+        }
+        __syncthreads();
+        // 1. histogram of targets by window tile
+#pragma unroll
+        for (uint32_t jj = 0; jj < kSegPerWave; ++jj) {
+            if (S[jj].s0 >= S[jj].len) continue;
+            const uint32_t wb = wbase[segjob[wv + kScatterWaves * jj]];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (S[jj].s0 + 64u * u + lane < S[jj].len) atomicAdd(&tcnt[wb + (S[jj].tg[u] >> kTileBits)], 1u);
+        }
+        __syncthreads();
+        // 2. scan and reservation in each window tile's bin
+        {
+            const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
+            const uint32_t v0 = t0i < W ? tcnt[t0i] : 0u;
+            const uint32_t v1 = t1i < W ? tcnt[t1i] : 0u;
+            const uint32_t sum = v0 + v1;
+            const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
+            if (lane == 63u) wsum[wv] = inc;
+            __syncthreads();
+            uint32_t off = inc - sum;
+            for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
+            for (uint32_t e = 0; e < 2u; ++e) {
+                const uint32_t w = 2u * tid + e;
+                if (w >= W) break;
+                const uint32_t v = e ? v1 : v0;
+                toff[w] = off;
+                tcnt[w] = off;
+                uint32_t lo = jl, hi = jh + 1u;   // wbase[lo] <= w < wbase[hi]
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (wbase[mid] <= w) lo = mid;
+                    else hi = mid;
+                }
+                tres[w] = v ? atomicAdd(&jobs[lo].a.bin_fill[w - wbase[lo]], v) : 0u;
+                off += v;
+            }
+        }
+        __syncthreads();
+        // 3. encode and stage sorted by window tile
+#pragma unroll
+        for (uint32_t jj = 0; jj < kSegPerWave; ++jj) {
+            if (S[jj].s0 >= S[jj].len) continue;
+            const uint32_t wb = wbase[segjob[wv + kScatterWaves * jj]];
+            const SegLoad& L = S[jj];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint32_t c = L.s0 + 64u * u;
+                if (c >= L.len) break;
+                const uint32_t kk = c + lane;
+                uint32_t bl = popc(__ballot(L.be <= c));
+                uint64_t inm = __ballot(L.be > c && L.be < c + 64u);
+                while (inm) {
+                    const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+                    inm &= inm - 1u;
+                    bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
+                }
+                if (kk < L.len) {
+                    const uint32_t p = atomicAdd(&tcnt[wb + (L.tg[u] >> kTileBits)], 1u);
+                    stage[p] = (L.tg[u] & (kTile - 1u)) | (bl << kTileBits) | (L.wf[u] << 15);
+                }
+            }
+        }
+        __syncthreads();
+        // 4. runs into the bins (one wave per window tile)
+        for (uint32_t w = wv; w < W; w += kScatterWaves) {
+            const uint32_t o0 = toff[w];
+            const uint32_t cnt = tcnt[w] - o0;
+            if (cnt == 0) continue;
+            uint32_t lo = jl, hi = jh + 1u;
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (wbase[mid] <= w) lo = mid;
+                else hi = mid;
+            }
+            lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);   // w is wave-uniform
+            const StepArgs& a = jobs[lo].a;
+            const uint32_t tt = w - wbase[lo];
+            const uint32_t r0 = tres[w];
+            const uint32_t cap = a.bin_cap_tile;
+            const uint32_t t = a.ctrl->t0 + k;
+            uint32_t* dst = a.bins + (size_t)tt * cap;
+            for (uint32_t e = lane; e < cnt; e += 64u) {
+                const uint32_t code = stage[o0 + e];
+                const uint32_t pos = r0 + e;
+                if (pos < cap) {
+                    dst[pos] = code;
+                } else {
+                    const uint32_t tgt = (tt << kTileBits) | (code & (kTile - 1u));
+                    const uint32_t b = (code >> kTileBits) & 31u;
+                    const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                    __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt,
+                                           decode_weight(code >> 15, false, nullptr, a.winh_q), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                    atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, 1ull);
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Batched phase B (+ fused update of the next step): workgroup b owns tile
+// b - tile_base of the job whose tile range contains b.
+template <bool UPD>
+__global__ __launch_bounds__(kTileThreads) void k_btile(const JobDesc* __restrict__ jobs, uint32_t k)
+{
+    extern __shared__ int32_t acc[];
+    const int j = job_of_block(jobs, blockIdx.x);
+    if (j < 0) return;
+    const JobDesc& J = jobs[j];
+    const StepArgs& a = J.a;
+    const uint32_t t = a.ctrl->t0 + k;
+    if (t >= J.t_end) return;
+    const bool binned = J.binned && a.ctrl->step_ev[t & 1u] >= a.bin_threshold;
+    tile_work<false, UPD, true>(a, blockIdx.x - J.blk_base, t, binned, t + 1u < J.t_end, acc);
+}
+
+__global__ void k_batch_advance(const JobDesc* __restrict__ jobs, uint32_t n)
+{
+    const uint32_t j = threadIdx.x;
+    if (j < kMaxJobs && jobs[j].active) {
+        Ctrl* c = jobs[j].a.ctrl;
+        const uint32_t te = jobs[j].t_end;
+        c->t0 = (c->t0 + n < te) ? c->t0 + n : te;
     }
 }
 
@@ -990,8 +1349,9 @@ hipError_t setup_kernels()
 {
     // phase B keeps D rows of 1024 int32 in LDS (up to 124 KB of the 160 KB per CU)
     const int lds = (int)(kMaxD * kTile * sizeof(int32_t));
-    const void* fns[4] = {(const void*)k_tile<true, false>, (const void*)k_tile<false, false>,
-                          (const void*)k_tile<true, true>, (const void*)k_tile<false, true>};
+    const void* fns[6] = {(const void*)k_tile<true, false>, (const void*)k_tile<false, false>,
+                          (const void*)k_tile<true, true>, (const void*)k_tile<false, true>,
+                          (const void*)k_btile<true>, (const void*)k_btile<false>};
     for (const void* f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
         if (e != hipSuccess) return e;
@@ -1010,6 +1370,32 @@ hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStrea
         if (update_next) hipLaunchKernelGGL((k_tile<false, true>), g, b, lds, s, a, k);
         else hipLaunchKernelGGL((k_tile<false, false>), g, b, lds, s, a, k);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_update(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_update, dim3(blocks), dim3(256), 0, s, jobs, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bscatter, dim3(blocks), dim3(kScatterThreads), 0, s, jobs, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tile(const JobDesc* jobs, uint32_t blocks, uint32_t k, bool update_next, hipStream_t s)
+{
+    const size_t lds = (size_t)kBatchMaxD * kTile * sizeof(int32_t);
+    if (update_next) hipLaunchKernelGGL((k_btile<true>), dim3(blocks), dim3(kTileThreads), lds, s, jobs, k);
+    else hipLaunchKernelGGL((k_btile<false>), dim3(blocks), dim3(kTileThreads), lds, s, jobs, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(const JobDesc* jobs, uint32_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, jobs, n);
     return hipGetLastError();
 }
 

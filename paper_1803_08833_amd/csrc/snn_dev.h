@@ -44,6 +44,7 @@ struct Ctrl {
     uint32_t max_len;       // longest projection row
     uint64_t bin_overflow;  // events delivered by the direct fallback (bin full)
     uint64_t step_ev[2];    // recurrent events of the step in flight, by step parity
+    uint32_t nspk_par[2];   // batched stepping: spikes appended this step, by parity
 };
 
 // Everything the step kernels read, passed by value.
@@ -82,6 +83,19 @@ struct StepArgs {
                               //   target & 1023 | bucket << 10 | weight field << 15
 };
 
+// One job of a batch: the job network's step arguments plus its schedule.
+constexpr uint32_t kMaxJobs = 64;
+constexpr uint32_t kBatchMaxD = 20;   // batched binned delivery: delay buckets per job at most
+struct JobDesc {
+    StepArgs a;
+    uint32_t t_end;      // steps to simulate
+    uint32_t active;     // the slot holds a job
+    uint32_t blk_base;   // first batch update block (= first tile) of the job
+    uint32_t smax;       // 256-record segments per spike row
+    uint32_t binned;     // the job may use binned delivery (F32 records, bins, D <= kBatchMaxD)
+    uint32_t pad;
+};
+
 // Arguments of the projection builder.
 struct BuildArgs {
     uint32_t N, M, n_exc, gx, gy, D, d_min, record;
@@ -111,6 +125,10 @@ hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint3
                           hipStream_t s);
 hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s);
 hipError_t setup_kernels();
+hipError_t launch_batch_update(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s);
+hipError_t launch_batch_scatter(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s);
+hipError_t launch_batch_tile(const JobDesc* jobs, uint32_t blocks, uint32_t k, bool update_next, hipStream_t s);
+hipError_t launch_batch_advance(const JobDesc* jobs, uint32_t n, hipStream_t s);
 hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s);
 hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v,
                             hipStream_t s);

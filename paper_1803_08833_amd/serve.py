@@ -1,0 +1,140 @@
+"""Serving of simulation jobs on one GPU: a request loop with continuous
+batching (jobs are admitted into the running batch as slots and HBM free up,
+and their steps overlap with the jobs already running), and the plain
+one-job-at-a-time server it is compared with.  Latency of a job = time from
+its arrival to its spike raster being readable on the host."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import snn
+
+
+def _hist_ok(spikes):
+    return spikes.ndim == 2
+
+
+class Result(dict):
+    pass
+
+
+def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chunk_ms=50,
+                  keep_spikes=False, clock=time.perf_counter):
+    """Continuous batching.  jobs: list of {"net": desc, "steps": duration};
+    arrivals: seconds after start (sorted).  Returns per-job latency and
+    events, wall time, and the rasters when keep_spikes."""
+    n = len(jobs)
+    lat = np.full(n, np.nan)
+    events = np.zeros(n, dtype=np.int64)
+    rasters = [None] * n
+    slot_job = {}
+    nxt = 0
+    queue = []
+    t0 = clock()
+    with snn.Batch(hbm_budget, max_neurons, stream=snn.current_stream_handle()) as b:
+        done_count = 0
+        while done_count < n:
+            now = clock() - t0
+            while nxt < n and arrivals[nxt] <= now:
+                queue.append(nxt)
+                nxt += 1
+            while queue:
+                j = queue[0]
+                slot = b.admit(jobs[j]["net"], jobs[j]["steps"])
+                if slot is None:
+                    break
+                slot_job[slot] = j
+                queue.pop(0)
+            if not slot_job:
+                if nxt < n:
+                    time.sleep(max(0.0, min(arrivals[nxt] - (clock() - t0), 0.01)))
+                continue
+            b.step(chunk_ms)
+            for slot in b.poll():
+                j = slot_job.pop(slot)
+                events[j] = b.job_stats(slot)["rec_events"]
+                sp = b.read_spikes(slot)
+                lat[j] = clock() - t0 - arrivals[j]
+                if keep_spikes:
+                    rasters[j] = sp
+                done_count += 1
+    wall = clock() - t0
+    return Result(latency=lat, events=events, wall=wall, rasters=rasters)
+
+
+def serve_plain(jobs, arrivals, keep_spikes=False, clock=time.perf_counter):
+    """One job at a time, each built and stepped alone with the plain path."""
+    n = len(jobs)
+    lat = np.full(n, np.nan)
+    events = np.zeros(n, dtype=np.int64)
+    rasters = [None] * n
+    t0 = clock()
+    for j in range(n):
+        wait = arrivals[j] - (clock() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        net = jobs[j]["net"]
+        N = net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
+        with snn.Net(net, hist_cap=int(N * jobs[j]["steps"] * 0.15) + 65536,
+                     stream=snn.current_stream_handle()) as g:
+            g.build_synapses()
+            g.step(jobs[j]["steps"])
+            sp = g.read_spikes()
+            events[j] = g.stats()["rec_events"]
+        lat[j] = clock() - t0 - arrivals[j]
+        if keep_spikes:
+            rasters[j] = sp
+    wall = clock() - t0
+    return Result(latency=lat, events=events, wall=wall, rasters=rasters)
+
+
+def poisson_arrivals(n, rate_per_s, seed=4):
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate_per_s, size=n))
+
+
+def summary(res, jobs):
+    lat = res["latency"]
+    sim_s = sum(j["steps"] for j in jobs) * 1e-3
+    return dict(jobs=len(jobs), wall_s=res["wall"], jobs_per_s=len(jobs) / res["wall"],
+                p50_s=float(np.nanpercentile(lat, 50)), p99_s=float(np.nanpercentile(lat, 99)),
+                events_per_s=float(res["events"].sum() / res["wall"]), sim_s_per_wall_s=sim_s / res["wall"])
+
+
+def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4, log=None,
+                 hbm_budget=160 << 30, max_neurons=6 << 20, chunk_ms=50):
+    """The served workload: the seeded stream of simulation jobs (grids
+    2x2..16x16, Gaussian/exponential, 0.5-5 s), Poisson arrivals at `load`
+    times the capacity measured by a saturated closed-loop batched run, served
+    with continuous batching; the plain one-job-at-a-time server is run on the
+    first `plain_jobs` jobs of the same stream with the same arrival process."""
+    from . import workloads as W
+
+    say = log or (lambda *a: None)
+    jobs = W.serving_stream(n_jobs, seed=seed)
+    cap_jobs = jobs[:capacity_jobs]
+    rc = serve_batched(cap_jobs, np.zeros(len(cap_jobs)), hbm_budget, max_neurons, chunk_ms)
+    capacity = len(cap_jobs) / rc["wall"]
+    say(f"# capacity (closed loop, {len(cap_jobs)} jobs): {capacity:.2f} jobs/s")
+    arrivals = poisson_arrivals(n_jobs, load * capacity, seed=seed)
+    rb = serve_batched(jobs, arrivals, hbm_budget, max_neurons, chunk_ms)
+    sb = summary(rb, jobs)
+    say(f"# served batched: {sb}")
+    out = dict(jobs=n_jobs, arrival_rate_jobs_per_s=load * capacity, capacity_jobs_per_s=capacity,
+               p50_s=sb["p50_s"], p99_s=sb["p99_s"], jobs_per_s=sb["jobs_per_s"],
+               events_per_s=sb["events_per_s"], sim_s_per_wall_s=sb["sim_s_per_wall_s"])
+    if plain_jobs:
+        pj = jobs[:plain_jobs]
+        rp = serve_plain(pj, arrivals[:plain_jobs])
+        sp = summary(rp, pj)
+        rb2 = serve_batched(pj, arrivals[:plain_jobs], hbm_budget, max_neurons, chunk_ms)
+        sb2 = summary(rb2, pj)
+        say(f"# first {plain_jobs} jobs: plain {sp} | batched {sb2}")
+        out["same_stream_first_jobs"] = dict(
+            jobs=plain_jobs,
+            plain=dict(p50_s=sp["p50_s"], p99_s=sp["p99_s"], wall_s=sp["wall_s"], events_per_s=sp["events_per_s"]),
+            batched=dict(p50_s=sb2["p50_s"], p99_s=sb2["p99_s"], wall_s=sb2["wall_s"],
+                         events_per_s=sb2["events_per_s"]))
+    return out

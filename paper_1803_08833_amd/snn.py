@@ -28,6 +28,8 @@ EXPORTS = [
     "snn_build_grid", "snn_build_synapses", "snn_step", "snn_step_forced", "snn_read_spikes",
     "snn_read_state", "snn_read_ring", "snn_export_rows", "snn_stats", "snn_time_kernels",
     "snn_set_option", "snn_host_tables", "snn_reset", "snn_destroy", "snn_last_error",
+    "snn_batch_create", "snn_batch_admit", "snn_batch_step", "snn_batch_poll", "snn_batch_read_spikes",
+    "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
 ]
 
 
@@ -103,6 +105,15 @@ def lib():
             "snn_set_option": ([P, C.c_int, C.c_int64], C.c_int),
             "snn_host_tables": ([C.POINTER(GridDesc), C.POINTER(SynDesc), P, P, P, P, P, P], C.c_int),
             "snn_reset": ([P], C.c_int),
+            "snn_batch_create": ([U64, U64, P, C.POINTER(P)], C.c_int),
+            "snn_batch_admit": ([P, C.POINTER(GridDesc), C.POINTER(SynDesc), U32, C.POINTER(C.c_int32)], C.c_int),
+            "snn_batch_step": ([P, U32], C.c_int),
+            "snn_batch_poll": ([P, P, SZ, C.POINTER(SZ)], C.c_int),
+            "snn_batch_read_spikes": ([P, C.c_int32, P, SZ, C.POINTER(SZ)], C.c_int),
+            "snn_batch_job_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
+            "snn_batch_usage": ([P, C.POINTER(U64), C.POINTER(U32)], C.c_int),
+            "snn_batch_destroy": ([P], None),
+            "snn_batch_last_error": ([P], C.c_char_p),
             "snn_destroy": ([P], None),
             "snn_last_error": ([P], C.c_char_p),
         }
@@ -259,3 +270,75 @@ class Net:
     def set_ext_rate(self, hz: float):
         self.set_option(OPT_EXT_RATE_UHZ, int(round(hz * 1e6)))
         self.net["ext_rate_hz"] = hz
+
+
+class Batch:
+    """Many networks ("jobs") stepped together by the batched multi-job
+    kernels (names follow the C ABI: admit, step, poll, read_spikes)."""
+
+    def __init__(self, hbm_budget: int, max_neurons: int, stream=None):
+        h = C.c_void_p()
+        st = lib().snn_batch_create(hbm_budget, max_neurons, stream, C.byref(h))
+        if st != SNN_OK:
+            raise SNNError(st, lib().snn_batch_last_error(None).decode())
+        self.h = h
+        self._descs = {}
+
+    def _check(self, st):
+        if st != SNN_OK:
+            raise SNNError(st, lib().snn_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.snn_batch_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def admit(self, net: dict, dur_ms: int):
+        """Slot of the admitted job, or None when it does not fit now."""
+        g, s = grid_desc(net), syn_desc(net)
+        slot = C.c_int32(-1)
+        st = lib().snn_batch_admit(self.h, C.byref(g), C.byref(s), dur_ms, C.byref(slot))
+        if st == SNN_E_NOMEM:
+            return None
+        self._check(st)
+        self._descs[slot.value] = (g, s)
+        return slot.value
+
+    def step(self, chunk_ms: int):
+        self._check(lib().snn_batch_step(self.h, chunk_ms))
+
+    def poll(self):
+        out = np.zeros(64, dtype=np.int32)
+        n = C.c_size_t(0)
+        self._check(lib().snn_batch_poll(self.h, _p(out), 64, C.byref(n)))
+        return [int(x) for x in out[: n.value]]
+
+    def job_stats(self, slot: int) -> dict:
+        s = Stats()
+        self._check(lib().snn_batch_job_stats(self.h, slot, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def read_spikes(self, slot: int):
+        n = C.c_size_t(0)
+        st = lib().snn_batch_read_spikes(self.h, slot, None, 0, C.byref(n))
+        if st not in (SNN_OK, SNN_E_TRUNC):
+            self._check(st)
+        out = np.zeros((max(n.value, 1), 2), dtype=np.uint32)
+        self._check(lib().snn_batch_read_spikes(self.h, slot, _p(out), n.value, C.byref(n)))
+        self._descs.pop(slot, None)
+        return out[: n.value]
+
+    def usage(self):
+        b = C.c_uint64(0)
+        j = C.c_uint32(0)
+        self._check(lib().snn_batch_usage(self.h, C.byref(b), C.byref(j)))
+        return b.value, j.value

@@ -52,7 +52,9 @@ WORKLOADS = {
     # 4x4 Gaussian, sigma 1 module: small enough for the oracle in seconds.
     "grid4_gauss": dict(net=make(4, 4, GAUSS, 1.0, 1100, 1), steps=1000),
     # 24x24 Gaussian, sigma 1.5 modules, 1100 synapses/neuron (~786 M synapses).
-    "grid24_gauss": dict(net=make(24, 24, GAUSS, 1.5, 1100, 2), steps=10000),
+    # Drive tuned like the exponential grid below: 2.044 Hz gives 3.2 Hz over
+    # the 10 s after the first second (5.3 Hz over the whole 11 s).
+    "grid24_gauss": dict(net=make(24, 24, GAUSS, 1.5, 1100, 2, ext_rate_hz=2.044), steps=10000),
     # 24x24 exponential, lambda 5 modules, 1100 synapses/neuron: the headline.
     # The external rate is tuned so that the mean rate is ~3-5 Hz: at these
     # parameters the network alternates ~55 Hz up-states with silence, and
@@ -74,12 +76,13 @@ def n_neurons(net):
     return net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
 
 
-def serving_stream(n_jobs=512, seed=4):
+def serving_stream(n_jobs=512, seed=4, ext_rate_hz=2.05):
     """Job stream of the batched/served workload: grid sizes uniform over
     {2,4,8,12,16}^2, exactly half Gaussian (sigma ~ U[1,2]) and half
     exponential (lambda ~ U[2,6]) in shuffled order, durations uniform in
-    0.5-5 s of biological time, per-job seeds.  Arrival times are attached by
-    the server from its measured capacity."""
+    0.5-5 s of biological time, per-job seeds, and the external drive of the
+    ~3-5 Hz regime of the 24x24 workloads.  Arrival times are attached by the
+    server from its measured capacity."""
     r = random.Random(seed)
     kinds = [GAUSS] * (n_jobs // 2) + [EXP] * (n_jobs - n_jobs // 2)
     r.shuffle(kinds)
@@ -88,5 +91,5 @@ def serving_stream(n_jobs=512, seed=4):
         g = r.choice([2, 4, 8, 12, 16])
         rng = r.uniform(1.0, 2.0) if kind == GAUSS else r.uniform(2.0, 6.0)
         dur = int(round(r.uniform(500.0, 5000.0)))
-        jobs.append(dict(net=make(g, g, kind, rng, 1100, 1_000_000 + i), steps=dur))
+        jobs.append(dict(net=make(g, g, kind, rng, 1100, 1_000_000 + i, ext_rate_hz=ext_rate_hz), steps=dur))
     return jobs
