@@ -143,15 +143,18 @@ hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
     if (e != hipSuccess) return e;
     e = snn::launch_update(a, k, n->stream);
     if (e != hipSuccess) return e;
-    e = snn::launch_compact(a, k, n->stream);
-    if (e != hipSuccess) return e;
+    if (n->mode != 1) {   // binned delivery compacts inside its scatter kernel
+        e = snn::launch_compact(a, k, n->stream);
+        if (e != hipSuccess) return e;
+    }
     return enqueue_deliver(n, a, k);
 }
 
-// Enqueue steps k0 .. k0+count-1.  With binned delivery the neuron update of
-// step k+1 runs inside step k's tile kernel, so only the first update is a
-// launch of its own; the last tile kernel does not update, leaving the state
-// at the end of the last step.
+// Enqueue steps k0 .. k0+count-1.  With binned delivery the spike compaction
+// runs inside the scatter kernel and the neuron update of step k+1 inside
+// step k's tile kernel, so a step is two launches and only the first update
+// is a launch of its own; the last tile kernel does not update, leaving the
+// state at the end of the last step.
 hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
 {
     if (count == 0) return hipSuccess;
@@ -165,8 +168,7 @@ hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
     hipError_t e = check_items(n);
     if (e == hipSuccess) e = snn::launch_update(n->a, k0, n->stream);
     for (uint32_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
-        e = snn::launch_compact(n->a, k, n->stream);
-        if (e == hipSuccess) e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream);
+        e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream);
         if (e == hipSuccess) e = snn::launch_tile(n->a, k, k + 1 < k0 + count, n->stream);
     }
     return e;
@@ -289,7 +291,7 @@ snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** ou
     ALLOC(a.W, n->N);
     ALLOC(a.ref, n->N);
     ALLOC(a.ring, (size_t)snn::kRing * n->N);
-    ALLOC(a.blk_cnt, a.nblk);
+    ALLOC(a.blk_stat, a.nblk);
     ALLOC(a.blk_list, (size_t)a.nblk * snn::kNeuronsPerBlock);
     ALLOC(a.grp_cnt, 2 * a.ngrp);
     ALLOC(a.spk, n->N);
@@ -450,6 +452,7 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
         else a.bin_threshold = (uint64_t)(0.039 * n->D * (double)n->N);
         n->mode = 1;
     }
+    n->a.grp_atomic = n->mode == 1 ? 0u : 1u;
     n->built = true;
     n->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SNN_OK;
@@ -612,53 +615,85 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     if (st) return st;
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
     if (!out) return fail(n, SNN_E_INVAL, "null output");
+    if (check_items(n) != hipSuccess) return fail(n, SNN_E_INVAL, "spike items exceed 32 bits");
     std::memset(out, 0, sizeof(*out));
-    hipEvent_t ev[5];
-    for (auto& e : ev) HIPCHK(n, hipEventCreate(&e));
-    Ctrl c0{}, c1{};
-    HIPCHK(n, hipStreamSynchronize(n->stream));
-    HIPCHK(n, hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    double tu = 0, tc = 0, td = 0, ts = 0, ta = 0, tb = 0;
-    for (uint32_t k = 0; k < n_ms; ++k) {
-        HIPCHK(n, hipEventRecord(ev[0], n->stream));
-        HIPCHK(n, snn::launch_update(n->a, 0, n->stream));
-        HIPCHK(n, hipEventRecord(ev[1], n->stream));
-        HIPCHK(n, snn::launch_compact(n->a, 0, n->stream));
-        HIPCHK(n, hipEventRecord(ev[2], n->stream));
-        if (n->mode == 1) {
-            HIPCHK(n, snn::launch_scatter(n->a, 0, n->max_len, n->scatter_blocks, n->stream));
-            HIPCHK(n, hipEventRecord(ev[3], n->stream));
-            HIPCHK(n, snn::launch_tile(n->a, 0, false, n->stream));
-        } else {
-            HIPCHK(n, snn::launch_deliver(n->a, 0, n->deliver_waves, n->unroll, n->max_len, n->stream));
-            HIPCHK(n, hipEventRecord(ev[3], n->stream));
-        }
-        HIPCHK(n, hipEventRecord(ev[4], n->stream));
-        HIPCHK(n, snn::launch_advance(n->a.ctrl, 1, n->stream));
-        HIPCHK(n, hipEventSynchronize(ev[4]));
-        float a = 0, b = 0, c = 0, d = 0, f = 0;
-        HIPCHK(n, hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIPCHK(n, hipEventElapsedTime(&b, ev[1], ev[2]));
-        HIPCHK(n, hipEventElapsedTime(&c, ev[2], ev[3]));
-        HIPCHK(n, hipEventElapsedTime(&f, ev[3], ev[4]));
-        HIPCHK(n, hipEventElapsedTime(&d, ev[0], ev[4]));
-        tu += a;
-        tc += b;
-        ta += c;
-        tb += f;
-        td += c + f;
-        ts += d;
+    // The steps are the ones snn_step enqueues (same kernels, same order), each
+    // launch stamped with its own start/stop events; steps go out in batches
+    // and the events of a batch are read once it has finished.
+    constexpr uint32_t kB = 128, kL = 3;   // steps per batch, launches per step
+    std::vector<snn::LaunchEv> ev(kB * kL);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev) {
+        if (e == hipSuccess) e = hipEventCreate(&x.start);
+        if (e == hipSuccess) e = hipEventCreate(&x.stop);
     }
-    HIPCHK(n, hipStreamSynchronize(n->stream));
-    HIPCHK(n, hipMemcpy(&c1, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    const double k = n_ms ? (double)n_ms : 1.0;
-    out->update_ms = tu / k;
-    out->compact_ms = tc / k;
-    out->deliver_ms = td / k;
-    out->scatter_ms = ta / k;
-    out->tile_ms = tb / k;
-    out->step_ms = ts / k;
+    auto destroy = [&]() {
+        for (auto& x : ev) {
+            if (x.start) (void)hipEventDestroy(x.start);
+            if (x.stop) (void)hipEventDestroy(x.stop);
+        }
+    };
+    if (e != hipSuccess) {
+        destroy();
+        return fail_hip(n, e, "hipEventCreate");
+    }
+    Ctrl c0{}, c1{};
+    e = hipStreamSynchronize(n->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    const bool fused = n->mode == 1 && n->a.d_min == 1;
+    // kind of each launch slot: 0 update, 1 compact, 2 direct deliver, 3 scatter, 4 tile
+    double sum[5] = {0, 0, 0, 0, 0};
+    uint32_t cnt[5] = {0, 0, 0, 0, 0};
+    std::vector<int> kind(kB * kL, -1);
+    for (uint32_t b0 = 0; b0 < n_ms && e == hipSuccess; b0 += kB) {
+        const uint32_t nb = (n_ms - b0) < kB ? (n_ms - b0) : kB;
+        std::fill(kind.begin(), kind.end(), -1);
+        for (uint32_t i = 0; i < nb && e == hipSuccess; ++i) {
+            const uint32_t k = b0 + i;
+            snn::LaunchEv* x = &ev[i * kL];
+            if (!fused || k == 0) {
+                e = snn::launch_update(n->a, k, n->stream, &x[0]);
+                kind[i * kL] = 0;
+            }
+            if (e != hipSuccess) break;
+            if (n->mode == 1) {
+                e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream, &x[1]);
+                kind[i * kL + 1] = 3;
+                if (e == hipSuccess) e = snn::launch_tile(n->a, k, fused && k + 1 < n_ms, n->stream, &x[2]);
+                kind[i * kL + 2] = 4;
+            } else {
+                e = snn::launch_compact(n->a, k, n->stream, &x[1]);
+                kind[i * kL + 1] = 1;
+                if (e == hipSuccess)
+                    e = snn::launch_deliver(n->a, k, n->deliver_waves, n->unroll, n->max_len, n->stream, &x[2]);
+                kind[i * kL + 2] = 2;
+            }
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+        for (uint32_t j = 0; j < nb * kL && e == hipSuccess; ++j) {
+            if (kind[j] < 0) continue;
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, ev[j].start, ev[j].stop);
+            sum[kind[j]] += ms;
+            cnt[kind[j]] += 1;
+        }
+    }
+    if (e == hipSuccess) e = snn::launch_advance(n->a.ctrl, n_ms, n->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c1, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    destroy();
+    if (e != hipSuccess) {
+        n->poisoned = true;
+        return fail_hip(n, e, "kernel timing");
+    }
+    auto avg = [&](int i) { return cnt[i] ? sum[i] / cnt[i] : 0.0; };
+    const double steps = n_ms ? (double)n_ms : 1.0;
+    out->update_ms = avg(0);
+    out->compact_ms = avg(1);
+    out->scatter_ms = avg(3);
+    out->tile_ms = avg(4);
+    out->deliver_ms = n->mode == 1 ? avg(3) + avg(4) : avg(2);
+    out->step_ms = (sum[0] + sum[1] + sum[2] + sum[3] + sum[4]) / steps;
     out->steps = n_ms;
     out->rec_events = c1.rec_events - c0.rec_events;
     out->spikes = c1.spikes - c0.spikes;
@@ -706,6 +741,11 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         }
         if (value == 1 && !n->binned_ok) return fail(n, SNN_E_INVAL, "this network cannot use binned delivery");
         n->mode = (uint32_t)value;
+        // direct delivery's compaction reads the group counts, which the
+        // update maintains only while direct delivery is selected
+        n->a.grp_atomic = n->mode == 1 ? 0u : 1u;
+        HIPCHK(n, hipStreamSynchronize(n->stream));
+        HIPCHK(n, hipMemset(n->a.grp_cnt, 0, sizeof(uint32_t) * 2 * n->a.ngrp));
         break;
     case SNN_OPT_BIN_FRAC_PPM:
         if (n->built) return fail(n, SNN_E_STATE, "bin capacity is fixed once synapses are built");

@@ -15,6 +15,8 @@
 // atomics (update, delivery) or by 32-bit integer multiplies (Philox), so no MFMA.
 #include "snn_dev.h"
 
+#include <hip/hip_ext.h>
+
 namespace snn {
 
 // ---------------------------------------------------------------------------
@@ -370,13 +372,17 @@ __device__ __forceinline__ uint32_t update_quad(const StepArgs& a, const uint32_
 
 // Ordered block-local compaction of the spikers of update block `blk` (1024
 // neurons; thread i < 256 holds the flags of quad 4*blk*256 + i): each spiker
-// is written as {gid, row length, row start} in ascending id, the block count
-// goes to blk_cnt and to its group counter of parity t & 1, and the block's
-// external-event and lock-step-disagreement counts are accumulated.
+// is written as {gid, row length, row start} in ascending id; the block's
+// spike count, recurrent events (the spikers' row lengths) and external
+// events are stored per block (the step's consumer totals them: no atomic on
+// a shared counter here); the spike count also goes to the group counter of
+// parity t & 1 while direct delivery is selected; lock-step disagreements are
+// accumulated.
 template <uint32_t NW>
 __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, uint32_t t, uint32_t q,
                                               uint32_t flags, uint32_t ext_tot, uint32_t dis,
-                                              uint32_t* wtot, unsigned long long* wext, uint32_t* wdis)
+                                              uint32_t* wtot, unsigned long long* wext, uint32_t* wdis,
+                                              unsigned long long* wev)
 {
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
@@ -396,6 +402,7 @@ __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, u
         if (i < wv) woff += wtot[i];
         btot += wtot[i];
     }
+    unsigned long long ev = 0;
     if (flags) {
         uint4* dst = a.blk_list + (size_t)blk * kNeuronsPerBlock + woff + pre;
         for (uint32_t s = 0; s < 4u; ++s) {
@@ -404,19 +411,24 @@ __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, u
                 const uint64_t rb = a.row_ptr[gid];
                 const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
                 *dst++ = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+                ev += len;
             }
         }
     }
+    ev = wave_sum<unsigned long long>(ev);
+    if (lane == 0) wev[wv] = ev;
+    __syncthreads();
     if (tid == 0) {
-        a.blk_cnt[blk] = btot;
-        if (btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blk / kGroup], btot);
-        unsigned long long be = 0;
+        unsigned long long be = 0, bv = 0;
         uint32_t bd = 0;
         for (uint32_t i = 0; i < NW; ++i) {
             be += wext[i];
             bd += wdis[i];
+            bv += wev[i];
         }
-        if (be) atomicAdd((unsigned long long*)&a.ctrl->ext_events, be);
+        // events: <= 1024 rows of < 2^16 records; external: <= 1024 x kMaxPois
+        a.blk_stat[blk] = make_uint4(btot, (uint32_t)bv, (uint32_t)be, 0u);
+        if (a.grp_atomic && btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blk / kGroup], btot);
         if (bd) atomicAdd((unsigned long long*)&a.ctrl->disagree, (unsigned long long)bd);
     }
 }
@@ -426,6 +438,7 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
     __shared__ uint32_t wtot[4];
     __shared__ unsigned long long wext[4];
     __shared__ uint32_t wdis[4];
+    __shared__ unsigned long long wev[4];
     __shared__ uint32_t pois_s[kMaxPois];
     const uint32_t tid = threadIdx.x;
     if (tid < a.npois) pois_s[tid] = a.poisc[tid];
@@ -439,17 +452,18 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
         *rp = make_int4(0, 0, 0, 0);
         flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
     }
-    block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, wtot, wext, wdis);
+    block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, wtot, wext, wdis, wev);
 }
 
 // ---------------------------------------------------------------------------
-// Ordered global compaction: block g owns update blocks [kGroup g, kGroup g +
-// kGroup); its base offset is the sum of the group counts before it (this
-// step's parity buffer).  Each thread places one spike (binary search over the
-// group's block offsets), copying its {gid, row length, row start} record to
-// the step's spike list and writing the AER history entry.  Also counts the
-// step's recurrent events and clears this group's entry of the other parity
-// buffer for the next step.
+// Ordered global compaction for direct delivery: block g owns update blocks
+// [kGroup g, kGroup g + kGroup); its base offset is the sum of the group
+// counts before it (this step's parity buffer).  Each thread places one spike
+// (binary search over the group's block offsets), copying its {gid, row
+// length, row start} record to the step's spike list and writing the AER
+// history entry.  Also clears this group's entry of the other parity buffer
+// for the next step and adds its blocks' event counts to the totals.  Binned
+// delivery does this compaction inside its scatter kernel instead.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kCompactThreads = 1024;
 
@@ -458,7 +472,6 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
     constexpr uint32_t NW = kCompactThreads / 64;
     __shared__ uint32_t red[NW];
     __shared__ uint32_t boff[kGroup + 1];
-    __shared__ unsigned long long wev[NW];
     const uint32_t g = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint32_t t = a.ctrl->t0 + k, par = t & 1u;
     const uint32_t* gc = a.grp_cnt + par * a.ngrp;
@@ -469,7 +482,7 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
     const uint32_t b0 = g * kGroup;
     const uint32_t nb = (a.nblk - b0) < kGroup ? (a.nblk - b0) : kGroup;
     if (wv == 0) {
-        const uint32_t c = lane < nb ? a.blk_cnt[b0 + lane] : 0u;
+        const uint32_t c = lane < nb ? a.blk_stat[b0 + lane].x : 0u;
         const uint32_t v = wave_incl_scan<uint32_t>(c, lane);
         if (lane < kGroup) boff[lane + 1u] = v;
         if (lane == 0) boff[0] = 0;
@@ -479,7 +492,6 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
     for (uint32_t i = 0; i < NW; ++i) base += red[i];
     const uint32_t gtot = boff[nb];
     const uint64_t h0 = a.ctrl->hist_n;
-    unsigned long long ev = 0;
     for (uint32_t i = tid; i < gtot; i += kCompactThreads) {
         uint32_t lo = 0, hi = nb;   // boff[lo] <= i < boff[hi]
         while (hi - lo > 1u) {
@@ -492,20 +504,17 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
         a.spk[p] = rec;
         const uint64_t hp = h0 + p;
         if (hp < a.hist_cap) a.hist[hp] = make_uint2(t, rec.x);
-        ev += rec.y;
     }
-    ev = wave_sum<unsigned long long>(ev);
-    if (lane == 0) wev[wv] = ev;
-    __syncthreads();
     if (tid == 0) {
         a.grp_cnt[(par ^ 1u) * a.ngrp + g] = 0u;
-        unsigned long long be = 0;
-        for (uint32_t i = 0; i < NW; ++i) be += wev[i];
-        if (be) {
-            atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
-            atomicAdd((unsigned long long*)&a.ctrl->step_ev[par], be);
+        unsigned long long be = 0, bx = 0;
+        for (uint32_t i = 0; i < nb; ++i) {
+            const uint4 st = a.blk_stat[b0 + i];
+            be += st.y;
+            bx += st.z;
         }
-        if (g == 0) a.ctrl->step_ev[par ^ 1u] = 0;
+        if (be) atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+        if (bx) atomicAdd((unsigned long long*)&a.ctrl->ext_events, bx);
         if (g == a.ngrp - 1u) {
             a.ctrl->nspk = base + gtot;
             a.ctrl->spikes += base + gtot;
@@ -609,8 +618,9 @@ __global__ __launch_bounds__(256) void k_deliver(StepArgs a, uint32_t k, uint32_
 
 // Binned delivery pays a fixed price per step (every tile's D ring rows are
 // read and written), so steps with few events are delivered directly instead.
-// The compaction kernel totals the step's events; every delivery kernel of the
-// step takes the same decision from that total.
+// The scatter kernel totals the step's events from the update blocks' counts
+// and takes the decision; it leaves the total in the control block for the
+// step's tile kernel.
 __device__ __forceinline__ bool step_binned(const StepArgs& a, uint32_t t)
 {
     return a.ctrl->step_ev[t & 1u] >= a.bin_threshold;
@@ -704,6 +714,46 @@ constexpr uint32_t kScatterThreads = 1024;
 constexpr uint32_t kScatterWaves = kScatterThreads / 64;
 constexpr uint32_t kSegPerWave = kChunkItems / kScatterWaves;   // 7 row segments per wave
 
+// Spike s of the step's ascending-id list: its update block is found in the
+// exclusive block offsets boff[0 .. nb] (s is wave-uniform).
+__device__ __forceinline__ uint4 spike_rec(const StepArgs& a, const uint32_t* boff, uint32_t nb, uint32_t s)
+{
+    uint32_t lo = 0, hi = nb;   // boff[lo] <= s < boff[hi]
+    while (hi - lo > 1u) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (boff[mid] <= s) lo = mid;
+        else hi = mid;
+    }
+    lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+    const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s - boff[lo]));
+    return a.blk_list[(size_t)lo * kNeuronsPerBlock + i];
+}
+
+// AER history of step t, written once the step's delivery is under way: the
+// workgroups share the spikes in ascending order.
+__device__ __forceinline__ void write_history(const StepArgs& a, const uint32_t* boff, uint32_t nb, uint32_t n,
+                                              uint32_t t)
+{
+    const uint64_t h0 = a.ctrl->hist_n;
+    for (uint32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n; s += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = nb;   // boff[lo] <= s < boff[hi]
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (boff[mid] <= s) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t gid = a.blk_list[(size_t)lo * kNeuronsPerBlock + (s - boff[lo])].x;
+        if (h0 + s < a.hist_cap) a.hist[h0 + s] = make_uint2(t, gid);
+    }
+}
+
+// Step t's delivery through the tile bins, or directly when the step is below
+// the switch threshold.  The ordered compaction of the step's spikes (the
+// update blocks' ascending lists placed by an exclusive scan of their counts)
+// happens here: every workgroup scans the block counts in LDS and addresses
+// spike records in the per-block lists; the workgroups write the AER history
+// in ascending order; workgroup 0 publishes the spike count and clears the
+// other parity's counters.
 template <bool CODE8>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
 {
@@ -711,17 +761,64 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     __shared__ uint32_t tcnt[kMaxTiles];   // counts, then fill cursor
     __shared__ uint32_t toff[kMaxTiles];   // start of each tile's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the tile's bin
+    __shared__ uint32_t boff[kMaxTiles + 1];
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
+    __shared__ unsigned long long red[2 * kScatterWaves + 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     if (CODE8 && tid < 256u) cb_s[tid] = a.cb[tid];
     const uint32_t t = a.ctrl->t0 + k;
-    const uint32_t n = a.ctrl->nspk;
-    if (blockIdx.x == 0 && tid == 0) a.ctrl->hist_n += n;
-    if (!step_binned(a, t)) {
-        if (CODE8) __syncthreads();
-        deliver_direct<4, CODE8>(a, t, n, smax, blockIdx.x * kScatterWaves + wv, gridDim.x * kScatterWaves,
-                                 lane, cb_s);
+    const uint32_t nb = a.nblk;          // <= kMaxTiles on this path
+    // exclusive scan of the update blocks' spike counts (two blocks per
+    // thread) and the step's recurrent and external event totals: the event
+    // total decides binned vs direct; workgroup 0 books the totals
+    {
+        const uint32_t i0 = 2u * tid, i1 = 2u * tid + 1u;
+        const uint4 s0 = i0 < nb ? a.blk_stat[i0] : make_uint4(0, 0, 0, 0);
+        const uint4 s1 = i1 < nb ? a.blk_stat[i1] : make_uint4(0, 0, 0, 0);
+        const uint32_t sum = s0.x + s1.x;
+        const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
+        const unsigned long long e = wave_sum<unsigned long long>((unsigned long long)s0.y + s1.y);
+        const unsigned long long x = wave_sum<unsigned long long>((unsigned long long)s0.z + s1.z);
+        if (lane == 63u) wsum[wv] = inc;
+        if (lane == 0) {
+            red[wv] = e;
+            red[kScatterWaves + wv] = x;
+        }
+        __syncthreads();
+        uint32_t off = inc - sum;
+        for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
+        if (i0 <= nb) boff[i0] = off;
+        if (i1 <= nb) boff[i1] = off + s0.x;
+        if (i1 + 1u == nb) boff[nb] = off + sum;
+        if (tid == 0) {
+            unsigned long long et = 0, xt = 0;
+            for (uint32_t i = 0; i < kScatterWaves; ++i) {
+                et += red[i];
+                xt += red[kScatterWaves + i];
+            }
+            red[2 * kScatterWaves] = et;
+            if (blockIdx.x == 0) {
+                a.ctrl->rec_events += et;
+                a.ctrl->ext_events += xt;
+                a.ctrl->step_ev[t & 1u] = et;   // the tile kernel's copy of the switch decision
+            }
+        }
+        __syncthreads();
+    }
+    const bool binned =
+        __builtin_amdgcn_readfirstlane(red[2 * kScatterWaves] >= a.bin_threshold ? 1 : 0) != 0;   // uniform
+    const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)boff[nb]);                    // uniform
+    if (blockIdx.x == 0 && tid == 0) {
+        a.ctrl->nspk = n;
+        a.ctrl->spikes += n;
+    }
+    if (!binned) {
+        const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
+        const uint32_t nw = gridDim.x * kScatterWaves;
+        for (uint32_t it = blockIdx.x * kScatterWaves + wv; it < items; it += nw)
+            deliver_item<4, CODE8>(a, t, spike_rec(a, boff, nb, it / smax), it % smax, lane, cb_s);
+        write_history(a, boff, nb, n, t);
         return;
     }
     const uint32_t items = n * smax;
@@ -739,7 +836,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
-            info[j] = it < c1 ? a.spk[it / smax] : make_uint4(0, 0, 0, 0);
+            info[j] = it < c1 ? spike_rec(a, boff, nb, it / smax) : make_uint4(0, 0, 0, 0);
         }
         SegLoad S[kSegPerWave];
 #pragma unroll
@@ -806,6 +903,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     }
     spill = wave_sum<unsigned long long>(spill);
     if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
+    write_history(a, boff, nb, n, t);
 }
 
 // ---------------------------------------------------------------------------
@@ -969,7 +1067,8 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
                              reinterpret_cast<unsigned long long*>(scratch + 128), scratch + 160);
         else
             block_compact<NW>(a, tt, t + 1u, q, flags, ext_tot, dis, scratch + 64,
-                              reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80);
+                              reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80,
+                              reinterpret_cast<unsigned long long*>(scratch + 128));
     }
 }
 
@@ -978,6 +1077,7 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
 {
     extern __shared__ int32_t acc[];      // [D][1024]
     const uint32_t t = a.ctrl->t0 + k;
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->hist_n += a.ctrl->nspk;   // step t's history is complete
     tile_work<CODE8, UPD, false>(a, blockIdx.x, t, step_binned(a, t), true, acc);
 }
 
@@ -1303,28 +1403,36 @@ hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t*
     return hipGetLastError();
 }
 
-hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s)
+// Launch on stream s; with timing events, the launch packet itself stamps the
+// kernel's start and end into them.
+#define SNN_LAUNCH(ev, kern, grid, block, shm, s, ...)                                                    \
+    do {                                                                                                 \
+        if (ev) hipExtLaunchKernelGGL(kern, grid, block, shm, s, (ev)->start, (ev)->stop, 0, __VA_ARGS__); \
+        else hipLaunchKernelGGL(kern, grid, block, shm, s, __VA_ARGS__);                                  \
+    } while (0)
+
+hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s, const LaunchEv* ev)
 {
-    hipLaunchKernelGGL(k_update, dim3(a.nblk), dim3(256), 0, s, a, k);
+    SNN_LAUNCH(ev, k_update, dim3(a.nblk), dim3(256), 0, s, a, k);
     return hipGetLastError();
 }
 
-hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s)
+hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s, const LaunchEv* ev)
 {
-    hipLaunchKernelGGL(k_compact, dim3(a.ngrp), dim3(kCompactThreads), 0, s, a, k);
+    SNN_LAUNCH(ev, k_compact, dim3(a.ngrp), dim3(kCompactThreads), 0, s, a, k);
     return hipGetLastError();
 }
 
 hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_t unroll,
-                          uint32_t max_len, hipStream_t s)
+                          uint32_t max_len, hipStream_t s, const LaunchEv* ev)
 {
     const uint32_t blocks = cdiv(waves < 4u ? 4u : waves, 4);
     const uint32_t seg = 64u * unroll;
     const uint32_t smax = max_len ? cdiv(max_len, seg) : 1u;
     const bool c8 = a.record == 1u;
 #define SNN_DELIVER(U)                                                                          \
-    if (c8) hipLaunchKernelGGL((k_deliver<U, true>), dim3(blocks), dim3(256), 0, s, a, k, smax); \
-    else hipLaunchKernelGGL((k_deliver<U, false>), dim3(blocks), dim3(256), 0, s, a, k, smax)
+    if (c8) SNN_LAUNCH(ev, (k_deliver<U, true>), dim3(blocks), dim3(256), 0, s, a, k, smax); \
+    else SNN_LAUNCH(ev, (k_deliver<U, false>), dim3(blocks), dim3(256), 0, s, a, k, smax)
     if (unroll == 1u) {
         SNN_DELIVER(1);
     } else if (unroll == 2u) {
@@ -1337,11 +1445,11 @@ hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_
 }
 
 hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
-                          hipStream_t s)
+                          hipStream_t s, const LaunchEv* ev)
 {
     const uint32_t smax = max_len ? cdiv(max_len, 256) : 1u;
-    if (a.record == 1u) hipLaunchKernelGGL((k_scatter<true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
-    else hipLaunchKernelGGL((k_scatter<false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    if (a.record == 1u) SNN_LAUNCH(ev, (k_scatter<true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    else SNN_LAUNCH(ev, (k_scatter<false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
     return hipGetLastError();
 }
 
@@ -1359,16 +1467,16 @@ hipError_t setup_kernels()
     return hipSuccess;
 }
 
-hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s)
+hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s, const LaunchEv* ev)
 {
     const size_t lds = (size_t)a.D * kTile * sizeof(int32_t);
     const dim3 g(a.ntiles), b(kTileThreads);
     if (a.record == 1u) {
-        if (update_next) hipLaunchKernelGGL((k_tile<true, true>), g, b, lds, s, a, k);
-        else hipLaunchKernelGGL((k_tile<true, false>), g, b, lds, s, a, k);
+        if (update_next) SNN_LAUNCH(ev, (k_tile<true, true>), g, b, lds, s, a, k);
+        else SNN_LAUNCH(ev, (k_tile<true, false>), g, b, lds, s, a, k);
     } else {
-        if (update_next) hipLaunchKernelGGL((k_tile<false, true>), g, b, lds, s, a, k);
-        else hipLaunchKernelGGL((k_tile<false, false>), g, b, lds, s, a, k);
+        if (update_next) SNN_LAUNCH(ev, (k_tile<false, true>), g, b, lds, s, a, k);
+        else SNN_LAUNCH(ev, (k_tile<false, false>), g, b, lds, s, a, k);
     }
     return hipGetLastError();
 }

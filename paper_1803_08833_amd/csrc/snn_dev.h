@@ -61,9 +61,11 @@ struct StepArgs {
     float* W;
     uint8_t* ref;
     int32_t* ring;          // [kRing][N]
-    uint32_t* blk_cnt;      // [nblk]
+    uint4* blk_stat;        // [nblk] per update block, step in flight: {spikers, their recurrent
+                            //   events (sum of row lengths), external Poisson events, 0}
     uint4* blk_list;        // [nblk * kNeuronsPerBlock] spikers {gid, row length, row start}
-    uint32_t* grp_cnt;      // [2][ngrp]
+    uint32_t* grp_cnt;      // [2][ngrp] spikers per group of kGroup blocks (direct delivery)
+    uint32_t grp_atomic;    // the update maintains grp_cnt (direct delivery selected)
     uint4* spk;             // [N] spikes of the step in flight: {gid, row length, row start lo, hi}
     uint2* hist;            // [hist_cap] (t, gid)
     Ctrl* ctrl;
@@ -117,13 +119,21 @@ hipError_t launch_syn_count(const BuildArgs& a, hipStream_t s);
 hipError_t launch_syn_fill(const BuildArgs& a, hipStream_t s);
 hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
                             uint32_t N, hipStream_t s);
-hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s);
-hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s);
+// Optional per-launch timing: the launch records the kernel's start and end
+// in these events (both created with timing enabled).
+struct LaunchEv {
+    hipEvent_t start, stop;
+};
+hipError_t launch_update(const StepArgs& a, uint32_t k, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_compact(const StepArgs& a, uint32_t k, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_t unroll,
-                          uint32_t max_len, hipStream_t s);
+                          uint32_t max_len, hipStream_t s,
+                          const LaunchEv* ev = nullptr);
 hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
-                          hipStream_t s);
-hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s);
+                          hipStream_t s,
+                          const LaunchEv* ev = nullptr);
+hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s,
+                       const LaunchEv* ev = nullptr);
 hipError_t setup_kernels();
 hipError_t launch_batch_update(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s);
 hipError_t launch_batch_scatter(const JobDesc* jobs, uint32_t blocks, uint32_t k, hipStream_t s);
