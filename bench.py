@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--serve-jobs", type=int, default=128, help="served-stream jobs (0: skip serving)")
     p.add_argument("--serve-plain", type=int, default=32, help="first jobs also served one at a time")
     p.add_argument("--serve-capacity", type=int, default=32, help="jobs of the closed-loop capacity run")
+    p.add_argument("--graph-chunk", type=int, default=250,
+                   help="steps per captured HIP graph (0: launch every kernel directly)")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="end with one plain device copy of this size (reference kernel for HBM counters)")
     return p.parse_args()
@@ -165,7 +167,7 @@ def main():
     build_s = time.perf_counter() - tb
     if args.deliver_mode is not None:
         g.set_option(snn.OPT_DELIVER_MODE, args.deliver_mode)
-    g.set_option(snn.OPT_GRAPH_CHUNK, 250)   # a bench step (1000 ms) is four captured graphs
+    g.set_option(snn.OPT_GRAPH_CHUNK, args.graph_chunk)   # default: a bench step (1000 ms) is four graphs
     st0 = g.stats()
     print(f"# built {args.workload}: {N} neurons, {st0['nnz']} synapses in {build_s:.2f} s", file=sys.stderr,
           flush=True)

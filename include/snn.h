@@ -226,42 +226,58 @@ void snn_destroy(snn_net* net);
  * launch per phase for all jobs together (multi-job kernels over a device job
  * table, replayed as HIP graphs), so many small networks share the GPU.  Each
  * job is an ordinary network (same definitions, same results as stepping it
- * alone) built on the batch's construction stream, so building a new job
- * overlaps with the steps already enqueued for the others.  Jobs stop at
- * their own duration.  Batched jobs use direct delivery. */
+ * alone).  Jobs are built by the batch's construction thread on its own
+ * stream, so construction overlaps with the steps of the jobs already
+ * running; a job joins the table at the first snn_batch_step after its build
+ * has finished and stops at its own duration.  Jobs with F32 records,
+ * d_min = 1 and at most 20 delay buckets use the binned delivery (per step,
+ * above the same event threshold as a single network); the others direct
+ * delivery.  The calls are meant for one controlling thread; the batch's own
+ * construction thread is synchronised internally. */
 typedef struct snn_batch snn_batch;
 
 /* hbm_budget: device bytes the batch may hold for its jobs (admission
  * control); max_neurons: total neurons of jobs admitted at once (sizes the
- * update grid); hip_stream: stepping stream (NULL = own stream). */
+ * update grid); hip_stream: stepping stream (NULL = own stream).  Starts the
+ * construction thread. */
 snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip_stream, snn_batch** out);
 
 /* Admit a job of dur_ms steps: checks the footprint estimate (including a
  * spike history with room for a 150 Hz mean rate) against the free budget,
- * builds the network (blocks the calling thread while the build
- * runs on the construction stream) and adds it to the job table.  *slot
- * receives the job's slot.  SNN_E_NOMEM: not now (budget, neurons or all 64
- * slots in use); SNN_E_INVAL: bad description. */
+ * reserves a slot, the estimated bytes and the job's update blocks, and queues
+ * the build; returns at once with the job's slot in *slot.  SNN_E_NOMEM: not
+ * now (budget, neurons or all 64 slots in use); SNN_E_INVAL: bad description.
+ * A build that fails later is reported by snn_batch_poll as a finished slot
+ * whose snn_batch_read_spikes returns the build's error and frees the slot. */
 snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_desc* s, uint32_t dur_ms,
                            int32_t* slot);
 
-/* Enqueue chunk_ms steps for every admitted, unfinished job. */
+/* Enqueue chunk_ms steps for every running, unfinished job (jobs whose build
+ * has finished join first).  With no running job but builds in progress it
+ * waits for a build to finish; with nothing to run it returns at once. */
 snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms);
 
-/* Finished jobs whose spikes have not been read yet (synchronises). */
+/* Finished jobs (and failed builds) whose spikes have not been read yet
+ * (synchronises the stepping stream). */
 snn_status snn_batch_poll(snn_batch* b, int32_t* done_slots, size_t cap, size_t* n_out);
 
 /* Copy a finished job's whole spike history, ordered by (t_ms, gid), then
- * free its slot and memory.  SNN_E_STATE if the job has not finished;
- * SNN_E_TRUNC (slot kept) if cap is too small, *n_out = count needed. */
+ * free its slot; its device memory is released by the construction thread
+ * once the stepping stream has passed the job's removal from the table.
+ * SNN_E_STATE if the job has not finished; SNN_E_TRUNC (slot kept) if cap is
+ * too small, *n_out = count needed. */
 snn_status snn_batch_read_spikes(snn_batch* b, int32_t slot, snn_spike* host_buf, size_t cap, size_t* n_out);
 
-/* Counters of one job (synchronises). */
+/* Counters of one running or finished job (synchronises the stepping
+ * stream). */
 snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out);
 
-/* Device bytes the batch's jobs hold now; number of admitted jobs. */
+/* Device bytes held or reserved by the batch's jobs; number of admitted jobs
+ * (building, running or finished and unread). */
 snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs);
 
+/* Stops the construction thread (pending builds are dropped), waits for the
+ * stepping stream and frees every job. */
 void snn_batch_destroy(snn_batch* b);
 const char* snn_batch_last_error(const snn_batch* b);
 

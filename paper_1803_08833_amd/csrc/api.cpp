@@ -8,8 +8,12 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "snn.h"
@@ -584,6 +588,10 @@ snn_status snn_export_rows(snn_net* n, uint32_t pre0, uint32_t cnt, uint64_t* ro
     return SNN_OK;
 }
 
+}  // extern "C"
+void fill_stats(const snn_net* n, const Ctrl& hc, snn_stats_t* out);
+extern "C" {
+
 snn_status snn_stats(snn_net* n, snn_stats_t* out)
 {
     snn_status st = check_usable(n);
@@ -592,6 +600,14 @@ snn_status snn_stats(snn_net* n, snn_stats_t* out)
     HIPCHK(n, hipStreamSynchronize(n->stream));
     Ctrl hc{};
     HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    fill_stats(n, hc, out);
+    return SNN_OK;
+}
+
+}  // extern "C"
+
+void fill_stats(const snn_net* n, const Ctrl& hc, snn_stats_t* out)
+{
     out->t = hc.t0;
     out->spikes = hc.spikes;
     out->rec_events = hc.rec_events;
@@ -606,8 +622,9 @@ snn_status snn_stats(snn_net* n, snn_stats_t* out)
     out->bin_threshold = n->a.bin_threshold;
     out->binned_ok = n->binned_ok ? 1u : 0u;
     out->build_ms = n->build_ms;
-    return SNN_OK;
 }
+
+extern "C" {
 
 snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
 {
@@ -832,16 +849,20 @@ struct snn_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t build_stream = nullptr;
-    uint64_t budget = 0, used = 0;
-    uint32_t blk_cap = 0, blk_used = 0;
-    uint32_t scatter_blocks = 512;
+    uint64_t budget = 0, used = 0;        // used: held or reserved by admitted jobs
+    uint32_t blk_cap = 0, blk_used = 0;   // blk_used: blocks of the jobs in the device table
+    uint32_t blk_reserved = 0;            // blocks of every admitted job (building included)
+    uint32_t scatter_blocks = 256;        // one 1024-thread workgroup per CU (its LDS use allows no more)
+    enum State { kFree, kBuilding, kActive, kFailed };
     struct Job {
         snn_net* net = nullptr;
         uint64_t bytes = 0;
         uint32_t dur = 0, nblk = 0;
         uint32_t t = 0;               // steps enqueued for the job (host-side schedule)
-        bool active = false;
+        State state = kFree;
         bool binned = false;          // built with delivery bins for the batched kernels
+        snn_status fail_st = SNN_OK;  // kFailed: why
+        std::string fail_msg;
     };
     Job jobs[snn::kMaxJobs];
     snn::JobDesc* d_jobs = nullptr;
@@ -849,9 +870,29 @@ struct snn_batch {
     snn::JobDesc* h_jobs[kTables] = {};
     hipEvent_t h_done[kTables] = {};
     int h_next = 0;
-    std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // captured chunks by (steps, grid blocks of the update and tile kernels)
+    std::map<std::pair<uint32_t, uint32_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     std::string err;
     bool poisoned = false;
+    // Construction worker: builds admitted jobs on build_stream while the
+    // caller keeps stepping, and frees retired jobs once the stepping stream
+    // has passed the table update that removed them.
+    struct BuildReq {
+        int slot;
+        snn_grid_desc g;
+        snn_syn_desc s;
+    };
+    struct Retired {
+        snn_net* net;
+        hipEvent_t after;
+    };
+    std::mutex mu;
+    std::condition_variable cv;        // worker: work to do; caller: a build finished
+    std::deque<BuildReq> todo;
+    std::vector<std::pair<int, snn_net*>> built;   // finished builds, activated at the next step
+    std::deque<Retired> retired;
+    bool stop = false;
+    std::thread worker;
 };
 
 namespace {
@@ -889,7 +930,7 @@ uint64_t estimate_bytes(const snn_grid_desc& g, const snn_syn_desc& s, uint64_t 
     const uint64_t nblk = (N + 1023) / 1024;
     const double k = s.k_in + 6.0 * std::sqrt(s.k_in + 1.0);
     const uint64_t rec = s.record == SNN_REC_CODE8 ? 4 : 8;
-    uint64_t b = N * (4 + 4 + 1) + 32 * N * 4 + nblk * 4 + nblk * 1024 * 16 + N * 16 + hist_cap * 8 + N * 5;
+    uint64_t b = N * (4 + 4 + 1) + 32 * N * 4 + nblk * 16 + nblk * 1024 * 16 + N * 16 + hist_cap * 8 + N * 5;
     b += (uint64_t)g.gx * g.gy * 4 + 65536 * 4 + 1024 + 256 + (N + 1) * 8 + N * D * 2;
     b += (uint64_t)((double)N * k) * rec + N * 4 + (1ull << 20);
     if (batch_binnable(s)) b += nblk * 4 + nblk * (uint64_t)(0.5 * 1024.0 * k + 4096.0) * 4;
@@ -908,6 +949,7 @@ void batch_drop_graphs(snn_batch* b)
 // Rewrite the device job table (block ranges are packed in slot order).  The
 // copy is ordered on the stepping stream after the steps already enqueued; the
 // pinned staging buffers are reused in turn once their previous copy is done.
+// Caller holds b->mu.
 hipError_t batch_upload(snn_batch* b)
 {
     const int i = b->h_next;
@@ -920,7 +962,7 @@ hipError_t batch_upload(snn_batch* b)
         snn::JobDesc& d = tab[j];
         std::memset(&d, 0, sizeof(d));
         const snn_batch::Job& J = b->jobs[j];
-        if (!J.active) continue;
+        if (J.state != snn_batch::kActive) continue;
         d.a = J.net->a;
         d.t_end = J.dur;
         d.active = 1;
@@ -935,9 +977,82 @@ hipError_t batch_upload(snn_batch* b)
     return hipEventRecord(b->h_done[i], b->stream);
 }
 
+// Jobs whose construction has finished join the table.  Caller holds b->mu.
+hipError_t batch_activate(snn_batch* b)
+{
+    if (b->built.empty()) return hipSuccess;
+    for (auto& kv : b->built) {
+        snn_batch::Job& J = b->jobs[kv.first];
+        if (!kv.second) continue;   // the worker already marked the job failed
+        J.net = kv.second;
+        b->used = b->used - J.bytes + J.net->bytes;   // the estimate gives way to the real footprint
+        J.bytes = J.net->bytes;
+        J.t = 0;
+        J.state = snn_batch::kActive;
+    }
+    b->built.clear();
+    return batch_upload(b);
+}
+
+void batch_worker(snn_batch* b)
+{
+    std::unique_lock<std::mutex> lk(b->mu);
+    for (;;) {
+        b->cv.wait(lk, [b] { return b->stop || !b->todo.empty() || !b->retired.empty(); });
+        if (!b->retired.empty()) {
+            const snn_batch::Retired r = b->retired.front();
+            b->retired.pop_front();
+            lk.unlock();
+            (void)hipEventSynchronize(r.after);   // no kernel still reads the job's descriptor
+            (void)hipEventDestroy(r.after);
+            snn_destroy(r.net);
+            lk.lock();
+            continue;
+        }
+        if (b->stop) break;
+        const snn_batch::BuildReq q = b->todo.front();
+        b->todo.pop_front();
+        lk.unlock();
+        snn_net* n = nullptr;
+        std::string msg;
+        snn_status st = snn_build_grid(&q.g, b->build_stream, &n);
+        if (st) {
+            msg = snn_last_error(nullptr);
+        } else {
+            if (!batch_binnable(q.s)) snn_set_option(n, SNN_OPT_DELIVER_MODE, 0);   // no bins to allocate
+            st = snn_build_synapses(n, &q.s);
+            if (st) {
+                msg = snn_last_error(n);
+                snn_destroy(n);
+                n = nullptr;
+            }
+        }
+        lk.lock();
+        if (st) {
+            snn_batch::Job& J = b->jobs[q.slot];
+            J.state = snn_batch::kFailed;
+            J.fail_st = st;
+            J.fail_msg = msg;
+        }
+        b->built.emplace_back(q.slot, n);
+        b->cv.notify_all();
+    }
+}
+
+// Grid of the per-block kernels for the blocks in use: the next power of two
+// (at least 64), so that a few captured graphs serve every batch size.
+uint32_t batch_grid(const snn_batch* b)
+{
+    uint32_t g = 64;
+    while (g < b->blk_used) g <<= 1;
+    return g < b->blk_cap ? g : b->blk_cap;
+}
+
 hipError_t batch_graph(snn_batch* b, uint32_t chunk, hipGraphExec_t* out)
 {
-    auto it = b->graphs.find(chunk);
+    const uint32_t grid = batch_grid(b);
+    const auto key = std::make_pair(chunk, grid);
+    auto it = b->graphs.find(key);
     if (it != b->graphs.end()) {
         *out = it->second.second;
         return hipSuccess;
@@ -950,10 +1065,10 @@ hipError_t batch_graph(snn_batch* b, uint32_t chunk, hipGraphExec_t* out)
     // step k: delivery of step k's spikes (binned or direct per job), then the
     // tiles, which also update the neurons for step k + 1; the chunk's first
     // update runs on its own and its last tile kernel updates nothing.
-    le = snn::launch_batch_update(b->d_jobs, b->blk_cap, 0, b->stream);
+    le = snn::launch_batch_update(b->d_jobs, grid, 0, b->stream);
     for (uint32_t k = 0; k < chunk && le == hipSuccess; ++k) {
         le = snn::launch_batch_scatter(b->d_jobs, b->scatter_blocks, k, b->stream);
-        if (le == hipSuccess) le = snn::launch_batch_tile(b->d_jobs, b->blk_cap, k, k + 1 < chunk, b->stream);
+        if (le == hipSuccess) le = snn::launch_batch_tile(b->d_jobs, grid, k, k + 1 < chunk, b->stream);
     }
     if (le == hipSuccess) le = snn::launch_batch_advance(b->d_jobs, chunk, b->stream);
     e = hipStreamEndCapture(b->stream, &gr);
@@ -967,7 +1082,7 @@ hipError_t batch_graph(snn_batch* b, uint32_t chunk, hipGraphExec_t* out)
         (void)hipGraphDestroy(gr);
         return e;
     }
-    b->graphs[chunk] = std::make_pair(gr, ex);
+    b->graphs[key] = std::make_pair(gr, ex);
     *out = ex;
     return hipSuccess;
 }
@@ -979,6 +1094,14 @@ snn_status batch_check(snn_batch* b)
     return SNN_OK;
 }
 
+// Release an admitted job's slot and reservation.  Caller holds b->mu.
+void batch_release(snn_batch* b, int slot)
+{
+    snn_batch::Job& J = b->jobs[slot];
+    b->used -= J.bytes;
+    b->blk_reserved -= J.nblk;
+    J = snn_batch::Job();
+}
 
 }  // namespace
 
@@ -1005,11 +1128,15 @@ snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip
         e = hipHostMalloc((void**)&b->h_jobs[i], sizeof(snn::JobDesc) * snn::kMaxJobs, 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming);
     }
-    if (e == hipSuccess) e = batch_upload(b);
+    if (e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(b->mu);
+        e = batch_upload(b);
+    }
     if (e != hipSuccess) {
         snn_batch_destroy(b);
         return bfail(nullptr, SNN_E_HIP, std::string("batch creation failed: ") + hipGetErrorString(e));
     }
+    b->worker = std::thread(batch_worker, b);
     *out = b;
     return SNN_OK;
 }
@@ -1021,43 +1148,33 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
     if (st) return st;
     if (!g || !s || !slot || dur_ms == 0) return bfail(b, SNN_E_INVAL, "bad job arguments");
     *slot = -1;
-    int free_slot = -1;
-    for (uint32_t j = 0; j < snn::kMaxJobs; ++j)
-        if (!b->jobs[j].active) {
-            free_slot = (int)j;
-            break;
-        }
-    if (free_slot < 0) return bfail(b, SNN_E_NOMEM, "all job slots in use");
     std::string why;
     if (!valid_grid(g, why)) return bfail(b, SNN_E_INVAL, why);
     const uint64_t N = (uint64_t)g->gx * g->gy * (g->n_exc + g->n_inh);
     const uint32_t nblk = (uint32_t)((N + 1023) / 1024);
-    if (b->blk_used + nblk > b->blk_cap) return bfail(b, SNN_E_NOMEM, "neuron capacity of the batch in use");
     snn_grid_desc gd = *g;
     gd.hist_cap = (uint64_t)((double)N * dur_ms * 0.15) + 65536;   // room for a 150 Hz mean rate
     const uint64_t est = estimate_bytes(gd, *s, gd.hist_cap);
+    std::lock_guard<std::mutex> lk(b->mu);
+    int free_slot = -1;
+    for (uint32_t j = 0; j < snn::kMaxJobs; ++j)
+        if (b->jobs[j].state == snn_batch::kFree) {
+            free_slot = (int)j;
+            break;
+        }
+    if (free_slot < 0) return bfail(b, SNN_E_NOMEM, "all job slots in use");
+    if (b->blk_reserved + nblk > b->blk_cap) return bfail(b, SNN_E_NOMEM, "neuron capacity of the batch in use");
     if (b->used + est > b->budget) return bfail(b, SNN_E_NOMEM, "HBM budget in use");
-    snn_net* n = nullptr;
-    st = snn_build_grid(&gd, b->build_stream, &n);
-    if (st) return bfail(b, st, snn_last_error(nullptr));
-    const bool binnable = batch_binnable(*s);
-    if (!binnable) snn_set_option(n, SNN_OPT_DELIVER_MODE, 0);   // no bins to allocate
-    st = snn_build_synapses(n, s);
-    if (st) {
-        std::string m = snn_last_error(n);
-        snn_destroy(n);
-        return bfail(b, st, m);
-    }
     snn_batch::Job& J = b->jobs[free_slot];
-    J.net = n;
-    J.bytes = n->bytes;
+    J.state = snn_batch::kBuilding;
+    J.bytes = est;
     J.dur = dur_ms;
     J.nblk = nblk;
-    J.t = 0;
-    J.active = true;
-    J.binned = binnable;
-    b->used += J.bytes;
-    BHIPCHK(b, batch_upload(b));
+    J.binned = batch_binnable(*s);
+    b->used += est;
+    b->blk_reserved += nblk;
+    b->todo.push_back(snn_batch::BuildReq{free_slot, gd, *s});
+    b->cv.notify_all();
     *slot = free_slot;
     return SNN_OK;
 }
@@ -1067,11 +1184,24 @@ snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms)
     snn_status st = batch_check(b);
     if (st) return st;
     if (chunk_ms == 0) return SNN_OK;
+    std::unique_lock<std::mutex> lk(b->mu);
+    auto count = [b](snn_batch::State s) {
+        uint32_t c = 0;
+        for (auto& J : b->jobs) c += J.state == s ? 1u : 0u;
+        return c;
+    };
+    // nothing to step yet but jobs under construction: wait for one of them
+    if (count(snn_batch::kActive) == 0 && b->built.empty() && count(snn_batch::kBuilding) > 0)
+        b->cv.wait(lk, [b] { return !b->built.empty() || b->stop; });
+    BHIPCHK(b, batch_activate(b));
+    bool any = false;
+    for (auto& J : b->jobs) any = any || (J.state == snn_batch::kActive && J.t < J.dur);
+    if (!any) return SNN_OK;
     hipGraphExec_t ex = nullptr;
     BHIPCHK(b, batch_graph(b, chunk_ms, &ex));
     BHIPCHK(b, hipGraphLaunch(ex, b->stream));
     for (auto& J : b->jobs)
-        if (J.active) J.t = (J.t + chunk_ms < J.dur) ? J.t + chunk_ms : J.dur;
+        if (J.state == snn_batch::kActive) J.t = (J.t + chunk_ms < J.dur) ? J.t + chunk_ms : J.dur;
     return SNN_OK;
 }
 
@@ -1081,13 +1211,15 @@ snn_status snn_batch_poll(snn_batch* b, int32_t* done, size_t cap, size_t* n_out
     if (st) return st;
     if (!n_out || (cap && !done)) return bfail(b, SNN_E_INVAL, "null output");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
+    std::lock_guard<std::mutex> lk(b->mu);
+    BHIPCHK(b, batch_activate(b));
     size_t n = 0;
     for (uint32_t j = 0; j < snn::kMaxJobs; ++j) {
-        if (!b->jobs[j].active) continue;
-        if (b->jobs[j].t >= b->jobs[j].dur) {
-            if (n < cap) done[n] = (int32_t)j;
-            ++n;
-        }
+        const snn_batch::Job& J = b->jobs[j];
+        const bool fin = (J.state == snn_batch::kActive && J.t >= J.dur) || J.state == snn_batch::kFailed;
+        if (!fin) continue;
+        if (n < cap) done[n] = (int32_t)j;
+        ++n;
     }
     *n_out = n;
     return n > cap ? bfail(b, SNN_E_TRUNC, "slot buffer too small") : SNN_OK;
@@ -1097,30 +1229,69 @@ snn_status snn_batch_read_spikes(snn_batch* b, int32_t slot, snn_spike* buf, siz
 {
     snn_status st = batch_check(b);
     if (st) return st;
-    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !b->jobs[slot].active || !n_out)
-        return bfail(b, SNN_E_INVAL, "no job in this slot");
+    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !n_out) return bfail(b, SNN_E_INVAL, "no job in this slot");
+    std::unique_lock<std::mutex> lk(b->mu);
     snn_batch::Job& J = b->jobs[slot];
+    if (J.state == snn_batch::kFailed) {
+        const snn_status fs = J.fail_st;
+        const std::string m = J.fail_msg;
+        batch_release(b, slot);
+        return bfail(b, fs, "job construction failed: " + m);
+    }
+    if (J.state != snn_batch::kActive) return bfail(b, SNN_E_INVAL, "no job in this slot");
     if (J.t < J.dur) return bfail(b, SNN_E_STATE, "job has not finished");
-    BHIPCHK(b, hipStreamSynchronize(b->stream));
-    std::vector<snn_spike> all;
-    size_t m = 0;
-    st = snn_read_spikes(J.net, 0, ~0ull, nullptr, 0, &m);
-    if (st && st != SNN_E_TRUNC) return bfail(b, st, snn_last_error(J.net));
-    *n_out = m;
+    BHIPCHK(b, hipStreamSynchronize(b->stream));   // the job's last steps are done
+    Ctrl hc{};
+    BHIPCHK(b, hipMemcpy(&hc, J.net->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    const bool truncated = hc.hist_n > J.net->g.hist_cap;
+    const uint64_t m = truncated ? J.net->g.hist_cap : hc.hist_n;
+    *n_out = (size_t)m;
     if (m > cap) return bfail(b, SNN_E_TRUNC, "spike buffer too small");
-    all.resize(m);
-    st = snn_read_spikes(J.net, 0, ~0ull, all.data(), m, &m);
-    const bool truncated = st == SNN_E_TRUNC;
-    if (st && !truncated) return bfail(b, st, snn_last_error(J.net));
-    // within a step the batched kernels append spikes in arrival order
-    std::sort(all.begin(), all.end(), [](const snn_spike& x, const snn_spike& y) {
-        return x.t_ms != y.t_ms ? x.t_ms < y.t_ms : x.gid < y.gid;
-    });
-    if (m) std::memcpy(buf, all.data(), m * sizeof(snn_spike));
-    snn_destroy(J.net);
-    b->used -= J.bytes;
-    J = snn_batch::Job();
+    if (m) BHIPCHK(b, hipMemcpy(buf, J.net->a.hist, m * sizeof(snn_spike), hipMemcpyDeviceToHost));
+    // Entries of one step are contiguous and steps ascend.  Within a step each
+    // update block (1024 neurons, gid >> 10) appended its spikers as one
+    // ascending run, the blocks in arrival order: put the runs in block order.
+    {
+        std::vector<std::pair<uint32_t, uint64_t>> runs;   // (block, start)
+        std::vector<snn_spike> tmp;
+        for (uint64_t i0 = 0; i0 < m;) {
+            uint64_t i1 = i0 + 1;
+            while (i1 < m && buf[i1].t_ms == buf[i0].t_ms) ++i1;
+            runs.clear();
+            bool ordered = true;
+            for (uint64_t i = i0; i < i1; ++i) {
+                const uint32_t blk = buf[i].gid >> 10;
+                if (i == i0 || blk != (buf[i - 1].gid >> 10)) {
+                    if (!runs.empty() && blk < runs.back().first) ordered = false;
+                    runs.emplace_back(blk, i);
+                }
+            }
+            if (!ordered) {
+                std::vector<std::pair<uint32_t, uint64_t>> sorted_runs(runs);
+                std::sort(sorted_runs.begin(), sorted_runs.end());
+                auto end_of = [&](uint64_t start) {
+                    uint64_t e = start + 1;
+                    while (e < i1 && (buf[e].gid >> 10) == (buf[start].gid >> 10)) ++e;
+                    return e;
+                };
+                tmp.clear();
+                for (auto& r : sorted_runs) tmp.insert(tmp.end(), buf + r.second, buf + end_of(r.second));
+                std::memcpy(buf + i0, tmp.data(), tmp.size() * sizeof(snn_spike));
+            }
+            i0 = i1;
+        }
+    }
+    // Leave the table, then hand the network to the worker, which frees it
+    // once the stepping stream has passed this table update.
+    snn_net* net = J.net;
+    J.state = snn_batch::kFree;
     BHIPCHK(b, batch_upload(b));
+    hipEvent_t after = nullptr;
+    BHIPCHK(b, hipEventCreateWithFlags(&after, hipEventDisableTiming));
+    BHIPCHK(b, hipEventRecord(after, b->stream));
+    batch_release(b, slot);
+    b->retired.push_back(snn_batch::Retired{net, after});
+    b->cv.notify_all();
     return truncated ? bfail(b, SNN_E_TRUNC, "job history overflowed its capacity") : SNN_OK;
 }
 
@@ -1128,19 +1299,24 @@ snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out)
 {
     snn_status st = batch_check(b);
     if (st) return st;
-    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !b->jobs[slot].active || !out)
-        return bfail(b, SNN_E_INVAL, "no job in this slot");
+    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs || !out) return bfail(b, SNN_E_INVAL, "no job in this slot");
+    std::lock_guard<std::mutex> lk(b->mu);
+    const snn_batch::Job& J = b->jobs[slot];
+    if (J.state != snn_batch::kActive) return bfail(b, SNN_E_INVAL, "no running or finished job in this slot");
     BHIPCHK(b, hipStreamSynchronize(b->stream));
-    st = snn_stats(b->jobs[slot].net, out);
-    return st ? bfail(b, st, snn_last_error(b->jobs[slot].net)) : SNN_OK;
+    Ctrl hc{};
+    BHIPCHK(b, hipMemcpy(&hc, J.net->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    fill_stats(J.net, hc, out);
+    return SNN_OK;
 }
 
 snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs)
 {
     snn_status st = batch_check(b);
     if (st) return st;
+    std::lock_guard<std::mutex> lk(b->mu);
     uint32_t n = 0;
-    for (auto& J : b->jobs) n += J.active ? 1u : 0u;
+    for (auto& J : b->jobs) n += J.state != snn_batch::kFree ? 1u : 0u;
     if (bytes) *bytes = b->used;
     if (jobs) *jobs = n;
     return SNN_OK;
@@ -1149,10 +1325,25 @@ snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs)
 void snn_batch_destroy(snn_batch* b)
 {
     if (!b) return;
+    if (b->worker.joinable()) {
+        {
+            std::lock_guard<std::mutex> lk(b->mu);
+            b->stop = true;
+            b->todo.clear();
+        }
+        b->cv.notify_all();
+        b->worker.join();   // finishes the build in progress and every pending free
+    }
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_drop_graphs(b);
+    for (auto& kv : b->built)
+        if (kv.second) snn_destroy(kv.second);
     for (auto& J : b->jobs)
         if (J.net) snn_destroy(J.net);
+    for (auto& r : b->retired) {
+        (void)hipEventDestroy(r.after);
+        snn_destroy(r.net);
+    }
     if (b->d_jobs) (void)hipFree(b->d_jobs);
     for (int i = 0; i < snn_batch::kTables; ++i) {
         if (b->h_jobs[i]) (void)hipHostFree(b->h_jobs[i]);

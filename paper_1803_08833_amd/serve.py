@@ -12,10 +12,6 @@ import numpy as np
 from . import snn
 
 
-def _hist_ok(spikes):
-    return spikes.ndim == 2
-
-
 class Result(dict):
     pass
 
@@ -30,6 +26,7 @@ def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chun
     events = np.zeros(n, dtype=np.int64)
     rasters = [None] * n
     slot_job = {}
+    failed = []
     nxt = 0
     queue = []
     t0 = clock()
@@ -40,6 +37,11 @@ def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chun
             while nxt < n and arrivals[nxt] <= now:
                 queue.append(nxt)
                 nxt += 1
+            # the next chunk of the running jobs goes out first, so that the
+            # admissions' synapse construction overlaps with it on the GPU
+            stepped = bool(slot_job)
+            if stepped:
+                b.step(chunk_ms)
             while queue:
                 j = queue[0]
                 slot = b.admit(jobs[j]["net"], jobs[j]["steps"])
@@ -47,21 +49,29 @@ def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chun
                     break
                 slot_job[slot] = j
                 queue.pop(0)
-            if not slot_job:
-                if nxt < n:
+            if not stepped:
+                if not slot_job and nxt < n:
                     time.sleep(max(0.0, min(arrivals[nxt] - (clock() - t0), 0.01)))
                 continue
-            b.step(chunk_ms)
             for slot in b.poll():
                 j = slot_job.pop(slot)
-                events[j] = b.job_stats(slot)["rec_events"]
-                sp = b.read_spikes(slot)
+                try:
+                    events[j] = b.job_stats(slot)["rec_events"]
+                    sp = b.read_spikes(slot)
+                except snn.SNNError as e:   # the job's construction failed
+                    try:
+                        b.read_spikes(slot)   # reports the build error and frees the slot
+                    except snn.SNNError as e2:
+                        e = e2
+                    failed.append((j, str(e)))
+                    done_count += 1
+                    continue
                 lat[j] = clock() - t0 - arrivals[j]
                 if keep_spikes:
                     rasters[j] = sp
                 done_count += 1
     wall = clock() - t0
-    return Result(latency=lat, events=events, wall=wall, rasters=rasters)
+    return Result(latency=lat, events=events, wall=wall, rasters=rasters, failed=failed)
 
 
 def serve_plain(jobs, arrivals, keep_spikes=False, clock=time.perf_counter):
@@ -109,7 +119,9 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
     2x2..16x16, Gaussian/exponential, 0.5-5 s), Poisson arrivals at `load`
     times the capacity measured by a saturated closed-loop batched run, served
     with continuous batching; the plain one-job-at-a-time server is run on the
-    first `plain_jobs` jobs of the same stream with the same arrival process."""
+    first `plain_jobs` jobs of the same stream with the same arrival process,
+    and both servers' closed-loop capacities (throughput with every job
+    queued at once) are measured on the first `capacity_jobs` jobs."""
     from . import workloads as W
 
     say = log or (lambda *a: None)
@@ -117,12 +129,18 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
     cap_jobs = jobs[:capacity_jobs]
     rc = serve_batched(cap_jobs, np.zeros(len(cap_jobs)), hbm_budget, max_neurons, chunk_ms)
     capacity = len(cap_jobs) / rc["wall"]
-    say(f"# capacity (closed loop, {len(cap_jobs)} jobs): {capacity:.2f} jobs/s")
+    rcp = serve_plain(cap_jobs, np.zeros(len(cap_jobs)))
+    capacity_plain = len(cap_jobs) / rcp["wall"]
+    say(f"# capacity (closed loop, {len(cap_jobs)} jobs): batched {capacity:.2f} jobs/s, "
+        f"plain {capacity_plain:.2f} jobs/s")
     arrivals = poisson_arrivals(n_jobs, load * capacity, seed=seed)
     rb = serve_batched(jobs, arrivals, hbm_budget, max_neurons, chunk_ms)
     sb = summary(rb, jobs)
     say(f"# served batched: {sb}")
     out = dict(jobs=n_jobs, arrival_rate_jobs_per_s=load * capacity, capacity_jobs_per_s=capacity,
+               capacity_plain_jobs_per_s=capacity_plain,
+               capacity_events_per_s=dict(batched=float(rc["events"].sum() / rc["wall"]),
+                                          plain=float(rcp["events"].sum() / rcp["wall"])),
                p50_s=sb["p50_s"], p99_s=sb["p99_s"], jobs_per_s=sb["jobs_per_s"],
                events_per_s=sb["events_per_s"], sim_s_per_wall_s=sb["sim_s_per_wall_s"])
     if plain_jobs:

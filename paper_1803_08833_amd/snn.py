@@ -328,9 +328,14 @@ class Batch:
         return {k: getattr(s, k) for k, _ in Stats._fields_}
 
     def read_spikes(self, slot: int):
+        """The finished job's raster ((t_ms, gid) rows); frees the slot."""
         n = C.c_size_t(0)
         st = lib().snn_batch_read_spikes(self.h, slot, None, 0, C.byref(n))
-        if st not in (SNN_OK, SNN_E_TRUNC):
+        if st == SNN_OK:   # no spikes: the slot is already free
+            self._descs.pop(slot, None)
+            return np.zeros((0, 2), dtype=np.uint32)
+        if st != SNN_E_TRUNC:
+            self._descs.pop(slot, None)
             self._check(st)
         out = np.zeros((max(n.value, 1), 2), dtype=np.uint32)
         self._check(lib().snn_batch_read_spikes(self.h, slot, _p(out), n.value, C.byref(n)))
