@@ -445,10 +445,10 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
         HIPCHK(n, snn::setup_kernels());
         const double c = n->bin_frac * (double)snn::kTile * (s->k_in + 6.0 * std::sqrt(s->k_in + 1.0)) + 4096.0;
         a.bin_cap_tile = (uint32_t)std::min(c, 1.0e9);
-        e = dalloc(n, &a.bin_fill, a.ntiles);
+        e = dalloc(n, &a.bin_fill, (size_t)a.ntiles * snn::kFillStride);
         if (e == hipSuccess) e = dalloc(n, &a.bins, (size_t)a.ntiles * a.bin_cap_tile);
         if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
-        HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles));
+        HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride));
         // Per-step switch: binning costs about one read and one write of every
         // future ring row (8 D N bytes at ~5.5 TB/s); direct delivery about one
         // global atomic per event (~27 G/s).  Equal at ~0.039 D N events.
@@ -725,7 +725,7 @@ snn_status snn_reset(snn_net* n)
     HIPCHK(n, hipMemsetAsync(a.ring, 0, sizeof(int32_t) * (size_t)snn::kRing * n->N, n->stream));
     HIPCHK(n, hipMemsetAsync(a.grp_cnt, 0, sizeof(uint32_t) * 2 * a.ngrp, n->stream));
     HIPCHK(n, hipMemsetAsync(a.ctrl, 0, sizeof(Ctrl), n->stream));
-    if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles, n->stream));
+    if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride, n->stream));
     HIPCHK(n, snn::launch_init(a, n->stream));
     if (n->built) {
         // the construction statistics live in the control block too
@@ -933,7 +933,7 @@ uint64_t estimate_bytes(const snn_grid_desc& g, const snn_syn_desc& s, uint64_t 
     uint64_t b = N * (4 + 4 + 1) + 32 * N * 4 + nblk * 16 + nblk * 1024 * 16 + N * 16 + hist_cap * 8 + N * 5;
     b += (uint64_t)g.gx * g.gy * 4 + 65536 * 4 + 1024 + 256 + (N + 1) * 8 + N * D * 2;
     b += (uint64_t)((double)N * k) * rec + N * 4 + (1ull << 20);
-    if (batch_binnable(s)) b += nblk * 4 + nblk * (uint64_t)(0.5 * 1024.0 * k + 4096.0) * 4;
+    if (batch_binnable(s)) b += nblk * 4 * snn::kFillStride + nblk * (uint64_t)(0.5 * 1024.0 * k + 4096.0) * 4;
     return b;
 }
 

@@ -379,12 +379,17 @@ __device__ __forceinline__ uint32_t update_quad(const StepArgs& a, const uint32_
 // parity t & 1 while direct delivery is selected; lock-step disagreements are
 // accumulated.
 template <uint32_t NW>
+//
+// The block's NW waves are threads [0, 64 NW) of a thread group (gtid = index
+// in the group); several groups of one workgroup may compact their own blocks
+// side by side (every thread of the workgroup takes part in the barriers, a
+// group that has no block passes live = false).
 __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, uint32_t t, uint32_t q,
-                                              uint32_t flags, uint32_t ext_tot, uint32_t dis,
-                                              uint32_t* wtot, unsigned long long* wext, uint32_t* wdis,
+                                              uint32_t flags, uint32_t ext_tot, uint32_t dis, uint32_t gtid,
+                                              bool live, uint32_t* wtot, unsigned long long* wext, uint32_t* wdis,
                                               unsigned long long* wev)
 {
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = gtid, lane = tid & 63u, wv = tid >> 6;
     const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
     const uint64_t m2 = __ballot(flags & 4u), m3 = __ballot(flags & 8u);
     const uint32_t pre = mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
@@ -418,7 +423,7 @@ __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, u
     ev = wave_sum<unsigned long long>(ev);
     if (lane == 0) wev[wv] = ev;
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && live) {
         unsigned long long be = 0, bv = 0;
         uint32_t bd = 0;
         for (uint32_t i = 0; i < NW; ++i) {
@@ -452,7 +457,7 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
         *rp = make_int4(0, 0, 0, 0);
         flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
     }
-    block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, wtot, wext, wdis, wev);
+    block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, threadIdx.x, true, wtot, wext, wdis, wev);
 }
 
 // ---------------------------------------------------------------------------
@@ -863,12 +868,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             if (t0i < nt) {
                 toff[t0i] = off;
                 tcnt[t0i] = off;
-                tres[t0i] = v0 ? atomicAdd(&a.bin_fill[t0i], v0) : 0u;
+                tres[t0i] = v0 ? atomicAdd(&a.bin_fill[(size_t)t0i * kFillStride], v0) : 0u;
             }
             if (t1i < nt) {
                 toff[t1i] = off + v0;
                 tcnt[t1i] = off + v0;
-                tres[t1i] = v1 ? atomicAdd(&a.bin_fill[t1i], v1) : 0u;
+                tres[t1i] = v1 ? atomicAdd(&a.bin_fill[(size_t)t1i * kFillStride], v1) : 0u;
             }
         }
         __syncthreads();
@@ -1005,7 +1010,7 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
             reinterpret_cast<int4*>(acc)[idx] = v;
         }
         __syncthreads();
-        const uint32_t fill = a.bin_fill[tt];
+        const uint32_t fill = a.bin_fill[(size_t)tt * kFillStride];
         const uint32_t cap = a.bin_cap_tile;
         const uint32_t n = fill < cap ? fill : cap;
         const uint32_t* ev = a.bins + (size_t)tt * cap;
@@ -1056,7 +1061,7 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
                 reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[qq] = v;
             }
         }
-        if (tid == 0) a.bin_fill[tt] = 0u;
+        if (tid == 0) a.bin_fill[(size_t)tt * kFillStride] = 0u;
     }
     if (do_upd) {
         __syncthreads();   // every thread is past its use of the Poisson table
@@ -1066,19 +1071,57 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
                              reinterpret_cast<unsigned long long*>(scratch + 96),
                              reinterpret_cast<unsigned long long*>(scratch + 128), scratch + 160);
         else
-            block_compact<NW>(a, tt, t + 1u, q, flags, ext_tot, dis, scratch + 64,
+            block_compact<NW>(a, tt, t + 1u, q, flags, ext_tot, dis, threadIdx.x, true, scratch + 64,
                               reinterpret_cast<unsigned long long*>(scratch + 96), scratch + 80,
                               reinterpret_cast<unsigned long long*>(scratch + 128));
     }
 }
 
+// Neuron update of step t for four blocks per pass, one per group of four
+// waves (a step without binned delivery needs no LDS rows, so a workgroup
+// covers four tiles and the whole grid fits the GPU at once).  The input is
+// read from ring slot t and cleared; the LDS at `scr` holds the Poisson table
+// and each group's compaction scratch.
+__device__ __forceinline__ void update_groups(const StepArgs& a, uint32_t t, uint32_t* scr)
+{
+    const uint32_t tid = threadIdx.x, g = tid >> 8, gtid = tid & 255u;
+    if (tid < a.npois) scr[tid] = a.poisc[tid];
+    __syncthreads();
+    uint32_t* gs = scr + 64 + 32 * g;   // per group: wtot[4] wdis[4] wext[4] wev[4] (u64)
+    for (uint32_t base = 4u * blockIdx.x; base < a.nblk; base += 4u * gridDim.x) {
+        const uint32_t blk = base + g;
+        const bool live = blk < a.nblk;
+        const uint32_t q = blk * 256u + gtid;
+        uint32_t flags = 0, ext_tot = 0, dis = 0;
+        if (live && q < a.nq) {
+            int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
+            const int4 in = *rp;
+            *rp = make_int4(0, 0, 0, 0);
+            flags = update_quad(a, scr, q, t, in, ext_tot, dis);
+        }
+        block_compact<4>(a, blk, t, q, flags, ext_tot, dis, gtid, live, gs, reinterpret_cast<unsigned long long*>(gs + 8),
+                         gs + 4, reinterpret_cast<unsigned long long*>(gs + 16));
+        __syncthreads();   // the groups' scratch is reused by the next pass
+    }
+}
+
+// Phase B of step t and, with UPD, the neuron update of step t + 1.  A binned
+// step takes the tiles in turn (tile b, b + grid, ...); otherwise the update
+// alone runs four blocks per workgroup pass.
 template <bool CODE8, bool UPD>
 __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
 {
     extern __shared__ int32_t acc[];      // [D][1024]
     const uint32_t t = a.ctrl->t0 + k;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->hist_n += a.ctrl->nspk;   // step t's history is complete
-    tile_work<CODE8, UPD, false>(a, blockIdx.x, t, step_binned(a, t), true, acc);
+    if (step_binned(a, t)) {
+        for (uint32_t tt = blockIdx.x; tt < a.ntiles; tt += gridDim.x) {
+            tile_work<CODE8, UPD, false>(a, tt, t, true, true, acc);
+            __syncthreads();   // the LDS rows are reloaded for the next tile
+        }
+    } else if (UPD) {
+        update_groups(a, t + 1u, reinterpret_cast<uint32_t*>(acc));
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1260,7 +1303,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
                     if (wbase[mid] <= w) lo = mid;
                     else hi = mid;
                 }
-                tres[w] = v ? atomicAdd(&jobs[lo].a.bin_fill[w - wbase[lo]], v) : 0u;
+                tres[w] = v ? atomicAdd(&jobs[lo].a.bin_fill[(size_t)(w - wbase[lo]) * kFillStride], v) : 0u;
                 off += v;
             }
         }
@@ -1403,6 +1446,8 @@ hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t*
     return hipGetLastError();
 }
 
+static uint32_t g_cus = 256;   // compute units of the device (set by setup_kernels)
+
 // Launch on stream s; with timing events, the launch packet itself stamps the
 // kernel's start and end into them.
 #define SNN_LAUNCH(ev, kern, grid, block, shm, s, ...)                                                    \
@@ -1455,6 +1500,11 @@ hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint3
 
 hipError_t setup_kernels()
 {
+    int dev = 0, cus = 0;
+    hipError_t ce = hipGetDevice(&dev);
+    if (ce == hipSuccess) ce = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (ce != hipSuccess) return ce;
+    if (cus > 0) g_cus = (uint32_t)cus;
     // phase B keeps D rows of 1024 int32 in LDS (up to 124 KB of the 160 KB per CU)
     const int lds = (int)(kMaxD * kTile * sizeof(int32_t));
     const void* fns[6] = {(const void*)k_tile<true, false>, (const void*)k_tile<false, false>,
@@ -1470,7 +1520,10 @@ hipError_t setup_kernels()
 hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s, const LaunchEv* ev)
 {
     const size_t lds = (size_t)a.D * kTile * sizeof(int32_t);
-    const dim3 g(a.ntiles), b(kTileThreads);
+    // as many workgroups as are resident at once: two per CU (1024 threads and
+    // up to 124 KB of LDS each)
+    const uint32_t grid = a.ntiles < 2u * g_cus ? a.ntiles : 2u * g_cus;
+    const dim3 g(grid), b(kTileThreads);
     if (a.record == 1u) {
         if (update_next) SNN_LAUNCH(ev, (k_tile<true, true>), g, b, lds, s, a, k);
         else SNN_LAUNCH(ev, (k_tile<true, false>), g, b, lds, s, a, k);

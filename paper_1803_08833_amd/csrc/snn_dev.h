@@ -22,6 +22,9 @@ constexpr uint32_t kMaxTiles = 2048;          // binned delivery needs N <= 2M n
 constexpr uint32_t kChunkItems = 112;       // row segments (256 records) per scatter chunk: 16 waves x 7
 constexpr uint32_t kStage = kChunkItems * 256;
 constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for the inhibitory weight
+// Bin fill counters sit one per 128-byte line: every scatter workgroup reserves
+// in every tile's bin each chunk, and counters sharing a line serialise there.
+constexpr uint32_t kFillStride = 32;
 
 // Philox stream identifiers (third counter word).
 constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
@@ -80,7 +83,7 @@ struct StepArgs {
     int32_t winh_q;
     uint32_t bin_cap_tile;    // capacity of every tile's bin (events)
     uint64_t bin_threshold;   // steps with fewer events are delivered directly
-    uint32_t* bin_fill;       // [ntiles] events binned this step
+    uint32_t* bin_fill;       // [ntiles * kFillStride] events binned this step (one counter per line)
     uint32_t* bins;           // [ntiles][bin_cap_tile] event codes:
                               //   target & 1023 | bucket << 10 | weight field << 15
 };
