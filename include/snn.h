@@ -116,22 +116,30 @@ typedef struct {
     uint64_t disagree;        /* lock-step: own threshold test != forced set     */
     uint64_t bin_overflow;    /* binned delivery: events that took the fallback  */
     uint32_t deliver_mode;    /* delivery schedule in use (SNN_OPT_DELIVER_MODE) */
-    uint32_t binned_ok;       /* 1 if the network supports binned delivery       */
+    uint32_t binned_ok;       /* bit 0: single-level binned delivery possible;
+                                 bit 1: two-level binned delivery possible     */
     uint64_t bin_threshold;   /* per-step switch to direct delivery (events)     */
     double build_ms;          /* wall time of snn_build_synapses                 */
 } snn_stats_t;
 
-/* Per-kernel average durations in ms (HIP events on the network's stream). */
+/* Per-launch average durations in ms, each launch stamped by its own start
+ * and stop events on the network's stream.  With binned delivery the update
+ * of the next step runs inside the tile kernel (update_ms is then the first
+ * step's own update launch only). */
 typedef struct {
-    double update_ms;         /* fused neuron update                             */
-    double compact_ms;        /* ordered spike compaction                        */
+    double update_ms;         /* neuron update launch                            */
+    double compact_ms;        /* ordered spike compaction launch (direct and
+                                 two-level delivery)                             */
     double deliver_ms;        /* projection fan-out into the delay ring (all phases) */
-    double scatter_ms;        /* binned delivery: events binned by target tile   */
-    double tile_ms;           /* binned delivery: per-tile LDS accumulation      */
-    double step_ms;           /* whole step, launched back to back               */
+    double scatter_ms;        /* binned delivery: compaction (single level) and
+                                 events binned by tile or super tile            */
+    double tile_ms;           /* binned delivery: per-tile LDS accumulation and
+                                 the next step's update                          */
+    double step_ms;           /* sum of all launches per step                    */
     uint64_t steps;
     uint64_t rec_events;      /* recurrent events delivered in the timed steps   */
     uint64_t spikes;
+    double sub_ms;            /* two-level binning: super-tile bins split by tile */
 } snn_kernel_times;
 
 /* Tuning knobs (snn_set_option). */
@@ -140,7 +148,12 @@ enum {
     SNN_OPT_DELIVER_WAVES = 2,   /* waves in the fan-out grid                      */
     SNN_OPT_DELIVER_UNROLL = 3,  /* direct delivery: records in flight per lane: 1, 2, 4 */
     SNN_OPT_DELIVER_MODE = 4,    /* 0: direct ring atomics; 1: tile-binned (default
-                                    when the network allows it, see snn_stats)      */
+                                    when the network allows it, see snn_stats);
+                                    2: two-level tile-binned (8-bit-code records;
+                                    default when the tiles exceed one level).
+                                    Before snn_build_synapses it selects which bins
+                                    are allocated; afterwards it switches between
+                                    direct delivery and the mode built for.     */
     SNN_OPT_SCATTER_BLOCKS = 5,  /* workgroups of the binned scatter phase          */
     SNN_OPT_BIN_FRAC_PPM = 6,    /* before snn_build_synapses: bin capacity per tile
                                     as a fraction (ppm) of its expected in-synapses;

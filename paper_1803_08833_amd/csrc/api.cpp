@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <condition_variable>
@@ -46,9 +47,10 @@ struct snn_net {
     uint32_t graph_chunk = 64;
     uint32_t deliver_waves = 8192;
     uint32_t unroll = 4;
-    uint32_t mode = 0;          // 0 direct atomics, 1 tile-binned
-    int mode_pref = -1;         // set before the build: -1 automatic, 0 direct only
-    bool binned_ok = false;
+    uint32_t mode = 0;          // 0 direct atomics, 1 tile-binned, 2 two-level tile-binned
+    int mode_pref = -1;         // set before the build: -1 automatic, 0 direct only, 1 / 2 levels
+    bool binned_ok = false;     // single-level binning possible
+    bool two_level_ok = false;  // two-level binning possible (bins allocated only when selected)
     uint32_t scatter_blocks = 256;
     double bin_frac = 0.5;      // bin capacity as a fraction of the tile's in-synapses
     bool bin_threshold_set = false;
@@ -123,19 +125,24 @@ snn_status check_usable(snn_net* n)
 }
 
 // Enqueue step k (0-based within the current chunk) of the plain path.
+// Binned delivery of step k (tile kernel without the next step's update).
+hipError_t enqueue_binned(snn_net* n, const StepArgs& a, uint32_t k, bool update_next)
+{
+    hipError_t e = snn::launch_scatter(a, k, n->max_len, n->scatter_blocks, n->stream);
+    if (e == hipSuccess && n->mode == 2) e = snn::launch_sub(a, k, n->scatter_blocks, n->stream);
+    if (e == hipSuccess) e = snn::launch_tile(a, k, update_next, n->stream);
+    return e;
+}
+
 hipError_t enqueue_deliver(snn_net* n, const StepArgs& a, uint32_t k)
 {
-    if (n->mode == 1) {
-        hipError_t e = snn::launch_scatter(a, k, n->max_len, n->scatter_blocks, n->stream);
-        if (e != hipSuccess) return e;
-        return snn::launch_tile(a, k, false, n->stream);
-    }
+    if (n->mode != 0) return enqueue_binned(n, a, k, false);
     return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
 }
 
 hipError_t check_items(snn_net* n)
 {
-    const uint64_t seg = 64ull * (n->mode == 1 ? 4 : n->unroll);
+    const uint64_t seg = 64ull * (n->mode != 0 ? 4 : n->unroll);
     const uint64_t smax = n->max_len ? (n->max_len + seg - 1) / seg : 1;
     return ((uint64_t)n->N * smax >= (1ull << 32)) ? hipErrorInvalidValue : hipSuccess;
 }
@@ -147,22 +154,23 @@ hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
     if (e != hipSuccess) return e;
     e = snn::launch_update(a, k, n->stream);
     if (e != hipSuccess) return e;
-    if (n->mode != 1) {   // binned delivery compacts inside its scatter kernel
+    if (n->mode != 1) {   // single-level binned delivery compacts inside its scatter kernel
         e = snn::launch_compact(a, k, n->stream);
         if (e != hipSuccess) return e;
     }
     return enqueue_deliver(n, a, k);
 }
 
-// Enqueue steps k0 .. k0+count-1.  With binned delivery the spike compaction
-// runs inside the scatter kernel and the neuron update of step k+1 inside
-// step k's tile kernel, so a step is two launches and only the first update
-// is a launch of its own; the last tile kernel does not update, leaving the
-// state at the end of the last step.
+// Enqueue steps k0 .. k0+count-1.  With binned delivery the neuron update of
+// step k+1 runs inside step k's tile kernel, so only the first update is a
+// launch of its own; the last tile kernel does not update, leaving the state
+// at the end of the last step.  Single level: the spike compaction runs inside
+// the scatter kernel, so a step is two launches; two levels: compaction,
+// scatter, second pass, tiles.
 hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
 {
     if (count == 0) return hipSuccess;
-    if (n->mode != 1 || n->a.d_min != 1) {
+    if (n->mode == 0 || n->a.d_min != 1) {
         for (uint32_t k = k0; k < k0 + count; ++k) {
             hipError_t e = enqueue_step(n, n->a, k);
             if (e != hipSuccess) return e;
@@ -172,8 +180,8 @@ hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
     hipError_t e = check_items(n);
     if (e == hipSuccess) e = snn::launch_update(n->a, k0, n->stream);
     for (uint32_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
-        e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream);
-        if (e == hipSuccess) e = snn::launch_tile(n->a, k, k + 1 < k0 + count, n->stream);
+        if (n->mode == 2) e = snn::launch_compact(n->a, k, n->stream);
+        if (e == hipSuccess) e = enqueue_binned(n, n->a, k, k + 1 < k0 + count);
     }
     return e;
 }
@@ -432,31 +440,48 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     HIPCHK(n, hipStreamSynchronize(n->stream));
     dfree(n, rowlen);
     dfree(n, tsum);
-    // Tile-binned delivery: possible when the tiles fit the LDS tables and
-    // every weight has a 17-bit event field (code, or w_q + 65536 in range).
+    // Tile-binned delivery.  Single level: the tiles fit the scatter kernel's
+    // LDS tables and every weight has a 17-bit event field (code, or w_q +
+    // 65536 in range).  Two levels (8-bit codes): first by super tile of 65536
+    // targets, then by tile; for networks with more tiles than one LDS table.
     a.ntiles = (n->N + snn::kTile - 1) / snn::kTile;
     a.winh_q = tb.winh_q;
-    bool ok = a.ntiles <= snn::kMaxTiles && n->mode_pref != 0;
+    bool ok1 = a.ntiles <= snn::kMaxTiles;
     if (s->record != SNN_REC_CODE8)
         for (int32_t w : tb.wtab)
-            if (w != tb.winh_q && (w < -65536 || w > 65534)) ok = false;
-    n->binned_ok = ok;
-    if (ok) {
+            if (w != tb.winh_q && (w < -65536 || w > 65534)) ok1 = false;
+    const uint32_t nsuper = (uint32_t)(((uint64_t)n->N + (1u << snn::kSuperBits) - 1) >> snn::kSuperBits);
+    const bool ok2 = s->record == SNN_REC_CODE8 && nsuper <= snn::kMaxTiles;
+    n->binned_ok = ok1;
+    n->two_level_ok = ok2;
+    uint32_t mode = 0;
+    if (n->mode_pref == 2) mode = ok2 ? 2 : 0;
+    else if (n->mode_pref == 1) mode = ok1 ? 1 : 0;
+    else if (n->mode_pref < 0) mode = ok1 ? 1 : (ok2 ? 2 : 0);
+    if (mode) {
         HIPCHK(n, snn::setup_kernels());
-        const double c = n->bin_frac * (double)snn::kTile * (s->k_in + 6.0 * std::sqrt(s->k_in + 1.0)) + 4096.0;
-        a.bin_cap_tile = (uint32_t)std::min(c, 1.0e9);
+        const double kin = s->k_in + 6.0 * std::sqrt(s->k_in + 1.0);
+        const double frac = mode == 2 ? 0.5 * n->bin_frac : n->bin_frac;   // two levels hold every event twice
+        a.bin_cap_tile = (uint32_t)std::min(frac * (double)snn::kTile * kin + 4096.0, 1.0e9);
         e = dalloc(n, &a.bin_fill, (size_t)a.ntiles * snn::kFillStride);
         if (e == hipSuccess) e = dalloc(n, &a.bins, (size_t)a.ntiles * a.bin_cap_tile);
+        if (e == hipSuccess && mode == 2) {
+            a.nsuper = nsuper;
+            a.sbin_cap = (uint32_t)std::min(frac * (double)(1u << snn::kSuperBits) * kin + 65536.0, 4.0e9);
+            e = dalloc(n, &a.sbin_fill, (size_t)nsuper * snn::kFillStride);
+            if (e == hipSuccess) e = dalloc(n, &a.sbins, (size_t)nsuper * a.sbin_cap);
+        }
         if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
         HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride));
+        if (mode == 2) HIPCHK(n, hipMemset(a.sbin_fill, 0, 4 * (size_t)nsuper * snn::kFillStride));
         // Per-step switch: binning costs about one read and one write of every
         // future ring row (8 D N bytes at ~5.5 TB/s); direct delivery about one
         // global atomic per event (~27 G/s).  Equal at ~0.039 D N events.
         if (n->bin_threshold_set) a.bin_threshold = n->bin_threshold_opt;
         else a.bin_threshold = (uint64_t)(0.039 * n->D * (double)n->N);
-        n->mode = 1;
     }
-    n->a.grp_atomic = n->mode == 1 ? 0u : 1u;
+    n->mode = mode;
+    a.grp_atomic = n->mode == 1 ? 0u : 1u;
     n->built = true;
     n->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SNN_OK;
@@ -620,7 +645,7 @@ void fill_stats(const snn_net* n, const Ctrl& hc, snn_stats_t* out)
     out->bin_overflow = hc.bin_overflow;
     out->deliver_mode = n->mode;
     out->bin_threshold = n->a.bin_threshold;
-    out->binned_ok = n->binned_ok ? 1u : 0u;
+    out->binned_ok = (n->binned_ok ? 1u : 0u) | (n->two_level_ok ? 2u : 0u);
     out->build_ms = n->build_ms;
 }
 
@@ -637,7 +662,7 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     // The steps are the ones snn_step enqueues (same kernels, same order), each
     // launch stamped with its own start/stop events; steps go out in batches
     // and the events of a batch are read once it has finished.
-    constexpr uint32_t kB = 128, kL = 3;   // steps per batch, launches per step
+    constexpr uint32_t kB = 128, kL = 5;   // steps per batch, launches per step (at most)
     std::vector<snn::LaunchEv> ev(kB * kL);
     hipError_t e = hipSuccess;
     for (auto& x : ev) {
@@ -657,10 +682,10 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     Ctrl c0{}, c1{};
     e = hipStreamSynchronize(n->stream);
     if (e == hipSuccess) e = hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
-    const bool fused = n->mode == 1 && n->a.d_min == 1;
-    // kind of each launch slot: 0 update, 1 compact, 2 direct deliver, 3 scatter, 4 tile
-    double sum[5] = {0, 0, 0, 0, 0};
-    uint32_t cnt[5] = {0, 0, 0, 0, 0};
+    const bool fused = n->mode != 0 && n->a.d_min == 1;
+    // kind of each launch slot: 0 update, 1 compact, 2 direct deliver, 3 scatter, 4 tile, 5 second pass
+    double sum[6] = {0, 0, 0, 0, 0, 0};
+    uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
     std::vector<int> kind(kB * kL, -1);
     for (uint32_t b0 = 0; b0 < n_ms && e == hipSuccess; b0 += kB) {
         const uint32_t nb = (n_ms - b0) < kB ? (n_ms - b0) : kB;
@@ -673,9 +698,17 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
                 kind[i * kL] = 0;
             }
             if (e != hipSuccess) break;
-            if (n->mode == 1) {
-                e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream, &x[1]);
+            if (n->mode != 0) {
+                if (n->mode == 2) {
+                    e = snn::launch_compact(n->a, k, n->stream, &x[3]);
+                    kind[i * kL + 3] = 1;
+                }
+                if (e == hipSuccess) e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream, &x[1]);
                 kind[i * kL + 1] = 3;
+                if (e == hipSuccess && n->mode == 2) {
+                    e = snn::launch_sub(n->a, k, n->scatter_blocks, n->stream, &x[4]);
+                    kind[i * kL + 4] = 5;
+                }
                 if (e == hipSuccess) e = snn::launch_tile(n->a, k, fused && k + 1 < n_ms, n->stream, &x[2]);
                 kind[i * kL + 2] = 4;
             } else {
@@ -709,8 +742,9 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     out->compact_ms = avg(1);
     out->scatter_ms = avg(3);
     out->tile_ms = avg(4);
-    out->deliver_ms = n->mode == 1 ? avg(3) + avg(4) : avg(2);
-    out->step_ms = (sum[0] + sum[1] + sum[2] + sum[3] + sum[4]) / steps;
+    out->sub_ms = avg(5);
+    out->deliver_ms = n->mode != 0 ? avg(3) + avg(4) + avg(5) : avg(2);
+    out->step_ms = (sum[0] + sum[1] + sum[2] + sum[3] + sum[4] + sum[5]) / steps;
     out->steps = n_ms;
     out->rec_events = c1.rec_events - c0.rec_events;
     out->spikes = c1.spikes - c0.spikes;
@@ -726,6 +760,7 @@ snn_status snn_reset(snn_net* n)
     HIPCHK(n, hipMemsetAsync(a.grp_cnt, 0, sizeof(uint32_t) * 2 * a.ngrp, n->stream));
     HIPCHK(n, hipMemsetAsync(a.ctrl, 0, sizeof(Ctrl), n->stream));
     if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride, n->stream));
+    if (a.sbin_fill) HIPCHK(n, hipMemsetAsync(a.sbin_fill, 0, 4 * (size_t)a.nsuper * snn::kFillStride, n->stream));
     HIPCHK(n, snn::launch_init(a, n->stream));
     if (n->built) {
         // the construction statistics live in the control block too
@@ -751,13 +786,21 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         n->deliver_waves = (uint32_t)value;
         break;
     case SNN_OPT_DELIVER_MODE:
-        if (value != 0 && value != 1) return fail(n, SNN_E_INVAL, "delivery mode must be 0 or 1");
+        if (value < 0 || value > 2) return fail(n, SNN_E_INVAL, "delivery mode must be 0, 1 or 2");
         if (!n->built) {
-            n->mode_pref = (int)value;    // 0 before the build: no bins are allocated
+            n->mode_pref = (int)value;    // before the build: selects which bins are allocated
             return SNN_OK;
         }
-        if (value == 1 && !n->binned_ok) return fail(n, SNN_E_INVAL, "this network cannot use binned delivery");
+        {
+            // bins exist for the mode chosen at the build (single level, or two levels)
+            const bool have1 = n->binned_ok && n->a.bins && !n->a.nsuper;
+            const bool have2 = n->a.nsuper != 0;
+            if ((value == 1 && !have1) || (value == 2 && !have2))
+                return fail(n, SNN_E_INVAL, "this delivery mode was not selected when the synapses were built");
+        }
         n->mode = (uint32_t)value;
+        HIPCHK(n, hipStreamSynchronize(n->stream));
+        HIPCHK(n, hipMemset(reinterpret_cast<char*>(n->a.ctrl) + offsetof(Ctrl, step_ev), 0, sizeof(uint64_t) * 2));
         // direct delivery's compaction reads the group counts, which the
         // update maintains only while direct delivery is selected
         n->a.grp_atomic = n->mode == 1 ? 0u : 1u;

@@ -467,7 +467,8 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
 // (binary search over the group's block offsets), copying its {gid, row
 // length, row start} record to the step's spike list and writing the AER
 // history entry.  Also clears this group's entry of the other parity buffer
-// for the next step and adds its blocks' event counts to the totals.  Binned
+// for the next step and adds its blocks' event counts to the totals (and to
+// the step's event total that decides two-level binning).  Single-level binned
 // delivery does this compaction inside its scatter kernel instead.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kCompactThreads = 1024;
@@ -518,8 +519,12 @@ __global__ __launch_bounds__(kCompactThreads) void k_compact(StepArgs a, uint32_
             be += st.y;
             bx += st.z;
         }
-        if (be) atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+        if (be) {
+            atomicAdd((unsigned long long*)&a.ctrl->rec_events, be);
+            atomicAdd((unsigned long long*)&a.ctrl->step_ev[par], be);   // two-level binning's switch
+        }
         if (bx) atomicAdd((unsigned long long*)&a.ctrl->ext_events, bx);
+        if (g == 0) a.ctrl->step_ev[par ^ 1u] = 0;
         if (g == a.ngrp - 1u) {
             a.ctrl->nspk = base + gtot;
             a.ctrl->spikes += base + gtot;
@@ -685,14 +690,20 @@ __device__ __forceinline__ void seg_load(const StepArgs& a, uint4 info, uint32_t
     }
 }
 
+// A bin covers 2^SHIFT targets: 1024-target tiles (SHIFT = kTileBits) or, for
+// two-level binning, 65536-target super tiles (SHIFT = kSuperBits).  The event
+// code keeps the target's low SHIFT bits, the delay bucket and the weight
+// field: target & (2^SHIFT - 1) | bucket << SHIFT | weight field << (SHIFT + 5).
+template <uint32_t SHIFT>
 __device__ __forceinline__ void seg_count(const SegLoad& L, uint32_t lane, uint32_t* tcnt)
 {
     if (L.s0 >= L.len) return;
 #pragma unroll
     for (int u = 0; u < 4; ++u)
-        if (L.s0 + 64u * u + lane < L.len) atomicAdd(&tcnt[L.tg[u] >> kTileBits], 1u);
+        if (L.s0 + 64u * u + lane < L.len) atomicAdd(&tcnt[L.tg[u] >> SHIFT], 1u);
 }
 
+template <uint32_t SHIFT>
 __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint32_t* tcnt, uint32_t* stage)
 {
     if (L.s0 >= L.len) return;
@@ -709,8 +720,8 @@ __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint3
             bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
         }
         if (kk < L.len) {
-            const uint32_t p = atomicAdd(&tcnt[L.tg[u] >> kTileBits], 1u);
-            stage[p] = (L.tg[u] & (kTile - 1u)) | (bl << kTileBits) | (L.wf[u] << 15);
+            const uint32_t p = atomicAdd(&tcnt[L.tg[u] >> SHIFT], 1u);
+            stage[p] = (L.tg[u] & ((1u << SHIFT) - 1u)) | (bl << SHIFT) | (L.wf[u] << (SHIFT + 5u));
         }
     }
 }
@@ -757,27 +768,39 @@ __device__ __forceinline__ void write_history(const StepArgs& a, const uint32_t*
 // update blocks' ascending lists placed by an exclusive scan of their counts)
 // happens here: every workgroup scans the block counts in LDS and addresses
 // spike records in the per-block lists; the workgroups write the AER history
-// in ascending order; workgroup 0 publishes the spike count and clears the
-// other parity's counters.
-template <bool CODE8>
+// in ascending order; workgroup 0 publishes the spike count and the step's
+// event totals.
+//
+// TWO (two-level binning, 8-bit-code records, networks with more update blocks
+// than one LDS scan covers): the spike list, history and totals come from the
+// compaction kernel before, and the events are binned by 65536-target super
+// tile; k_sub then splits each super tile's bin into its tiles' bins.
+template <bool CODE8, bool TWO>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
 {
+    constexpr uint32_t SHIFT = TWO ? kSuperBits : kTileBits;
     __shared__ uint32_t stage[kStage];
     __shared__ uint32_t tcnt[kMaxTiles];   // counts, then fill cursor
-    __shared__ uint32_t toff[kMaxTiles];   // start of each tile's run in `stage`
-    __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the tile's bin
-    __shared__ uint32_t boff[kMaxTiles + 1];
+    __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
+    __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
+    __shared__ uint32_t boff[TWO ? 1 : kMaxTiles + 1];
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
     __shared__ unsigned long long red[2 * kScatterWaves + 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     if (CODE8 && tid < 256u) cb_s[tid] = a.cb[tid];
     const uint32_t t = a.ctrl->t0 + k;
-    const uint32_t nb = a.nblk;          // <= kMaxTiles on this path
-    // exclusive scan of the update blocks' spike counts (two blocks per
-    // thread) and the step's recurrent and external event totals: the event
-    // total decides binned vs direct; workgroup 0 books the totals
-    {
+    const uint32_t nb = a.nblk;          // single level: <= kMaxTiles
+    bool binned;
+    uint32_t n;
+    if (TWO) {
+        if (CODE8) __syncthreads();
+        binned = step_binned(a, t);
+        n = a.ctrl->nspk;
+    } else {
+        // exclusive scan of the update blocks' spike counts (two blocks per
+        // thread) and the step's recurrent and external event totals: the
+        // event total decides binned vs direct; workgroup 0 books the totals
         const uint32_t i0 = 2u * tid, i1 = 2u * tid + 1u;
         const uint4 s0 = i0 < nb ? a.blk_stat[i0] : make_uint4(0, 0, 0, 0);
         const uint4 s1 = i1 < nb ? a.blk_stat[i1] : make_uint4(0, 0, 0, 0);
@@ -810,25 +833,28 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             }
         }
         __syncthreads();
+        binned = __builtin_amdgcn_readfirstlane(red[2 * kScatterWaves] >= a.bin_threshold ? 1 : 0) != 0;
+        n = (uint32_t)__builtin_amdgcn_readfirstlane((int)boff[nb]);
+        if (blockIdx.x == 0 && tid == 0) {
+            a.ctrl->nspk = n;
+            a.ctrl->spikes += n;
+        }
     }
-    const bool binned =
-        __builtin_amdgcn_readfirstlane(red[2 * kScatterWaves] >= a.bin_threshold ? 1 : 0) != 0;   // uniform
-    const uint32_t n = (uint32_t)__builtin_amdgcn_readfirstlane((int)boff[nb]);                    // uniform
-    if (blockIdx.x == 0 && tid == 0) {
-        a.ctrl->nspk = n;
-        a.ctrl->spikes += n;
-    }
+    // spike s of the step (wave-uniform s)
+    auto spike = [&](uint32_t s) { return TWO ? a.spk[s] : spike_rec(a, boff, nb, s); };
     if (!binned) {
         const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
         const uint32_t nw = gridDim.x * kScatterWaves;
         for (uint32_t it = blockIdx.x * kScatterWaves + wv; it < items; it += nw)
-            deliver_item<4, CODE8>(a, t, spike_rec(a, boff, nb, it / smax), it % smax, lane, cb_s);
-        write_history(a, boff, nb, n, t);
+            deliver_item<4, CODE8>(a, t, spike(it / smax), it % smax, lane, cb_s);
+        if (!TWO) write_history(a, boff, nb, n, t);
         return;
     }
     const uint32_t items = n * smax;
-    const uint32_t nt = a.ntiles;
-    const uint32_t cap = a.bin_cap_tile;
+    const uint32_t nt = TWO ? a.nsuper : a.ntiles;
+    const uint32_t cap = TWO ? a.sbin_cap : a.bin_cap_tile;
+    uint32_t* const fill = TWO ? a.sbin_fill : a.bin_fill;
+    uint32_t* const bins = TWO ? a.sbins : a.bins;
     // chunk size: large chunks bin better, but every workgroup should get work
     uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
     per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
@@ -841,7 +867,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
-            info[j] = it < c1 ? spike_rec(a, boff, nb, it / smax) : make_uint4(0, 0, 0, 0);
+            info[j] = it < c1 ? spike(it / smax) : make_uint4(0, 0, 0, 0);
         }
         SegLoad S[kSegPerWave];
 #pragma unroll
@@ -850,11 +876,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             seg_load<CODE8>(a, info[j], it < c1 ? it % smax : 0u, lane, S[j]);
         }
         __syncthreads();
-        // 1. histogram of targets by tile
+        // 1. histogram of targets by bin
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count(S[j], lane, tcnt);
+        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count<SHIFT>(S[j], lane, tcnt);
         __syncthreads();
-        // 2. exclusive scan of the counts (2 tiles per thread) and bin reservation
+        // 2. exclusive scan of the counts (2 bins per thread) and reservation
         {
             const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
             const uint32_t v0 = t0i < nt ? tcnt[t0i] : 0u;
@@ -868,35 +894,35 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             if (t0i < nt) {
                 toff[t0i] = off;
                 tcnt[t0i] = off;
-                tres[t0i] = v0 ? atomicAdd(&a.bin_fill[(size_t)t0i * kFillStride], v0) : 0u;
+                tres[t0i] = v0 ? atomicAdd(&fill[(size_t)t0i * kFillStride], v0) : 0u;
             }
             if (t1i < nt) {
                 toff[t1i] = off + v0;
                 tcnt[t1i] = off + v0;
-                tres[t1i] = v1 ? atomicAdd(&a.bin_fill[(size_t)t1i * kFillStride], v1) : 0u;
+                tres[t1i] = v1 ? atomicAdd(&fill[(size_t)t1i * kFillStride], v1) : 0u;
             }
         }
         __syncthreads();
-        // 3. encode and stage sorted by tile
+        // 3. encode and stage sorted by bin
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage(S[j], lane, tcnt, stage);
+        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage<SHIFT>(S[j], lane, tcnt, stage);
         __syncthreads();
-        // 4. contiguous runs into the bins (one wave per tile)
+        // 4. contiguous runs into the bins (one wave per bin)
         for (uint32_t tt = wv; tt < nt; tt += kScatterWaves) {
             const uint32_t o0 = toff[tt];
             const uint32_t cnt = tcnt[tt] - o0;
             if (cnt == 0) continue;
             const uint32_t r0 = tres[tt];
-            uint32_t* dst = a.bins + (size_t)tt * cap;
+            uint32_t* dst = bins + (size_t)tt * cap;
             for (uint32_t e = lane; e < cnt; e += 64u) {
                 const uint32_t code = stage[o0 + e];
                 const uint32_t pos = r0 + e;
                 if (pos < cap) {
                     dst[pos] = code;
                 } else {
-                    const uint32_t tgt = (tt << kTileBits) | (code & (kTile - 1u));
-                    const uint32_t b = (code >> kTileBits) & 31u;
-                    const int32_t w = decode_weight(code >> 15, CODE8, cb_s, a.winh_q);
+                    const uint32_t tgt = (tt << SHIFT) | (code & ((1u << SHIFT) - 1u));
+                    const uint32_t b = (code >> SHIFT) & 31u;
+                    const int32_t w = decode_weight(code >> (SHIFT + 5u), CODE8, cb_s, a.winh_q);
                     const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
                     __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, w, __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_AGENT);
@@ -908,7 +934,120 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     }
     spill = wave_sum<unsigned long long>(spill);
     if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
-    write_history(a, boff, nb, n, t);
+    if (!TWO) write_history(a, boff, nb, n, t);
+}
+
+// Two-level binning, second pass: every super tile's bin (codes of 65536
+// targets) is cut into chunks of up to kStage events; a workgroup takes a
+// chunk, counts its events by tile (64 tiles per super tile), reserves room in
+// those tiles' bins, stages the events sorted by tile with the tile code
+// (target & 1023 | bucket << 10 | code << 15) and writes the runs.  Events
+// beyond a tile bin's capacity take the direct atomic path.
+constexpr uint32_t kSubPerThread = kStage / kScatterThreads;   // 28 codes per thread
+__global__ __launch_bounds__(kScatterThreads) void k_sub(StepArgs a, uint32_t k)
+{
+    constexpr uint32_t NSUB = 1u << (kSuperBits - kTileBits);   // tiles per super tile
+    __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t cpre[kMaxTiles + 1];   // chunks before each super tile
+    __shared__ uint32_t scnt[kMaxTiles];       // events held by each super tile's bin
+    __shared__ uint32_t tcnt[NSUB], toff[NSUB], tres[NSUB];
+    __shared__ int32_t cb_s[256];
+    __shared__ uint32_t wsum[kScatterWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t t = a.ctrl->t0 + k;
+    if (!step_binned(a, t)) return;
+    if (tid < 256u) cb_s[tid] = a.cb[tid];
+    const uint32_t ns = a.nsuper;   // <= kMaxTiles
+    {
+        const uint32_t i0 = 2u * tid, i1 = 2u * tid + 1u;
+        uint32_t f0 = i0 < ns ? a.sbin_fill[(size_t)i0 * kFillStride] : 0u;
+        uint32_t f1 = i1 < ns ? a.sbin_fill[(size_t)i1 * kFillStride] : 0u;
+        f0 = f0 < a.sbin_cap ? f0 : a.sbin_cap;
+        f1 = f1 < a.sbin_cap ? f1 : a.sbin_cap;
+        if (i0 < ns) scnt[i0] = f0;
+        if (i1 < ns) scnt[i1] = f1;
+        const uint32_t c0 = (f0 + kStage - 1u) / kStage, c1 = (f1 + kStage - 1u) / kStage;
+        const uint32_t sum = c0 + c1;
+        const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
+        if (lane == 63u) wsum[wv] = inc;
+        __syncthreads();
+        uint32_t off = inc - sum;
+        for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
+        if (i0 <= ns) cpre[i0] = off;
+        if (i1 <= ns) cpre[i1] = off + c0;
+        if (i1 + 1u == ns) cpre[ns] = off + sum;
+        __syncthreads();
+    }
+    const uint32_t total = cpre[ns];
+    unsigned long long spill = 0;
+    for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
+        uint32_t lo = 0, hi = ns;   // cpre[lo] <= c < cpre[hi]
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cpre[mid] <= c) lo = mid;
+            else hi = mid;
+        }
+        const uint32_t sup = lo;
+        const uint32_t e0 = (c - cpre[sup]) * kStage;
+        const uint32_t cnt = (scnt[sup] - e0) < kStage ? scnt[sup] - e0 : kStage;
+        const uint32_t* src = a.sbins + (size_t)sup * a.sbin_cap + e0;
+        uint32_t code[kSubPerThread];
+#pragma unroll
+        for (uint32_t i = 0; i < kSubPerThread; ++i) {
+            const uint32_t p = i * kScatterThreads + tid;
+            code[i] = p < cnt ? src[p] : 0xFFFFFFFFu;
+        }
+        if (tid < NSUB) tcnt[tid] = 0;
+        __syncthreads();
+#pragma unroll
+        for (uint32_t i = 0; i < kSubPerThread; ++i)
+            if (code[i] != 0xFFFFFFFFu) atomicAdd(&tcnt[(code[i] & 0xFFFFu) >> kTileBits], 1u);
+        __syncthreads();
+        if (wv == 0) {   // NSUB == 64: one wave scans and reserves
+            const uint32_t v = tcnt[lane];
+            const uint32_t inc = wave_incl_scan<uint32_t>(v, lane);
+            const uint32_t tile = sup * NSUB + lane;
+            toff[lane] = inc - v;
+            tcnt[lane] = inc - v;
+            tres[lane] = v ? atomicAdd(&a.bin_fill[(size_t)tile * kFillStride], v) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t i = 0; i < kSubPerThread; ++i) {
+            if (code[i] == 0xFFFFFFFFu) continue;
+            const uint32_t c16 = code[i] & 0xFFFFu;
+            const uint32_t p = atomicAdd(&tcnt[c16 >> kTileBits], 1u);
+            const uint32_t bucket = (code[i] >> kSuperBits) & 31u, wf = code[i] >> (kSuperBits + 5u);
+            stage[p] = (c16 & (kTile - 1u)) | (bucket << kTileBits) | (wf << 15);
+        }
+        __syncthreads();
+        const uint32_t cap = a.bin_cap_tile;
+        for (uint32_t st = wv; st < NSUB; st += kScatterWaves) {
+            const uint32_t o0 = toff[st];
+            const uint32_t m = tcnt[st] - o0;
+            if (m == 0) continue;
+            const uint32_t tile = sup * NSUB + st;
+            const uint32_t r0 = tres[st];
+            uint32_t* dst = a.bins + (size_t)tile * cap;
+            for (uint32_t e = lane; e < m; e += 64u) {
+                const uint32_t cd = stage[o0 + e];
+                const uint32_t pos = r0 + e;
+                if (pos < cap) {
+                    dst[pos] = cd;
+                } else {
+                    const uint32_t tgt = (tile << kTileBits) | (cd & (kTile - 1u));
+                    const uint32_t b = (cd >> kTileBits) & 31u;
+                    const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                    __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, decode_weight(cd >> 15, true, cb_s, 0),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    spill += 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    spill = wave_sum<unsigned long long>(spill);
+    if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,6 +1254,8 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
     const uint32_t t = a.ctrl->t0 + k;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->hist_n += a.ctrl->nspk;   // step t's history is complete
     if (step_binned(a, t)) {
+        for (uint32_t i = blockIdx.x * kTileThreads + threadIdx.x; i < a.nsuper; i += gridDim.x * kTileThreads)
+            a.sbin_fill[(size_t)i * kFillStride] = 0u;   // the second pass has consumed them
         for (uint32_t tt = blockIdx.x; tt < a.ntiles; tt += gridDim.x) {
             tile_work<CODE8, UPD, false>(a, tt, t, true, true, acc);
             __syncthreads();   // the LDS rows are reloaded for the next tile
@@ -1493,8 +1634,15 @@ hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint3
                           hipStream_t s, const LaunchEv* ev)
 {
     const uint32_t smax = max_len ? cdiv(max_len, 256) : 1u;
-    if (a.record == 1u) SNN_LAUNCH(ev, (k_scatter<true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
-    else SNN_LAUNCH(ev, (k_scatter<false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    if (a.nsuper) SNN_LAUNCH(ev, (k_scatter<true, true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    else if (a.record == 1u) SNN_LAUNCH(ev, (k_scatter<true, false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    else SNN_LAUNCH(ev, (k_scatter<false, false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    return hipGetLastError();
+}
+
+hipError_t launch_sub(const StepArgs& a, uint32_t k, uint32_t blocks, hipStream_t s, const LaunchEv* ev)
+{
+    SNN_LAUNCH(ev, k_sub, dim3(blocks), dim3(kScatterThreads), 0, s, a, k);
     return hipGetLastError();
 }
 

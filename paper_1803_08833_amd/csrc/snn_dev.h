@@ -25,6 +25,9 @@ constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for th
 // Bin fill counters sit one per 128-byte line: every scatter workgroup reserves
 // in every tile's bin each chunk, and counters sharing a line serialise there.
 constexpr uint32_t kFillStride = 32;
+// Two-level binning (networks whose update blocks exceed one LDS scan): first
+// by super tile of 2^kSuperBits targets, then by tile.
+constexpr uint32_t kSuperBits = 16;
 
 // Philox stream identifiers (third counter word).
 constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
@@ -86,6 +89,11 @@ struct StepArgs {
     uint32_t* bin_fill;       // [ntiles * kFillStride] events binned this step (one counter per line)
     uint32_t* bins;           // [ntiles][bin_cap_tile] event codes:
                               //   target & 1023 | bucket << 10 | weight field << 15
+    // two-level binning (nsuper > 0; 8-bit-code records only)
+    uint32_t nsuper;          // super tiles of 65536 targets
+    uint32_t sbin_cap;        // capacity of every super tile's bin (events)
+    uint32_t* sbin_fill;      // [nsuper * kFillStride]
+    uint32_t* sbins;          // [nsuper][sbin_cap] codes: target & 0xFFFF | bucket << 16 | code << 21
 };
 
 // One job of a batch: the job network's step arguments plus its schedule.
@@ -135,6 +143,7 @@ hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_
 hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
                           hipStream_t s,
                           const LaunchEv* ev = nullptr);
+hipError_t launch_sub(const StepArgs& a, uint32_t k, uint32_t blocks, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s,
                        const LaunchEv* ev = nullptr);
 hipError_t setup_kernels();

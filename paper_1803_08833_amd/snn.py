@@ -70,7 +70,7 @@ class KernelTimes(C.Structure):
     _fields_ = [
         ("update_ms", C.c_double), ("compact_ms", C.c_double), ("deliver_ms", C.c_double),
         ("scatter_ms", C.c_double), ("tile_ms", C.c_double), ("step_ms", C.c_double), ("steps", C.c_uint64), ("rec_events", C.c_uint64),
-        ("spikes", C.c_uint64),
+        ("spikes", C.c_uint64), ("sub_ms", C.c_double),
     ]
 
 

@@ -294,3 +294,57 @@ def test_reset_and_drive_change_reproduce_fresh_networks(snn):
         h.build_synapses()
         h.step(150)
         np.testing.assert_array_equal(changed, h.read_spikes())
+
+
+def test_two_level_lockstep_code8(snn, oracle_mod):
+    """Two-level binned delivery (super tiles, then tiles) of 8-bit-code
+    records, every step binned: ring and raster bit-exact against the oracle
+    in lock-step."""
+    net = W.workload("grid4_gauss", record=W.REC_CODE8, seed=12)["net"]
+    say("case: grid4_gauss CODE8, two-level binned delivery, lock-step 300 steps")
+    o = oracle_mod.Net(net).build()
+    with snn.Net(net) as g:
+        g.set_option(snn.OPT_DELIVER_MODE, 2)
+        g.build_synapses()
+        g.set_option(snn.OPT_BIN_THRESHOLD, 0)
+        assert g.stats()["deliver_mode"] == 2
+        for t in range(300):
+            o.step(1)
+            sp = o.spikes()
+            g.step_forced(sp[sp[:, 0] == t, 1])
+            if t % 25 == 0:
+                _compare_state(net, g.read_state(), o.state(), t)
+                np.testing.assert_array_equal(g.read_ring(), o.ring(), err_msg=f"ring at step {t}")
+        np.testing.assert_array_equal(g.read_ring(), o.ring())
+        np.testing.assert_array_equal(g.read_spikes(), o.spikes())
+        assert g.stats()["rec_events"] == o.stats()["rec_events"]
+
+
+def test_two_level_matches_direct_over_super_tiles(snn):
+    """A 12x12 grid (178,560 neurons: three super tiles, the last partial):
+    two-level binned delivery, fused and unfused, with ample and with tiny
+    bins (fallback), gives the direct schedule's ring and raster."""
+    net = W.make(12, 12, W.EXP, 4.0, 400, 21, record=W.REC_CODE8, ext_rate_hz=3.0)
+    say("case: 12x12 exp CODE8, two-level vs direct, 150 steps")
+    out = []
+    for pref, ppm, chunk in ((0, 500000, 64), (2, 500000, 64), (2, 500000, 0), (2, 2000, 16)):
+        with snn.Net(net) as g:
+            g.set_option(snn.OPT_DELIVER_MODE, pref)
+            g.set_option(snn.OPT_BIN_FRAC_PPM, ppm)
+            g.build_synapses()
+            assert g.stats()["deliver_mode"] == pref
+            if pref:
+                g.set_option(snn.OPT_BIN_THRESHOLD, 0)
+            g.set_option(snn.OPT_GRAPH_CHUNK, chunk)
+            g.step(150)
+            out.append((g.read_ring(), g.read_spikes(), g.stats()))
+    for r, s, st in out[1:]:
+        np.testing.assert_array_equal(r, out[0][0])
+        np.testing.assert_array_equal(s, out[0][1])
+        assert st["rec_events"] == out[0][2]["rec_events"]
+    sp = out[0][1]
+    assert len(sp) > 1000
+    per_step = np.bincount(sp[:, 0].astype(np.int64), minlength=150)
+    say("max spikes per step:", int(per_step.max()), "overflow events:", out[3][2]["bin_overflow"])
+    if per_step.max() * 300 > 3 * 65536:   # some step overfilled a super tile's 65,536-event bin
+        assert out[3][2]["bin_overflow"] > 0
