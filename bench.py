@@ -209,6 +209,10 @@ def main():
         # + the next step's neuron update)
         name = "k_scatter+k_tile (one 1 ms step: compaction, delivery, fused neuron update)"
         ms = kt["scatter_ms"] + kt["tile_ms"]
+    elif stf["deliver_mode"] == 2:
+        name = ("k_compact+k_scatter+k_sub+k_tile (one 1 ms step: compaction, two-level binned "
+                "delivery, fused neuron update)")
+        ms = kt["compact_ms"] + kt["scatter_ms"] + kt["sub_ms"] + kt["tile_ms"]
     else:
         name = "k_update+k_compact+k_deliver (one 1 ms step, direct atomics)"
         ms = kt["update_ms"] + kt["compact_ms"] + kt["deliver_ms"]
@@ -246,7 +250,8 @@ def main():
         "mean_rate_hz": rate_hz,
         "build_s": build_s,
         "kernels_avg_ms": {"k_update": round(kt["update_ms"], 6), "k_compact": round(kt["compact_ms"], 6),
-                           "k_scatter": round(kt["scatter_ms"], 6), "k_tile": round(kt["tile_ms"], 6),
+                           "k_scatter": round(kt["scatter_ms"], 6), "k_sub": round(kt["sub_ms"], 6),
+                           "k_tile": round(kt["tile_ms"], 6),
                            "deliver": round(kt["deliver_ms"], 6), "kernels_per_step": round(kt["step_ms"], 6)},
         "deliver_mode": stf["deliver_mode"],
         "bin_overflow_events": stf["bin_overflow"],

@@ -12,6 +12,7 @@
 * Closed-form interspike intervals under constant drive; free-running
   population rate within 2 % of the oracle's.
 """
+import os
 import sys
 
 import numpy as np
@@ -348,3 +349,52 @@ def test_two_level_matches_direct_over_super_tiles(snn):
     say("max spikes per step:", int(per_step.max()), "overflow events:", out[3][2]["bin_overflow"])
     if per_step.max() * 300 > 3 * 65536:   # some step overfilled a super tile's 65,536-event bin
         assert out[3][2]["bin_overflow"] > 0
+
+
+@pytest.mark.skipif(os.environ.get("SNN_FULL_SCALE") != "1",
+                    reason="full-scale 96x96 run (about 190 GB of HBM, 2-3 minutes): set SNN_FULL_SCALE=1")
+def test_full_scale_96x96_code8(snn, oracle_mod):
+    """The 96x96 exponential grid with 8-bit codes (11.4 M neurons, 29.7 G
+    synapses) at full size, in the configuration bench.py times (two-level
+    binned delivery): sampled rows bit-exact, step 0 (about 3 % of the neurons
+    fire from their initial state and drive) with every neuron's state and the
+    charge queued for sampled targets against the oracle."""
+    wl = W.workload("grid96_exp_code8")
+    net = wl["net"]
+    say("case: grid96_exp_code8 full-size build (about two minutes)")
+    o = oracle_mod.Net(net)
+    V0, _, _ = o.state()
+    o.step(1)
+    Vo, Wo, Ro = o.state()
+    s0 = o.spikes()[:, 1]
+    with snn.Net(net) as g:
+        g.build_synapses()
+        st = g.stats()
+        say("built:", st["nnz"], "synapses, mode", st["deliver_mode"])
+        assert st["deliver_mode"] == 2
+        assert abs(st["nnz"] / g.N - net["k_in"]) < 1.0
+        rng = np.random.default_rng(6)
+        rows = sorted(set([0, 1, 991, 992, g.N - 1] + [int(x) for x in rng.integers(0, g.N, 12)]))
+        for r in rows:
+            rl, be, rc = g.export_rows(r, 1)
+            orl, obe, orc = oracle_mod.build_rows(net, r, 1)
+            np.testing.assert_array_equal(rl, orl)
+            np.testing.assert_array_equal(be, obe)
+            np.testing.assert_array_equal(rc, orc)
+        say("sampled rows bit-exact")
+        g.step(1)
+        gsp = g.read_spikes()[:, 1]
+        diff = np.setxor1d(gsp, s0)
+        assert diff.size <= 8
+        ok = np.setdiff1d(np.arange(g.N), diff)
+        Vg, Wg, Rg = g.read_state()
+        _compare_state(net, (Vg[ok], Wg[ok], Rg[ok]), (Vo[ok], Wo[ok], Ro[ok]), 0)
+        assert g.stats()["ext_events"] == o.stats()["ext_events"]
+        assert g.stats()["bin_overflow"] == 0
+        ring = g.read_ring()
+        pres = np.sort(gsp).astype(np.uint32)
+        say("step 0:", pres.size, "spikes; checking queued charge of sampled targets")
+        for j in rng.integers(0, g.N, 12):
+            want = oracle_mod.col_input(net, int(j), pres)
+            got = ring[net["d_min"]:net["d_max"] + 1, j].astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
