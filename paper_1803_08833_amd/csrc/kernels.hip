@@ -678,13 +678,30 @@ __device__ __forceinline__ void seg_load(const StepArgs& a, uint4 info, uint32_t
         uint32_t kk = L.s0 + 64u * u + lane;
         kk = kk < L.len ? kk : L.len - 1u;
         if (CODE8) {
-            const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
+            L.tg[u] = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];   // raw: decoded by seg_decode
+        } else {
+            const uint2 r = reinterpret_cast<const uint2*>(a.recs)[rb + kk];  // {target, weight bits}
+            L.tg[u] = r.x;
+            L.wf[u] = r.y;
+        }
+    }
+}
+
+// The loaded records as (target, weight field): kept raw until here so that
+// the loads of a chunk can stay in flight while the previous chunk's runs are
+// written.
+template <bool CODE8>
+__device__ __forceinline__ void seg_decode(const StepArgs& a, SegLoad& L)
+{
+    if (L.s0 >= L.len) return;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        if (CODE8) {
+            const uint32_t v = L.tg[u];
             L.tg[u] = v >> 8;
             L.wf[u] = v & 255u;
         } else {
-            const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
-            L.tg[u] = r.tgt;
-            const int32_t wq = __float2int_rn(r.w * 65536.0f);
+            const int32_t wq = __float2int_rn(__uint_as_float(L.wf[u]) * 65536.0f);
             L.wf[u] = wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536);
         }
     }
@@ -859,22 +876,29 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
     per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
     unsigned long long spill = 0;
-    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += gridDim.x * per) {
-        const uint32_t c1 = (items - c0) < per ? items : c0 + per;
-        for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
-        // this wave's row segments: items c0 + wv + 16 j; all loads issued before use
+    // this wave's row segments of chunk [c0, c1): items c0 + wv + 16 j, all
+    // loads issued before use; the next chunk's segments are loaded while the
+    // current chunk's runs are written (phase 4)
+    SegLoad S[kSegPerWave];
+    auto load_chunk = [&](uint32_t c0, uint32_t c1) {
         uint4 info[kSegPerWave];
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
             info[j] = it < c1 ? spike(it / smax) : make_uint4(0, 0, 0, 0);
         }
-        SegLoad S[kSegPerWave];
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
             seg_load<CODE8>(a, info[j], it < c1 ? it % smax : 0u, lane, S[j]);
         }
+    };
+    auto chunk_end = [&](uint32_t c0) { return (items - c0) < per ? items : c0 + per; };
+    if (blockIdx.x * per < items) load_chunk(blockIdx.x * per, chunk_end(blockIdx.x * per));
+    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += gridDim.x * per) {
+        for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_decode<CODE8>(a, S[j]);
         __syncthreads();
         // 1. histogram of targets by bin
 #pragma unroll
@@ -907,6 +931,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage<SHIFT>(S[j], lane, tcnt, stage);
         __syncthreads();
+        {
+            const uint32_t n0 = c0 + gridDim.x * per;
+            if (n0 < items) load_chunk(n0, chunk_end(n0));
+        }
         // 4. contiguous runs into the bins (one wave per bin)
         for (uint32_t tt = wv; tt < nt; tt += kScatterWaves) {
             const uint32_t o0 = toff[tt];
@@ -1408,6 +1436,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
                 const StepArgs& a = jobs[j].a;
                 const uint32_t local = it - ibase[j];
                 seg_load<false>(a, a.spk[local / jobs[j].smax], local % jobs[j].smax, lane, S[jj]);
+                seg_decode<false>(a, S[jj]);
             }
         }
         __syncthreads();
