@@ -43,6 +43,23 @@ def mix(n, seed=9):
     return jobs
 
 
+def mixed_schedules(n, seed=13):
+    """Jobs the batched kernels treat differently: F32 records (binned),
+    8-bit codes and more than 20 delay buckets (both delivered directly)."""
+    r = np.random.default_rng(seed)
+    jobs = []
+    for i in range(n):
+        g = int(r.choice([1, 2, 3]))
+        over = dict(ext_rate_hz=float(r.uniform(2.0, 3.0)))
+        if i % 3 == 1:
+            over["record"] = W.REC_CODE8
+        elif i % 3 == 2:
+            over["d_max"] = 28
+        jobs.append(dict(net=W.make(g, g, W.EXP, float(r.uniform(2.0, 5.0)), 500, 700 + i, **over),
+                         steps=int(r.integers(80, 300))))
+    return jobs
+
+
 def alone(snn, job):
     with snn.Net(job["net"], hist_cap=1 << 22) as g:
         g.build_synapses()
@@ -124,3 +141,25 @@ def test_serving_loop_matches_plain(snn):
     np.testing.assert_array_equal(rb["events"], rp["events"])
     say("batched", serve.summary(rb, jobs))
     say("plain", serve.summary(rp, jobs))
+
+
+def test_batch_mixes_binned_and_direct_jobs(snn):
+    """Binned F32 jobs, 8-bit-code jobs and jobs with 28 delay buckets (direct
+    delivery in the batch) share the batch: every raster equals the job run
+    alone."""
+    jobs = mixed_schedules(9)
+    say("case: 9 jobs mixing binned and direct batch schedules")
+    ref = [alone(snn, j) for j in jobs]
+    got = {}
+    with snn.Batch(16 << 30, 1 << 20) as b:
+        slots = {b.admit(j["net"], j["steps"]): i for i, j in enumerate(jobs)}
+        assert None not in slots
+        while len(got) < len(jobs):
+            b.step(41)
+            for s in b.poll():
+                i = slots[s]
+                assert b.job_stats(s)["rec_events"] == ref[i][1]["rec_events"]
+                got[i] = b.read_spikes(s)
+    for i, (r, _) in enumerate(ref):
+        assert len(r) > 0
+        np.testing.assert_array_equal(got[i], r, err_msg=f"job {i}")

@@ -1,0 +1,44 @@
+"""Host-side pieces of the serving benchmark: the seeded job stream, the
+arrival process and the latency summary (no GPU)."""
+import numpy as np
+
+from paper_1803_08833_amd import serve
+from paper_1803_08833_amd import workloads as W
+
+
+def test_serving_stream_composition():
+    jobs = W.serving_stream(512, seed=4)
+    assert len(jobs) == 512
+    kinds = [j["net"]["kernel"] for j in jobs]
+    assert kinds.count(W.GAUSS) == 256 and kinds.count(W.EXP) == 256
+    grids = {(j["net"]["gx"], j["net"]["gy"]) for j in jobs}
+    assert grids <= {(g, g) for g in (2, 4, 8, 12, 16)} and len(grids) == 5
+    for j in jobs:
+        assert 500 <= j["steps"] <= 5000
+        lo, hi = (1.0, 2.0) if j["net"]["kernel"] == W.GAUSS else (2.0, 6.0)
+        assert lo <= j["net"]["range"] <= hi
+    seeds = [j["net"]["seed"] for j in jobs]
+    assert seeds == list(range(1_000_000, 1_000_512))
+    # same seed, same stream; different seed, different order
+    assert W.serving_stream(512, seed=4) == jobs
+    assert [j["net"]["kernel"] for j in W.serving_stream(512, seed=5)] != kinds
+
+
+def test_poisson_arrivals_rate_and_order():
+    a = serve.poisson_arrivals(20000, rate_per_s=8.0, seed=3)
+    assert np.all(np.diff(a) > 0)
+    gaps = np.diff(np.concatenate([[0.0], a]))
+    assert abs(gaps.mean() - 1 / 8.0) < 0.01 * (1 / 8.0) * 3
+    # exponential gaps: coefficient of variation ~ 1
+    assert abs(gaps.std() / gaps.mean() - 1.0) < 0.05
+
+
+def test_summary_percentiles_and_rates():
+    jobs = [dict(net={}, steps=1000), dict(net={}, steps=3000)]
+    res = serve.Result(latency=np.array([0.5, 1.5]), events=np.array([10, 30]), wall=2.0)
+    s = serve.summary(res, jobs)
+    assert s["jobs"] == 2 and s["jobs_per_s"] == 1.0
+    assert s["p50_s"] == 1.0
+    assert abs(s["p99_s"] - (0.5 + 0.99 * 1.0)) < 1e-12
+    assert s["events_per_s"] == 20.0
+    assert s["sim_s_per_wall_s"] == 2.0
