@@ -239,20 +239,20 @@ void snn_destroy(snn_net* net);
  * launch per phase for all jobs together (multi-job kernels over a device job
  * table, replayed as HIP graphs), so many small networks share the GPU.  Each
  * job is an ordinary network (same definitions, same results as stepping it
- * alone).  Jobs are built by the batch's construction thread on its own
- * stream, so construction overlaps with the steps of the jobs already
+ * alone).  Jobs are built by the batch's two construction threads, each on
+ * its own stream, so construction overlaps with the steps of the jobs already
  * running; a job joins the table at the first snn_batch_step after its build
  * has finished and stops at its own duration.  Jobs with F32 records,
  * d_min = 1 and at most 20 delay buckets use the binned delivery (per step,
  * above the same event threshold as a single network); the others direct
  * delivery.  The calls are meant for one controlling thread; the batch's own
- * construction thread is synchronised internally. */
+ * construction threads are synchronised internally. */
 typedef struct snn_batch snn_batch;
 
 /* hbm_budget: device bytes the batch may hold for its jobs (admission
  * control); max_neurons: total neurons of jobs admitted at once (sizes the
  * update grid); hip_stream: stepping stream (NULL = own stream).  Starts the
- * construction thread. */
+ * construction threads. */
 snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip_stream, snn_batch** out);
 
 /* Admit a job of dur_ms steps: checks the footprint estimate (including a
@@ -275,7 +275,7 @@ snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms);
 snn_status snn_batch_poll(snn_batch* b, int32_t* done_slots, size_t cap, size_t* n_out);
 
 /* Copy a finished job's whole spike history, ordered by (t_ms, gid), then
- * free its slot; its device memory is released by the construction thread
+ * free its slot; its device memory is released by a construction thread
  * once the stepping stream has passed the job's removal from the table.
  * SNN_E_STATE if the job has not finished; SNN_E_TRUNC (slot kept) if cap is
  * too small, *n_out = count needed. */
@@ -289,7 +289,7 @@ snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out);
  * (building, running or finished and unread). */
 snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs);
 
-/* Stops the construction thread (pending builds are dropped), waits for the
+/* Stops the construction threads (pending builds are dropped), waits for the
  * stepping stream and frees every job. */
 void snn_batch_destroy(snn_batch* b);
 const char* snn_batch_last_error(const snn_batch* b);

@@ -13,6 +13,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -891,7 +892,8 @@ void snn_destroy(snn_net* n)
 struct snn_batch {
     hipStream_t stream = nullptr;
     bool own_stream = false;
-    hipStream_t build_stream = nullptr;
+    static constexpr int kBuilders = 2;   // construction threads, each with its own stream
+    hipStream_t build_stream[kBuilders] = {};
     uint64_t budget = 0, used = 0;        // used: held or reserved by admitted jobs
     uint32_t blk_cap = 0, blk_used = 0;   // blk_used: blocks of the jobs in the device table
     uint32_t blk_reserved = 0;            // blocks of every admitted job (building included)
@@ -917,9 +919,9 @@ struct snn_batch {
     std::map<std::pair<uint32_t, uint32_t>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     std::string err;
     bool poisoned = false;
-    // Construction worker: builds admitted jobs on build_stream while the
-    // caller keeps stepping, and frees retired jobs once the stepping stream
-    // has passed the table update that removed them.
+    // Construction threads: build admitted jobs, two at a time, each on its
+    // own stream, while the caller keeps stepping, and free retired jobs once
+    // the stepping stream has passed the table update that removed them.
     struct BuildReq {
         int slot;
         snn_grid_desc g;
@@ -931,11 +933,15 @@ struct snn_batch {
     };
     std::mutex mu;
     std::condition_variable cv;        // worker: work to do; caller: a build finished
+    // Graph capture on the stepping stream excludes the construction threads'
+    // runtime calls (allocation, frees that synchronise the device, memsets),
+    // which would invalidate a capture in progress; builds share the lock.
+    std::shared_mutex capture_mu;
     std::deque<BuildReq> todo;
     std::vector<std::pair<int, snn_net*>> built;   // finished builds, activated at the next step
     std::deque<Retired> retired;
     bool stop = false;
-    std::thread worker;
+    std::thread workers[kBuilders];
 };
 
 namespace {
@@ -1037,7 +1043,7 @@ hipError_t batch_activate(snn_batch* b)
     return batch_upload(b);
 }
 
-void batch_worker(snn_batch* b)
+void batch_worker(snn_batch* b, int w)
 {
     std::unique_lock<std::mutex> lk(b->mu);
     for (;;) {
@@ -1047,8 +1053,11 @@ void batch_worker(snn_batch* b)
             b->retired.pop_front();
             lk.unlock();
             (void)hipEventSynchronize(r.after);   // no kernel still reads the job's descriptor
-            (void)hipEventDestroy(r.after);
-            snn_destroy(r.net);
+            {
+                std::shared_lock<std::shared_mutex> cap(b->capture_mu);
+                (void)hipEventDestroy(r.after);
+                snn_destroy(r.net);
+            }
             lk.lock();
             continue;
         }
@@ -1058,16 +1067,20 @@ void batch_worker(snn_batch* b)
         lk.unlock();
         snn_net* n = nullptr;
         std::string msg;
-        snn_status st = snn_build_grid(&q.g, b->build_stream, &n);
-        if (st) {
-            msg = snn_last_error(nullptr);
-        } else {
-            if (!batch_binnable(q.s)) snn_set_option(n, SNN_OPT_DELIVER_MODE, 0);   // no bins to allocate
-            st = snn_build_synapses(n, &q.s);
+        snn_status st;
+        {
+            std::shared_lock<std::shared_mutex> cap(b->capture_mu);
+            st = snn_build_grid(&q.g, b->build_stream[w], &n);
             if (st) {
-                msg = snn_last_error(n);
-                snn_destroy(n);
-                n = nullptr;
+                msg = snn_last_error(nullptr);
+            } else {
+                if (!batch_binnable(q.s)) snn_set_option(n, SNN_OPT_DELIVER_MODE, 0);   // no bins to allocate
+                st = snn_build_synapses(n, &q.s);
+                if (st) {
+                    msg = snn_last_error(n);
+                    snn_destroy(n);
+                    n = nullptr;
+                }
             }
         }
         lk.lock();
@@ -1102,6 +1115,7 @@ hipError_t batch_graph(snn_batch* b, uint32_t chunk, hipGraphExec_t* out)
     }
     hipGraph_t gr = nullptr;
     hipGraphExec_t ex = nullptr;
+    std::unique_lock<std::shared_mutex> cap(b->capture_mu);   // no construction call during the capture
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return e;
     hipError_t le = hipSuccess;
@@ -1164,7 +1178,8 @@ snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip
         e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
         b->own_stream = e == hipSuccess;
     }
-    if (e == hipSuccess) e = hipStreamCreateWithFlags(&b->build_stream, hipStreamNonBlocking);
+    for (int w = 0; w < snn_batch::kBuilders && e == hipSuccess; ++w)
+        e = hipStreamCreateWithFlags(&b->build_stream[w], hipStreamNonBlocking);
     if (e == hipSuccess) e = snn::setup_kernels();
     if (e == hipSuccess) e = hipMalloc((void**)&b->d_jobs, sizeof(snn::JobDesc) * snn::kMaxJobs);
     for (int i = 0; i < snn_batch::kTables && e == hipSuccess; ++i) {
@@ -1179,7 +1194,7 @@ snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip
         snn_batch_destroy(b);
         return bfail(nullptr, SNN_E_HIP, std::string("batch creation failed: ") + hipGetErrorString(e));
     }
-    b->worker = std::thread(batch_worker, b);
+    for (int w = 0; w < snn_batch::kBuilders; ++w) b->workers[w] = std::thread(batch_worker, b, w);
     *out = b;
     return SNN_OK;
 }
@@ -1368,15 +1383,14 @@ snn_status snn_batch_usage(snn_batch* b, uint64_t* bytes, uint32_t* jobs)
 void snn_batch_destroy(snn_batch* b)
 {
     if (!b) return;
-    if (b->worker.joinable()) {
-        {
-            std::lock_guard<std::mutex> lk(b->mu);
-            b->stop = true;
-            b->todo.clear();
-        }
-        b->cv.notify_all();
-        b->worker.join();   // finishes the build in progress and every pending free
+    {
+        std::lock_guard<std::mutex> lk(b->mu);
+        b->stop = true;
+        b->todo.clear();
     }
+    b->cv.notify_all();
+    for (auto& w : b->workers)
+        if (w.joinable()) w.join();   // each finishes its build in progress; pending frees are drained
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     batch_drop_graphs(b);
     for (auto& kv : b->built)
@@ -1392,7 +1406,8 @@ void snn_batch_destroy(snn_batch* b)
         if (b->h_jobs[i]) (void)hipHostFree(b->h_jobs[i]);
         if (b->h_done[i]) (void)hipEventDestroy(b->h_done[i]);
     }
-    if (b->build_stream) (void)hipStreamDestroy(b->build_stream);
+    for (auto& bs : b->build_stream)
+        if (bs) (void)hipStreamDestroy(bs);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }

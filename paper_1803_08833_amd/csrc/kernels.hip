@@ -17,6 +17,8 @@
 
 #include <hip/hip_ext.h>
 
+#include <mutex>
+
 namespace snn {
 
 // ---------------------------------------------------------------------------
@@ -1092,11 +1094,14 @@ constexpr uint32_t kTileThreads = 1024;
 // the block's spike, external and recurrent event counts are accumulated
 // (including the step's event total used by the delivery switch).
 template <uint32_t NW>
+// The block's NW waves are threads [0, 64 NW) of a thread group (gtid = index
+// in the group, as in block_compact); a group without a block passes
+// live = false and takes part in the barriers only.
 __device__ __forceinline__ void block_append(const StepArgs& a, uint32_t t, uint32_t q, uint32_t flags,
-                                             uint32_t ext_tot, uint32_t* wtot, unsigned long long* wext,
-                                             unsigned long long* wev, uint32_t* sbase)
+                                             uint32_t ext_tot, uint32_t gtid, bool live, uint32_t* wtot,
+                                             unsigned long long* wext, unsigned long long* wev, uint32_t* sbase)
 {
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = gtid, lane = tid & 63u, wv = tid >> 6;
     const uint64_t m0 = __ballot(flags & 1u), m1 = __ballot(flags & 2u);
     const uint64_t m2 = __ballot(flags & 4u), m3 = __ballot(flags & 8u);
     const uint32_t pre = mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
@@ -1114,7 +1119,7 @@ __device__ __forceinline__ void block_append(const StepArgs& a, uint32_t t, uint
         btot += wtot[i];
         bext += wext[i];
     }
-    if (tid == 0) {
+    if (tid == 0 && live) {
         *sbase = btot ? atomicAdd(&a.ctrl->nspk_par[t & 1u], btot) : 0u;
         if (bext) atomicAdd((unsigned long long*)&a.ctrl->ext_events, bext);
         if (btot) atomicAdd((unsigned long long*)&a.ctrl->spikes, (unsigned long long)btot);
@@ -1139,7 +1144,7 @@ __device__ __forceinline__ void block_append(const StepArgs& a, uint32_t t, uint
     ev = wave_sum<unsigned long long>(ev);
     if (lane == 0) wev[wv] = ev;
     __syncthreads();
-    if (tid == 0) {
+    if (tid == 0 && live) {
         unsigned long long be = 0;
         for (uint32_t i = 0; i < NW; ++i) be += wev[i];
         if (be) {
@@ -1234,7 +1239,7 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
         __syncthreads();   // every thread is past its use of the Poisson table
         constexpr uint32_t NW = kTileThreads / 64;
         if (APPEND)
-            block_append<NW>(a, t + 1u, q, flags, ext_tot, scratch + 64,
+            block_append<NW>(a, t + 1u, q, flags, ext_tot, threadIdx.x, true, scratch + 64,
                              reinterpret_cast<unsigned long long*>(scratch + 96),
                              reinterpret_cast<unsigned long long*>(scratch + 128), scratch + 160);
         else
@@ -1334,7 +1339,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const JobDesc* __restrict_
         *rp = make_int4(0, 0, 0, 0);
         flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
     }
-    block_append<4>(a, t, q, flags, ext_tot, wtot, wext, wev, &sbase);
+    block_append<4>(a, t, q, flags, ext_tot, threadIdx.x, true, wtot, wext, wev, &sbase);
 }
 
 // Batched phase A: the concatenated row segments of all jobs are cut into
@@ -1541,20 +1546,61 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
     }
 }
 
-// Batched phase B (+ fused update of the next step): workgroup b owns tile
-// b - tile_base of the job whose tile range contains b.
+// Batched phase B (+ fused update of the next step) over the batch's blocks
+// [0, nb_total) (block b belongs to the job whose block range holds it), with
+// as many workgroups as are resident at once.  First the tiles of the jobs
+// binned this step, one per workgroup pass (accumulation, write-back and the
+// next step's update); then the next step's update of every other running
+// job, four blocks per pass (one per group of four waves, no LDS rows needed).
 template <bool UPD>
-__global__ __launch_bounds__(kTileThreads) void k_btile(const JobDesc* __restrict__ jobs, uint32_t k)
+__global__ __launch_bounds__(kTileThreads) void k_btile(const JobDesc* __restrict__ jobs, uint32_t k,
+                                                         uint32_t nb_total)
 {
     extern __shared__ int32_t acc[];
-    const int j = job_of_block(jobs, blockIdx.x);
-    if (j < 0) return;
-    const JobDesc& J = jobs[j];
-    const StepArgs& a = J.a;
-    const uint32_t t = a.ctrl->t0 + k;
-    if (t >= J.t_end) return;
-    const bool binned = J.binned && a.ctrl->step_ev[t & 1u] >= a.bin_threshold;
-    tile_work<false, UPD, true>(a, blockIdx.x - J.blk_base, t, binned, t + 1u < J.t_end, acc);
+    auto binned_now = [&](const JobDesc& J, uint32_t t) {
+        return J.binned && J.a.ctrl->step_ev[t & 1u] >= J.a.bin_threshold;
+    };
+    for (uint32_t b = blockIdx.x; b < nb_total; b += gridDim.x) {
+        const int j = job_of_block(jobs, b);
+        if (j < 0) continue;
+        const JobDesc& J = jobs[j];
+        const uint32_t t = J.a.ctrl->t0 + k;
+        if (t >= J.t_end || !binned_now(J, t)) continue;
+        tile_work<false, UPD, true>(J.a, b - J.blk_base, t, true, t + 1u < J.t_end, acc);
+        __syncthreads();   // the LDS rows are reloaded for the next tile
+    }
+    if (!UPD) return;
+    uint32_t* scr = reinterpret_cast<uint32_t*>(acc);
+    const uint32_t tid = threadIdx.x, g = tid >> 8, gtid = tid & 255u;
+    uint32_t* pois = scr + 64u * g;          // the group's job's Poisson table
+    uint32_t* gs = scr + 256u + 32u * g;     // wtot[4], sbase, wext[4] (u64), wev[4] (u64)
+    for (uint32_t base = 4u * blockIdx.x; base < nb_total; base += 4u * gridDim.x) {
+        const uint32_t b = base + g;
+        const int j = b < nb_total ? job_of_block(jobs, b) : -1;
+        bool live = false;
+        uint32_t t = 0;
+        if (j >= 0) {
+            const JobDesc& J = jobs[j];
+            t = J.a.ctrl->t0 + k;
+            live = t + 1u < J.t_end && !binned_now(J, t);
+        }
+        const StepArgs& a = jobs[j >= 0 ? j : 0].a;   // read only when live
+        if (live && gtid < a.npois) pois[gtid] = a.poisc[gtid];
+        __syncthreads();
+        uint32_t q = 0, flags = 0, ext_tot = 0, dis = 0;
+        if (live) {
+            q = (b - jobs[j].blk_base) * 256u + gtid;
+            if (q < a.nq) {
+                int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)((t + 1u) & (kRing - 1u)) * a.N) + q;
+                const int4 in = *rp;
+                *rp = make_int4(0, 0, 0, 0);
+                flags = update_quad(a, pois, q, t + 1u, in, ext_tot, dis);
+            }
+        }
+        block_append<4>(a, t + 1u, q, flags, ext_tot, gtid, live, gs, reinterpret_cast<unsigned long long*>(gs + 8),
+                        reinterpret_cast<unsigned long long*>(gs + 16), gs + 4);
+        __syncthreads();   // scratch reused by the next pass
+    }
 }
 
 __global__ void k_batch_advance(const JobDesc* __restrict__ jobs, uint32_t n)
@@ -1675,7 +1721,7 @@ hipError_t launch_sub(const StepArgs& a, uint32_t k, uint32_t blocks, hipStream_
     return hipGetLastError();
 }
 
-hipError_t setup_kernels()
+static hipError_t setup_kernels_once()
 {
     int dev = 0, cus = 0;
     hipError_t ce = hipGetDevice(&dev);
@@ -1692,6 +1738,15 @@ hipError_t setup_kernels()
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+// Once per process (several construction threads may ask at the same time).
+hipError_t setup_kernels()
+{
+    static std::once_flag once;
+    static hipError_t result = hipSuccess;
+    std::call_once(once, [] { result = setup_kernels_once(); });
+    return result;
 }
 
 hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s, const LaunchEv* ev)
@@ -1726,8 +1781,9 @@ hipError_t launch_batch_scatter(const JobDesc* jobs, uint32_t blocks, uint32_t k
 hipError_t launch_batch_tile(const JobDesc* jobs, uint32_t blocks, uint32_t k, bool update_next, hipStream_t s)
 {
     const size_t lds = (size_t)kBatchMaxD * kTile * sizeof(int32_t);
-    if (update_next) hipLaunchKernelGGL((k_btile<true>), dim3(blocks), dim3(kTileThreads), lds, s, jobs, k);
-    else hipLaunchKernelGGL((k_btile<false>), dim3(blocks), dim3(kTileThreads), lds, s, jobs, k);
+    const uint32_t grid = blocks < 2u * g_cus ? blocks : 2u * g_cus;   // resident workgroups
+    if (update_next) hipLaunchKernelGGL((k_btile<true>), dim3(grid), dim3(kTileThreads), lds, s, jobs, k, blocks);
+    else hipLaunchKernelGGL((k_btile<false>), dim3(grid), dim3(kTileThreads), lds, s, jobs, k, blocks);
     return hipGetLastError();
 }
 
