@@ -147,8 +147,8 @@ def cpu_baseline(net, spikes_per_step, seconds_budget=12.0):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; multi-GPU scaling is not "
-                                   "implemented (see the sharding design note)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "bench.py runs on exactly one GPU: the simulator has no multi-GPU "
+                                   "path (a network runs on one device)", "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 

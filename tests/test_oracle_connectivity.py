@@ -97,7 +97,8 @@ def test_offset_histogram_follows_law(c0):
     assert np.abs(z).max() < 5
     chi2 = (((counts - exp_counts) ** 2) / exp_counts).sum()
     assert stats.chi2.sf(chi2, gx * gy - 1) > 1e-4
-    # mean target distance (survey: 1.06 module spacings for this workload)
+    # mean target distance (1.06 module spacings for this workload, summed by
+    # hand over the law's offsets)
     dist = np.sqrt(r2[dyr, dxr].astype(np.float64))
     assert dist.mean() == pytest.approx(1.06, abs=0.02)
 

@@ -48,7 +48,7 @@ def test_isi_without_adaptation(oracle_mod, J, want):
     Jq = round(J * 65536) / 65536
     isi, margin = _closed_form_isi(Jq, net["tau_m"], net["tau_w"], net["v_reset"], net["v_th"], 0, 0)
     assert margin > 1e-9
-    assert isi == want  # values derived independently in the survey
+    assert isi == want  # values worked out by hand from the closed form
     for g in range(8):
         t, d = _isis(sp, g)
         assert len(d) >= 5
@@ -93,9 +93,9 @@ def test_isi_with_adaptation(oracle_mod, J):
     assert np.all(w[4:] == 0.0)
 
 
-def test_adaptation_survey_sequences(oracle_mod):
-    # derived independently in the survey: J = 1.2 mV, alpha = 0.2 mV: first
-    # intervals 16, 16, 17, 17; J = 2 mV settles at 9; J = 3 mV at 5
+def test_adaptation_interval_sequences(oracle_mod):
+    # worked out by hand from the one-step map: J = 1.2 mV, alpha = 0.2 mV:
+    # first intervals 16, 16, 17, 17; J = 2 mV settles at 9; J = 3 mV at 5
     for J, head, tail in ((1.2, [16, 16, 17, 17], None), (2.0, None, 9), (3.0, None, 5)):
         net = _net(J, alpha=0.2)
         o = oracle_mod.Net(net).build()

@@ -2,8 +2,9 @@
 
 * Connection thresholds: normalisation (expected in-degree equals k_in), the
   two limits with a textbook answer (uniform law, purely local law), torus
-  symmetry and monotone decrease with distance, and the prefactors the survey
-  derived independently for the five workloads.
+  symmetry and monotone decrease with distance, and the prefactors of the
+  workloads computed by hand from the lateral laws, independently of the
+  oracle's code.
 * Weight table and codebook: conditional means of normal bins against
   scipy.stats.truncnorm.
 * Poisson CDF thresholds against scipy.stats.poisson.
@@ -49,8 +50,8 @@ def test_threshold_normalisation(oracle_mod, name):
     assert abs(expected_k - net["k_in"]) <= n.sum() * 0.5 / 2**32 + 1e-9
 
 
-# Prefactors B derived independently (survey appendix) from the lateral laws on
-# the torus with n(0) = module size - 1.
+# Prefactors B computed by hand from the lateral laws on the torus with
+# n(0) = module size - 1 (independently of the oracle's code).
 @pytest.mark.parametrize("name,B", [("grid4_gauss", 0.160876), ("grid24_gauss", 0.0627528),
                                     ("grid24_exp", 0.0075768), ("grid96_exp_code8", 0.00527054)])
 def test_threshold_prefactor(oracle_mod, name, B):
