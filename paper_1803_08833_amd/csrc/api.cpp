@@ -411,34 +411,44 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     b.rowlen = rowlen;
     b.row_ptr = row_ptr;
     b.ctrl = a.ctrl;
-    // Rows are built in slices so that no single launch runs for long.
+    // Rows are built in slices so that no single launch runs for long: the
+    // slice's rows are generated into a buffer of slab_cap hits per row
+    // (8 standard deviations above the expected in-degree), their offsets
+    // scanned, and the records written out.  The record buffer is sized to a
+    // bound on the total (expected total + 10 standard deviations).
     const uint32_t slice = 1u << 16;
+    const double kin = s->k_in + 1.0;
+    b.slab_cap = (uint32_t)std::min(kin + 8.0 * std::sqrt(kin) + 256.0, 65536.0);
+    const double tot_bound = (double)n->N * kin + 10.0 * std::sqrt((double)n->N * kin) + 65536.0;
+    const size_t rb = s->record == SNN_REC_CODE8 ? 4 : 8;
+    b.rec_cap = (uint64_t)tot_bound;
+    void* recs = nullptr;
+    uint32_t* slab = nullptr;
+    e = dalloc(n, (uint8_t**)&recs, (size_t)b.rec_cap * rb);
+    if (e == hipSuccess) e = dalloc(n, &slab, (size_t)std::min(n->N, slice) * b.slab_cap);
+    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (synapse records)");
+    b.recs = recs;
+    b.slab = slab;
+    HIPCHK(n, hipMemsetAsync(row_ptr, 0, 8, n->stream));   // offset of row 0
     for (uint32_t r0 = 0; r0 < n->N; r0 += slice) {
         b.row0 = r0;
         b.nrows = (n->N - r0) < slice ? (n->N - r0) : slice;
-        HIPCHK(n, snn::launch_syn_count(b, n->stream));
+        HIPCHK(n, snn::launch_syn_gen(b, n->stream));
+        HIPCHK(n, snn::launch_scan_rows(rowlen + r0, row_ptr + r0, tsum, b.nrows, n->stream));
+        HIPCHK(n, snn::launch_syn_out(b, n->stream));
     }
-    HIPCHK(n, snn::launch_scan_rows(rowlen, row_ptr, tsum, n->N, n->stream));
     Ctrl hc{};
     HIPCHK(n, hipMemcpyAsync(&hc, a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, n->stream));
     uint64_t nnz = 0;
     HIPCHK(n, hipMemcpyAsync(&nnz, row_ptr + n->N, 8, hipMemcpyDeviceToHost, n->stream));
     HIPCHK(n, hipStreamSynchronize(n->stream));
+    dfree(n, slab);
     if (hc.err & 1u) return fail(n, SNN_E_OVERFLOW, "a projection row exceeds 65535 synapses");
+    if (hc.err & 2u) return fail(n, SNN_E_OVERFLOW, "a projection row exceeds the construction buffer");
+    if (hc.err & 4u) return fail(n, SNN_E_OVERFLOW, "the synapse total exceeds its bound");
     n->nnz = nnz;
     n->max_len = hc.max_len;
-    const size_t rb = s->record == SNN_REC_CODE8 ? 4 : 8;
-    void* recs = nullptr;
-    e = dalloc(n, (uint8_t**)&recs, (size_t)nnz * rb);
-    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (synapse records)");
-    b.recs = recs;
     a.recs = recs;
-    for (uint32_t r0 = 0; r0 < n->N; r0 += slice) {
-        b.row0 = r0;
-        b.nrows = (n->N - r0) < slice ? (n->N - r0) : slice;
-        HIPCHK(n, snn::launch_syn_fill(b, n->stream));
-    }
-    HIPCHK(n, hipStreamSynchronize(n->stream));
     dfree(n, rowlen);
     dfree(n, tsum);
     // Tile-binned delivery.  Single level: the tiles fit the scatter kernel's

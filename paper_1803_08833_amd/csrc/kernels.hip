@@ -1,9 +1,9 @@
 // kernels.hip -- gfx950 kernels of the spiking-network hot path.
 //
 //   k_init        initial membrane potentials (INIT stream)
-//   k_syn<false>  projection count pass: per-pair Bernoulli trials, delay histogram per row
+//   k_syn_gen     projection generation: per-pair Bernoulli trials, hits per row
 //   k_scan_*      row offsets (exclusive scan of row lengths)
-//   k_syn<true>   projection fill pass: records ordered by (delay, target)
+//   k_syn_out     projection write-out: delay buckets, records ordered by (delay, target)
 //   k_update      fused neuron step: ring read+clear, Poisson drive, LIF+SFA, ordered
 //                 block-local spike compaction
 //   k_compact     ordered global spike list + AER history
@@ -102,19 +102,18 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// Projection construction.  One wave per presynaptic row.  The wave walks the
-// target modules in ascending index (so targets come out ascending), and for
-// each module tests its candidates 256 at a time: lane l draws Philox CONN at
-// (row, j/4) and compares the four words with the module's threshold.  Hits
-// are appended in target order to a per-wave LDS queue; full queues are
-// flushed 64 hits at a time: each lane draws the ATTR word of one hit (delay
-// bucket, weight), and per-bucket ballots give each hit its rank among the
-// same-delay hits before it, so records land in (delay, target) order.
-// Count pass: per-bucket counts -> bucket ends and row length.
-// Fill pass: lane b holds the next free offset of bucket b.
+// Projection construction, in slices of rows, each drawing every candidate
+// pair once.  Generation: one wave per presynaptic row walks the target
+// modules in ascending index (so targets come out ascending) and tests each
+// module's candidates 256 at a time: lane l draws Philox CONN at (row, j/4)
+// and compares the four words with the module's threshold; hits are appended
+// in target order to the row's slot of a slice buffer.  After the slice's row
+// offsets are scanned, write-out takes the hits 64 at a time: each lane draws
+// the ATTR word of one hit (delay bucket, weight), and per-bucket ballots give
+// each hit its rank among the same-delay hits before it, so records land in
+// (delay, target) order.  syn_flush counts (lane b: hits of bucket b) or, with
+// FILL, writes (lane b: the next free offset of bucket b).
 // ---------------------------------------------------------------------------
-constexpr uint32_t kQCap = 512;
-
 template <bool FILL>
 __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q, uint32_t n,
                                           uint32_t row, bool exc, uint32_t lane, uint32_t& pos,
@@ -156,25 +155,18 @@ __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q,
     wave_sync();
 }
 
-template <bool FILL>
-__global__ __launch_bounds__(256) void k_syn(BuildArgs a)
+// Generation (one wave per row): the row's hits, targets ascending, go to the
+// row's slot of the slice buffer (capacity slab_cap); the row length too.
+__global__ __launch_bounds__(256) void k_syn_gen(BuildArgs a)
 {
-    __shared__ uint32_t qs[4][kQCap];
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
     const uint32_t rl = blockIdx.x * 4u + wv;
     if (rl >= a.nrows) return;
     const uint32_t row = a.row0 + rl;
-    uint32_t* q = qs[wv];
+    uint32_t* const out = a.slab + (size_t)rl * a.slab_cap;
     const uint32_t M = a.M, gx = a.gx, gy = a.gy;
     const uint32_t mi = row / M, xi = mi % gx, yi = mi / gx;
-    const bool exc = (row - mi * M) < a.n_exc;
-    uint32_t pos = 0;
-    uint64_t rbase = 0;
-    if (FILL) {
-        rbase = a.row_ptr[row];
-        pos = (lane >= 1u && lane < a.D) ? (uint32_t)a.bend[(size_t)row * a.D + lane - 1u] : 0u;
-    }
-    uint32_t qn = 0;
+    uint32_t n = 0;   // hits so far (wave-uniform)
     for (uint32_t yj = 0; yj < gy; ++yj) {
         const uint32_t dyr = yj >= yi ? yj - yi : yj + gy - yi;
         const uint32_t* Trow = a.T + dyr * gx;
@@ -198,32 +190,50 @@ __global__ __launch_bounds__(256) void k_syn(BuildArgs a)
                 const uint64_t m2 = __ballot(h & 4u), m3 = __ballot(h & 8u);
                 const uint32_t tot = popc(m0) + popc(m1) + popc(m2) + popc(m3);
                 if (tot) {
-                    uint32_t o = qn + mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
+                    uint32_t o = n + mbcnt(m0) + mbcnt(m1) + mbcnt(m2) + mbcnt(m3);
                     const uint32_t j0 = jb + jo;
-                    if (h & 1u) q[o++] = j0;
-                    if (h & 2u) q[o++] = j0 + 1u;
-                    if (h & 4u) q[o++] = j0 + 2u;
-                    if (h & 8u) q[o++] = j0 + 3u;
-                    qn += tot;
-                    if (qn >= 256u) {
-                        syn_flush<FILL>(a, q, qn, row, exc, lane, pos, rbase);
-                        qn = 0;
-                    }
+                    for (uint32_t s = 0; s < 4u; ++s)
+                        if (h & (1u << s)) {
+                            if (o < a.slab_cap) out[o] = j0 + s;
+                            ++o;
+                        }
+                    n += tot;
                 }
             }
         }
     }
-    if (qn) syn_flush<FILL>(a, q, qn, row, exc, lane, pos, rbase);
-    if (!FILL) {
-        const uint32_t v = wave_incl_scan<uint32_t>(lane < a.D ? pos : 0u, lane);
-        if (lane < a.D) a.bend[(size_t)row * a.D + lane] = (uint16_t)(v > 65535u ? 65535u : v);
-        const uint32_t len = readlane(v, a.D - 1u);
-        if (lane == 0) {
-            a.rowlen[row] = len;
-            atomicMax(&a.ctrl->max_len, len);
-            if (len > 65535u) atomicOr(&a.ctrl->err, 1u);
-        }
+    if (lane == 0) {
+        a.rowlen[row] = n;
+        atomicMax(&a.ctrl->max_len, n);
+        if (n > 65535u) atomicOr(&a.ctrl->err, 1u);
+        if (n > a.slab_cap) atomicOr(&a.ctrl->err, 2u);
     }
+}
+
+// Write-out (one wave per row): the delay bucket of every hit from its ATTR
+// draw gives the bucket ends, then the records are written in (delay, target)
+// order at the row's offset.
+__global__ __launch_bounds__(256) void k_syn_out(BuildArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t rl = blockIdx.x * 4u + wv;
+    if (rl >= a.nrows) return;
+    const uint32_t row = a.row0 + rl;
+    const uint32_t* const hits = a.slab + (size_t)rl * a.slab_cap;
+    const bool exc = (row % a.M) < a.n_exc;
+    uint32_t n = a.rowlen[row];
+    n = n < a.slab_cap ? n : a.slab_cap;
+    const uint64_t rbase = a.row_ptr[row];
+    if (rbase + n > a.rec_cap) {   // the record buffer's bound was too small: report, write nothing
+        if (lane == 0) atomicOr(&a.ctrl->err, 4u);
+        return;
+    }
+    uint32_t pos = 0;   // lane b: hits of bucket b
+    syn_flush<false>(a, hits, n, row, exc, lane, pos, 0);
+    const uint32_t v = wave_incl_scan<uint32_t>(lane < a.D ? pos : 0u, lane);
+    if (lane < a.D) a.bend[(size_t)row * a.D + lane] = (uint16_t)(v > 65535u ? 65535u : v);
+    pos = v - (lane < a.D ? pos : 0u);   // lane b: start of bucket b
+    syn_flush<true>(a, hits, n, row, exc, lane, pos, rbase);
 }
 
 // ---------------------------------------------------------------------------
@@ -284,12 +294,13 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* x, const uin
         s += v[u];
     }
     uint64_t tot;
-    uint64_t o = toff[blockIdx.x] + block_excl_scan(s, ws, tot);
+    const uint64_t base = out[0];   // offset of the first row (set before; rewritten unchanged)
+    uint64_t o = base + toff[blockIdx.x] + block_excl_scan(s, ws, tot);
     for (uint32_t u = 0; u < 4u; ++u) {
         if (i0 + u < N) out[i0 + u] = o;
         o += v[u];
     }
-    if (blockIdx.x == gridDim.x - 1u && threadIdx.x == 0) out[N] = toff[blockIdx.x] + tot;
+    if (blockIdx.x == gridDim.x - 1u && threadIdx.x == 0) out[N] = base + toff[blockIdx.x] + tot;
 }
 
 // ---------------------------------------------------------------------------
@@ -1636,17 +1647,17 @@ hipError_t launch_init(const StepArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_syn_count(const BuildArgs& a, hipStream_t s)
+hipError_t launch_syn_gen(const BuildArgs& a, hipStream_t s)
 {
     if (a.nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_syn<false>, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_syn_gen, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_syn_fill(const BuildArgs& a, hipStream_t s)
+hipError_t launch_syn_out(const BuildArgs& a, hipStream_t s)
 {
     if (a.nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_syn<true>, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_syn_out, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -119,15 +119,20 @@ struct BuildArgs {
     const int32_t* wtab;       // [65536]
     uint16_t* bend;            // [N][D]
     uint32_t* rowlen;          // [N]
-    const uint64_t* row_ptr;   // [N+1] (fill pass)
+    const uint64_t* row_ptr;   // [N+1] (write-out)
     void* recs;
+    uint64_t rec_cap;          // records the buffer holds
+    uint32_t* slab;            // [nrows][slab_cap] hits of the slice's rows
+    uint32_t slab_cap;
     Ctrl* ctrl;
 };
 
 // ---- launchers (kernels.hip) ----
 hipError_t launch_init(const StepArgs& a, hipStream_t s);
-hipError_t launch_syn_count(const BuildArgs& a, hipStream_t s);
-hipError_t launch_syn_fill(const BuildArgs& a, hipStream_t s);
+hipError_t launch_syn_gen(const BuildArgs& a, hipStream_t s);
+hipError_t launch_syn_out(const BuildArgs& a, hipStream_t s);
+// row_ptr[i] = row_ptr[0] + sum of rowlen[0 .. i) for i <= N (row_ptr[0] is
+// the offset of the first row, set before).
 hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
                             uint32_t N, hipStream_t s);
 // Optional per-launch timing: the launch records the kernel's start and end
