@@ -352,7 +352,7 @@ def test_two_level_matches_direct_over_super_tiles(snn):
 
 
 @pytest.mark.skipif(os.environ.get("SNN_FULL_SCALE") != "1",
-                    reason="full-scale 96x96 run (about 190 GB of HBM, 2-3 minutes): set SNN_FULL_SCALE=1")
+                    reason="full-scale 96x96 run (about 190 GB of HBM, 1-2 minutes): set SNN_FULL_SCALE=1")
 def test_full_scale_96x96_code8(snn, oracle_mod):
     """The 96x96 exponential grid with 8-bit codes (11.4 M neurons, 29.7 G
     synapses) at full size, in the configuration bench.py times (two-level
@@ -361,7 +361,7 @@ def test_full_scale_96x96_code8(snn, oracle_mod):
     charge queued for sampled targets against the oracle."""
     wl = W.workload("grid96_exp_code8")
     net = wl["net"]
-    say("case: grid96_exp_code8 full-size build (about two minutes)")
+    say("case: grid96_exp_code8 full-size build (about one minute)")
     o = oracle_mod.Net(net)
     V0, _, _ = o.state()
     o.step(1)
