@@ -759,9 +759,14 @@ __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint3
 constexpr uint32_t kScatterThreads = 1024;
 constexpr uint32_t kScatterWaves = kScatterThreads / 64;
 constexpr uint32_t kSegPerWave = kChunkItems / kScatterWaves;   // 7 row segments per wave
+// Lanes that write one bin's run in the last scatter phase: a chunk puts a few
+// dozen events in a typical bin, and the phase is bound by the latency of its
+// per-bin steps, so four bins go at once per wave.
+constexpr uint32_t kRunLanes = 16;
 
 // Spike s of the step's ascending-id list: its update block is found in the
-// exclusive block offsets boff[0 .. nb] (s is wave-uniform).
+// exclusive block offsets boff[0 .. nb] (UNIFORM: s is wave-uniform).
+template <bool UNIFORM = true>
 __device__ __forceinline__ uint4 spike_rec(const StepArgs& a, const uint32_t* boff, uint32_t nb, uint32_t s)
 {
     uint32_t lo = 0, hi = nb;   // boff[lo] <= s < boff[hi]
@@ -770,8 +775,11 @@ __device__ __forceinline__ uint4 spike_rec(const StepArgs& a, const uint32_t* bo
         if (boff[mid] <= s) lo = mid;
         else hi = mid;
     }
-    lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
-    const uint32_t i = (uint32_t)__builtin_amdgcn_readfirstlane((int)(s - boff[lo]));
+    uint32_t i = s - boff[lo];
+    if (UNIFORM) {
+        lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+        i = (uint32_t)__builtin_amdgcn_readfirstlane((int)i);
+    }
     return a.blk_list[(size_t)lo * kNeuronsPerBlock + i];
 }
 
@@ -814,6 +822,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
     __shared__ uint32_t boff[TWO ? 1 : kMaxTiles + 1];
+    __shared__ uint4 info_s[kChunkItems];  // spike records of the chunk whose segments load next
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
     __shared__ unsigned long long red[2 * kScatterWaves + 1];
@@ -892,24 +901,43 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     // this wave's row segments of chunk [c0, c1): items c0 + wv + 16 j, all
     // loads issued before use; the next chunk's segments are loaded while the
     // current chunk's runs are written (phase 4)
+    //
+    // The spike records a chunk's segments start from are fetched one chunk
+    // earlier still: lane j of a wave fetches its segment j's record (a
+    // register while phase 4 runs), the top of the next chunk parks it in
+    // info_s, and the segments' loads read it there.
     SegLoad S[kSegPerWave];
+    uint4 nxt = make_uint4(0, 0, 0, 0);
+    auto fetch_info = [&](uint32_t c0, uint32_t c1) {
+        const uint32_t it = c0 + wv + kScatterWaves * lane;
+        nxt = make_uint4(0, 0, 0, 0);
+        if (lane < kSegPerWave && it < c1)
+            nxt = TWO ? a.spk[it / smax] : spike_rec<false>(a, boff, nb, it / smax);
+    };
+    auto park_info = [&]() {
+        if (lane < kSegPerWave) info_s[wv + kScatterWaves * lane] = nxt;
+    };
     auto load_chunk = [&](uint32_t c0, uint32_t c1) {
-        uint4 info[kSegPerWave];
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
-            info[j] = it < c1 ? spike(it / smax) : make_uint4(0, 0, 0, 0);
-        }
-#pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) {
-            const uint32_t it = c0 + wv + kScatterWaves * j;
-            seg_load<CODE8>(a, info[j], it < c1 ? it % smax : 0u, lane, S[j]);
+            seg_load<CODE8>(a, info_s[wv + kScatterWaves * j], it < c1 ? it % smax : 0u, lane, S[j]);
         }
     };
     auto chunk_end = [&](uint32_t c0) { return (items - c0) < per ? items : c0 + per; };
-    if (blockIdx.x * per < items) load_chunk(blockIdx.x * per, chunk_end(blockIdx.x * per));
-    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += gridDim.x * per) {
+    const uint32_t stride = gridDim.x * per;
+    if (blockIdx.x * per < items) {
+        fetch_info(blockIdx.x * per, chunk_end(blockIdx.x * per));
+        park_info();
+        __syncthreads();
+        load_chunk(blockIdx.x * per, chunk_end(blockIdx.x * per));
+        const uint32_t n1 = blockIdx.x * per + stride;
+        nxt = make_uint4(0, 0, 0, 0);
+        if (n1 < items) fetch_info(n1, chunk_end(n1));
+    }
+    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += stride) {
         for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
+        park_info();   // the next chunk's spike records (zeros past the end)
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_decode<CODE8>(a, S[j]);
         __syncthreads();
@@ -918,8 +946,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count<SHIFT>(S[j], lane, tcnt);
         __syncthreads();
         // 2. exclusive scan of the counts (2 bins per thread) and reservation
+        // in the bins; the reservations' results are first needed in phase 4,
+        // so they stay in registers (in flight) while phase 3 stages
+        const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
+        uint32_t res0 = 0, res1 = 0;
         {
-            const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
             const uint32_t v0 = t0i < nt ? tcnt[t0i] : 0u;
             const uint32_t v1 = t1i < nt ? tcnt[t1i] : 0u;
             const uint32_t sum = v0 + v1;
@@ -931,31 +962,37 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             if (t0i < nt) {
                 toff[t0i] = off;
                 tcnt[t0i] = off;
-                tres[t0i] = v0 ? atomicAdd(&fill[(size_t)t0i * kFillStride], v0) : 0u;
+                if (v0) res0 = atomicAdd(&fill[(size_t)t0i * kFillStride], v0);
             }
             if (t1i < nt) {
                 toff[t1i] = off + v0;
                 tcnt[t1i] = off + v0;
-                tres[t1i] = v1 ? atomicAdd(&fill[(size_t)t1i * kFillStride], v1) : 0u;
+                if (v1) res1 = atomicAdd(&fill[(size_t)t1i * kFillStride], v1);
             }
         }
         __syncthreads();
         // 3. encode and stage sorted by bin
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage<SHIFT>(S[j], lane, tcnt, stage);
+        if (t0i < nt) tres[t0i] = res0;
+        if (t1i < nt) tres[t1i] = res1;
         __syncthreads();
         {
-            const uint32_t n0 = c0 + gridDim.x * per;
-            if (n0 < items) load_chunk(n0, chunk_end(n0));
+            const uint32_t n1 = c0 + stride, n2 = n1 + stride;
+            if (n1 < items) load_chunk(n1, chunk_end(n1));
+            nxt = make_uint4(0, 0, 0, 0);
+            if (n2 < items) fetch_info(n2, chunk_end(n2));
         }
-        // 4. contiguous runs into the bins (one wave per bin)
-        for (uint32_t tt = wv; tt < nt; tt += kScatterWaves) {
+        // 4. contiguous runs into the bins: each group of kRunLanes lanes
+        // writes one bin's run at a time
+        constexpr uint32_t kRunGroups = 64u / kRunLanes;
+        const uint32_t rl = lane % kRunLanes;
+        for (uint32_t tt = kRunGroups * wv + lane / kRunLanes; tt < nt; tt += kRunGroups * kScatterWaves) {
             const uint32_t o0 = toff[tt];
             const uint32_t cnt = tcnt[tt] - o0;
-            if (cnt == 0) continue;
             const uint32_t r0 = tres[tt];
             uint32_t* dst = bins + (size_t)tt * cap;
-            for (uint32_t e = lane; e < cnt; e += 64u) {
+            for (uint32_t e = rl; e < cnt; e += kRunLanes) {
                 const uint32_t code = stage[o0 + e];
                 const uint32_t pos = r0 + e;
                 if (pos < cap) {
