@@ -822,11 +822,12 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
     __shared__ uint32_t boff[TWO ? 1 : kMaxTiles + 1];
-    __shared__ uint4 info_s[kChunkItems];  // spike records of the chunk whose segments load next
+    __shared__ uint4 info_s[kChunkItems + kScatterWaves];  // spike records of the chunk whose segments load next
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
     __shared__ unsigned long long red[2 * kScatterWaves + 1];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));   // uniform: scalar registers
     if (CODE8 && tid < 256u) cb_s[tid] = a.cb[tid];
     const uint32_t t = a.ctrl->t0 + k;
     const uint32_t nb = a.nblk;          // single level: <= kMaxTiles
@@ -910,12 +911,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     uint4 nxt = make_uint4(0, 0, 0, 0);
     auto fetch_info = [&](uint32_t c0, uint32_t c1) {
         const uint32_t it = c0 + wv + kScatterWaves * lane;
-        nxt = make_uint4(0, 0, 0, 0);
         if (lane < kSegPerWave && it < c1)
             nxt = TWO ? a.spk[it / smax] : spike_rec<false>(a, boff, nb, it / smax);
+        else
+            nxt = make_uint4(0, 0, 0, 0);
     };
-    auto park_info = [&]() {
-        if (lane < kSegPerWave) info_s[wv + kScatterWaves * lane] = nxt;
+    auto park_info = [&]() {   // every lane stores (lanes past the segments to a spare slot)
+        info_s[lane < kSegPerWave ? wv + kScatterWaves * lane : kChunkItems + wv] = nxt;
     };
     auto load_chunk = [&](uint32_t c0, uint32_t c1) {
 #pragma unroll
@@ -932,8 +934,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         __syncthreads();
         load_chunk(blockIdx.x * per, chunk_end(blockIdx.x * per));
         const uint32_t n1 = blockIdx.x * per + stride;
-        nxt = make_uint4(0, 0, 0, 0);
-        if (n1 < items) fetch_info(n1, chunk_end(n1));
+        fetch_info(n1, n1 < items ? chunk_end(n1) : n1);
     }
     for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += stride) {
         for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
@@ -979,15 +980,13 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         __syncthreads();
         {
             const uint32_t n1 = c0 + stride, n2 = n1 + stride;
+            fetch_info(n2, n2 < items ? chunk_end(n2) : n2);
             if (n1 < items) load_chunk(n1, chunk_end(n1));
-            nxt = make_uint4(0, 0, 0, 0);
-            if (n2 < items) fetch_info(n2, chunk_end(n2));
         }
         // 4. contiguous runs into the bins: each group of kRunLanes lanes
         // writes one bin's run at a time
-        constexpr uint32_t kRunGroups = 64u / kRunLanes;
-        const uint32_t rl = lane % kRunLanes;
-        for (uint32_t tt = kRunGroups * wv + lane / kRunLanes; tt < nt; tt += kRunGroups * kScatterWaves) {
+        const uint32_t rl = tid % kRunLanes;
+        for (uint32_t tt = tid / kRunLanes; tt < nt; tt += kScatterThreads / kRunLanes) {
             const uint32_t o0 = toff[tt];
             const uint32_t cnt = tcnt[tt] - o0;
             const uint32_t r0 = tres[tt];
