@@ -818,7 +818,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 {
     constexpr uint32_t SHIFT = TWO ? kSuperBits : kTileBits;
     __shared__ uint32_t stage[kStage];
-    __shared__ uint32_t tcnt[kMaxTiles];   // counts, then fill cursor
+    __shared__ uint32_t tcnt2[2][kMaxTiles];   // counts, then fill cursor (by chunk parity)
     __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
     __shared__ uint32_t boff[TWO ? 1 : kMaxTiles + 1];
@@ -928,6 +928,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     };
     auto chunk_end = [&](uint32_t c0) { return (items - c0) < per ? items : c0 + per; };
     const uint32_t stride = gridDim.x * per;
+    // a chunk counts into one of two arrays; the other is cleared while the
+    // chunk writes its runs, so no barrier separates clearing from counting
+    for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt2[0][i] = 0;
+    uint32_t par = 0;
     if (blockIdx.x * per < items) {
         fetch_info(blockIdx.x * per, chunk_end(blockIdx.x * per));
         park_info();
@@ -936,12 +940,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         const uint32_t n1 = blockIdx.x * per + stride;
         fetch_info(n1, n1 < items ? chunk_end(n1) : n1);
     }
-    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += stride) {
-        for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt[i] = 0;
+    for (uint32_t c0 = blockIdx.x * per; c0 < items; c0 += stride, par ^= 1u) {
+        uint32_t* const tcnt = tcnt2[par];
         park_info();   // the next chunk's spike records (zeros past the end)
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_decode<CODE8>(a, S[j]);
-        __syncthreads();
         // 1. histogram of targets by bin
 #pragma unroll
         for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count<SHIFT>(S[j], lane, tcnt);
@@ -983,6 +986,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
             fetch_info(n2, n2 < items ? chunk_end(n2) : n2);
             if (n1 < items) load_chunk(n1, chunk_end(n1));
         }
+        for (uint32_t i = tid; i < nt; i += kScatterThreads) tcnt2[par ^ 1u][i] = 0;
         // 4. contiguous runs into the bins: each group of kRunLanes lanes
         // writes one bin's run at a time
         const uint32_t rl = tid % kRunLanes;
