@@ -1408,6 +1408,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
     __shared__ uint32_t wbase[kMaxJobs + 1];
     __shared__ uint32_t jbin[kMaxJobs];
     __shared__ uint8_t segjob[kChunkItems];   // job of each row segment of the chunk
+    __shared__ uint8_t tjob[kMaxTiles];       // job of each window tile
     __shared__ uint32_t wsum[kScatterWaves];
     __shared__ uint32_t wtotal;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
@@ -1507,6 +1508,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
         }
         __syncthreads();
         // 2. scan and reservation in each window tile's bin
+        uint32_t res0 = 0, res1 = 0;
         {
             const uint32_t t0i = 2u * tid, t1i = 2u * tid + 1u;
             const uint32_t v0 = t0i < W ? tcnt[t0i] : 0u;
@@ -1529,7 +1531,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
                     if (wbase[mid] <= w) lo = mid;
                     else hi = mid;
                 }
-                tres[w] = v ? atomicAdd(&jobs[lo].a.bin_fill[(size_t)(w - wbase[lo]) * kFillStride], v) : 0u;
+                tjob[w] = (uint8_t)lo;
+                // the reservation's result is first needed in phase 4: it
+                // stays in a register while phase 3 stages
+                if (v) (e ? res1 : res0) = atomicAdd(&jobs[lo].a.bin_fill[(size_t)(w - wbase[lo]) * kFillStride], v);
                 off += v;
             }
         }
@@ -1558,31 +1563,29 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
                 }
             }
         }
+        if (2u * tid < W) tres[2u * tid] = res0;
+        if (2u * tid + 1u < W) tres[2u * tid + 1u] = res1;
         __syncthreads();
-        // 4. runs into the bins (one wave per window tile)
-        for (uint32_t w = wv; w < W; w += kScatterWaves) {
+        // 4. runs into the bins: each group of kRunLanes lanes writes one
+        // window tile's run at a time (the tile's job differs between groups)
+        const uint32_t rl = tid % kRunLanes;
+        for (uint32_t w = tid / kRunLanes; w < W; w += kScatterThreads / kRunLanes) {
             const uint32_t o0 = toff[w];
             const uint32_t cnt = tcnt[w] - o0;
             if (cnt == 0) continue;
-            uint32_t lo = jl, hi = jh + 1u;
-            while (hi - lo > 1u) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (wbase[mid] <= w) lo = mid;
-                else hi = mid;
-            }
-            lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);   // w is wave-uniform
+            const uint32_t lo = tjob[w];
             const StepArgs& a = jobs[lo].a;
             const uint32_t tt = w - wbase[lo];
             const uint32_t r0 = tres[w];
             const uint32_t cap = a.bin_cap_tile;
-            const uint32_t t = a.ctrl->t0 + k;
             uint32_t* dst = a.bins + (size_t)tt * cap;
-            for (uint32_t e = lane; e < cnt; e += 64u) {
+            for (uint32_t e = rl; e < cnt; e += kRunLanes) {
                 const uint32_t code = stage[o0 + e];
                 const uint32_t pos = r0 + e;
                 if (pos < cap) {
                     dst[pos] = code;
                 } else {
+                    const uint32_t t = a.ctrl->t0 + k;
                     const uint32_t tgt = (tt << kTileBits) | (code & (kTile - 1u));
                     const uint32_t b = (code >> kTileBits) & 31u;
                     const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
