@@ -9,6 +9,9 @@
   refractory counters and the whole delay ring bit-exact, every step.
 * Step 0 at full 24x24 size: state of every neuron, the spike set, and the
   charge queued for sampled targets (oracle column sums) bit-exact.
+* Full 24x24 size, free-running with the bench's schedule through an up-state
+  burst: the charge in flight for sampled targets equals the oracle's column
+  sums over the GPU's own spike sets (binned and direct steps).
 * Closed-form interspike intervals under constant drive; free-running
   population rate within 2 % of the oracle's.
 """
@@ -178,6 +181,62 @@ def test_step0_full_size_exp(snn, oracle_mod):
         for j in rng.integers(0, g.N, 24):
             want = oracle_mod.col_input(net, int(j), pres)
             got = ring[net["d_min"]:net["d_max"] + 1, j].astype(np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
+
+
+def _pending_charge(oracle_mod, net, raster, T, j):
+    """Charge queued for target j after steps 0..T-1, by arrival time T ..
+    T - 1 + d_max: the oracle's per-delay column sums of each recent step's
+    spike set, placed at step + delay."""
+    dmin, dmax = net["d_min"], net["d_max"]
+    out = np.zeros(dmax, dtype=np.int64)          # arrival T + i, i < d_max
+    for s in range(max(0, T - dmax), T):
+        pres = np.sort(raster[raster[:, 0] == s, 1]).astype(np.uint32)
+        if pres.size == 0:
+            continue
+        col = oracle_mod.col_input(net, int(j), pres)   # delays d_min .. d_max
+        for d in range(dmin, dmax + 1):
+            a = s + d - T
+            if 0 <= a < dmax:
+                out[a] += col[d - dmin]
+    return out
+
+
+def test_full_size_burst_in_flight_bench_schedule(snn, oracle_mod):
+    """24x24 exponential grid at full size, free-running with the bench's
+    schedule (graphs of 250 steps, per-step binned/direct switch): stopped a
+    few steps after its largest up-state step, the charge queued in the ring
+    for sampled targets equals the oracle's column sums over the spike sets
+    the GPU produced in the last d_max steps (binned and direct steps both)."""
+    net = W.workload("grid24_exp")["net"]
+    say("case: grid24_exp full size, burst in flight, bench schedule")
+    with snn.Net(net, hist_cap=1 << 25) as g:
+        g.build_synapses()
+        g.set_option(snn.OPT_GRAPH_CHUNK, 250)
+        thr = g.stats()["bin_threshold"]
+        g.step(1000)
+        raster = g.read_spikes()
+        counts = np.bincount(raster[:, 0].astype(np.int64), minlength=1000)
+        s_max = int(np.argmax(counts))
+        assert counts[s_max] * 900 > thr, "the first second holds no binned step"
+        # stop just after the first direct step that follows the burst, so that
+        # both kinds of step are in flight
+        after = [t for t in range(s_max + 1, 1000) if counts[t] * 1300 < thr]
+        T = (after[0] + 1) if after else s_max + 3
+        g.reset()
+        g.step(T)
+        raster = g.read_spikes()
+        recent = counts[max(0, T - net["d_max"]):T]
+        n_bin, n_dir = int((recent * 900 > thr).sum()), int((recent * 1300 < thr).sum())
+        say(f"  largest step {s_max}: {counts[s_max]} spikes; stopped at {T}; steps in flight "
+            f"binned {n_bin}, direct {n_dir}")
+        assert n_bin > 0
+        np.testing.assert_array_equal(np.bincount(raster[:, 0].astype(np.int64), minlength=T), counts[:T])
+        ring = g.read_ring()
+        rng = np.random.default_rng(11)
+        for j in rng.integers(0, g.N, 16):
+            want = _pending_charge(oracle_mod, net, raster, T, int(j))
+            got = np.array([ring[(T + a) % ring.shape[0], j] for a in range(net["d_max"])], dtype=np.int64)
             np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
 
 
