@@ -48,13 +48,15 @@ class Cfg(C.Structure):
         ("record", C.c_uint32), ("ext_mode", C.c_uint32),
         ("ext_n", C.c_double), ("ext_rate_hz", C.c_double), ("ext_w", C.c_double),
         ("ext_const_q", C.c_int32), ("pad_", C.c_uint32),
+        ("preset", C.c_uint32), ("pad2_", C.c_uint32),
+        ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
     ]
 
 
 def cfg(net: dict) -> Cfg:
     c = Cfg()
     for name, _ in Cfg._fields_:
-        if name != "pad_":
+        if not name.startswith("pad"):
             setattr(c, name, net[name])
     return c
 
@@ -118,10 +120,11 @@ def philox(ctr, key):
 
 
 def tables(net: dict):
-    """Host tables: thresholds T[gy, gx], weight table, codebook, Poisson CDF
-    thresholds, propagator constants (dm, dw, kappa), (nref, jext_q, winh_q)."""
+    """Host tables: thresholds T[gy, gx] of excitatory sources and T_inh of
+    inhibitory ones, weight table, codebook, Poisson CDF thresholds,
+    propagator constants (dm, dw, kappa), (nref, jext_q, winh_q)."""
     c = cfg(net)
-    T = np.zeros(net["gx"] * net["gy"], dtype=np.uint32)
+    T = np.zeros(2 * net["gx"] * net["gy"], dtype=np.uint32)
     wtab = np.zeros(65536, dtype=np.int32)
     cb = np.zeros(256, dtype=np.int32)
     poisc = np.zeros(64, dtype=np.uint32)
@@ -132,7 +135,8 @@ def tables(net: dict):
                               _p(consts), _p(iconsts))
     if st != 0:
         raise ValueError(f"oracle tables: status {st}")
-    return dict(T=T.reshape(net["gy"], net["gx"]), wtab=wtab, cb=cb,
+    T = T.reshape(2, net["gy"], net["gx"])
+    return dict(T=T[0].copy(), T_inh=T[1].copy(), wtab=wtab, cb=cb,
                 poisc=poisc[: int(npois[0])].copy(), dm=consts[0], dw=consts[1], kappa=consts[2],
                 nref=int(iconsts[0]), jext_q=int(iconsts[1]), winh_q=int(iconsts[2]))
 

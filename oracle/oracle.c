@@ -53,6 +53,8 @@
 #define OR_REC_CODE8 1
 #define OR_EXT_POISSON 0
 #define OR_EXT_CONST 1
+#define OR_PRESET_LATERAL 0
+#define OR_PRESET_PAPER 1
 
 #define RING 32            /* delay ring slots: must exceed the largest delay */
 #define POIS_MAX 64        /* longest Poisson CDF threshold table            */
@@ -80,6 +82,11 @@ typedef struct {
     double ext_n, ext_rate_hz, ext_w;
     int32_t ext_const_q;      /* charge per step in const mode (2^-16 mV)    */
     uint32_t pad_;
+    uint32_t preset;          /* OR_PRESET_LATERAL / OR_PRESET_PAPER          */
+    uint32_t pad2_;
+    double p_local;           /* paper preset: probability inside a module    */
+    double amp;               /* paper preset: remote law amplitude A         */
+    double p_cut;             /* paper preset: stencil cut-off probability    */
 } or_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -152,7 +159,8 @@ static int32_t fixq(double mv) { return (int32_t)nearbyint(mv * 65536.0); }
 /* Tables                                                                   */
 /* ------------------------------------------------------------------------ */
 typedef struct {
-    uint32_t *T;            /* [gy*gx] connection thresholds per torus offset */
+    uint32_t *T;            /* [2][gy*gx] connection thresholds per torus offset,
+                               for excitatory (0) and inhibitory (1) sources    */
     int32_t wtab[65536];    /* excitatory weight by top 16 bits of the draw   */
     int32_t cb[256];        /* 8-bit weight codebook                          */
     uint32_t poisc[POIS_MAX];
@@ -175,14 +183,59 @@ static double law(const or_cfg *c, int r2)
     return exp(-sqrt((double)r2) / c->range);
 }
 
-/* Connection thresholds.  The prefactor B fixes the expected number of
- * recurrent synapses per neuron to k_in (Sec. I: "fixes the total"):
- * B = k_in / sum_off n(off) f(r_off), with n = module size for a remote
- * offset and module size - 1 for the own module (no self-connection).
- * The pair probability p = B f(r) is stored as round(p * 2^32). */
+/* Connection thresholds, stored as round(p * 2^32) per torus offset and
+ * source type.
+ *
+ * Lateral preset (one law for every pair): the prefactor B fixes the expected
+ * number of recurrent synapses per neuron to k_in (Sec. I: "fixes the
+ * total"): B = k_in / sum_off n(off) f(r_off), with n = module size for a
+ * remote offset and module size - 1 for the own module (no self-connection);
+ * p = B f(r) for both source types.
+ *
+ * Paper preset (Sec. III.B, the two lateral rules and the Fig. 2 caption):
+ * every neuron connects inside its own module with probability p_local;
+ * excitatory neurons also project to other modules with probability
+ * amp * f(r); inhibitory neurons project only locally.  Remote projection is
+ * cut off where the probability falls to p_cut, which the paper states as
+ * square stencils centred on the source (7x7 Gaussian, 21x21 exponential):
+ * read as the square of half-width ceil(r_c), r_c the distance at which
+ * amp * f(r_c) = p_cut. */
+static int stencil_half_width(const or_cfg *c)
+{
+    if (!(c->amp > c->p_cut)) return 0;
+    double rc = (c->kernel == OR_GAUSS) ? c->range * sqrt(2.0 * log(c->amp / c->p_cut))
+                                        : c->range * log(c->amp / c->p_cut);
+    return (int)ceil(rc);
+}
+
+static int put_threshold(double p, uint32_t *dst)
+{
+    double q = nearbyint(p * 4294967296.0);
+    if (!(q >= 0.0 && q < 4294967296.0)) return OR_E_INVAL;
+    *dst = (uint32_t)q;
+    return OR_OK;
+}
+
 static int make_thresholds(const or_cfg *c, uint32_t *T)
 {
     int gx = (int)c->gx, gy = (int)c->gy;
+    size_t S = (size_t)gx * gy;
+    if (c->preset == OR_PRESET_PAPER) {
+        int h = stencil_half_width(c);
+        for (int dyr = 0; dyr < gy; dyr++)
+            for (int dxr = 0; dxr < gx; dxr++) {
+                int dx = torus_off(dxr, gx), dy = torus_off(dyr, gy);
+                double pe = 0.0, pi = 0.0;
+                if (dxr == 0 && dyr == 0) {
+                    pe = pi = c->p_local;
+                } else if (abs(dx) <= h && abs(dy) <= h) {
+                    pe = c->amp * law(c, dx * dx + dy * dy);
+                }
+                if (put_threshold(pe, &T[dyr * gx + dxr]) || put_threshold(pi, &T[S + dyr * gx + dxr]))
+                    return OR_E_INVAL;
+            }
+        return OR_OK;
+    }
     double M = (double)module_size(c);
     double s = 0.0;
     for (int dyr = 0; dyr < gy; dyr++)
@@ -195,10 +248,8 @@ static int make_thresholds(const or_cfg *c, uint32_t *T)
     for (int dyr = 0; dyr < gy; dyr++)
         for (int dxr = 0; dxr < gx; dxr++) {
             int dx = torus_off(dxr, gx), dy = torus_off(dyr, gy);
-            double p = B * law(c, dx * dx + dy * dy);
-            double q = nearbyint(p * 4294967296.0);
-            if (!(q < 4294967296.0)) return OR_E_INVAL;
-            T[dyr * gx + dxr] = (uint32_t)q;
+            if (put_threshold(B * law(c, dx * dx + dy * dy), &T[dyr * gx + dxr])) return OR_E_INVAL;
+            T[S + dyr * gx + dxr] = T[dyr * gx + dxr];
         }
     return OR_OK;
 }
@@ -252,8 +303,12 @@ static int make_tables(const or_cfg *c, or_tables *tb)
     if (!c->periodic) return OR_E_INVAL;
     if (c->d_min < 1 || c->d_max < c->d_min || c->d_max >= RING) return OR_E_INVAL;
     if (!(c->range > 0.0) || c->k_in < 0.0) return OR_E_INVAL;
+    if (c->preset > OR_PRESET_PAPER) return OR_E_INVAL;
+    if (c->preset == OR_PRESET_PAPER &&
+        !(c->p_local >= 0.0 && c->p_local < 1.0 && c->amp >= 0.0 && c->amp < 1.0 && c->p_cut > 0.0))
+        return OR_E_INVAL;
     if (!(c->tau_m > 0.0) || !(c->tau_w > 0.0) || c->t_ref < 0.0) return OR_E_INVAL;
-    tb->T = (uint32_t *)calloc((size_t)c->gx * c->gy, sizeof(uint32_t));
+    tb->T = (uint32_t *)calloc(2 * (size_t)c->gx * c->gy, sizeof(uint32_t));
     if (!tb->T) return OR_E_NOMEM;
     int st = make_thresholds(c, tb->T);
     if (st) return st;
@@ -288,7 +343,7 @@ int or_make_tables(const or_cfg *c, uint32_t *T, int32_t *wtab, int32_t *cb,
     if (!tb) return OR_E_NOMEM;
     int st = make_tables(c, tb);
     if (st == OR_OK) {
-        if (T) memcpy(T, tb->T, sizeof(uint32_t) * c->gx * c->gy);
+        if (T) memcpy(T, tb->T, 2 * sizeof(uint32_t) * c->gx * c->gy);
         if (wtab) memcpy(wtab, tb->wtab, sizeof(tb->wtab));
         if (cb) memcpy(cb, tb->cb, sizeof(tb->cb));
         if (poisc) memcpy(poisc, tb->poisc, sizeof(uint32_t) * tb->npois);
@@ -305,14 +360,16 @@ int or_make_tables(const or_cfg *c, uint32_t *T, int32_t *wtab, int32_t *cb,
 /* Connectivity (Sec. II.B, Sec. III.B)                                     */
 /* ------------------------------------------------------------------------ */
 
-/* Threshold of the ordered pair (i -> j) from the torus offset of their modules. */
+/* Threshold of the ordered pair (i -> j): the source's type selects the
+ * table, the torus offset of the two modules the entry. */
 static uint32_t pair_threshold(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t j)
 {
     uint32_t M = module_size(c);
     uint32_t mi = i / M, mj = j / M;
     uint32_t xi = mi % c->gx, yi = mi / c->gx, xj = mj % c->gx, yj = mj / c->gx;
     uint32_t dxr = (xj + c->gx - xi) % c->gx, dyr = (yj + c->gy - yi) % c->gy;
-    return tb->T[dyr * c->gx + dxr];
+    size_t type = (i % M) < c->n_exc ? 0 : 1;
+    return tb->T[type * c->gx * c->gy + dyr * c->gx + dxr];
 }
 
 /* Does neuron i project a synapse onto neuron j?  One Bernoulli trial per

@@ -31,11 +31,23 @@ NEURON = dict(
     alpha_w=0.2, tau_w=500.0, sfa_on_inh=0,
 )
 
+PRESET_LATERAL = 0
+PRESET_PAPER = 1
+
 SYNAPSE = dict(
     d_min=1, d_max=20, w_exc=0.4, w_exc_sd=0.04, w_inh=-1.6,
     record=REC_F32, ext_mode=EXT_POISSON, ext_n=800.0, ext_rate_hz=3.0, ext_w=0.4,
     ext_const_q=0,
+    # lateral preset: one distance law normalised to k_in; the paper preset's
+    # parameters below are unused by it
+    preset=PRESET_LATERAL, p_local=0.0, amp=0.0, p_cut=0.0,
 )
+
+# The paper's own connectivity (Sec. III.B): 80 % inside the module, remote
+# probability A f(r) for excitatory sources only, cut off at 1/1000; at one
+# module spacing = 100 um, sigma = 100 um and lambda = 290 um are 1.0 and 2.9.
+PAPER_GAUSS = dict(kernel=GAUSS, range=1.0, amp=0.05)
+PAPER_EXP = dict(kernel=EXP, range=2.9, amp=0.03)
 
 
 def make(gx, gy, kernel, rng, k_in, seed, **over):
@@ -43,6 +55,15 @@ def make(gx, gy, kernel, rng, k_in, seed, **over):
     d = dict(NEURON)
     d.update(SYNAPSE)
     d.update(gx=gx, gy=gy, kernel=kernel, range=float(rng), k_in=float(k_in), seed=int(seed))
+    d.update(over)
+    return d
+
+
+def make_paper(gx, gy, law, seed, **over):
+    """A network with the paper's connectivity preset; `law` is PAPER_GAUSS or
+    PAPER_EXP.  k_in is unused (the in-degree follows from the law)."""
+    d = make(gx, gy, law["kernel"], law["range"], 0.0, seed, preset=PRESET_PAPER, p_local=0.8,
+             amp=law["amp"], p_cut=1e-3)
     d.update(over)
     return d
 
