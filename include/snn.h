@@ -54,6 +54,7 @@ typedef enum {
 enum { SNN_GAUSS = 0, SNN_EXP = 1 };
 enum { SNN_REC_F32 = 0, SNN_REC_CODE8 = 1 };
 enum { SNN_EXT_POISSON = 0, SNN_EXT_CONST = 1 };
+enum { SNN_PRESET_LATERAL = 0, SNN_PRESET_PAPER = 1 };
 
 typedef struct snn_net snn_net;
 
@@ -85,11 +86,18 @@ typedef struct {
 } snn_grid_desc;
 
 /* Recurrent projections and external drive (Sec. II.B, Sec. III.A-B).
- * Connection probability of a pair at torus distance r (module spacings):
- * p = B f(r), f = exp(-r^2 / 2 range^2) (Gaussian) or exp(-r / range)
- * (exponential), B chosen so that the expected number of recurrent synapses
- * per neuron is k_in.  Delays are uniform integers in [d_min, d_max] ms;
- * excitatory weights Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh. */
+ * Connection probability of a pair at torus distance r (module spacings),
+ * f = exp(-r^2 / 2 range^2) (Gaussian) or exp(-r / range) (exponential):
+ *   SNN_PRESET_LATERAL: p = B f(r) for every pair, B chosen so that the
+ *     expected number of recurrent synapses per neuron is k_in;
+ *   SNN_PRESET_PAPER (the paper's own rules, Sec. III.B and the Fig. 2
+ *     caption): p = p_local inside the source's module for every source;
+ *     p = amp f(r) to other modules for excitatory sources only, inside the
+ *     square stencil of half-width ceil(r_c) where amp f(r_c) = p_cut
+ *     (7x7 for the Gaussian, 21x21 for the exponential parameters of the
+ *     paper); k_in is unused.
+ * Delays are uniform integers in [d_min, d_max] ms; excitatory weights
+ * Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh. */
 typedef struct {
     uint32_t kernel;          /* SNN_GAUSS or SNN_EXP                           */
     uint32_t record;          /* SNN_REC_F32 (8 B) or SNN_REC_CODE8 (4 B)       */
@@ -102,6 +110,11 @@ typedef struct {
     double ext_n;             /* number of external synapses per neuron          */
     double ext_rate_hz;       /* their Poisson rate                              */
     double ext_w;             /* their weight (mV)                               */
+    uint32_t preset;          /* SNN_PRESET_LATERAL or SNN_PRESET_PAPER          */
+    uint32_t pad1_;
+    double p_local;           /* paper preset: probability inside a module, [0, 1) */
+    double amp;               /* paper preset: remote amplitude A, [0, 1)         */
+    double p_cut;             /* paper preset: stencil cut-off probability, > 0   */
 } snn_syn_desc;
 
 typedef struct {
@@ -222,8 +235,9 @@ snn_status snn_reset(snn_net* net);
 snn_status snn_set_option(snn_net* net, int key, int64_t value);
 
 /* Host-only (no device work): the integer tables the library derives from a
- * description, for inspection and tests.  T[gy*gx] connection thresholds
- * round(B f(r) 2^32) indexed by torus offset (dy mod gy) * gx + (dx mod gx);
+ * description, for inspection and tests.  T[2][gy*gx] connection thresholds
+ * round(p 2^32) for excitatory (first half) and inhibitory sources, indexed
+ * by torus offset (dy mod gy) * gx + (dx mod gx);
  * wtab[65536] excitatory weights by the top 16 bits of the weight draw;
  * cb[256] the 8-bit codebook; poisc[64] Poisson CDF thresholds (*npois
  * used); consts[3] = {1 - exp(-1/tau_m), 1 - exp(-1/tau_w), kappa} of the

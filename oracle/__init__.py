@@ -158,16 +158,22 @@ def build_rows(net: dict, pre0: int, cnt: int, cap: int | None = None):
     Returns (row_len u64[cnt], bend u16[cnt, D], records bytes)."""
     c = cfg(net)
     D = n_delays(net)
+    grow = cap is None   # no capacity given: start from the in-degree and grow on overflow
     if cap is None:
         cap = int(cnt * (net["k_in"] * 1.5 + 200))
-    row_len = np.zeros(cnt, dtype=np.uint64)
-    bend = np.zeros((cnt, D), dtype=np.uint16)
-    recs = np.zeros(cap * rec_bytes(net), dtype=np.uint8)
-    n_out = C.c_uint64(0)
-    st = lib().or_build_rows(C.byref(c), pre0, cnt, _p(row_len), _p(bend), _p(recs), cap,
-                             C.byref(n_out))
-    if st != 0:
-        raise ValueError(f"oracle build_rows: status {st}")
+    while True:
+        row_len = np.zeros(cnt, dtype=np.uint64)
+        bend = np.zeros((cnt, D), dtype=np.uint16)
+        recs = np.zeros(cap * rec_bytes(net), dtype=np.uint8)
+        n_out = C.c_uint64(0)
+        st = lib().or_build_rows(C.byref(c), pre0, cnt, _p(row_len), _p(bend), _p(recs), cap,
+                                 C.byref(n_out))
+        if st == -5 and grow:
+            cap *= 4
+            continue
+        if st != 0:
+            raise ValueError(f"oracle build_rows: status {st}")
+        break
     return row_len, bend, recs[: int(n_out.value) * rec_bytes(net)].copy()
 
 

@@ -225,6 +225,11 @@ snn::TableParams table_params(const snn_grid_desc& g, const snn_syn_desc& s)
     tp.kernel = s.kernel;
     tp.range = s.range;
     tp.k_in = s.k_in;
+    tp.n_exc = g.n_exc;
+    tp.preset = s.preset;
+    tp.p_local = s.p_local;
+    tp.amp = s.amp;
+    tp.p_cut = s.p_cut;
     tp.w_exc = s.w_exc;
     tp.w_exc_sd = s.w_exc_sd;
     tp.w_inh = s.w_inh;
@@ -341,6 +346,7 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     if (s->kernel > 1u) return fail(n, SNN_E_INVAL, "unknown lateral kernel");
     if (s->record > 1u) return fail(n, SNN_E_INVAL, "unknown record format");
     if (s->ext_mode > 1u) return fail(n, SNN_E_INVAL, "unknown external drive mode");
+    if (s->preset > 1u) return fail(n, SNN_E_INVAL, "unknown connectivity preset");
     if (s->d_min < 1 || s->d_max < s->d_min || s->d_max > snn::kMaxD)
         return fail(n, SNN_E_INVAL, "delays must satisfy 1 <= d_min <= d_max <= 31");
     if (!(s->range > 0) || !(s->k_in >= 0)) return fail(n, SNN_E_INVAL, "bad range or in-degree");
@@ -413,12 +419,13 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     b.ctrl = a.ctrl;
     // Rows are built in slices so that no single launch runs for long: the
     // slice's rows are generated into a buffer of slab_cap hits per row
-    // (8 standard deviations above the expected in-degree), their offsets
-    // scanned, and the records written out.  The record buffer is sized to a
-    // bound on the total (expected total + 10 standard deviations).
+    // (8 standard deviations above the busiest source type's expected row
+    // length), their offsets scanned, and the records written out.  The
+    // record buffer is sized to a bound on the total (expected total + 10
+    // standard deviations).
     const uint32_t slice = 1u << 16;
-    const double kin = s->k_in + 1.0;
-    b.slab_cap = (uint32_t)std::min(kin + 8.0 * std::sqrt(kin) + 256.0, 65536.0);
+    const double kmax = tb.max_out + 1.0, kin = tb.mean_out + 1.0;
+    b.slab_cap = (uint32_t)std::min(kmax + 8.0 * std::sqrt(kmax) + 256.0, 65536.0);
     const double tot_bound = (double)n->N * kin + 10.0 * std::sqrt((double)n->N * kin) + 65536.0;
     const size_t rb = s->record == SNN_REC_CODE8 ? 4 : 8;
     b.rec_cap = (uint64_t)tot_bound;
@@ -471,7 +478,8 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     else if (n->mode_pref < 0) mode = ok1 ? 1 : (ok2 ? 2 : 0);
     if (mode) {
         HIPCHK(n, snn::setup_kernels());
-        const double kin = s->k_in + 6.0 * std::sqrt(s->k_in + 1.0);
+        // the expected in-degree equals the mean row length (every module alike)
+        const double kin = tb.mean_out + 6.0 * std::sqrt(tb.mean_out + 1.0);
         const double frac = mode == 2 ? 0.5 * n->bin_frac : n->bin_frac;   // two levels hold every event twice
         a.bin_cap_tile = (uint32_t)std::min(frac * (double)snn::kTile * kin + 4096.0, 1.0e9);
         e = dalloc(n, &a.bin_fill, (size_t)a.ntiles * snn::kFillStride);
@@ -987,7 +995,10 @@ uint64_t estimate_bytes(const snn_grid_desc& g, const snn_syn_desc& s, uint64_t 
     const uint64_t M = (uint64_t)g.n_exc + g.n_inh, N = (uint64_t)g.gx * g.gy * M;
     const uint64_t D = s.d_max - s.d_min + 1;
     const uint64_t nblk = (N + 1023) / 1024;
-    const double k = s.k_in + 6.0 * std::sqrt(s.k_in + 1.0);
+    std::vector<uint32_t> T;
+    double mean_out = 0.0, max_out = 0.0;
+    if (!snn::connection_tables(table_params(g, s), T, mean_out, max_out).empty()) mean_out = s.k_in;
+    const double k = mean_out + 6.0 * std::sqrt(mean_out + 1.0);
     const uint64_t rec = s.record == SNN_REC_CODE8 ? 4 : 8;
     uint64_t b = N * (4 + 4 + 1) + 32 * N * 4 + nblk * 16 + nblk * 1024 * 16 + N * 16 + hist_cap * 8 + N * 5;
     b += (uint64_t)g.gx * g.gy * 4 + 65536 * 4 + 1024 + 256 + (N + 1) * 8 + N * D * 2;

@@ -166,10 +166,12 @@ __global__ __launch_bounds__(256) void k_syn_gen(BuildArgs a)
     uint32_t* const out = a.slab + (size_t)rl * a.slab_cap;
     const uint32_t M = a.M, gx = a.gx, gy = a.gy;
     const uint32_t mi = row / M, xi = mi % gx, yi = mi / gx;
+    // the source's type selects its threshold table (excitatory first)
+    const uint32_t* const Tsrc = a.T + ((row % M) < a.n_exc ? 0u : gx * gy);
     uint32_t n = 0;   // hits so far (wave-uniform)
     for (uint32_t yj = 0; yj < gy; ++yj) {
         const uint32_t dyr = yj >= yi ? yj - yi : yj + gy - yi;
-        const uint32_t* Trow = a.T + dyr * gx;
+        const uint32_t* Trow = Tsrc + dyr * gx;
         for (uint32_t xj = 0; xj < gx; ++xj) {
             const uint32_t dxr = xj >= xi ? xj - xi : xj + gx - xi;
             const uint32_t T = Trow[dxr];

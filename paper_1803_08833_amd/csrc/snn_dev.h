@@ -115,7 +115,7 @@ struct BuildArgs {
     uint32_t key0, key1;
     int32_t winh_q;
     uint32_t row0, nrows;      // rows built by this launch
-    const uint32_t* T;         // [gy][gx] thresholds per torus offset
+    const uint32_t* T;         // [2][gy][gx] thresholds per torus offset (excitatory, inhibitory sources)
     const int32_t* wtab;       // [65536]
     uint16_t* bend;            // [N][D]
     uint32_t* rowlen;          // [N]

@@ -1,10 +1,13 @@
 // tables.cpp -- FP64 host tables that turn the model's real-valued laws into the
 // integer tables the kernels use.
 //
-//   * connection thresholds: p(offset) = B f(r) with f the Gaussian
-//     exp(-r^2/2 sigma^2) or exponential exp(-r/lambda) lateral law (Sec. I,
-//     Sec. III.B); B makes the expected recurrent in-degree equal to k_in
-//     ("fixes the total"); stored as round(p * 2^32);
+//   * connection thresholds, per source type: p(offset) = B f(r) with f the
+//     Gaussian exp(-r^2/2 sigma^2) or exponential exp(-r/lambda) lateral law
+//     (Sec. I, Sec. III.B), B making the expected recurrent in-degree equal
+//     to k_in ("fixes the total"); or the paper's own rules (Sec. III.B, Fig. 2
+//     caption): p_local inside the module, amp f(r) elsewhere for excitatory
+//     sources only, within the square stencil the 1/1000 cut-off gives;
+//     stored as round(p * 2^32);
 //   * excitatory weights: Gaussian efficacies (Sec. II.B) as the conditional
 //     means of 65536 equiprobable bins (and of 255 bins for the 8-bit codebook);
 //   * external drive: Poisson count per 1 ms step (Sec. III.A) by integer CDF
@@ -74,29 +77,84 @@ double inv_norm_cdf(double u)
     return inv_lower(u);
 }
 
-std::string build_tables(const TableParams& p, HostTables& out)
+namespace {
+
+// Half-width of the paper preset's square stencil: the first whole number of
+// module spacings at or past the distance where amp f(r) falls to p_cut.
+int stencil_half_width(const TableParams& p)
+{
+    if (!(p.amp > p.p_cut)) return 0;
+    const double ratio = std::log(p.amp / p.p_cut);
+    const double rc = p.kernel == 0 ? p.range * std::sqrt(2.0 * ratio) : p.range * ratio;
+    return (int)std::ceil(rc);
+}
+
+std::string threshold(double prob, uint32_t& out)
+{
+    const double thr = std::nearbyint(prob * kTwo32);
+    if (!(thr >= 0.0 && thr < kTwo32)) return "connection probability outside [0, 1)";
+    out = (uint32_t)thr;
+    return std::string();
+}
+
+}  // namespace
+
+std::string connection_tables(const TableParams& p, std::vector<uint32_t>& T, double& mean_out, double& max_out)
 {
     const int gx = (int)p.gx, gy = (int)p.gy;
+    const size_t S = (size_t)gx * gy;
+    T.assign(2 * S, 0u);
+    std::string why;
+    if (p.preset == 1) {
+        if (!(p.p_local >= 0.0 && p.p_local < 1.0) || !(p.amp >= 0.0 && p.amp < 1.0) || !(p.p_cut > 0.0))
+            return "paper preset needs 0 <= p_local < 1, 0 <= amp < 1 and p_cut > 0";
+        const int h = stencil_half_width(p);
+        for (int ry = 0; ry < gy; ++ry) {
+            for (int rx = 0; rx < gx; ++rx) {
+                const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
+                double pe = 0.0, pi = 0.0;
+                if (rx == 0 && ry == 0) pe = pi = p.p_local;
+                else if (std::abs(dx) <= h && std::abs(dy) <= h) pe = p.amp * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
+                why = threshold(pe, T[(size_t)ry * gx + rx]);
+                if (why.empty()) why = threshold(pi, T[S + (size_t)ry * gx + rx]);
+                if (!why.empty()) return why;
+            }
+        }
+    } else {
+        double total = 0.0;
+        for (int ry = 0; ry < gy; ++ry) {
+            for (int rx = 0; rx < gx; ++rx) {
+                const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
+                const double cand = (rx == 0 && ry == 0) ? (double)p.M - 1.0 : (double)p.M;
+                total += cand * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
+            }
+        }
+        const double B = p.k_in > 0.0 ? p.k_in / total : 0.0;
+        for (int ry = 0; ry < gy; ++ry) {
+            for (int rx = 0; rx < gx; ++rx) {
+                const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
+                why = threshold(B * lateral_law(p.kernel, p.range, dx * dx + dy * dy), T[(size_t)ry * gx + rx]);
+                if (!why.empty()) return "connection probability reaches 1: k_in too large for this grid";
+                T[S + (size_t)ry * gx + rx] = T[(size_t)ry * gx + rx];
+            }
+        }
+    }
+    // expected out-degree per source type: sum over offsets of candidates x p
+    double out_deg[2] = {0.0, 0.0};
+    for (int type = 0; type < 2; ++type)
+        for (size_t o = 0; o < S; ++o)
+            out_deg[type] += ((o == 0) ? (double)p.M - 1.0 : (double)p.M) * (double)T[type * S + o] / kTwo32;
+    const double fe = p.M ? (double)p.n_exc / (double)p.M : 1.0;
+    mean_out = fe * out_deg[0] + (1.0 - fe) * out_deg[1];
+    max_out = std::max(p.n_exc ? out_deg[0] : 0.0, p.n_exc < p.M ? out_deg[1] : 0.0);
+    return std::string();
+}
+
+std::string build_tables(const TableParams& p, HostTables& out)
+{
     // --- connection thresholds -------------------------------------------
-    double total = 0.0;
-    for (int ry = 0; ry < gy; ++ry) {
-        for (int rx = 0; rx < gx; ++rx) {
-            const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
-            const double cand = (rx == 0 && ry == 0) ? (double)p.M - 1.0 : (double)p.M;
-            total += cand * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
-        }
-    }
-    out.B = p.k_in > 0.0 ? p.k_in / total : 0.0;
-    out.T.assign((size_t)gx * gy, 0u);
-    for (int ry = 0; ry < gy; ++ry) {
-        for (int rx = 0; rx < gx; ++rx) {
-            const int dx = signed_offset(rx, gx), dy = signed_offset(ry, gy);
-            const double prob = out.B * lateral_law(p.kernel, p.range, dx * dx + dy * dy);
-            const double thr = std::nearbyint(prob * kTwo32);
-            if (!(thr < kTwo32)) return "connection probability reaches 1: k_in too large for this grid";
-            out.T[(size_t)ry * gx + rx] = (uint32_t)thr;
-        }
-    }
+    std::string why = connection_tables(p, out.T, out.mean_out, out.max_out);
+    if (!why.empty()) return why;
     // --- weights -----------------------------------------------------------
     out.wtab.resize(65536);
     for (int k = 0; k < 65536; ++k)

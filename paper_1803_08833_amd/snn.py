@@ -52,6 +52,8 @@ class SynDesc(C.Structure):
         ("w_exc", C.c_double), ("w_exc_sd", C.c_double), ("w_inh", C.c_double),
         ("ext_mode", C.c_uint32), ("ext_const_q", C.c_int32),
         ("ext_n", C.c_double), ("ext_rate_hz", C.c_double), ("ext_w", C.c_double),
+        ("preset", C.c_uint32), ("pad1_", C.c_uint32),
+        ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
     ]
 
 
@@ -143,6 +145,8 @@ def syn_desc(net: dict) -> SynDesc:
     for k in ("kernel", "record", "range", "k_in", "d_min", "d_max", "w_exc", "w_exc_sd", "w_inh",
               "ext_mode", "ext_const_q", "ext_n", "ext_rate_hz", "ext_w"):
         setattr(s, k, net[k])
+    for k in ("preset", "p_local", "amp", "p_cut"):   # connectivity preset (absent: the lateral law)
+        setattr(s, k, net.get(k, 0))
     return s
 
 
@@ -156,7 +160,7 @@ def current_stream_handle():
 def host_tables(net: dict) -> dict:
     """The library's own integer tables for a description (host computation)."""
     g, s = grid_desc(net), syn_desc(net)
-    T = np.zeros(net["gx"] * net["gy"], dtype=np.uint32)
+    T = np.zeros(2 * net["gx"] * net["gy"], dtype=np.uint32)
     wtab = np.zeros(65536, dtype=np.int32)
     cb = np.zeros(256, dtype=np.int32)
     poisc = np.zeros(64, dtype=np.uint32)
@@ -166,7 +170,8 @@ def host_tables(net: dict) -> dict:
                                _p(consts))
     if st != SNN_OK:
         raise SNNError(st, lib().snn_last_error(None).decode())
-    return dict(T=T.reshape(net["gy"], net["gx"]), wtab=wtab, cb=cb, poisc=poisc[: int(npois[0])].copy(),
+    T = T.reshape(2, net["gy"], net["gx"])
+    return dict(T=T[0].copy(), T_inh=T[1].copy(), wtab=wtab, cb=cb, poisc=poisc[: int(npois[0])].copy(),
                 dm=consts[0], dw=consts[1], kappa=consts[2])
 
 

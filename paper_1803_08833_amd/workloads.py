@@ -84,6 +84,21 @@ WORKLOADS = {
     "grid24_exp": dict(net=make(24, 24, EXP, 5.0, 1100, 3, ext_rate_hz=2.05), steps=10000),
     # 96x96 exponential, lambda 8 modules, 2600 synapses/neuron, 8-bit codes.
     "grid96_exp_code8": dict(net=make(96, 96, EXP, 8.0, 2600, 5, record=REC_CODE8), steps=2000),
+    # The paper's own connectivity (80 % local, remote A f(r) for excitatory
+    # sources within the 7x7 / 21x21 stencil): ~1253 / ~2393 synapses per
+    # neuron, of which ~1055 / ~2195 excitatory and ~198 inhibitory.  The
+    # paper prints no weights; with the excitatory weight kept at 0.4 mV the
+    # inhibitory weight is scaled so that the mean inhibitory input is 1.2 x
+    # the excitatory one (at -1.6 mV both grids fire at the refractory limit);
+    # 2 Hz drive then gives asynchronous activity at ~2 Hz.  24x24 with 8-byte
+    # records (single-level binning); 48x48, the middle size of the paper's
+    # problem table (2.9 M neurons, 6.8 G synapses on the torus), with 8-bit
+    # codes (two-level binning).
+    "grid24_gauss_paper": dict(net=make_paper(24, 24, PAPER_GAUSS, 6, w_inh=-2.6, ext_rate_hz=2.0),
+                               steps=10000),
+    "grid24_exp_paper": dict(net=make_paper(24, 24, PAPER_EXP, 7, w_inh=-5.3, ext_rate_hz=2.0), steps=10000),
+    "grid48_exp_paper_code8": dict(net=make_paper(48, 48, PAPER_EXP, 8, w_inh=-5.3, ext_rate_hz=2.0,
+                                                  record=REC_CODE8), steps=2000),
 }
 
 

@@ -54,12 +54,14 @@ def test_product_never_touches_the_oracle():
                 assert "or_net" not in src and "liboracle" not in src, f
 
 
-@pytest.mark.parametrize("name", ["grid4_gauss", "grid24_gauss", "grid24_exp", "grid96_exp_code8"])
+@pytest.mark.parametrize("name", ["grid4_gauss", "grid24_gauss", "grid24_exp", "grid96_exp_code8",
+                                  "grid24_gauss_paper", "grid48_exp_paper_code8"])
 def test_library_tables_equal_oracle_tables(snn, oracle_mod, name):
     net = W.workload(name)["net"]
     lt = snn.host_tables(net)
     ot = oracle_mod.tables(net)
     np.testing.assert_array_equal(lt["T"], ot["T"])
+    np.testing.assert_array_equal(lt["T_inh"], ot["T_inh"])
     np.testing.assert_array_equal(lt["wtab"], ot["wtab"])
     np.testing.assert_array_equal(lt["cb"], ot["cb"])
     np.testing.assert_array_equal(lt["poisc"], ot["poisc"])
@@ -86,3 +88,8 @@ def test_invalid_descriptions_are_rejected_on_the_host(snn):
         snn.host_tables(dict(base, k_in=19839.0))
     with pytest.raises(snn.SNNError):
         snn.host_tables(dict(base, ext_rate_hz=1e5))
+    # paper preset: probabilities outside [0, 1), no cut-off
+    paper = W.make_paper(4, 4, W.PAPER_GAUSS, 1)
+    for over in (dict(p_local=1.0), dict(amp=-0.1), dict(p_cut=0.0)):
+        with pytest.raises(snn.SNNError):
+            snn.host_tables(dict(paper, **over))
