@@ -64,6 +64,12 @@
 #define ST_ATTR 2u
 #define ST_EXT 3u
 #define ST_INIT 4u
+#define ST_COUNT 5u        /* binomial generator: synapse count per (source, module) */
+#define ST_PICK 6u         /* binomial generator: Floyd's draws                     */
+
+#define OR_GEN_PAIRWISE 0
+#define OR_GEN_BINOMIAL 1
+#define BINOM_MAX_M 4096   /* binomial generator: largest module               */
 
 /* Flat description of one network.  Times in ms, potentials in mV. */
 typedef struct {
@@ -87,6 +93,8 @@ typedef struct {
     double p_local;           /* paper preset: probability inside a module    */
     double amp;               /* paper preset: remote law amplitude A         */
     double p_cut;             /* paper preset: stencil cut-off probability    */
+    uint32_t gen;             /* OR_GEN_PAIRWISE / OR_GEN_BINOMIAL            */
+    uint32_t pad3_;
 } or_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -158,9 +166,18 @@ static int32_t fixq(double mv) { return (int32_t)nearbyint(mv * 65536.0); }
 /* ------------------------------------------------------------------------ */
 /* Tables                                                                   */
 /* ------------------------------------------------------------------------ */
+/* Binomial count table of one (source type, offset): thresholds of counts
+ * k0 .. k0 + len - 1 at thr[at ..]; counts below k0 have threshold 0. */
+typedef struct {
+    uint32_t k0, len;
+    size_t at;
+} or_binom;
+
 typedef struct {
     uint32_t *T;            /* [2][gy*gx] connection thresholds per torus offset,
                                for excitatory (0) and inhibitory (1) sources    */
+    or_binom *bt;           /* binomial generator: [2][gy*gx] count tables      */
+    uint32_t *bthr;         /* their thresholds                                 */
     int32_t wtab[65536];    /* excitatory weight by top 16 bits of the draw   */
     int32_t cb[256];        /* 8-bit weight codebook                          */
     uint32_t poisc[POIS_MAX];
@@ -297,6 +314,58 @@ static int make_poisson(const or_cfg *c, uint32_t *poisc, uint32_t *npois)
     return OR_E_INVAL; /* distribution not exhausted within the table */
 }
 
+/* Binomial generator (the exact-distribution alternative to one trial per
+ * pair): for a source and a target module with n candidates and pair
+ * probability p = T / 2^32, the number of synapses is Binomial(n, p), drawn
+ * by integer CDF thresholds round(2^32 F(k)), F summed in increasing k from
+ * pmf(k) = exp(lgamma(n+1) - lgamma(k+1) - lgamma(n-k+1) + k log p +
+ * (n-k) log1p(-p)); counts whose threshold rounds to 2^32 are never drawn. */
+static int make_binomial(const or_cfg *c, or_tables *tb)
+{
+    size_t S = (size_t)c->gx * c->gy, cap = 4096, used = 0;
+    uint32_t M = module_size(c);
+    tb->bt = (or_binom *)calloc(2 * S, sizeof(or_binom));
+    tb->bthr = (uint32_t *)malloc(cap * sizeof(uint32_t));
+    if (!tb->bt || !tb->bthr) return OR_E_NOMEM;
+    for (size_t e = 0; e < 2 * S; e++) {
+        uint32_t T = tb->T[e];
+        tb->bt[e].at = used;
+        if (T == 0) continue;
+        uint32_t n = (e % S == 0) ? M - 1 : M;
+        double p = (double)T / 4294967296.0;
+        double lp = log(p), lq = log1p(-p), ln = lgamma((double)n + 1.0), F = 0.0;
+        uint32_t k0 = 0, len = 0;   /* k0: leading counts whose threshold rounds to 0 */
+        for (uint32_t k = 0; k <= n; k++) {
+            F += exp(ln - lgamma((double)k + 1.0) - lgamma((double)(n - k) + 1.0) + (double)k * lp +
+                     (double)(n - k) * lq);
+            double q = nearbyint(F * 4294967296.0);
+            if (q >= 4294967296.0) break;
+            if (q <= 0.0) {
+                k0++;
+                continue;
+            }
+            if (used == cap) {
+                cap *= 2;
+                uint32_t *nb = (uint32_t *)realloc(tb->bthr, cap * sizeof(uint32_t));
+                if (!nb) return OR_E_NOMEM;
+                tb->bthr = nb;
+            }
+            tb->bthr[used++] = (uint32_t)q;
+            len++;
+        }
+        tb->bt[e].k0 = k0;
+        tb->bt[e].len = len;
+    }
+    return OR_OK;
+}
+
+static void free_tables(or_tables *tb)
+{
+    free(tb->T);
+    free(tb->bt);
+    free(tb->bthr);
+}
+
 static int make_tables(const or_cfg *c, or_tables *tb)
 {
     if (c->gx == 0 || c->gy == 0 || module_size(c) == 0) return OR_E_INVAL;
@@ -312,6 +381,12 @@ static int make_tables(const or_cfg *c, or_tables *tb)
     if (!tb->T) return OR_E_NOMEM;
     int st = make_thresholds(c, tb->T);
     if (st) return st;
+    if (c->gen > OR_GEN_BINOMIAL) return OR_E_INVAL;
+    if (c->gen == OR_GEN_BINOMIAL) {
+        if (module_size(c) > BINOM_MAX_M) return OR_E_INVAL;
+        st = make_binomial(c, tb);
+        if (st) return st;
+    }
     make_wtab(c, tb->wtab);
     make_codebook(c, tb->cb);
     tb->npois = 0;
@@ -351,7 +426,7 @@ int or_make_tables(const or_cfg *c, uint32_t *T, int32_t *wtab, int32_t *cb,
         if (consts) { consts[0] = tb->dm; consts[1] = tb->dw; consts[2] = tb->kappa; }
         if (iconsts) { iconsts[0] = (int32_t)tb->nref; iconsts[1] = tb->jext_q; iconsts[2] = tb->winh_q; }
     }
-    free(tb->T);
+    free_tables(tb);
     free(tb);
     return st;
 }
@@ -374,9 +449,18 @@ static uint32_t pair_threshold(const or_cfg *c, const or_tables *tb, uint32_t i,
 
 /* Does neuron i project a synapse onto neuron j?  One Bernoulli trial per
  * ordered pair, no self-connections, at most one synapse per pair. */
+static uint32_t module_subset(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t mj, uint8_t *in);
+
 static int connects(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t j)
 {
     if (i == j) return 0;
+    if (c->gen == OR_GEN_BINOMIAL) {
+        uint8_t in[BINOM_MAX_M];
+        uint32_t M = module_size(c), mj = j / M, l = j % M;
+        module_subset(c, tb, i, mj, in);
+        if (mj == i / M && l > i % M) l--;
+        return in[l];
+    }
     uint32_t r[4];
     philox_draw(c->seed, i, j >> 2, ST_CONN, r);
     return r[j & 3u] < pair_threshold(c, tb, i, j);
@@ -421,6 +505,41 @@ typedef struct {
 
 /* The projection of neuron i: every j with connects(i, j), ordered by
  * (delay, target).  Returns the count; *out is malloc'ed. */
+/* Binomial generator, one (source i, target module mj): the count is the
+ * number of the table's thresholds not above the draw Philox(i, mj, COUNT)[0];
+ * the targets are a uniform random c-subset of the n candidates by Floyd's
+ * algorithm (for j = n - c .. n - 1: t uniform in [0, j] from Philox(i, mj,
+ * PICK, j / 4)[j % 4] as mulhi(draw, j + 1); take t, or j if t is already
+ * taken).  Candidate l is neuron l of module mj, skipping the source itself
+ * in its own module.  in[] (n flags) receives the subset; returns c. */
+static uint32_t module_subset(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_t mj, uint8_t *in)
+{
+    uint32_t M = module_size(c), mi = i / M;
+    uint32_t xi = mi % c->gx, yi = mi / c->gx, xj = mj % c->gx, yj = mj / c->gx;
+    size_t S = (size_t)c->gx * c->gy;
+    size_t off = ((yj + c->gy - yi) % c->gy) * c->gx + (xj + c->gx - xi) % c->gx;
+    size_t e = ((i % M) < c->n_exc ? 0 : S) + off;
+    uint32_t n = (mj == mi) ? M - 1 : M;
+    memset(in, 0, n);
+    if (tb->T[e] == 0) return 0;
+    uint32_t r[4];
+    philox_draw(c->seed, i, mj, ST_COUNT, r);
+    const or_binom *b = &tb->bt[e];
+    uint32_t cnt = b->k0;
+    for (uint32_t k = 0; k < b->len; k++)
+        if (tb->bthr[b->at + k] <= r[0]) cnt++;
+    for (uint32_t j = n - cnt; j < n; j++) {
+        uint32_t w[4];
+        uint32_t ctr[4] = {i, mj, ST_PICK, j >> 2};
+        uint32_t key[2] = {(uint32_t)c->seed, (uint32_t)(c->seed >> 32)};
+        or_philox(ctr, key, w);
+        uint32_t t = (uint32_t)(((uint64_t)w[j & 3u] * (uint64_t)(j + 1u)) >> 32);
+        if (in[t]) in[j] = 1;
+        else in[t] = 1;
+    }
+    return cnt;
+}
+
 static int64_t build_row(const or_cfg *c, const or_tables *tb, uint32_t i, or_syn **out, int want_fp64)
 {
     uint32_t N = c->gx * c->gy * module_size(c);
@@ -428,8 +547,22 @@ static int64_t build_row(const or_cfg *c, const or_tables *tb, uint32_t i, or_sy
     size_t cap = 1024, n = 0;
     or_syn *hits = (or_syn *)malloc(cap * sizeof(or_syn));
     if (!hits) return OR_E_NOMEM;
+    uint8_t *in = NULL;
+    if (c->gen == OR_GEN_BINOMIAL) {
+        in = (uint8_t *)malloc(module_size(c));
+        if (!in) { free(hits); return OR_E_NOMEM; }
+    }
     for (uint32_t j = 0; j < N; j++) {
-        if (!connects(c, tb, i, j)) continue;
+        if (c->gen == OR_GEN_BINOMIAL) {
+            /* module by module: the module's subset, targets ascending */
+            uint32_t M = module_size(c), mj = j / M;
+            if (j % M == 0) module_subset(c, tb, i, mj, in);
+            uint32_t l = j % M, self = (mj == i / M) ? i % M : M;
+            if (l == self) continue;
+            if (!in[l < self ? l : l - 1]) continue;
+        } else if (!connects(c, tb, i, j)) {
+            continue;
+        }
         if (n == cap) {
             cap *= 2;
             or_syn *nh = (or_syn *)realloc(hits, cap * sizeof(or_syn));
@@ -442,6 +575,7 @@ static int64_t build_row(const or_cfg *c, const or_tables *tb, uint32_t i, or_sy
         s.wf = want_fp64 ? attributes_fp64_weight(c, i, j) : 0.0;
         hits[n++] = s;
     }
+    free(in);
     /* stable counting sort by delay: targets stay ascending within a delay */
     or_syn *sorted = (or_syn *)malloc((n ? n : 1) * sizeof(or_syn));
     if (!sorted) { free(hits); return OR_E_NOMEM; }
@@ -610,7 +744,7 @@ int or_build_rows(const or_cfg *c, uint32_t pre0, uint32_t cnt, uint64_t *row_le
         free(row);
     }
     *n_out = total;
-    free(tb->T);
+    free_tables(tb);
     free(tb);
     if (st == OR_OK && total > rec_cap) return OR_E_OVERFLOW;
     return st;
@@ -633,7 +767,7 @@ int or_col_input(const or_cfg *c, uint32_t j, const uint32_t *pres, uint64_t np,
         attributes(c, tb, i, j, &delay, &wq, &code);
         per_delay[delay - c->d_min] += wq;
     }
-    free(tb->T);
+    free_tables(tb);
     free(tb);
     return st;
 }

@@ -41,7 +41,12 @@ SYNAPSE = dict(
     # lateral preset: one distance law normalised to k_in; the paper preset's
     # parameters below are unused by it
     preset=PRESET_LATERAL, p_local=0.0, amp=0.0, p_cut=0.0,
+    # synapse generator: one Bernoulli trial per ordered pair, or a binomial
+    # count per (source, target module) and a uniform subset of that size
+    gen=0,
 )
+GEN_PAIRWISE = 0
+GEN_BINOMIAL = 1
 
 # The paper's own connectivity (Sec. III.B): 80 % inside the module, remote
 # probability A f(r) for excitatory sources only, cut off at 1/1000; at one
