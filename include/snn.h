@@ -55,6 +55,7 @@ enum { SNN_GAUSS = 0, SNN_EXP = 1 };
 enum { SNN_REC_F32 = 0, SNN_REC_CODE8 = 1 };
 enum { SNN_EXT_POISSON = 0, SNN_EXT_CONST = 1 };
 enum { SNN_PRESET_LATERAL = 0, SNN_PRESET_PAPER = 1 };
+enum { SNN_GEN_PAIRWISE = 0, SNN_GEN_BINOMIAL = 1 };
 
 typedef struct snn_net snn_net;
 
@@ -97,7 +98,13 @@ typedef struct {
  *     (7x7 for the Gaussian, 21x21 for the exponential parameters of the
  *     paper); k_in is unused.
  * Delays are uniform integers in [d_min, d_max] ms; excitatory weights
- * Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh. */
+ * Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh.
+ * Generator: SNN_GEN_PAIRWISE draws one Bernoulli trial per ordered pair
+ * (Philox stream 1); SNN_GEN_BINOMIAL draws, per source and target module,
+ * the number of synapses from Binomial(n, p) by integer CDF thresholds
+ * (stream 5) and then which n candidates by Floyd's algorithm (stream 6) --
+ * the same law with different bits, in work proportional to modules and
+ * synapses instead of pairs (modules of at most 4096 neurons). */
 typedef struct {
     uint32_t kernel;          /* SNN_GAUSS or SNN_EXP                           */
     uint32_t record;          /* SNN_REC_F32 (8 B) or SNN_REC_CODE8 (4 B)       */
@@ -115,6 +122,8 @@ typedef struct {
     double p_local;           /* paper preset: probability inside a module, [0, 1) */
     double amp;               /* paper preset: remote amplitude A, [0, 1)         */
     double p_cut;             /* paper preset: stencil cut-off probability, > 0   */
+    uint32_t gen;             /* SNN_GEN_PAIRWISE or SNN_GEN_BINOMIAL            */
+    uint32_t pad2_;
 } snn_syn_desc;
 
 typedef struct {

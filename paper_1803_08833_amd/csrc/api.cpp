@@ -230,6 +230,7 @@ snn::TableParams table_params(const snn_grid_desc& g, const snn_syn_desc& s)
     tp.p_local = s.p_local;
     tp.amp = s.amp;
     tp.p_cut = s.p_cut;
+    tp.gen = s.gen;
     tp.w_exc = s.w_exc;
     tp.w_exc_sd = s.w_exc_sd;
     tp.w_inh = s.w_inh;
@@ -388,7 +389,16 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     if (e == hipSuccess) e = dalloc(n, &bend, (size_t)n->N * n->D);
     if (e == hipSuccess) e = dalloc(n, &rowlen, n->N);
     if (e == hipSuccess) e = dalloc(n, &tsum, snn::scan_tiles(n->N) + 1);
+    uint32_t* btab = nullptr;   // binomial generator tables (construction only)
+    uint32_t* bthr = nullptr;
+    if (e == hipSuccess && s->gen == SNN_GEN_BINOMIAL) {
+        e = dalloc(n, &btab, tb.btab.size());
+        if (e == hipSuccess) e = dalloc(n, &bthr, tb.bthr.size());
+    }
     if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (tables/offsets)");
+    if (btab) HIPCHK(n, hipMemcpyAsync(btab, tb.btab.data(), tb.btab.size() * 4, hipMemcpyHostToDevice, n->stream));
+    if (bthr && !tb.bthr.empty())
+        HIPCHK(n, hipMemcpyAsync(bthr, tb.bthr.data(), tb.bthr.size() * 4, hipMemcpyHostToDevice, n->stream));
     HIPCHK(n, hipMemcpyAsync(n->T, tb.T.data(), tb.T.size() * 4, hipMemcpyHostToDevice, n->stream));
     HIPCHK(n, hipMemcpyAsync(n->wtab, tb.wtab.data(), 65536 * 4, hipMemcpyHostToDevice, n->stream));
     HIPCHK(n, hipMemcpyAsync(cb, tb.cb.data(), 256 * 4, hipMemcpyHostToDevice, n->stream));
@@ -400,6 +410,9 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     a.bend = bend;
 
     snn::BuildArgs b{};
+    b.gen = s->gen;
+    b.btab = reinterpret_cast<const uint4*>(btab);
+    b.bthr = bthr;
     b.N = n->N;
     b.M = n->M;
     b.n_exc = n->g.n_exc;
@@ -450,6 +463,8 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     HIPCHK(n, hipMemcpyAsync(&nnz, row_ptr + n->N, 8, hipMemcpyDeviceToHost, n->stream));
     HIPCHK(n, hipStreamSynchronize(n->stream));
     dfree(n, slab);
+    dfree(n, btab);
+    dfree(n, bthr);
     if (hc.err & 1u) return fail(n, SNN_E_OVERFLOW, "a projection row exceeds 65535 synapses");
     if (hc.err & 2u) return fail(n, SNN_E_OVERFLOW, "a projection row exceeds the construction buffer");
     if (hc.err & 4u) return fail(n, SNN_E_OVERFLOW, "the synapse total exceeds its bound");

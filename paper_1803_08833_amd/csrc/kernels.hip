@@ -155,6 +155,76 @@ __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q,
     wave_sync();
 }
 
+// Binomial generator, one row (one wave): the lanes take 64 target modules at
+// a time and draw each module's count (one COUNT draw, binary search of the
+// module's CDF thresholds); the modules with a nonzero count then take turns,
+// in ascending order: Floyd's algorithm picks the subset into a bitmap held
+// two 32-bit words per lane (candidates 0..4095), and the set bits are written
+// out ascending.  Candidate l of the source's own module skips the source.
+__device__ void syn_gen_binomial(const BuildArgs& a, uint32_t row, uint32_t lane, uint32_t* out, uint32_t& n)
+{
+    const uint32_t M = a.M, gx = a.gx, gy = a.gy, S = gx * gy;
+    const uint32_t mi = row / M, xi = mi % gx, yi = mi / gx, li = row % M;
+    const uint32_t tsel = li < a.n_exc ? 0u : S;
+    for (uint32_t m0 = 0; m0 < S; m0 += 64u) {
+        const uint32_t mj = m0 + lane;
+        uint32_t cnt = 0;
+        if (mj < S) {
+            const uint32_t xj = mj % gx, yj = mj / gx;
+            const uint32_t e = tsel + ((yj + gy - yi) % gy) * gx + (xj + gx - xi) % gx;
+            if (a.T[e] != 0u) {
+                const uint32_t u = philox(row, mj, kStreamCount, 0u, a.key0, a.key1).x;
+                const uint4 b = a.btab[e];
+                const uint32_t* thr = a.bthr + ((uint64_t)b.w << 32 | b.z);
+                uint32_t lo = 0, hi = b.y;   // thresholds not above u: [0, lo)
+                while (lo < hi) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (thr[mid] <= u) lo = mid + 1u;
+                    else hi = mid;
+                }
+                cnt = b.x + lo;
+            }
+        }
+        uint64_t has = __ballot(cnt != 0u);
+        while (has) {
+            const uint32_t l = (uint32_t)__builtin_ctzll(has);
+            has &= has - 1u;
+            const uint32_t c = readlane(cnt, l), mt = m0 + l;
+            const uint32_t nn = mt == mi ? M - 1u : M;
+            uint32_t w0 = 0, w1 = 0;   // candidate bits [32 lane, +32) and [2048 + 32 lane, +32)
+            uint4 pr = make_uint4(0, 0, 0, 0);
+            for (uint32_t j = nn - c; j < nn; ++j) {
+                if (j == nn - c || (j & 3u) == 0u) pr = philox(row, mt, kStreamPick, j >> 2, a.key0, a.key1);
+                const uint32_t q = j & 3u;
+                const uint32_t w = q == 0u ? pr.x : (q == 1u ? pr.y : (q == 2u ? pr.z : pr.w));
+                const uint32_t t = __umulhi(w, j + 1u);
+                const uint32_t wt = t >> 5;
+                const uint32_t word = (wt >> 6) ? readlane(w1, wt & 63u) : readlane(w0, wt & 63u);
+                const uint32_t x = ((word >> (t & 31u)) & 1u) ? j : t;
+                const uint32_t wx = x >> 5;
+                if (lane == (wx & 63u)) {
+                    if (wx >> 6) w1 |= 1u << (x & 31u);
+                    else w0 |= 1u << (x & 31u);
+                }
+            }
+            for (uint32_t h = 0; h < 2u; ++h) {
+                uint32_t bits = h ? w1 : w0;
+                const uint32_t pc = popc(bits);
+                const uint32_t incl = wave_incl_scan<uint32_t>(pc, lane);
+                uint32_t o = n + incl - pc;
+                while (bits) {
+                    uint32_t cand = 2048u * h + 32u * lane + (uint32_t)__builtin_ctz(bits);
+                    bits &= bits - 1u;
+                    if (mt == mi && cand >= li) ++cand;
+                    if (o < a.slab_cap) out[o] = mt * M + cand;
+                    ++o;
+                }
+                n += readlane(incl, 63u);
+            }
+        }
+    }
+}
+
 // Generation (one wave per row): the row's hits, targets ascending, go to the
 // row's slot of the slice buffer (capacity slab_cap); the row length too.
 __global__ __launch_bounds__(256) void k_syn_gen(BuildArgs a)
@@ -164,6 +234,17 @@ __global__ __launch_bounds__(256) void k_syn_gen(BuildArgs a)
     if (rl >= a.nrows) return;
     const uint32_t row = a.row0 + rl;
     uint32_t* const out = a.slab + (size_t)rl * a.slab_cap;
+    if (a.gen) {
+        uint32_t n = 0;
+        syn_gen_binomial(a, row, lane, out, n);
+        if (lane == 0) {
+            a.rowlen[row] = n;
+            atomicMax(&a.ctrl->max_len, n);
+            if (n > 65535u) atomicOr(&a.ctrl->err, 1u);
+            if (n > a.slab_cap) atomicOr(&a.ctrl->err, 2u);
+        }
+        return;
+    }
     const uint32_t M = a.M, gx = a.gx, gy = a.gy;
     const uint32_t mi = row / M, xi = mi % gx, yi = mi / gx;
     // the source's type selects its threshold table (excitatory first)

@@ -31,6 +31,8 @@ constexpr uint32_t kSuperBits = 16;
 
 // Philox stream identifiers (third counter word).
 constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
+// binomial synapse generator: count per (source, module), then Floyd's draws
+constexpr uint32_t kStreamCount = 5u, kStreamPick = 6u;
 
 struct Rec8 {        // 8-byte record: target and weight in mV (an exact multiple of 2^-16)
     uint32_t tgt;
@@ -125,6 +127,9 @@ struct BuildArgs {
     uint32_t* slab;            // [nrows][slab_cap] hits of the slice's rows
     uint32_t slab_cap;
     Ctrl* ctrl;
+    uint32_t gen;              // 0 one trial per pair, 1 binomial count + Floyd subset
+    const uint4* btab;         // gen 1: [2][gy][gx] {k0, len, at lo, at hi} count tables
+    const uint32_t* bthr;      // gen 1: their thresholds
 };
 
 // ---- launchers (kernels.hip) ----

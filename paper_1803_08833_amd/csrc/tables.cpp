@@ -150,11 +150,55 @@ std::string connection_tables(const TableParams& p, std::vector<uint32_t>& T, do
     return std::string();
 }
 
+// Binomial generator: for a (source type, offset) with threshold T > 0 and n
+// candidates, the count thresholds round(2^32 F(k)) of Binomial(n, T / 2^32),
+// F summed in increasing k from pmf(k) = exp(lgamma(n+1) - lgamma(k+1) -
+// lgamma(n-k+1) + k log p + (n-k) log1p(-p)); leading counts whose threshold
+// rounds to 0 are folded into k0, and the table ends before the first
+// threshold that rounds to 2^32.
+static void binomial_tables(const TableParams& p, HostTables& out)
+{
+    const size_t S = (size_t)p.gx * p.gy;
+    out.btab.assign(4 * 2 * S, 0u);
+    out.bthr.clear();
+    for (size_t e = 0; e < 2 * S; ++e) {
+        const uint64_t at = out.bthr.size();
+        out.btab[4 * e + 2] = (uint32_t)at;
+        out.btab[4 * e + 3] = (uint32_t)(at >> 32);
+        const uint32_t T = out.T[e];
+        if (T == 0) continue;
+        const uint32_t n = (e % S == 0) ? p.M - 1 : p.M;
+        const double pr = (double)T / 4294967296.0;
+        const double lp = std::log(pr), lq = std::log1p(-pr), ln = std::lgamma((double)n + 1.0);
+        double F = 0.0;
+        uint32_t k0 = 0, len = 0;
+        for (uint32_t k = 0; k <= n; ++k) {
+            F += std::exp(ln - std::lgamma((double)k + 1.0) - std::lgamma((double)(n - k) + 1.0) + (double)k * lp +
+                          (double)(n - k) * lq);
+            const double q = std::nearbyint(F * kTwo32);
+            if (q >= kTwo32) break;
+            if (q <= 0.0) {
+                ++k0;
+                continue;
+            }
+            out.bthr.push_back((uint32_t)q);
+            ++len;
+        }
+        out.btab[4 * e] = k0;
+        out.btab[4 * e + 1] = len;
+    }
+}
+
 std::string build_tables(const TableParams& p, HostTables& out)
 {
     // --- connection thresholds -------------------------------------------
     std::string why = connection_tables(p, out.T, out.mean_out, out.max_out);
     if (!why.empty()) return why;
+    if (p.gen > 1) return "unknown synapse generator";
+    if (p.gen == 1) {
+        if (p.M > 4096) return "the binomial generator needs modules of at most 4096 neurons";
+        binomial_tables(p, out);
+    }
     // --- weights -----------------------------------------------------------
     out.wtab.resize(65536);
     for (int k = 0; k < 65536; ++k)
