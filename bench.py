@@ -41,6 +41,8 @@ def parse():
     p.add_argument("--serve-jobs", type=int, default=128, help="served-stream jobs (0: skip serving)")
     p.add_argument("--serve-plain", type=int, default=32, help="first jobs also served one at a time")
     p.add_argument("--serve-capacity", type=int, default=32, help="jobs of the closed-loop capacity run")
+    p.add_argument("--serve-gen", type=int, default=1,
+                   help="synapse generator of the served jobs: 0 one trial per pair, 1 binomial + Floyd")
     p.add_argument("--graph-chunk", type=int, default=250,
                    help="steps per captured HIP graph (0: launch every kernel directly)")
     p.add_argument("--copy-mib", type=int, default=0,
@@ -264,7 +266,9 @@ def main():
         from paper_1803_08833_amd import serve
 
         say = lambda *a: print(*a, file=sys.stderr, flush=True)
-        result["served"] = serve.bench_served(args.serve_jobs, args.serve_plain, args.serve_capacity, log=say)
+        result["served"] = serve.bench_served(args.serve_jobs, args.serve_plain, args.serve_capacity, log=say,
+                                              gen=args.serve_gen)
+        result["served"]["generator"] = "binomial + Floyd" if args.serve_gen else "one trial per pair"
     if not args.no_cpu_baseline:
         sps = spikes / max(1, args.steps * 1000)
         result["cpu_baseline"] = cpu_baseline(net, max(1, int(round(sps))))

@@ -114,7 +114,7 @@ def summary(res, jobs):
 
 
 def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4, log=None,
-                 hbm_budget=160 << 30, max_neurons=6 << 20, chunk_ms=50):
+                 hbm_budget=160 << 30, max_neurons=6 << 20, chunk_ms=50, gen=0):
     """The served workload: the seeded stream of simulation jobs (grids
     2x2..16x16, Gaussian/exponential, 0.5-5 s), Poisson arrivals at `load`
     times the capacity measured by a saturated closed-loop batched run, served
@@ -125,7 +125,7 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
     from . import workloads as W
 
     say = log or (lambda *a: None)
-    jobs = W.serving_stream(n_jobs, seed=seed)
+    jobs = W.serving_stream(n_jobs, seed=seed, gen=gen)
     cap_jobs = jobs[:capacity_jobs]
     rc = serve_batched(cap_jobs, np.zeros(len(cap_jobs)), hbm_budget, max_neurons, chunk_ms)
     capacity = len(cap_jobs) / rc["wall"]

@@ -117,13 +117,14 @@ def n_neurons(net):
     return net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
 
 
-def serving_stream(n_jobs=512, seed=4, ext_rate_hz=2.05):
+def serving_stream(n_jobs=512, seed=4, ext_rate_hz=2.05, gen=GEN_PAIRWISE):
     """Job stream of the batched/served workload: grid sizes uniform over
     {2,4,8,12,16}^2, exactly half Gaussian (sigma ~ U[1,2]) and half
     exponential (lambda ~ U[2,6]) in shuffled order, durations uniform in
     0.5-5 s of biological time, per-job seeds, and the external drive of the
-    ~3-5 Hz regime of the 24x24 workloads.  Arrival times are attached by the
-    server from its measured capacity."""
+    ~3-5 Hz regime of the 24x24 workloads; `gen` selects the synapse
+    generator of every job.  Arrival times are attached by the server from its
+    measured capacity."""
     r = random.Random(seed)
     kinds = [GAUSS] * (n_jobs // 2) + [EXP] * (n_jobs - n_jobs // 2)
     r.shuffle(kinds)
@@ -132,5 +133,6 @@ def serving_stream(n_jobs=512, seed=4, ext_rate_hz=2.05):
         g = r.choice([2, 4, 8, 12, 16])
         rng = r.uniform(1.0, 2.0) if kind == GAUSS else r.uniform(2.0, 6.0)
         dur = int(round(r.uniform(500.0, 5000.0)))
-        jobs.append(dict(net=make(g, g, kind, rng, 1100, 1_000_000 + i, ext_rate_hz=ext_rate_hz), steps=dur))
+        jobs.append(dict(net=make(g, g, kind, rng, 1100, 1_000_000 + i, ext_rate_hz=ext_rate_hz, gen=gen),
+                         steps=dur))
     return jobs
