@@ -50,7 +50,7 @@ class Cfg(C.Structure):
         ("ext_const_q", C.c_int32), ("pad_", C.c_uint32),
         ("preset", C.c_uint32), ("pad2_", C.c_uint32),
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
-        ("gen", C.c_uint32), ("pad3_", C.c_uint32),
+        ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
     ]
 
 

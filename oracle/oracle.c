@@ -70,6 +70,8 @@
 #define OR_GEN_PAIRWISE 0
 #define OR_GEN_BINOMIAL 1
 #define BINOM_MAX_M 4096   /* binomial generator: largest module               */
+#define OR_DELAY_UNIFORM 0
+#define OR_DELAY_EXP 1
 
 /* Flat description of one network.  Times in ms, potentials in mV. */
 typedef struct {
@@ -94,7 +96,8 @@ typedef struct {
     double amp;               /* paper preset: remote law amplitude A         */
     double p_cut;             /* paper preset: stencil cut-off probability    */
     uint32_t gen;             /* OR_GEN_PAIRWISE / OR_GEN_BINOMIAL            */
-    uint32_t pad3_;
+    uint32_t delay_dist;      /* OR_DELAY_UNIFORM / OR_DELAY_EXP              */
+    double delay_tau;         /* exponential delays: scale (ms)               */
 } or_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -176,6 +179,7 @@ typedef struct {
 typedef struct {
     uint32_t *T;            /* [2][gy*gx] connection thresholds per torus offset,
                                for excitatory (0) and inhibitory (1) sources    */
+    uint32_t dthr[RING];    /* exponential delays: CDF thresholds of the bucket */
     or_binom *bt;           /* binomial generator: [2][gy*gx] count tables      */
     uint32_t *bthr;         /* their thresholds                                 */
     int32_t wtab[65536];    /* excitatory weight by top 16 bits of the draw   */
@@ -382,6 +386,22 @@ static int make_tables(const or_cfg *c, or_tables *tb)
     int st = make_thresholds(c, tb->T);
     if (st) return st;
     if (c->gen > OR_GEN_BINOMIAL) return OR_E_INVAL;
+    /* Delays (Sec. II.B: uniform or exponential).  Exponential: bucket k of
+     * the D integer delays has probability exp(-k/tau) / sum_i exp(-i/tau);
+     * the bucket is the number of thresholds round(2^32 F(k)), k < D - 1,
+     * not above the pair's first ATTR word. */
+    if (c->delay_dist > OR_DELAY_EXP) return OR_E_INVAL;
+    if (c->delay_dist == OR_DELAY_EXP) {
+        uint32_t D = c->d_max - c->d_min + 1;
+        if (!(c->delay_tau > 0.0)) return OR_E_INVAL;
+        double total = 0.0, acc = 0.0;
+        for (uint32_t k = 0; k < D; k++) total += exp(-(double)k / c->delay_tau);
+        for (uint32_t k = 0; k + 1 < D; k++) {
+            acc += exp(-(double)k / c->delay_tau);
+            double q = nearbyint(acc / total * 4294967296.0);
+            tb->dthr[k] = (q >= 4294967296.0) ? 0xFFFFFFFFu : (uint32_t)q;
+        }
+    }
     if (c->gen == OR_GEN_BINOMIAL) {
         if (module_size(c) > BINOM_MAX_M) return OR_E_INVAL;
         st = make_binomial(c, tb);
@@ -474,7 +494,14 @@ static void attributes(const or_cfg *c, const or_tables *tb, uint32_t i, uint32_
     uint32_t a[4];
     philox_draw(c->seed, i, j, ST_ATTR, a);
     uint32_t span = c->d_max - c->d_min + 1;
-    *delay = c->d_min + (uint32_t)(((uint64_t)a[0] * span) >> 32);
+    if (c->delay_dist == OR_DELAY_EXP) {
+        uint32_t b = 0;
+        for (uint32_t k = 0; k + 1 < span; k++)
+            if (tb->dthr[k] <= a[0]) b++;
+        *delay = c->d_min + b;
+    } else {
+        *delay = c->d_min + (uint32_t)(((uint64_t)a[0] * span) >> 32);
+    }
     int exc = (i % module_size(c)) < c->n_exc;
     if (c->record == OR_REC_CODE8) {
         uint32_t k = exc ? (uint32_t)(((uint64_t)a[1] * 255u) >> 32) : 255u;

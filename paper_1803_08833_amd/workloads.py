@@ -44,7 +44,11 @@ SYNAPSE = dict(
     # synapse generator: one Bernoulli trial per ordered pair, or a binomial
     # count per (source, target module) and a uniform subset of that size
     gen=0,
+    # delays: uniform over [d_min, d_max], or exponential with scale delay_tau ms
+    delay_dist=0, delay_tau=0.0,
 )
+DELAY_UNIFORM = 0
+DELAY_EXP = 1
 GEN_PAIRWISE = 0
 GEN_BINOMIAL = 1
 
