@@ -56,6 +56,7 @@ enum { SNN_REC_F32 = 0, SNN_REC_CODE8 = 1 };
 enum { SNN_EXT_POISSON = 0, SNN_EXT_CONST = 1 };
 enum { SNN_PRESET_LATERAL = 0, SNN_PRESET_PAPER = 1 };
 enum { SNN_GEN_PAIRWISE = 0, SNN_GEN_BINOMIAL = 1 };
+enum { SNN_DELAY_UNIFORM = 0, SNN_DELAY_EXP = 1 };
 
 typedef struct snn_net snn_net;
 
@@ -97,8 +98,12 @@ typedef struct {
  *     square stencil of half-width ceil(r_c) where amp f(r_c) = p_cut
  *     (7x7 for the Gaussian, 21x21 for the exponential parameters of the
  *     paper); k_in is unused.
- * Delays are uniform integers in [d_min, d_max] ms; excitatory weights
- * Gaussian (w_exc, w_exc_sd), inhibitory weight w_inh.
+ * Delays are integers in [d_min, d_max] ms (Sec. II.B: uniform or
+ * exponential): SNN_DELAY_UNIFORM, d = d_min + mulhi(a0, D); SNN_DELAY_EXP,
+ * P(d) proportional to exp(-(d - d_min) / delay_tau), drawn as d_min plus the
+ * number of CDF thresholds round(2^32 F(k)), k < D - 1, not above a0 (a0 the
+ * first word of the pair's ATTR draw).  Excitatory weights Gaussian (w_exc,
+ * w_exc_sd), inhibitory weight w_inh.
  * Generator: SNN_GEN_PAIRWISE draws one Bernoulli trial per ordered pair
  * (Philox stream 1); SNN_GEN_BINOMIAL draws, per source and target module,
  * the number of synapses from Binomial(n, p) by integer CDF thresholds
@@ -123,7 +128,8 @@ typedef struct {
     double amp;               /* paper preset: remote amplitude A, [0, 1)         */
     double p_cut;             /* paper preset: stencil cut-off probability, > 0   */
     uint32_t gen;             /* SNN_GEN_PAIRWISE or SNN_GEN_BINOMIAL            */
-    uint32_t pad2_;
+    uint32_t delay_dist;      /* SNN_DELAY_UNIFORM or SNN_DELAY_EXP              */
+    double delay_tau;         /* exponential delays: scale in ms, > 0            */
 } snn_syn_desc;
 
 typedef struct {

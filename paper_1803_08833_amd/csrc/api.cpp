@@ -231,6 +231,9 @@ snn::TableParams table_params(const snn_grid_desc& g, const snn_syn_desc& s)
     tp.amp = s.amp;
     tp.p_cut = s.p_cut;
     tp.gen = s.gen;
+    tp.D = s.d_max >= s.d_min ? s.d_max - s.d_min + 1 : 0;
+    tp.delay_exp = s.delay_dist;
+    tp.delay_tau = s.delay_tau;
     tp.w_exc = s.w_exc;
     tp.w_exc_sd = s.w_exc_sd;
     tp.w_inh = s.w_inh;
@@ -411,6 +414,8 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
 
     snn::BuildArgs b{};
     b.gen = s->gen;
+    b.delay_exp = s->delay_dist;
+    for (size_t k = 0; k < tb.dthr.size() && k < snn::kMaxD; ++k) b.dthr[k] = tb.dthr[k];
     b.btab = reinterpret_cast<const uint4*>(btab);
     b.bthr = bthr;
     b.N = n->N;

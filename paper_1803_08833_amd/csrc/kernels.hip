@@ -127,7 +127,12 @@ __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q,
         if (valid) {
             j = q[e];
             const uint4 r = philox(row, j, kStreamAttr, 0u, a.key0, a.key1);
-            b = __umulhi(r.x, a.D);
+            if (a.delay_exp) {
+                b = 0;
+                for (uint32_t k = 0; k + 1u < a.D; ++k) b += a.dthr[k] <= r.x ? 1u : 0u;
+            } else {
+                b = __umulhi(r.x, a.D);
+            }
             wsel = r.y;
         }
         for (uint32_t bb = 0; bb < a.D; ++bb) {

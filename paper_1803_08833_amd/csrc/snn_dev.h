@@ -128,6 +128,8 @@ struct BuildArgs {
     uint32_t slab_cap;
     Ctrl* ctrl;
     uint32_t gen;              // 0 one trial per pair, 1 binomial count + Floyd subset
+    uint32_t delay_exp;        // 1: delay bucket = thresholds of dthr not above the draw
+    uint32_t dthr[kMaxD];      //    (D - 1 of them); 0: mulhi(draw, D)
     const uint4* btab;         // gen 1: [2][gy][gx] {k0, len, at lo, at hi} count tables
     const uint32_t* bthr;      // gen 1: their thresholds
 };

@@ -195,6 +195,20 @@ std::string build_tables(const TableParams& p, HostTables& out)
     std::string why = connection_tables(p, out.T, out.mean_out, out.max_out);
     if (!why.empty()) return why;
     if (p.gen > 1) return "unknown synapse generator";
+    // --- exponential delays: P(bucket k) ~ exp(-k / tau), k < D, by CDF thresholds
+    out.dthr.clear();
+    if (p.delay_exp > 1) return "unknown delay distribution";
+    if (p.delay_exp == 1) {
+        if (!(p.delay_tau > 0.0)) return "exponential delays need delay_tau > 0";
+        double total = 0.0;
+        for (uint32_t k = 0; k < p.D; ++k) total += std::exp(-(double)k / p.delay_tau);
+        double acc = 0.0;
+        for (uint32_t k = 0; k + 1 < p.D; ++k) {
+            acc += std::exp(-(double)k / p.delay_tau);
+            const double q = std::nearbyint(acc / total * kTwo32);
+            out.dthr.push_back(q >= kTwo32 ? 0xFFFFFFFFu : (uint32_t)q);
+        }
+    }
     if (p.gen == 1) {
         if (p.M > 4096) return "the binomial generator needs modules of at most 4096 neurons";
         binomial_tables(p, out);

@@ -13,6 +13,7 @@ struct HostTables {
     std::vector<int32_t> wtab;   // [65536] excitatory weights, 2^-16 mV
     std::vector<int32_t> cb;     // [256] 8-bit weight codebook, 2^-16 mV
     std::vector<uint32_t> poisc; // Poisson CDF thresholds of the external drive
+    std::vector<uint32_t> dthr;  // exponential delays: D - 1 CDF thresholds of the delay bucket
     std::vector<uint32_t> btab;  // binomial generator: [2][gy][gx] x {k0, len, at lo, at hi}
     std::vector<uint32_t> bthr;  //   count thresholds of counts k0 .. k0 + len - 1 at bthr[at ..]
     double mean_out = 0.0;       // expected synapses per source, averaged over neurons
@@ -30,6 +31,9 @@ struct TableParams {
     uint32_t preset;             // 0 one normalised law, 1 the paper's local + remote rules
     double p_local, amp, p_cut;  // paper preset parameters
     uint32_t gen;                // 0 one trial per pair, 1 binomial count + uniform subset
+    uint32_t D;                  // delay buckets
+    uint32_t delay_exp;          // 0 uniform delays, 1 exponential with scale delay_tau
+    double delay_tau;
     double w_exc, w_exc_sd, w_inh;
     uint32_t ext_poisson;
     double ext_n, ext_rate_hz, ext_w;

@@ -54,7 +54,7 @@ class SynDesc(C.Structure):
         ("ext_n", C.c_double), ("ext_rate_hz", C.c_double), ("ext_w", C.c_double),
         ("preset", C.c_uint32), ("pad1_", C.c_uint32),
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
-        ("gen", C.c_uint32), ("pad2_", C.c_uint32),
+        ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
     ]
 
 
@@ -146,7 +146,7 @@ def syn_desc(net: dict) -> SynDesc:
     for k in ("kernel", "record", "range", "k_in", "d_min", "d_max", "w_exc", "w_exc_sd", "w_inh",
               "ext_mode", "ext_const_q", "ext_n", "ext_rate_hz", "ext_w"):
         setattr(s, k, net[k])
-    for k in ("preset", "p_local", "amp", "p_cut", "gen"):   # absent: the lateral law, pairwise
+    for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau"):   # absent: defaults
         setattr(s, k, net.get(k, 0))
     return s
 
