@@ -121,3 +121,21 @@ def test_built_rows_respect_the_preset(oracle_mod, which):
     expect = (net["n_exc"] - 1) * pe[0, 0] + net["n_inh"] * pe[0, 0] + net["n_exc"] * (pe.sum() - pe[0, 0])
     indeg = np.bincount(tgt, minlength=N)
     assert abs(indeg.mean() - expect) < 4.0 * math.sqrt(expect / N)
+
+
+def test_problem_table_sizes(oracle_mod):
+    """Neurons of the paper's three grids, and the Gaussian preset's recurrent
+    synapse totals on the torus within 3 % of the printed ones."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_problem_sizes.txt")
+    rows = [line.split("#", 1)[0].split() for line in open(path)]
+    for g, neurons_m, syn_g, tol in (r for r in rows if r):
+        g = int(g)
+        net = W.make_paper(g, g, W.PAPER_GAUSS, 1)
+        N = W.n_neurons(net)
+        assert round(N / 1e6, 1) == float(neurons_m)
+        tb = oracle_mod.tables(net)
+        M = net["n_exc"] + net["n_inh"]
+        n = np.full(tb["T"].shape, float(M))
+        n[0, 0] = M - 1
+        mean = (net["n_exc"] * (n * tb["T"]).sum() + net["n_inh"] * (n * tb["T_inh"]).sum()) / 2.0**32 / M
+        assert abs(N * mean / 1e9 - float(syn_g)) <= float(tol) * float(syn_g), g
