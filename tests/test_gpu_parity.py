@@ -296,6 +296,39 @@ def test_determinism_and_schedules(snn):
         np.testing.assert_array_equal(s, spikes[0])
 
 
+@pytest.mark.parametrize("mode,record", [(1, W.REC_F32), (0, W.REC_F32), (2, W.REC_CODE8)])
+def test_degenerate_steps_all_schedules(snn, oracle_mod, mode, record):
+    """Degenerate inputs through every delivery schedule (binned at every step,
+    direct, two-level): a network smaller than one 1024-neuron tile (a single
+    ragged tile and super tile), steps with no spike, with every neuron forced
+    to spike (refractory ones cannot), single spikers at both ends of the id
+    range, and a zero-length step call; the ring must equal the oracle's after
+    every step, and the state stay within the lock-step tolerance."""
+    net = W.make(2, 1, W.EXP, 2.0, 150, 71, n_exc=80, n_inh=20, record=record)
+    N = W.n_neurons(net)
+    rng = np.random.default_rng(3)
+    sets = [[], list(range(N)), [], [], sorted(rng.choice(N, N // 2, replace=False).tolist()), list(range(N)),
+            [0], [N - 1], [], list(range(N)), [], [0, N - 1]]
+    say(f"case: degenerate steps, schedule {mode}, record {record}, N {N}")
+    o = oracle_mod.Net(net).build()
+    with snn.Net(net) as g:
+        if mode == 2:
+            g.set_option(snn.OPT_DELIVER_MODE, 2)   # before the build: two-level bins
+        g.build_synapses()
+        g.set_option(snn.OPT_DELIVER_MODE, mode)
+        g.set_option(snn.OPT_BIN_THRESHOLD, 0)       # binned schedules bin every step
+        g.step(0)
+        for t, s in enumerate(sets):
+            o.step_forced(np.array(s, dtype=np.uint32))
+            g.step_forced(np.array(s, dtype=np.uint32))
+            np.testing.assert_array_equal(g.read_ring(), o.ring(), err_msg=f"ring after step {t}")
+            _compare_state(net, g.read_state(), o.state(), t)
+        np.testing.assert_array_equal(g.read_spikes(), o.spikes())
+        st, ost = g.stats(), o.stats()
+        assert st["rec_events"] == ost["rec_events"] and st["spikes"] == ost["spikes"]
+        assert st["deliver_mode"] == mode
+
+
 def test_bin_overflow_fallback_is_exact(snn):
     """Bins far too small: most events take the direct fallback, the ring and
     raster must still equal the direct schedule's."""
