@@ -14,9 +14,10 @@
  * Conventions for every call:
  *   - Status codes: SNN_OK (0) or a negative snn_status; no C++ exception
  *     crosses the ABI.  snn_last_error() gives the text of the last error.
- *   - Ownership: the library owns every device buffer it allocates (plain
- *     hipMalloc) and frees it in snn_destroy().  Host buffers passed in are
- *     owned by the caller and only read or written during the call.
+ *   - Ownership: the library owns every device buffer it allocates (with
+ *     hipMalloc, or the allocator installed by snn_set_allocator) and frees
+ *     it in snn_destroy().  Host buffers passed in are owned by the caller
+ *     and only read or written during the call.
  *   - Streams: all device work of a network runs on the HIP stream given to
  *     snn_build_grid (NULL = the default stream).  Calls that return host
  *     data synchronise that stream; the others only enqueue work.
@@ -326,6 +327,25 @@ const char* snn_batch_last_error(const snn_batch* b);
 /* Text of the last error of this handle (or of the last failed create when
  * net is NULL).  Valid until the next call on the handle. */
 const char* snn_last_error(const snn_net* net);
+
+/* Route the library's device allocations through the caller's allocator (for
+ * example a framework's caching allocator), so that networks share its pool
+ * instead of holding hipMalloc blocks of their own.  Process-wide.
+ *   alloc(bytes, ctx): return device memory of the current device, aligned to
+ *     256 bytes, or NULL.  A NULL or misaligned result fails the call that
+ *     allocated with SNN_E_NOMEM (a misaligned block is handed back first).
+ *   free_(ptr, ctx): take back a block alloc returned.  The library calls it
+ *     only after the stream that used the block has finished with it.
+ *   ctx: passed through untouched; owned by the caller.
+ * Both NULL restores hipMalloc / hipFree; exactly one NULL is SNN_E_INVAL.
+ * Each network (snn_build_grid) and each batch (snn_batch_create, and the
+ * networks it builds for its jobs) takes the allocator in force when it is
+ * created and releases its buffers through the same pair, so the pair and ctx
+ * must stay valid until every such handle is destroyed.  Either function may
+ * be called from the library's construction threads.  Memory from the
+ * allocator need not be zeroed: the library clears what it reads before
+ * writing it. */
+snn_status snn_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx);
 
 #ifdef __cplusplus
 }

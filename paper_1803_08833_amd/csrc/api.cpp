@@ -25,6 +25,15 @@
 using snn::Ctrl;
 using snn::StepArgs;
 
+// A device allocator: the caller's pair installed by snn_set_allocator, or
+// hipMalloc / hipFree when none is.  Networks and batches take a copy when
+// they are created and release every buffer through that copy.
+struct DevAllocator {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free_)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+
 struct snn_net {
     snn_grid_desc g{};
     snn_syn_desc s{};
@@ -34,6 +43,7 @@ struct snn_net {
     bool poisoned = false;
     std::string err;
     StepArgs a{};
+    DevAllocator dev_alloc;
     std::vector<std::pair<void*, size_t>> allocs;
     uint64_t bytes = 0;
     uint32_t N = 0, M = 0, D = 0;
@@ -83,12 +93,46 @@ snn_status fail_hip(snn_net* n, hipError_t e, const char* what)
         if (e_ != hipSuccess) return fail_hip(net, e_, #x); \
     } while (0)
 
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;   // the allocator new networks and batches take
+
+DevAllocator current_allocator()
+{
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+// Every buffer is used with 16-byte vector accesses and the staging layouts
+// assume 256-byte alignment, which hipMalloc gives; a caller's allocator must
+// give it too.
+constexpr uintptr_t kDevAlign = 256;
+
+hipError_t dev_malloc(const DevAllocator& al, void** p, size_t b)
+{
+    if (!al.alloc) return hipMalloc(p, b);
+    void* q = al.alloc(b, al.ctx);
+    if (!q) return hipErrorOutOfMemory;
+    if (reinterpret_cast<uintptr_t>(q) % kDevAlign) {
+        al.free_(q, al.ctx);
+        return hipErrorInvalidValue;
+    }
+    *p = q;
+    return hipSuccess;
+}
+
+void dev_free(const DevAllocator& al, void* p)
+{
+    if (!p) return;
+    if (al.free_) al.free_(p, al.ctx);
+    else (void)hipFree(p);
+}
+
 template <typename T>
 hipError_t dalloc(snn_net* n, T** p, size_t count)
 {
     void* q = nullptr;
     const size_t b = count * sizeof(T) > 0 ? count * sizeof(T) : 16;
-    hipError_t e = hipMalloc(&q, b);
+    hipError_t e = dev_malloc(n->dev_alloc, &q, b);
     if (e != hipSuccess) return e;
     n->allocs.push_back(std::make_pair(q, b));
     n->bytes += b;
@@ -106,7 +150,7 @@ void dfree(snn_net* n, void* p)
             break;
         }
     }
-    (void)hipFree(p);
+    dev_free(n->dev_alloc, p);
 }
 
 void drop_graphs(snn_net* n)
@@ -270,6 +314,17 @@ const char* snn_last_error(const snn_net* net)
     return net ? net->err.c_str() : g_create_err.c_str();
 }
 
+snn_status snn_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx)
+{
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(nullptr, SNN_E_INVAL, "snn_set_allocator: give both functions, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return SNN_OK;
+}
+
 snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** out)
 {
     if (!g || !out) return fail(nullptr, SNN_E_INVAL, "null argument");
@@ -277,6 +332,7 @@ snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** ou
     std::string why;
     if (!valid_grid(g, why)) return fail(nullptr, SNN_E_INVAL, why);
     snn_net* n = new snn_net();
+    n->dev_alloc = current_allocator();
     n->g = *g;
     if (n->g.hist_cap == 0) n->g.hist_cap = 1ull << 24;
     n->M = g->n_exc + g->n_inh;
@@ -916,7 +972,7 @@ void snn_destroy(snn_net* n)
     if (!n) return;
     if (n->stream) (void)hipStreamSynchronize(n->stream);
     drop_graphs(n);
-    for (auto& p : n->allocs) (void)hipFree(p.first);
+    for (auto& p : n->allocs) dev_free(n->dev_alloc, p.first);
     n->allocs.clear();
     if (n->own_stream && n->stream) (void)hipStreamDestroy(n->stream);
     delete n;
@@ -949,6 +1005,7 @@ struct snn_batch {
     };
     Job jobs[snn::kMaxJobs];
     snn::JobDesc* d_jobs = nullptr;
+    DevAllocator dev_alloc;            // the allocator d_jobs came from
     static constexpr int kTables = 8;  // pinned staging copies of the table, used in turn
     snn::JobDesc* h_jobs[kTables] = {};
     hipEvent_t h_done[kTables] = {};
@@ -1222,7 +1279,8 @@ snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip
     for (int w = 0; w < snn_batch::kBuilders && e == hipSuccess; ++w)
         e = hipStreamCreateWithFlags(&b->build_stream[w], hipStreamNonBlocking);
     if (e == hipSuccess) e = snn::setup_kernels();
-    if (e == hipSuccess) e = hipMalloc((void**)&b->d_jobs, sizeof(snn::JobDesc) * snn::kMaxJobs);
+    b->dev_alloc = current_allocator();
+    if (e == hipSuccess) e = dev_malloc(b->dev_alloc, (void**)&b->d_jobs, sizeof(snn::JobDesc) * snn::kMaxJobs);
     for (int i = 0; i < snn_batch::kTables && e == hipSuccess; ++i) {
         e = hipHostMalloc((void**)&b->h_jobs[i], sizeof(snn::JobDesc) * snn::kMaxJobs, 0);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&b->h_done[i], hipEventDisableTiming);
@@ -1442,7 +1500,7 @@ void snn_batch_destroy(snn_batch* b)
         (void)hipEventDestroy(r.after);
         snn_destroy(r.net);
     }
-    if (b->d_jobs) (void)hipFree(b->d_jobs);
+    dev_free(b->dev_alloc, b->d_jobs);
     for (int i = 0; i < snn_batch::kTables; ++i) {
         if (b->h_jobs[i]) (void)hipHostFree(b->h_jobs[i]);
         if (b->h_done[i]) (void)hipEventDestroy(b->h_done[i]);

@@ -3,7 +3,8 @@
 Argument marshalling only: every step of the path runs in the HIP kernels of
 libsnn.so.  PyTorch is imported first so that the process uses one HIP runtime
 (torch's) and so that callers can hand in a torch stream; the library owns its
-device memory.  There is no CPU fallback: if libsnn.so is missing this module
+device memory, which it takes from hipMalloc or from an allocator installed with
+set_allocator (use_torch_allocator: torch's caching allocator).  There is no CPU fallback: if libsnn.so is missing this module
 raises on import of the library.
 """
 from __future__ import annotations
@@ -30,7 +31,12 @@ EXPORTS = [
     "snn_set_option", "snn_host_tables", "snn_reset", "snn_destroy", "snn_last_error",
     "snn_batch_create", "snn_batch_admit", "snn_batch_step", "snn_batch_poll", "snn_batch_read_spikes",
     "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
+    "snn_set_allocator",
 ]
+
+# snn_set_allocator's function types: alloc(bytes, ctx) -> pointer, free(ptr, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class GridDesc(C.Structure):
@@ -119,6 +125,7 @@ def lib():
             "snn_batch_last_error": ([P], C.c_char_p),
             "snn_destroy": ([P], None),
             "snn_last_error": ([P], C.c_char_p),
+            "snn_set_allocator": ([ALLOC_FN, FREE_FN, P], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -149,6 +156,44 @@ def syn_desc(net: dict) -> SynDesc:
     for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau"):   # absent: defaults
         setattr(s, k, net.get(k, 0))
     return s
+
+
+# Every callback pair ever installed stays referenced: networks created under
+# a pair release their buffers through it even after another is installed.
+_installed_allocators = []
+
+
+def set_allocator(alloc=None, free=None):
+    """Install a process-wide device allocator (snn_set_allocator).
+
+    alloc(nbytes) -> int device address (256-byte aligned) or 0 on failure;
+    free(address) takes a block back.  Both None restores hipMalloc / hipFree.
+    Networks and batches keep the allocator in force when they were created.
+    """
+    if (alloc is None) != (free is None):
+        raise ValueError("give both alloc and free, or neither")
+    if alloc is None:
+        st = lib().snn_set_allocator(ALLOC_FN(), FREE_FN(), None)
+    else:
+        fa = ALLOC_FN(lambda nbytes, ctx: alloc(int(nbytes)) or None)
+        ff = FREE_FN(lambda ptr, ctx: free(int(ptr)))
+        _installed_allocators.append((fa, ff))
+        st = lib().snn_set_allocator(fa, ff, None)
+    if st != SNN_OK:
+        raise SNNError(st, lib().snn_last_error(None).decode())
+
+
+def use_torch_allocator(device=None):
+    """Route the library's device memory through torch's caching allocator.
+
+    Blocks are taken on the calling thread's current stream of `device` (the
+    current device by default); the library returns a block only once the
+    stream that used it has finished with it, so the cache may hand it out
+    again at once.  Memory shows up in torch.cuda.memory_allocated().
+    """
+    dev = torch.cuda.current_device() if device is None else int(device)
+    set_allocator(lambda n: torch.cuda.caching_allocator_alloc(n, dev),
+                  lambda p: torch.cuda.caching_allocator_delete(p))
 
 
 def current_stream_handle():

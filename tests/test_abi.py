@@ -45,6 +45,18 @@ def test_library_exports_every_declared_symbol(snn):
     assert sorted(snn.EXPORTS) == declared()
 
 
+def test_allocator_arguments_are_checked_on_the_host(snn):
+    L = snn.lib()
+    assert L.snn_set_allocator(snn.ALLOC_FN(lambda n, c: None), snn.FREE_FN(), None) == snn.SNN_E_INVAL
+    assert b"both" in L.snn_last_error(None)
+    assert L.snn_set_allocator(snn.ALLOC_FN(), snn.FREE_FN(lambda p, c: None), None) == snn.SNN_E_INVAL
+    with pytest.raises(ValueError):
+        snn.set_allocator(alloc=lambda n: 0)
+    snn.set_allocator(lambda n: 0, lambda p: None)   # installs (nothing is allocated here)
+    snn.set_allocator()                              # and back to hipMalloc / hipFree
+    assert L.snn_set_allocator(snn.ALLOC_FN(), snn.FREE_FN(), None) == snn.SNN_OK
+
+
 def test_product_never_touches_the_oracle():
     for dirpath, _, files in os.walk(PKG):
         for f in files:
