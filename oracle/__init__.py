@@ -51,14 +51,18 @@ class Cfg(C.Structure):
         ("preset", C.c_uint32), ("pad2_", C.c_uint32),
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
         ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
+        ("solver", C.c_uint32), ("pad3_", C.c_uint32),
     ]
+
+SOLVER_STEP, SOLVER_EXACT = 0, 1
+OPTIONAL = ("solver",)   # absent from a description: 0
 
 
 def cfg(net: dict) -> Cfg:
     c = Cfg()
     for name, _ in Cfg._fields_:
         if not name.startswith("pad"):
-            setattr(c, name, net[name])
+            setattr(c, name, net.get(name, 0) if name in OPTIONAL else net[name])
     return c
 
 
@@ -102,6 +106,14 @@ def lib():
         L.or_net_hist.argtypes = [P, P, U64]
         L.or_net_hist.restype = U64
         L.or_net_stats.argtypes = [P, P]
+        L.or_net_step_forced_exact.argtypes = [P, P, P, U64]
+        L.or_net_step_forced_exact.restype = C.c_int
+        L.or_net_hist_frac.argtypes = [P, P, U64]
+        L.or_net_hist_frac.restype = U64
+        L.or_net_queue.argtypes = [P, U32, P, P, P, U64]
+        L.or_net_queue.restype = U64
+        L.or_net_rend.argtypes = [P, P]
+        L.or_net_rend.restype = C.c_int
         L.or_net_stats.restype = None
         _lib = L
     return _lib
@@ -261,6 +273,37 @@ class Net:
         out = np.zeros((max(n, 1), 2), dtype=np.uint32)
         lib().or_net_hist(self.h, _p(out), n)
         return out[:n]
+
+    def step_forced_exact(self, gids, fracs):
+        """Exact solver, lock-step: neuron gids[k] spikes at offset fracs[k]."""
+        g = np.ascontiguousarray(gids, dtype=np.uint32)
+        f = np.ascontiguousarray(fracs, dtype=np.uint32)
+        assert g.size == f.size
+        st = lib().or_net_step_forced_exact(self.h, _p(g), _p(f), g.size)
+        if st != 0:
+            raise ValueError(f"oracle step_forced_exact: status {st}")
+
+    def spike_fracs(self):
+        """Emission offsets (2^-32 ms) of the history, aligned with spikes()."""
+        n = int(lib().or_net_hist_frac(self.h, None, 0))
+        out = np.zeros(max(n, 1), dtype=np.uint32)
+        lib().or_net_hist_frac(self.h, _p(out), n)
+        return out[:n]
+
+    def queue(self, slot):
+        """Exact solver: inputs queued for ring slot `slot` as (target, offset,
+        charge) rows, ordered."""
+        n = int(lib().or_net_queue(self.h, slot, None, None, None, 0))
+        tgt = np.zeros(max(n, 1), dtype=np.uint32)
+        fr = np.zeros(max(n, 1), dtype=np.uint32)
+        wq = np.zeros(max(n, 1), dtype=np.int32)
+        lib().or_net_queue(self.h, slot, _p(tgt), _p(fr), _p(wq), n)
+        return np.stack([tgt[:n].astype(np.int64), fr[:n].astype(np.int64), wq[:n].astype(np.int64)], axis=1)
+
+    def rend(self):
+        re = np.zeros(self.N, dtype=np.uint64)
+        lib().or_net_rend(self.h, _p(re))
+        return re
 
     def stats(self):
         out = np.zeros(6, dtype=np.uint64)

@@ -24,7 +24,11 @@
  *     (Sec. III.A), instantaneous (delta) synapses;
  *   - the 1 ms time-driven step: find spikers, send spikes, queue them by
  *     delay, inject charge at arrival, integrate (Sec. II.A);
- *   - counting of recurrent and external synaptic events (Sec. III.D).
+ *   - counting of recurrent and external synaptic events (Sec. III.D);
+ *   - optionally, the exact-time event-driven solver (Sec. II.A, Sec. II.C):
+ *     spikes carry their emission time inside the step, each neuron takes its
+ *     queued and external inputs in time order and integrates Eq. (1)-(2)
+ *     exactly between them.
  *
  * Readings of points where the paper is silent or ambiguous are listed in the
  * design document; the ones that change arithmetic are repeated next to the
@@ -35,7 +39,11 @@
  * implementation; tables against closed forms and library distributions;
  * the neuron map against closed-form interspike intervals; connectivity
  * against its expected in-degree and distance statistics; delivery against
- * a dense brute-force simulation and exact charge conservation.
+ * a dense brute-force simulation and exact charge conservation.  The
+ * exact-time solver against the step solver (to which it reduces when every
+ * input arrives at offset 0), closed-form superposition of sub-threshold
+ * inputs, closed-form spike times of isolated neurons, and causality of
+ * every spike of a recurrent network.
  */
 #include <math.h>
 #include <stdint.h>
@@ -72,6 +80,9 @@
 #define BINOM_MAX_M 4096   /* binomial generator: largest module               */
 #define OR_DELAY_UNIFORM 0
 #define OR_DELAY_EXP 1
+#define OR_SOLVER_STEP 0   /* charge summed per 1 ms step, one jump per step   */
+#define OR_SOLVER_EXACT 1  /* exact-time event-driven integration              */
+#define ST_EXT_TIME 7u     /* exact solver: arrival times of external events    */
 
 /* Flat description of one network.  Times in ms, potentials in mV. */
 typedef struct {
@@ -98,6 +109,8 @@ typedef struct {
     uint32_t gen;             /* OR_GEN_PAIRWISE / OR_GEN_BINOMIAL            */
     uint32_t delay_dist;      /* OR_DELAY_UNIFORM / OR_DELAY_EXP              */
     double delay_tau;         /* exponential delays: scale (ms)               */
+    uint32_t solver;          /* OR_SOLVER_STEP / OR_SOLVER_EXACT             */
+    uint32_t pad3_;
 } or_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -381,6 +394,10 @@ static int make_tables(const or_cfg *c, or_tables *tb)
         !(c->p_local >= 0.0 && c->p_local < 1.0 && c->amp >= 0.0 && c->amp < 1.0 && c->p_cut > 0.0))
         return OR_E_INVAL;
     if (!(c->tau_m > 0.0) || !(c->tau_w > 0.0) || c->t_ref < 0.0) return OR_E_INVAL;
+    if (c->solver > OR_SOLVER_EXACT) return OR_E_INVAL;
+    /* exact solver: a refractory period of at least one step keeps spikes to
+     * one per neuron and step, and bounds it below 2^32 steps */
+    if (c->solver == OR_SOLVER_EXACT && !(c->t_ref >= 1.0 && c->t_ref < 1e6)) return OR_E_INVAL;
     tb->T = (uint32_t *)calloc(2 * (size_t)c->gx * c->gy, sizeof(uint32_t));
     if (!tb->T) return OR_E_NOMEM;
     int st = make_thresholds(c, tb->T);
@@ -618,6 +635,13 @@ static int64_t build_row(const or_cfg *c, const or_tables *tb, uint32_t i, or_sy
 /* ------------------------------------------------------------------------ */
 /* Network                                                                  */
 /* ------------------------------------------------------------------------ */
+/* Exact solver: one queued input, arriving at (slot step, offset f). */
+typedef struct or_ev {
+    uint32_t tgt;           /* target neuron                     */
+    uint32_t f;             /* offset in the step, 2^-32 ms      */
+    int32_t wq;             /* charge, 2^-16 mV                  */
+} or_ev;
+
 typedef struct {
     or_cfg c;
     or_tables tb;
@@ -642,6 +666,12 @@ typedef struct {
     size_t hist_n, hist_cap;
     uint64_t n_spikes, rec_events, ext_events;
     int overflow;
+    /* exact-time solver */
+    uint64_t *rend;         /* [N] end of the refractory period, ms in 32.32 fixed point */
+    uint32_t *fs;           /* [N] emission offset of this step's spike (2^-32 ms)       */
+    struct or_ev *q[RING];  /* per arrival slot: queued events, unsorted                 */
+    size_t qn[RING], qcap[RING];
+    uint32_t *hist_f;       /* emission offset of each history entry                     */
 } or_net;
 
 void or_net_free(void *h)
@@ -651,6 +681,8 @@ void or_net_free(void *h)
     free(n->tb.T); free(n->row_ptr); free(n->bend); free(n->syn);
     free(n->V); free(n->w); free(n->ref); free(n->ring); free(n->ring64); free(n->ringf);
     free(n->flag); free(n->hist);
+    free(n->rend); free(n->fs); free(n->hist_f);
+    for (int k = 0; k < RING; k++) free(n->q[k]);
     free(n);
 }
 
@@ -674,7 +706,11 @@ void *or_net_create(const or_cfg *c, int fp64_weights)
     n->flag = (uint8_t *)calloc(n->N, 1);
     n->hist_cap = 1024;
     n->hist = (uint32_t *)malloc(2 * n->hist_cap * sizeof(uint32_t));
-    if (!n->V || !n->w || !n->ref || !n->ring || !n->ring64 || !n->ringf || !n->flag || !n->hist) {
+    n->rend = (uint64_t *)calloc(n->N, sizeof(uint64_t));
+    n->fs = (uint32_t *)calloc(n->N, sizeof(uint32_t));
+    n->hist_f = (uint32_t *)malloc(n->hist_cap * sizeof(uint32_t));
+    if (!n->V || !n->w || !n->ref || !n->ring || !n->ring64 || !n->ringf || !n->flag || !n->hist ||
+        !n->rend || !n->fs || !n->hist_f) {
         or_net_free(n);
         return NULL;
     }
@@ -857,17 +893,21 @@ static uint32_t ext_count(const or_net *n, uint32_t g, uint32_t t)
     return k;
 }
 
-static void hist_push(or_net *n, uint32_t t, uint32_t g)
+static void hist_push(or_net *n, uint32_t t, uint32_t g, uint32_t f)
 {
     if (n->hist_n == n->hist_cap) {
         size_t nc = n->hist_cap * 2;
         uint32_t *nh = (uint32_t *)realloc(n->hist, 2 * nc * sizeof(uint32_t));
         if (!nh) { n->overflow = 1; return; }
         n->hist = nh;
+        uint32_t *nf = (uint32_t *)realloc(n->hist_f, nc * sizeof(uint32_t));
+        if (!nf) { n->overflow = 1; return; }
+        n->hist_f = nf;
         n->hist_cap = nc;
     }
     n->hist[2 * n->hist_n] = t;
     n->hist[2 * n->hist_n + 1] = g;
+    n->hist_f[n->hist_n] = f;
     n->hist_n++;
 }
 
@@ -925,7 +965,7 @@ static int step_once(or_net *n, const uint8_t *forced)
     }
     for (uint32_t i = 0; i < N; i++) {
         if (!n->flag[i]) continue;
-        hist_push(n, t, i);
+        hist_push(n, t, i, 0u);
         n->n_spikes++;
         if (!n->built) continue;
         for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
@@ -941,13 +981,241 @@ static int step_once(or_net *n, const uint8_t *forced)
     return n->overflow ? OR_E_OVERFLOW : OR_OK;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Exact-time event-driven solver (Sec. II.A, Sec. II.C)                    */
+/* ------------------------------------------------------------------------ */
+/* Times are absolute, in ms, in 32.32 fixed point: step t, offset f, is
+ * (t << 32) | f.  A spike is emitted at the time of the input that takes V
+ * above threshold (with delta synapses and E below V_th the potential only
+ * falls between inputs, so threshold is crossed only at an input); it
+ * reaches each target at emission time + the synapse's integer delay, so it
+ * keeps its offset inside the step.  External inputs of a step: the same
+ * Poisson count as the step solver, arriving at offsets drawn uniformly from
+ * the EXT_TIME stream; the constant drive arrives at offset 0.  Inputs that
+ * arrive at the same instant are summed before the threshold test.  A spike
+ * at time s holds V at V_r over [s, s + t_ref), inputs inside it are
+ * discarded, and w keeps decaying.  With every offset 0 and t_ref one step
+ * longer this is exactly the step solver. */
+
+static void ev_push(or_net *n, uint32_t slot, uint32_t tgt, uint32_t f, int32_t wq)
+{
+    if (n->qn[slot] == n->qcap[slot]) {
+        size_t nc = n->qcap[slot] ? 2 * n->qcap[slot] : 1024;
+        or_ev *nq = (or_ev *)realloc(n->q[slot], nc * sizeof(or_ev));
+        if (!nq) { n->overflow = 1; return; }
+        n->q[slot] = nq;
+        n->qcap[slot] = nc;
+    }
+    or_ev *e = &n->q[slot][n->qn[slot]++];
+    e->tgt = tgt;
+    e->f = f;
+    e->wq = wq;
+}
+
+static int ev_cmp(const void *a, const void *b)
+{
+    const or_ev *x = (const or_ev *)a, *y = (const or_ev *)b;
+    if (x->tgt != y->tgt) return x->tgt < y->tgt ? -1 : 1;
+    if (x->f != y->f) return x->f < y->f ? -1 : 1;
+    if (x->wq != y->wq) return x->wq < y->wq ? -1 : 1;
+    return 0;
+}
+
+/* Exact solution of du/dt = -(u + w)/tau_m, dw/dt = -w/tau_w over h ms. */
+static void propagate(const or_cfg *c, double h, double *V, double *w)
+{
+    double em = exp(-h / c->tau_m), ew = exp(-h / c->tau_w);
+    double kap = (c->tau_w != c->tau_m) ? c->tau_w / (c->tau_w - c->tau_m) * (ew - em) : (h / c->tau_m) * em;
+    double u = *V - c->e_rest;
+    u = u * em - kap * *w;
+    *V = c->e_rest + u;
+    *w = *w * ew;
+}
+
+/* Advance one neuron from absolute time a to b (a <= b), holding V at V_r
+ * while refractory (before re). */
+static void advance(const or_cfg *c, uint64_t a, uint64_t b, uint64_t re, double *V, double *w)
+{
+    const double q = 1.0 / 4294967296.0;
+    if (a < re) {
+        uint64_t e = re < b ? re : b;
+        *w = *w * exp(-(double)(e - a) * q / c->tau_w);
+        *V = c->v_reset;
+        a = e;
+    }
+    if (a < b) propagate(c, (double)(b - a) * q, V, w);
+}
+
+/* External input times of neuron g in step t: offsets of the k-th event. */
+static uint32_t ext_offset(const or_net *n, uint32_t g, uint32_t t, uint32_t k)
+{
+    uint32_t ctr[4] = {g, t, ST_EXT_TIME, k >> 2}, key[2], r[4];
+    key[0] = (uint32_t)n->c.seed;
+    key[1] = (uint32_t)(n->c.seed >> 32);
+    or_philox(ctr, key, r);
+    return r[k & 3u];
+}
+
+typedef struct {
+    uint32_t f;
+    int32_t wq;
+} or_in;
+
+static int in_cmp(const void *a, const void *b)
+{
+    const or_in *x = (const or_in *)a, *y = (const or_in *)b;
+    if (x->f != y->f) return x->f < y->f ? -1 : 1;
+    return (x->wq > y->wq) - (x->wq < y->wq);
+}
+
+/* One 1 ms step of the exact solver.  forced != NULL: lock-step mode, neuron
+ * j spikes exactly at offset ff[j] when forced[j] is set (and it is not
+ * refractory and an input arrives then), never otherwise. */
+static int step_exact(or_net *n, const uint8_t *forced, const uint32_t *ff)
+{
+    const or_cfg *c = &n->c;
+    const uint32_t t = n->t, slot = t % RING, N = n->N;
+    const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
+    const uint64_t tref = (uint64_t)llround(c->t_ref * 4294967296.0);
+    or_ev *q = n->q[slot];
+    const size_t nq = n->qn[slot];
+    if (nq) qsort(q, nq, sizeof(or_ev), ev_cmp);
+    size_t k = 0;
+    size_t cap = 64;
+    or_in *in = (or_in *)malloc(cap * sizeof(or_in));
+    if (!in) return OR_E_NOMEM;
+    for (uint32_t j = 0; j < N; j++) {
+        /* this step's inputs: queued recurrent ones, then external ones */
+        size_t m = 0, k1 = k;
+        while (k1 < nq && q[k1].tgt == j) k1++;
+        uint32_t next = 0;
+        if (c->ext_mode == OR_EXT_CONST) {
+            next = 1;
+        } else {
+            next = ext_count(n, j, t);
+            n->ext_events += next;
+        }
+        size_t need = (k1 - k) + next;
+        if (need > cap) {
+            while (cap < need) cap *= 2;
+            or_in *ni = (or_in *)realloc(in, cap * sizeof(or_in));
+            if (!ni) { free(in); return OR_E_NOMEM; }
+            in = ni;
+        }
+        for (size_t e = k; e < k1; e++) { in[m].f = q[e].f; in[m].wq = q[e].wq; m++; }
+        k = k1;
+        if (c->ext_mode == OR_EXT_CONST) {
+            in[m].f = 0; in[m].wq = c->ext_const_q; m++;
+        } else {
+            for (uint32_t e = 0; e < next; e++) { in[m].f = ext_offset(n, j, t, e); in[m].wq = n->tb.jext_q; m++; }
+        }
+        qsort(in, m, sizeof(or_in), in_cmp);
+        double V = n->V[j], w = n->w[j];
+        uint64_t now = t0, re = n->rend[j];
+        const int exc = (j % module_size(c)) < c->n_exc;
+        n->flag[j] = 0;
+        for (size_t e = 0; e < m;) {
+            const uint32_t f = in[e].f;
+            int64_t J = 0;
+            while (e < m && in[e].f == f) J += in[e++].wq;
+            const uint64_t T = t0 | f;
+            advance(c, now, T, re, &V, &w);
+            now = T;
+            if (T < re) continue;   /* refractory: input discarded */
+            V += (double)J / 65536.0;
+            int spike = forced ? (forced[j] && ff[j] == f) : (V > c->v_th);
+            if (spike) {
+                n->flag[j] = 1;
+                n->fs[j] = f;
+                V = c->v_reset;
+                re = T + tref;
+                if (exc || c->sfa_on_inh) w += c->alpha_w;
+            }
+        }
+        advance(c, now, t1, re, &V, &w);
+        n->V[j] = V;
+        n->w[j] = w;
+        n->rend[j] = re;
+        /* whole steps of refractoriness left at the end of the step */
+        n->ref[j] = re > t1 ? (int32_t)((re - t1 + 0xFFFFFFFFull) >> 32) : 0;
+    }
+    free(in);
+    n->qn[slot] = 0;
+    for (uint32_t i = 0; i < N; i++) {
+        if (!n->flag[i]) continue;
+        hist_push(n, t, i, n->fs[i]);
+        n->n_spikes++;
+        if (!n->built) continue;
+        for (uint64_t s = n->row_ptr[i]; s < n->row_ptr[i + 1]; s++) {
+            const or_syn *y = &n->syn[s];
+            ev_push(n, (t + y->delay) % RING, y->tgt, n->fs[i], y->wq);
+            n->rec_events++;
+        }
+    }
+    n->t = t + 1;
+    return n->overflow ? OR_E_OVERFLOW : OR_OK;
+}
+
 int or_net_step(void *h, uint32_t steps)
 {
     or_net *n = (or_net *)h;
     for (uint32_t s = 0; s < steps; s++) {
-        int st = step_once(n, NULL);
+        int st = n->c.solver == OR_SOLVER_EXACT ? step_exact(n, NULL, NULL) : step_once(n, NULL);
         if (st) return st;
     }
+    return OR_OK;
+}
+
+/* Exact solver, lock-step mode: spikes (gids[k], at offset fr[k]) this step. */
+int or_net_step_forced_exact(void *h, const uint32_t *gids, const uint32_t *fr, uint64_t cnt)
+{
+    or_net *n = (or_net *)h;
+    if (n->c.solver != OR_SOLVER_EXACT) return OR_E_INVAL;
+    uint8_t *forced = (uint8_t *)calloc(n->N, 1);
+    uint32_t *ff = (uint32_t *)calloc(n->N, sizeof(uint32_t));
+    if (!forced || !ff) { free(forced); free(ff); return OR_E_NOMEM; }
+    int st = OR_OK;
+    for (uint64_t k = 0; k < cnt; k++) {
+        if (gids[k] >= n->N) { st = OR_E_INVAL; break; }
+        forced[gids[k]] = 1;
+        ff[gids[k]] = fr[k];
+    }
+    if (st == OR_OK) st = step_exact(n, forced, ff);
+    free(forced);
+    free(ff);
+    return st;
+}
+
+/* Emission offsets of the history entries, in history order. */
+uint64_t or_net_hist_frac(void *h, uint32_t *fr, uint64_t cap)
+{
+    or_net *n = (or_net *)h;
+    uint64_t m = n->hist_n < cap ? n->hist_n : cap;
+    if (fr) memcpy(fr, n->hist_f, (size_t)m * sizeof(uint32_t));
+    return n->hist_n;
+}
+
+/* Queued inputs of arrival slot `slot`, ordered by (target, offset, charge):
+ * returns their number; copies at most cap. */
+uint64_t or_net_queue(void *h, uint32_t slot, uint32_t *tgt, uint32_t *fr, int32_t *wq, uint64_t cap)
+{
+    or_net *n = (or_net *)h;
+    if (slot >= RING) return 0;
+    const size_t m = n->qn[slot];
+    if (m) qsort(n->q[slot], m, sizeof(or_ev), ev_cmp);
+    for (size_t e = 0; e < m && e < cap; e++) {
+        tgt[e] = n->q[slot][e].tgt;
+        fr[e] = n->q[slot][e].f;
+        wq[e] = n->q[slot][e].wq;
+    }
+    return m;
+}
+
+/* Exact solver: refractory ends, 32.32 fixed-point ms. */
+int or_net_rend(void *h, uint64_t *re)
+{
+    or_net *n = (or_net *)h;
+    memcpy(re, n->rend, n->N * sizeof(uint64_t));
     return OR_OK;
 }
 
@@ -961,6 +1229,7 @@ int or_net_step_forced(void *h, const uint32_t *gids, uint64_t cnt)
         if (gids[k] >= n->N) { free(forced); return OR_E_INVAL; }
         forced[gids[k]] = 1;
     }
+    if (n->c.solver == OR_SOLVER_EXACT) { free(forced); return OR_E_INVAL; }
     int st = step_once(n, forced);
     free(forced);
     return st;

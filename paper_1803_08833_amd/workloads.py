@@ -46,7 +46,11 @@ SYNAPSE = dict(
     gen=0,
     # delays: uniform over [d_min, d_max], or exponential with scale delay_tau ms
     delay_dist=0, delay_tau=0.0,
+    # neuron solver: charge summed per 1 ms step, or exact-time event-driven
+    solver=0,
 )
+SOLVER_STEP = 0
+SOLVER_EXACT = 1
 DELAY_UNIFORM = 0
 DELAY_EXP = 1
 GEN_PAIRWISE = 0
