@@ -58,6 +58,7 @@ enum { SNN_EXT_POISSON = 0, SNN_EXT_CONST = 1 };
 enum { SNN_PRESET_LATERAL = 0, SNN_PRESET_PAPER = 1 };
 enum { SNN_GEN_PAIRWISE = 0, SNN_GEN_BINOMIAL = 1 };
 enum { SNN_DELAY_UNIFORM = 0, SNN_DELAY_EXP = 1 };
+enum { SNN_SOLVER_STEP = 0, SNN_SOLVER_EXACT = 1 };
 
 typedef struct snn_net snn_net;
 
@@ -110,7 +111,20 @@ typedef struct {
  * the number of synapses from Binomial(n, p) by integer CDF thresholds
  * (stream 5) and then which n candidates by Floyd's algorithm (stream 6) --
  * the same law with different bits, in work proportional to modules and
- * synapses instead of pairs (modules of at most 4096 neurons). */
+ * synapses instead of pairs (modules of at most 4096 neurons).
+ * Solver: SNN_SOLVER_STEP sums each neuron's inputs per 1 ms step and
+ * applies them as one jump before the threshold test (spike times are whole
+ * steps).  SNN_SOLVER_EXACT is the event-driven solver of Sec. II.A / II.C:
+ * times are 32.32 fixed-point ms; a spike is emitted at the instant of the
+ * input that takes V above V_th and reaches each target the synapse's delay
+ * later, keeping its offset inside the step; a step's external inputs (the
+ * same Poisson count) arrive at offsets drawn from Philox stream 7, counter
+ * (gid, t, 7, k / 4), word k % 4 (the constant drive at offset 0); inputs of
+ * one instant are summed before the threshold test; Eq. (1)-(2) are solved
+ * exactly between inputs; a spike at s holds V at V_r over [s, s + t_ref),
+ * discarding inputs there (t_ref >= 1 ms).  The exact solver delivers through
+ * its own per-slot input queues (SNN_OPT_QUEUE_CAP), not the delay ring, and
+ * is not available to batches. */
 typedef struct {
     uint32_t kernel;          /* SNN_GAUSS or SNN_EXP                           */
     uint32_t record;          /* SNN_REC_F32 (8 B) or SNN_REC_CODE8 (4 B)       */
@@ -131,6 +145,8 @@ typedef struct {
     uint32_t gen;             /* SNN_GEN_PAIRWISE or SNN_GEN_BINOMIAL            */
     uint32_t delay_dist;      /* SNN_DELAY_UNIFORM or SNN_DELAY_EXP              */
     double delay_tau;         /* exponential delays: scale in ms, > 0            */
+    uint32_t solver;          /* SNN_SOLVER_STEP or SNN_SOLVER_EXACT              */
+    uint32_t pad2_;
 } snn_syn_desc;
 
 typedef struct {
@@ -190,8 +206,13 @@ enum {
     SNN_OPT_BIN_THRESHOLD = 7,   /* binned schedule: steps with fewer recurrent
                                     events than this are delivered directly
                                     (0 = always binned)                             */
-    SNN_OPT_EXT_RATE_UHZ = 8     /* after snn_build_synapses: external Poisson rate
+    SNN_OPT_EXT_RATE_UHZ = 8,    /* after snn_build_synapses: external Poisson rate
                                     in micro-hertz (rebuilds the CDF thresholds)    */
+    SNN_OPT_QUEUE_CAP = 9        /* before snn_build_synapses, exact solver: inputs
+                                    one arrival slot holds (0 = automatic: a step's
+                                    events at a 150 Hz mean rate + 65536); inputs
+                                    beyond it are dropped and reported as
+                                    SNN_E_OVERFLOW by the reads and snn_stats       */
 };
 
 /* Create the grid (Sec. III.B) and the initial neuron state: V uniform in
@@ -210,8 +231,17 @@ snn_status snn_step(snn_net* net, uint32_t n_ms);
 
 /* One step in lock-step mode: the spike set of this step is gids[0..n)
  * (host array, any order) instead of each neuron's own threshold test; the
- * threshold test is still evaluated and disagreements are counted. */
+ * threshold test is still evaluated and disagreements are counted.  Step
+ * solver only (SNN_E_STATE under the exact solver). */
 snn_status snn_step_forced(snn_net* net, const uint32_t* gids, size_t n);
+
+/* Exact solver, lock-step mode (Sec. II.C): neuron gids[k] spikes this step
+ * at offset frac[k] (2^-32 ms) -- at its input of that instant, if it is not
+ * refractory then -- and no other neuron spikes; each neuron's own threshold
+ * test is still evaluated and disagreements are counted.  Host arrays of n
+ * entries, each id at most once.  Synchronises.  SNN_E_STATE under the step
+ * solver. */
+snn_status snn_step_forced_exact(snn_net* net, const uint32_t* gids, const uint32_t* frac, size_t n);
 
 /* Copy recorded spikes with t0_ms <= t_ms < t1_ms, ordered by (t_ms, gid),
  * into host_buf.  Synchronises.  SNN_E_TRUNC when more than cap match, or
@@ -219,8 +249,22 @@ snn_status snn_step_forced(snn_net* net, const uint32_t* gids, size_t n);
 snn_status snn_read_spikes(snn_net* net, uint64_t t0_ms, uint64_t t1_ms,
                            snn_spike* host_buf, size_t cap, size_t* n_out);
 
+/* Exact solver: snn_read_spikes plus each spike's emission offset inside
+ * its step, frac[i] in 2^-32 ms for host_buf[i] (both cap entries).
+ * SNN_E_STATE under the step solver. */
+snn_status snn_read_spike_times(snn_net* net, uint64_t t0_ms, uint64_t t1_ms, snn_spike* host_buf,
+                                uint32_t* frac, size_t cap, size_t* n_out);
+
+/* Exact solver: the inputs queued to arrive k steps after the last step taken
+ * (0 <= k <= d_max), unordered: target, offset (2^-32 ms), charge (2^-16 mV),
+ * host arrays of cap entries; *n_out = their number (SNN_E_TRUNC above cap).
+ * Synchronises.  SNN_E_STATE under the step solver. */
+snn_status snn_read_queue(snn_net* net, uint32_t k, uint32_t* tgt, uint32_t* frac, int32_t* wq,
+                          size_t cap, size_t* n_out);
+
 /* Copy the neuron state to host arrays of n_neurons entries each (any may be
- * NULL): membrane potential, fatigue (mV), refractory steps left. */
+ * NULL): membrane potential, fatigue (mV), refractory steps left (exact
+ * solver: whole steps until the refractory period ends, rounded up). */
 snn_status snn_read_state(snn_net* net, float* v, float* w, uint8_t* ref);
 
 /* Copy the delay ring, int32 [32][n_neurons], slot = arrival step mod 32. */
@@ -239,7 +283,9 @@ snn_status snn_stats(snn_net* net, snn_stats_t* out);
 
 /* Run n_ms steps launching each kernel separately between HIP events on the
  * network's stream and report average kernel durations.  The steps are real
- * simulation steps (state advances). */
+ * simulation steps (state advances).  Exact solver: update_ms is the neuron
+ * update, scatter_ms the placing of the arriving inputs by target,
+ * deliver_ms the fan-out into the input queues, step_ms a whole step. */
 snn_status snn_time_kernels(snn_net* net, uint32_t n_ms, snn_kernel_times* out);
 
 /* Return the network to its initial state (as after snn_build_grid: V from the

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "snn.h"
+#include "exact_dev.h"
 #include "snn_dev.h"
 #include "tables.h"
 
@@ -67,6 +68,15 @@ struct snn_net {
     bool bin_threshold_set = false;
     uint64_t bin_threshold_opt = 0;
     std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+    // exact-time solver (SNN_SOLVER_EXACT)
+    bool exact = false;
+    snn::XArgs x{};
+    uint32_t xt = 0;                  // steps taken
+    uint64_t qcap_opt = 0;            // SNN_OPT_QUEUE_CAP, set before the build (0: automatic)
+    uint64_t* xtsum = nullptr;        // scan scratch: per-target counts
+    uint64_t* xtsum2 = nullptr;       // scan scratch: per-workgroup spike counts
+    uint8_t* xforced = nullptr;       // lock-step flags and offsets
+    uint32_t* xforced_f = nullptr;
 };
 
 namespace {
@@ -397,6 +407,113 @@ snn_status snn_build_grid(const snn_grid_desc* g, void* hip_stream, snn_net** ou
     return SNN_OK;
 }
 
+// Exact-time solver state (after the projections exist): refractory ends,
+// spike offsets, the arrival slots' input lists and counts, scan scratch.
+static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
+{
+    const StepArgs& a = n->a;
+    snn::XArgs& x = n->x;
+    const snn_grid_desc& g = n->g;
+    x.N = n->N;
+    x.M = n->M;
+    x.n_exc = g.n_exc;
+    x.sfa_on_inh = g.sfa_on_inh;
+    x.D = n->D;
+    x.d_min = n->s.d_min;
+    x.R = n->s.d_max + 1;    // every arrival slot but the current one is ahead
+    x.record = n->s.record;
+    x.npois = a.npois;
+    x.ext_const = a.ext_const;
+    x.ext_const_q = a.ext_const_q;
+    x.jext_q = a.jext_q;
+    x.key0 = a.key0;
+    x.key1 = a.key1;
+    x.nblk = (n->N + snn::kXBlock - 1) / snn::kXBlock;
+    x.tau_equal = g.tau_w == g.tau_m;
+    x.hist_cap = g.hist_cap;
+    x.tref_q = (uint64_t)std::llround(g.t_ref * 4294967296.0);
+    x.v_th = a.v_th;
+    x.v_reset = a.v_reset;
+    x.e_rest = a.e_rest;
+    x.alpha = a.alpha;
+    x.inv_tau_m = (float)(1.0 / g.tau_m);
+    x.inv_tau_w = (float)(1.0 / g.tau_w);
+    x.ck = x.tau_equal ? 0.0f : (float)(g.tau_w / (g.tau_w - g.tau_m));
+    // inputs queued per slot: a step's events at a 150 Hz mean rate, or the option
+    const double qc = n->qcap_opt ? (double)n->qcap_opt : (double)n->N * (tb.mean_out + 1.0) * 0.15 + 65536.0;
+    x.qcap = (uint64_t)std::min(qc, 4.0e9);
+    hipError_t e = hipSuccess;
+#define XALLOC(p, cnt) \
+    if (e == hipSuccess) e = dalloc(n, &(p), (size_t)(cnt))
+    XALLOC(x.rend, n->N);
+    XALLOC(x.fs, n->N);
+    XALLOC(x.qcnt, (size_t)x.R * n->N);
+    XALLOC(x.qlist, (size_t)x.R * x.qcap);
+    XALLOC(x.qn, x.R);
+    XALLOC(x.dropped, 1);
+    XALLOC(x.qoff, (size_t)n->N + 1);
+    XALLOC(x.qsorted, x.qcap);
+    XALLOC(x.blk_cnt, x.nblk);
+    XALLOC(x.blk_list, (size_t)x.nblk * snn::kXBlock);
+    XALLOC(x.blk_off, (size_t)x.nblk + 1);
+    XALLOC(x.hist_f, g.hist_cap);
+    XALLOC(n->xtsum, snn::scan_tiles(n->N) + 1);
+    XALLOC(n->xtsum2, snn::scan_tiles(x.nblk) + 1);
+    XALLOC(n->xforced, n->N);
+    XALLOC(n->xforced_f, n->N);
+#undef XALLOC
+    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (exact-solver queues)");
+    HIPCHK(n, hipMemsetAsync(x.rend, 0, 8 * (size_t)n->N, n->stream));
+    HIPCHK(n, hipMemsetAsync(x.qcnt, 0, 4 * (size_t)x.R * n->N, n->stream));
+    HIPCHK(n, hipMemsetAsync(x.qn, 0, 8 * (size_t)x.R, n->stream));
+    HIPCHK(n, hipMemsetAsync(x.dropped, 0, 8, n->stream));
+    HIPCHK(n, hipMemsetAsync(x.qoff, 0, 8, n->stream));      // offset of the first target
+    HIPCHK(n, hipMemsetAsync(x.blk_off, 0, 8, n->stream));   // offset of the first workgroup
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    x.V = a.V;
+    x.W = a.W;
+    x.hist = a.hist;
+    x.ctrl = a.ctrl;
+    x.row_ptr = a.row_ptr;
+    x.bend = a.bend;
+    x.recs = a.recs;
+    x.poisc = a.poisc;
+    x.cb = a.cb;
+    x.forced = nullptr;
+    x.forced_f = nullptr;
+    n->xt = 0;
+    n->exact = true;
+    return SNN_OK;
+}
+
+// One step of the exact solver on the network's stream (x: the network's
+// arguments, possibly with lock-step flags); ev, if given: timing events of
+// the place, update and deliver launches.
+static hipError_t enqueue_exact_step(snn_net* n, const snn::XArgs& x, const snn::LaunchEv* ev)
+{
+    const uint32_t t = n->xt;
+    const uint32_t slot = t % x.R;
+    hipError_t e = snn::launch_scan_rows(x.qcnt + (size_t)slot * n->N, x.qoff, n->xtsum, n->N, n->stream);
+    if (e == hipSuccess) e = snn::launch_x_place(x, t, n->stream, ev ? &ev[0] : nullptr);
+    if (e == hipSuccess) e = snn::launch_x_update(x, t, n->stream, ev ? &ev[1] : nullptr);
+    if (e == hipSuccess) e = snn::launch_scan_rows(x.blk_cnt, x.blk_off, n->xtsum2, x.nblk, n->stream);
+    if (e == hipSuccess) e = snn::launch_x_deliver(x, t, n->stream, ev ? &ev[2] : nullptr);
+    if (e == hipSuccess) e = snn::launch_x_finish(x, n->stream);
+    if (e == hipSuccess) n->xt = t + 1;
+    return e;
+}
+
+// Inputs dropped because an arrival slot's list was full (exact solver).
+static snn_status check_dropped(snn_net* n)
+{
+    if (!n->exact) return SNN_OK;
+    unsigned long long d = 0;
+    HIPCHK(n, hipMemcpy(&d, n->x.dropped, 8, hipMemcpyDeviceToHost));
+    if (d) return fail(n, SNN_E_OVERFLOW, "exact solver: " + std::to_string(d) +
+                                          " inputs found their arrival slot full (raise SNN_OPT_QUEUE_CAP)");
+    return SNN_OK;
+}
+
 snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
 {
     snn_status st = check_usable(n);
@@ -414,6 +531,9 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
         return fail(n, SNN_E_INVAL, "8-bit code records need fewer than 2^24 neurons");
     if (s->ext_mode == SNN_EXT_POISSON && !(s->ext_n * s->ext_rate_hz >= 0))
         return fail(n, SNN_E_INVAL, "bad external drive");
+    if (s->solver > SNN_SOLVER_EXACT) return fail(n, SNN_E_INVAL, "unknown solver");
+    if (s->solver == SNN_SOLVER_EXACT && !(n->g.t_ref >= 1.0 && n->g.t_ref < 1.0e6))
+        return fail(n, SNN_E_INVAL, "the exact solver needs 1 <= t_ref < 1e6 ms");
     const auto t_start = std::chrono::steady_clock::now();
     snn::TableParams tp = table_params(n->g, *s);
     snn::HostTables tb;
@@ -549,7 +669,11 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     n->binned_ok = ok1;
     n->two_level_ok = ok2;
     uint32_t mode = 0;
-    if (n->mode_pref == 2) mode = ok2 ? 2 : 0;
+    if (s->solver == SNN_SOLVER_EXACT) {
+        n->binned_ok = n->two_level_ok = false;   // the exact solver has its own queues
+        st = setup_exact(n, tb);
+        if (st) return st;
+    } else if (n->mode_pref == 2) mode = ok2 ? 2 : 0;
     else if (n->mode_pref == 1) mode = ok1 ? 1 : 0;
     else if (n->mode_pref < 0) mode = ok1 ? 1 : (ok2 ? 2 : 0);
     if (mode) {
@@ -587,6 +711,10 @@ snn_status snn_step(snn_net* n, uint32_t n_ms)
     snn_status st = check_usable(n);
     if (st) return st;
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (n->exact) {
+        for (uint32_t i = 0; i < n_ms; ++i) HIPCHK(n, enqueue_exact_step(n, n->x, nullptr));
+        return SNN_OK;
+    }
     uint32_t left = n_ms;
     if (n->graph_chunk > 0) {
         while (left >= n->graph_chunk) {
@@ -608,6 +736,7 @@ snn_status snn_step_forced(snn_net* n, const uint32_t* gids, size_t cnt)
     snn_status st = check_usable(n);
     if (st) return st;
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (n->exact) return fail(n, SNN_E_STATE, "the exact solver takes spike times: use snn_step_forced_exact");
     if (cnt > n->N || (cnt && !gids)) return fail(n, SNN_E_INVAL, "bad forced spike set");
     for (size_t i = 0; i < cnt; ++i)
         if (gids[i] >= n->N) return fail(n, SNN_E_INVAL, "forced spike id out of range");
@@ -622,12 +751,12 @@ snn_status snn_step_forced(snn_net* n, const uint32_t* gids, size_t cnt)
     return SNN_OK;
 }
 
-snn_status snn_read_spikes(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, size_t cap,
-                           size_t* n_out)
+static snn_status read_history(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, uint32_t* frac, size_t cap,
+                        size_t* n_out)
 {
     snn_status st = check_usable(n);
     if (st) return st;
-    if (!n_out || (cap && !buf)) return fail(n, SNN_E_INVAL, "null output");
+    if (!n_out || (cap && (!buf || (frac && !n->exact)))) return fail(n, SNN_E_INVAL, "null output");
     HIPCHK(n, hipStreamSynchronize(n->stream));
     Ctrl hc{};
     HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
@@ -660,8 +789,74 @@ snn_status snn_read_spikes(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf,
     *n_out = (size_t)m;
     if (m > cap) return fail(n, SNN_E_TRUNC, "spike buffer too small");
     if (m) HIPCHK(n, hipMemcpy(buf, n->a.hist + p0, m * sizeof(snn_spike), hipMemcpyDeviceToHost));
+    if (m && frac) HIPCHK(n, hipMemcpy(frac, n->x.hist_f + p0, m * sizeof(uint32_t), hipMemcpyDeviceToHost));
     if (hc.hist_n > n->g.hist_cap) return fail(n, SNN_E_TRUNC, "spike history overflowed its capacity");
+    return check_dropped(n);
+}
+
+snn_status snn_read_spikes(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, size_t cap,
+                           size_t* n_out)
+{
+    return read_history(n, t0, t1, buf, nullptr, cap, n_out);
+}
+
+snn_status snn_read_spike_times(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, uint32_t* frac,
+                                size_t cap, size_t* n_out)
+{
+    if (n && !n->exact) return fail(n, SNN_E_STATE, "spike offsets exist only under the exact solver");
+    if (cap && !frac) return fail(n, SNN_E_INVAL, "null output");
+    return read_history(n, t0, t1, buf, frac, cap, n_out);
+}
+
+snn_status snn_step_forced_exact(snn_net* n, const uint32_t* gids, const uint32_t* frac, size_t cnt)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (!n->exact) return fail(n, SNN_E_STATE, "snn_step_forced_exact needs the exact solver");
+    if (cnt > n->N || (cnt && (!gids || !frac))) return fail(n, SNN_E_INVAL, "bad forced spike set");
+    std::vector<uint8_t> flags(n->N, 0);
+    std::vector<uint32_t> ff(n->N, 0);
+    for (size_t i = 0; i < cnt; ++i) {
+        if (gids[i] >= n->N) return fail(n, SNN_E_INVAL, "forced spike id out of range");
+        if (flags[gids[i]]) return fail(n, SNN_E_INVAL, "a neuron is forced twice in one step");
+        flags[gids[i]] = 1;
+        ff[gids[i]] = frac[i];
+    }
+    HIPCHK(n, hipMemcpyAsync(n->xforced, flags.data(), n->N, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, hipMemcpyAsync(n->xforced_f, ff.data(), 4 * (size_t)n->N, hipMemcpyHostToDevice, n->stream));
+    snn::XArgs x = n->x;
+    x.forced = n->xforced;
+    x.forced_f = n->xforced_f;
+    HIPCHK(n, enqueue_exact_step(n, x, nullptr));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
     return SNN_OK;
+}
+
+snn_status snn_read_queue(snn_net* n, uint32_t k, uint32_t* tgt, uint32_t* frac, int32_t* wq, size_t cap,
+                          size_t* n_out)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->exact) return fail(n, SNN_E_STATE, "input queues exist only under the exact solver");
+    if (!n_out || (cap && (!tgt || !frac || !wq))) return fail(n, SNN_E_INVAL, "null output");
+    if (k >= n->x.R) return fail(n, SNN_E_INVAL, "arrival step beyond the largest delay");
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    const uint32_t slot = (n->xt + k) % n->x.R;
+    unsigned long long qn = 0;
+    HIPCHK(n, hipMemcpy(&qn, n->x.qn + slot, 8, hipMemcpyDeviceToHost));
+    const uint64_t m = qn < n->x.qcap ? qn : n->x.qcap;
+    *n_out = (size_t)m;
+    if (m > cap) return fail(n, SNN_E_TRUNC, "queue buffer too small");
+    std::vector<uint4> q(m);
+    if (m) HIPCHK(n, hipMemcpy(q.data(), n->x.qlist + (size_t)slot * n->x.qcap, m * sizeof(uint4),
+                               hipMemcpyDeviceToHost));
+    for (uint64_t i = 0; i < m; ++i) {
+        tgt[i] = q[i].x;
+        frac[i] = q[i].y;
+        wq[i] = (int32_t)q[i].z;
+    }
+    return check_dropped(n);
 }
 
 snn_status snn_read_state(snn_net* n, float* v, float* w, uint8_t* ref)
@@ -671,7 +866,16 @@ snn_status snn_read_state(snn_net* n, float* v, float* w, uint8_t* ref)
     HIPCHK(n, hipStreamSynchronize(n->stream));
     if (v) HIPCHK(n, hipMemcpy(v, n->a.V, (size_t)n->N * 4, hipMemcpyDeviceToHost));
     if (w) HIPCHK(n, hipMemcpy(w, n->a.W, (size_t)n->N * 4, hipMemcpyDeviceToHost));
-    if (ref) HIPCHK(n, hipMemcpy(ref, n->a.ref, (size_t)n->N, hipMemcpyDeviceToHost));
+    if (ref && n->exact) {
+        // whole steps of refractoriness left after the last step
+        std::vector<uint64_t> re(n->N);
+        HIPCHK(n, hipMemcpy(re.data(), n->x.rend, (size_t)n->N * 8, hipMemcpyDeviceToHost));
+        const uint64_t now = (uint64_t)n->xt << 32;
+        for (uint32_t i = 0; i < n->N; ++i)
+            ref[i] = re[i] > now ? (uint8_t)std::min<uint64_t>((re[i] - now + 0xFFFFFFFFull) >> 32, 255) : 0;
+    } else if (ref) {
+        HIPCHK(n, hipMemcpy(ref, n->a.ref, (size_t)n->N, hipMemcpyDeviceToHost));
+    }
     return SNN_OK;
 }
 
@@ -721,7 +925,7 @@ snn_status snn_stats(snn_net* n, snn_stats_t* out)
     Ctrl hc{};
     HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     fill_stats(n, hc, out);
-    return SNN_OK;
+    return check_dropped(n);
 }
 
 }  // extern "C"
@@ -746,12 +950,67 @@ void fill_stats(const snn_net* n, const Ctrl& hc, snn_stats_t* out)
 
 extern "C" {
 
+// Kernel timing of the exact solver: place, update and deliver launches
+// stamped by their own events, and each whole step between two events.
+static snn_status time_exact(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
+{
+    std::memset(out, 0, sizeof(*out));
+    constexpr uint32_t kB = 64;   // steps per batch
+    std::vector<snn::LaunchEv> ev(kB * 4);
+    hipError_t e = hipSuccess;
+    for (auto& x : ev) {
+        if (e == hipSuccess) e = hipEventCreate(&x.start);
+        if (e == hipSuccess) e = hipEventCreate(&x.stop);
+    }
+    auto destroy = [&]() {
+        for (auto& x : ev) {
+            if (x.start) (void)hipEventDestroy(x.start);
+            if (x.stop) (void)hipEventDestroy(x.stop);
+        }
+    };
+    Ctrl c0{}, c1{};
+    if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    double sum[4] = {0, 0, 0, 0};
+    for (uint32_t b0 = 0; b0 < n_ms && e == hipSuccess; b0 += kB) {
+        const uint32_t nb = (n_ms - b0) < kB ? (n_ms - b0) : kB;
+        for (uint32_t i = 0; i < nb && e == hipSuccess; ++i) {
+            snn::LaunchEv* x = &ev[i * 4];
+            e = hipEventRecord(x[3].start, n->stream);
+            if (e == hipSuccess) e = enqueue_exact_step(n, n->x, x);
+            if (e == hipSuccess) e = hipEventRecord(x[3].stop, n->stream);
+        }
+        if (e == hipSuccess) e = hipStreamSynchronize(n->stream);
+        for (uint32_t j = 0; j < nb * 4 && e == hipSuccess; ++j) {
+            float ms = 0;
+            e = hipEventElapsedTime(&ms, ev[j].start, ev[j].stop);
+            sum[j % 4] += ms;
+        }
+    }
+    if (e == hipSuccess) e = hipMemcpy(&c1, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
+    destroy();
+    if (e != hipSuccess) {
+        n->poisoned = true;
+        return fail_hip(n, e, "kernel timing");
+    }
+    const double steps = n_ms ? (double)n_ms : 1.0;
+    out->scatter_ms = sum[0] / steps;
+    out->update_ms = sum[1] / steps;
+    out->deliver_ms = sum[2] / steps;
+    out->step_ms = sum[3] / steps;
+    out->steps = n_ms;
+    out->rec_events = c1.rec_events - c0.rec_events;
+    out->spikes = c1.spikes - c0.spikes;
+    return check_dropped(n);
+}
+
 snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
 {
     snn_status st = check_usable(n);
     if (st) return st;
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
     if (!out) return fail(n, SNN_E_INVAL, "null output");
+    if (n->exact) return time_exact(n, n_ms, out);
     if (check_items(n) != hipSuccess) return fail(n, SNN_E_INVAL, "spike items exceed 32 bits");
     std::memset(out, 0, sizeof(*out));
     // The steps are the ones snn_step enqueues (same kernels, same order), each
@@ -857,6 +1116,14 @@ snn_status snn_reset(snn_net* n)
     if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride, n->stream));
     if (a.sbin_fill) HIPCHK(n, hipMemsetAsync(a.sbin_fill, 0, 4 * (size_t)a.nsuper * snn::kFillStride, n->stream));
     HIPCHK(n, snn::launch_init(a, n->stream));
+    if (n->exact) {
+        const snn::XArgs& x = n->x;
+        HIPCHK(n, hipMemsetAsync(x.rend, 0, 8 * (size_t)n->N, n->stream));
+        HIPCHK(n, hipMemsetAsync(x.qcnt, 0, 4 * (size_t)x.R * n->N, n->stream));
+        HIPCHK(n, hipMemsetAsync(x.qn, 0, 8 * (size_t)x.R, n->stream));
+        HIPCHK(n, hipMemsetAsync(x.dropped, 0, 8, n->stream));
+        n->xt = 0;
+    }
     if (n->built) {
         // the construction statistics live in the control block too
         snn::Ctrl keep{};
@@ -880,8 +1147,14 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         if (value < 4 || value > (1 << 20)) return fail(n, SNN_E_INVAL, "wave count out of range");
         n->deliver_waves = (uint32_t)value;
         break;
+    case SNN_OPT_QUEUE_CAP:
+        if (n->built) return fail(n, SNN_E_STATE, "queue capacity is fixed once synapses are built");
+        if (value < 0 || value > 4000000000ll) return fail(n, SNN_E_INVAL, "queue capacity out of range");
+        n->qcap_opt = (uint64_t)value;
+        return SNN_OK;
     case SNN_OPT_DELIVER_MODE:
         if (value < 0 || value > 2) return fail(n, SNN_E_INVAL, "delivery mode must be 0, 1 or 2");
+        if (n->exact) return fail(n, SNN_E_STATE, "the exact solver delivers through its own input queues");
         if (!n->built) {
             n->mode_pref = (int)value;    // before the build: selects which bins are allocated
             return SNN_OK;
@@ -1304,6 +1577,7 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
     snn_status st = batch_check(b);
     if (st) return st;
     if (!g || !s || !slot || dur_ms == 0) return bfail(b, SNN_E_INVAL, "bad job arguments");
+    if (s->solver != SNN_SOLVER_STEP) return bfail(b, SNN_E_INVAL, "batches run the step solver only");
     *slot = -1;
     std::string why;
     if (!valid_grid(g, why)) return bfail(b, SNN_E_INVAL, why);

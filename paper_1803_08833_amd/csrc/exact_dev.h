@@ -1,0 +1,69 @@
+// exact_dev.h -- the exact-time event-driven solver (Sec. II.A, Sec. II.C):
+// device layout, kernel arguments and launchers.
+//
+// Times are ms in 32.32 fixed point, (step << 32) | offset.  A spike is
+// emitted at the instant of the input that takes V above V_th and reaches each
+// target an integer delay later, keeping its offset.  Per arrival slot the
+// queued inputs are held twice: as an unsorted list appended by delivery
+// (one 16-byte {target, offset, charge} entry per event, and a per-target
+// count), and, at the step they arrive, counting-sorted by target into
+// {offset, charge} pairs.  The update takes each neuron's inputs, with its
+// external ones, in time order and integrates Eq. (1)-(2) exactly between
+// them.
+#pragma once
+#include "snn_dev.h"
+
+namespace snn {
+
+constexpr uint32_t kStreamExtTime = 7u;   // offsets of the external inputs of a step
+constexpr uint32_t kXBlock = 256;          // neurons per update workgroup
+constexpr uint32_t kXLocal = 32;           // inputs per neuron sorted in LDS (more: slow path)
+
+struct XArgs {
+    uint32_t N, M, n_exc, sfa_on_inh;
+    uint32_t D, d_min, R, record;          // R: arrival slots (d_max + 1)
+    uint32_t npois, ext_const;
+    int32_t ext_const_q, jext_q;
+    uint32_t key0, key1;
+    uint32_t nblk;                         // update workgroups (kXBlock neurons each)
+    uint32_t tau_equal;                    // tau_w == tau_m
+    uint64_t hist_cap;
+    uint64_t qcap;                         // queued inputs per slot
+    uint64_t tref_q;                       // refractory period, 2^-32 ms
+    float v_th, v_reset, e_rest, alpha;
+    float inv_tau_m, inv_tau_w, ck;        // ck = tau_w / (tau_w - tau_m)
+    float* V;
+    float* W;
+    uint64_t* rend;                        // [N] end of the refractory period
+    uint32_t* fs;                          // [N] offset of the neuron's last spike
+    uint32_t* qcnt;                        // [R][N] queued inputs per target
+    uint4* qlist;                          // [R][qcap] {target, offset, charge, 0}
+    unsigned long long* qn;                // [R] entries appended per slot (may exceed qcap)
+    unsigned long long* dropped;           // inputs that found their slot full
+    uint64_t* qoff;                        // [N + 1] exclusive scan of this step's counts
+    uint2* qsorted;                        // [qcap] {offset, charge} by target
+    uint32_t* blk_cnt;                     // [nblk] spikers per update workgroup
+    uint32_t* blk_list;                    // [nblk * kXBlock] their ids, ascending
+    uint64_t* blk_off;                     // [nblk + 1] exclusive scan of blk_cnt
+    uint2* hist;                           // [hist_cap] (t, gid)
+    uint32_t* hist_f;                      // [hist_cap] emission offsets
+    Ctrl* ctrl;                            // counters shared with the step solver's reads
+    const uint64_t* row_ptr;
+    const uint16_t* bend;
+    const void* recs;
+    const uint32_t* poisc;
+    const int32_t* cb;
+    const uint8_t* forced;                 // lock-step: spike flags, or nullptr
+    const uint32_t* forced_f;              //            and their offsets
+};
+
+// One step t of the solver, after the caller has scanned qcnt[t mod R] into
+// qoff: place the slot's inputs by target, update every neuron, then (after
+// the caller has scanned blk_cnt into blk_off) record and deliver the spikes
+// and close the step.
+hipError_t launch_x_place(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_x_update(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_x_deliver(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_x_finish(const XArgs& a, hipStream_t s);
+
+}  // namespace snn

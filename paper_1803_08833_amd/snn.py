@@ -23,6 +23,8 @@ OPT_GRAPH_CHUNK, OPT_DELIVER_WAVES, OPT_DELIVER_UNROLL, OPT_DELIVER_MODE, OPT_SC
 OPT_BIN_FRAC_PPM = 6
 OPT_BIN_THRESHOLD = 7
 OPT_EXT_RATE_UHZ = 8
+OPT_QUEUE_CAP = 9
+SOLVER_STEP, SOLVER_EXACT = 0, 1
 RING = 32
 
 EXPORTS = [
@@ -31,7 +33,7 @@ EXPORTS = [
     "snn_set_option", "snn_host_tables", "snn_reset", "snn_destroy", "snn_last_error",
     "snn_batch_create", "snn_batch_admit", "snn_batch_step", "snn_batch_poll", "snn_batch_read_spikes",
     "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
-    "snn_set_allocator",
+    "snn_set_allocator", "snn_step_forced_exact", "snn_read_spike_times", "snn_read_queue",
 ]
 
 # snn_set_allocator's function types: alloc(bytes, ctx) -> pointer, free(ptr, ctx)
@@ -61,6 +63,7 @@ class SynDesc(C.Structure):
         ("preset", C.c_uint32), ("pad1_", C.c_uint32),
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
         ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
+        ("solver", C.c_uint32), ("pad2_", C.c_uint32),
     ]
 
 
@@ -126,6 +129,9 @@ def lib():
             "snn_destroy": ([P], None),
             "snn_last_error": ([P], C.c_char_p),
             "snn_set_allocator": ([ALLOC_FN, FREE_FN, P], C.c_int),
+            "snn_step_forced_exact": ([P, P, P, SZ], C.c_int),
+            "snn_read_spike_times": ([P, U64, U64, P, P, SZ, C.POINTER(SZ)], C.c_int),
+            "snn_read_queue": ([P, U32, P, P, P, SZ, C.POINTER(SZ)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -153,7 +159,7 @@ def syn_desc(net: dict) -> SynDesc:
     for k in ("kernel", "record", "range", "k_in", "d_min", "d_max", "w_exc", "w_exc_sd", "w_inh",
               "ext_mode", "ext_const_q", "ext_n", "ext_rate_hz", "ext_w"):
         setattr(s, k, net[k])
-    for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau"):   # absent: defaults
+    for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau", "solver"):   # absent: defaults
         setattr(s, k, net.get(k, 0))
     return s
 
@@ -275,6 +281,39 @@ class Net:
         out = np.zeros((max(n.value, 1), 2), dtype=np.uint32)
         self._check(lib().snn_read_spikes(self.h, t0, t1, _p(out), n.value, C.byref(n)))
         return out[: n.value]
+
+    def step_forced_exact(self, gids, fracs):
+        """Exact solver, lock-step: neuron gids[k] spikes at offset fracs[k] (2^-32 ms)."""
+        g = np.ascontiguousarray(gids, dtype=np.uint32)
+        f = np.ascontiguousarray(fracs, dtype=np.uint32)
+        if g.size != f.size:
+            raise ValueError("one offset per forced spike")
+        self._check(lib().snn_step_forced_exact(self.h, _p(g), _p(f), g.size))
+
+    def read_spike_times(self, t0=0, t1=2**63):
+        """Exact solver: (t_ms, gid) rows and each spike's offset (2^-32 ms)."""
+        n = C.c_size_t(0)
+        st = lib().snn_read_spike_times(self.h, t0, t1, None, None, 0, C.byref(n))
+        if st not in (SNN_OK, SNN_E_TRUNC):
+            self._check(st)
+        out = np.zeros((max(n.value, 1), 2), dtype=np.uint32)
+        fr = np.zeros(max(n.value, 1), dtype=np.uint32)
+        self._check(lib().snn_read_spike_times(self.h, t0, t1, _p(out), _p(fr), n.value, C.byref(n)))
+        return out[: n.value], fr[: n.value]
+
+    def read_queue(self, k: int):
+        """Exact solver: inputs arriving k steps ahead, (target, offset, charge)
+        rows ordered by target, offset, charge."""
+        n = C.c_size_t(0)
+        st = lib().snn_read_queue(self.h, k, None, None, None, 0, C.byref(n))
+        if st not in (SNN_OK, SNN_E_TRUNC):
+            self._check(st)
+        m = max(n.value, 1)
+        tgt, fr, wq = np.zeros(m, np.uint32), np.zeros(m, np.uint32), np.zeros(m, np.int32)
+        self._check(lib().snn_read_queue(self.h, k, _p(tgt), _p(fr), _p(wq), n.value, C.byref(n)))
+        q = np.stack([tgt[: n.value].astype(np.int64), fr[: n.value].astype(np.int64),
+                      wq[: n.value].astype(np.int64)], axis=1)
+        return q[np.lexsort((q[:, 2], q[:, 1], q[:, 0]))] if len(q) else q
 
     def read_state(self):
         V = np.zeros(self.N, dtype=np.float32)
