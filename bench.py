@@ -27,6 +27,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E peak
 BYTES_PER_EVENT = {0: 16, 1: 12}      # record + ring slot read + write (F32 / 8-bit code records)
 BYTES_PER_NEURON_STEP = 26            # V 4+4, w 4+4, ref 1+1, ring slot 4+4
+# Exact-time solver: per event the record (8 / 4 B), the queue entry written
+# (16) and read back (16), its count raised (4) and lowered (4), the placed
+# {offset, charge} pair written (8) and read by the update (8); per neuron and
+# step V, w and the refractory end read and written (32), the input count
+# scanned (4 read, 8 written) and the neuron's offset read (8).
+BYTES_EXACT_PER_EVENT = {0: 64, 1: 60}
+BYTES_EXACT_PER_NEURON_STEP = 52
 
 
 def parse():
@@ -45,6 +52,9 @@ def parse():
                    help="synapse generator of the served jobs: 0 one trial per pair, 1 binomial + Floyd")
     p.add_argument("--graph-chunk", type=int, default=250,
                    help="steps per captured HIP graph (0: launch every kernel directly)")
+    p.add_argument("--queue-cap", type=float, default=0.3,
+                   help="exact solver: queued inputs per arrival slot, as a mean rate in kHz "
+                        "times neurons times synapses per neuron")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="end with one plain device copy of this size (reference kernel for HBM counters)")
     return p.parse_args()
@@ -163,11 +173,14 @@ def main():
     N = net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
     hist_cap = int(min(2**27, N * 60 * (args.steps + args.warmup) + (1 << 22)))
     g = snn.Net(net, hist_cap=hist_cap, stream=stream)
+    exact = net.get("solver", 0) == snn.SOLVER_EXACT
+    if exact:
+        g.set_option(snn.OPT_QUEUE_CAP, int(N * (net["k_in"] + 1) * args.queue_cap))
     tb = time.perf_counter()
     g.build_synapses()
     torch.cuda.synchronize()
     build_s = time.perf_counter() - tb
-    if args.deliver_mode is not None:
+    if args.deliver_mode is not None and not exact:
         g.set_option(snn.OPT_DELIVER_MODE, args.deliver_mode)
     g.set_option(snn.OPT_GRAPH_CHUNK, args.graph_chunk)   # default: a bench step (1000 ms) is four graphs
     st0 = g.stats()
@@ -205,8 +218,15 @@ def main():
     replay_ok = kt["rec_events"] == rec and kt["spikes"] == spikes
     steps_k = max(1, kt["steps"])
     bpe = BYTES_PER_EVENT[net["record"]]
+    bpn = BYTES_PER_NEURON_STEP
     ev_per_step = kt["rec_events"] / steps_k
-    if stf["deliver_mode"] == 1:
+    if exact:
+        # one step: count scan, k_x_place, k_x_update, spike scan, k_x_deliver, k_x_finish
+        name = ("k_x_place+k_x_update+k_x_deliver with their scans (one 1 ms step of the exact-time "
+                "solver)")
+        ms = kt["step_ms"]
+        bpe, bpn = BYTES_EXACT_PER_EVENT[net["record"]], BYTES_EXACT_PER_NEURON_STEP
+    elif stf["deliver_mode"] == 1:
         # one step = k_scatter (compaction + delivery phase A) + k_tile (phase B
         # + the next step's neuron update)
         name = "k_scatter+k_tile (one 1 ms step: compaction, delivery, fused neuron update)"
@@ -218,15 +238,15 @@ def main():
     else:
         name = "k_update+k_compact+k_deliver (one 1 ms step, direct atomics)"
         ms = kt["update_ms"] + kt["compact_ms"] + kt["deliver_ms"]
-    step_bytes = ev_per_step * bpe + N * BYTES_PER_NEURON_STEP
+    step_bytes = ev_per_step * bpe + N * bpn
     achieved = step_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
     roofline = {"bound": "hbm", "kernel": name,
                 "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profile(args, steps_k),
+                "traffic": None if exact else traffic_from_profile(args, steps_k),
                 "bytes_per_launch": round(step_bytes, 1), "avg_launch_ms": round(ms, 6),
                 "events_per_launch": round(ev_per_step, 1),
-                "bytes_per_event": bpe, "bytes_per_neuron_step": BYTES_PER_NEURON_STEP,
+                "bytes_per_event": bpe, "bytes_per_neuron_step": bpn,
                 "launches_timed": kt["steps"], "replay_identical": bool(replay_ok)}
     result = {
         "metric": "synaptic events/s + sim-s per wall-s, 24x24 exp grid; served-job p50/p99",
@@ -251,6 +271,7 @@ def main():
         "total_equiv_events_per_s": (rec + ext) / wall,
         "mean_rate_hz": rate_hz,
         "build_s": build_s,
+        "solver": "exact-time event-driven" if exact else "1 ms step",
         "kernels_avg_ms": {"k_update": round(kt["update_ms"], 6), "k_compact": round(kt["compact_ms"], 6),
                            "k_scatter": round(kt["scatter_ms"], 6), "k_sub": round(kt["sub_ms"], 6),
                            "k_tile": round(kt["tile_ms"], 6),
@@ -269,7 +290,7 @@ def main():
         result["served"] = serve.bench_served(args.serve_jobs, args.serve_plain, args.serve_capacity, log=say,
                                               gen=args.serve_gen)
         result["served"]["generator"] = "binomial + Floyd" if args.serve_gen else "one trial per pair"
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not exact:
         sps = spikes / max(1, args.steps * 1000)
         result["cpu_baseline"] = cpu_baseline(net, max(1, int(round(sps))))
     if args.copy_mib:

@@ -74,9 +74,10 @@ struct snn_net {
     uint32_t xt = 0;                  // steps taken
     uint64_t qcap_opt = 0;            // SNN_OPT_QUEUE_CAP, set before the build (0: automatic)
     uint64_t* xtsum = nullptr;        // scan scratch: per-target counts
-    uint64_t* xtsum2 = nullptr;       // scan scratch: per-workgroup spike counts
     uint8_t* xforced = nullptr;       // lock-step flags and offsets
     uint32_t* xforced_f = nullptr;
+    hipGraph_t xgraph = nullptr;      // R captured steps from a step t with t mod R = 0
+    hipGraphExec_t xgraph_ex = nullptr;
 };
 
 namespace {
@@ -170,6 +171,10 @@ void drop_graphs(snn_net* n)
         (void)hipGraphDestroy(kv.second.first);
     }
     n->graphs.clear();
+    if (n->xgraph_ex) (void)hipGraphExecDestroy(n->xgraph_ex);
+    if (n->xgraph) (void)hipGraphDestroy(n->xgraph);
+    n->xgraph_ex = nullptr;
+    n->xgraph = nullptr;
 }
 
 snn_status check_usable(snn_net* n)
@@ -429,6 +434,7 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
     x.key0 = a.key0;
     x.key1 = a.key1;
     x.nblk = (n->N + snn::kXBlock - 1) / snn::kXBlock;
+    x.smax = (n->max_len + 255u) / 256u;
     x.tau_equal = g.tau_w == g.tau_m;
     x.hist_cap = g.hist_cap;
     x.tref_q = (uint64_t)std::llround(g.t_ref * 4294967296.0);
@@ -450,15 +456,17 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
     XALLOC(x.qcnt, (size_t)x.R * n->N);
     XALLOC(x.qlist, (size_t)x.R * x.qcap);
     XALLOC(x.qn, x.R);
+    XALLOC(x.qn_prev, x.R);
+    XALLOC(x.blk_ext, x.nblk);
     XALLOC(x.dropped, 1);
     XALLOC(x.qoff, (size_t)n->N + 1);
     XALLOC(x.qsorted, x.qcap);
     XALLOC(x.blk_cnt, x.nblk);
     XALLOC(x.blk_list, (size_t)x.nblk * snn::kXBlock);
     XALLOC(x.blk_off, (size_t)x.nblk + 1);
+    XALLOC(x.spk, n->N);
     XALLOC(x.hist_f, g.hist_cap);
     XALLOC(n->xtsum, snn::scan_tiles(n->N) + 1);
-    XALLOC(n->xtsum2, snn::scan_tiles(x.nblk) + 1);
     XALLOC(n->xforced, n->N);
     XALLOC(n->xforced_f, n->N);
 #undef XALLOC
@@ -494,13 +502,51 @@ static hipError_t enqueue_exact_step(snn_net* n, const snn::XArgs& x, const snn:
     const uint32_t t = n->xt;
     const uint32_t slot = t % x.R;
     hipError_t e = snn::launch_scan_rows(x.qcnt + (size_t)slot * n->N, x.qoff, n->xtsum, n->N, n->stream);
-    if (e == hipSuccess) e = snn::launch_x_place(x, t, n->stream, ev ? &ev[0] : nullptr);
-    if (e == hipSuccess) e = snn::launch_x_update(x, t, n->stream, ev ? &ev[1] : nullptr);
-    if (e == hipSuccess) e = snn::launch_scan_rows(x.blk_cnt, x.blk_off, n->xtsum2, x.nblk, n->stream);
-    if (e == hipSuccess) e = snn::launch_x_deliver(x, t, n->stream, ev ? &ev[2] : nullptr);
+    if (e == hipSuccess) e = snn::launch_x_place(x, n->stream, ev ? &ev[0] : nullptr);
+    if (e == hipSuccess) e = snn::launch_x_update(x, n->stream, ev ? &ev[1] : nullptr);
+    if (e == hipSuccess) e = snn::launch_x_list(x, n->stream);
+    if (e == hipSuccess) e = snn::launch_x_deliver(x, n->stream, ev ? &ev[2] : nullptr);
     if (e == hipSuccess) e = snn::launch_x_finish(x, n->stream);
     if (e == hipSuccess) n->xt = t + 1;
     return e;
+}
+
+// Exact solver, n_ms steps: whenever the step index is a multiple of R and R
+// steps are left, the R steps are replayed from a captured graph (the scans'
+// slot pointers are fixed in it, the kernels read the step from the device);
+// other steps are launched one by one.
+static hipError_t step_exact(snn_net* n, uint32_t n_ms)
+{
+    const uint32_t R = n->x.R;
+    uint32_t left = n_ms;
+    while (left) {
+        if (n->xt % R == 0 && left >= R) {
+            if (!n->xgraph_ex) {
+                const uint32_t xt0 = n->xt;
+                hipError_t e = hipStreamBeginCapture(n->stream, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) return e;
+                hipError_t le = hipSuccess;
+                for (uint32_t i = 0; i < R && le == hipSuccess; ++i) le = enqueue_exact_step(n, n->x, nullptr);
+                n->xt = xt0;
+                e = hipStreamEndCapture(n->stream, &n->xgraph);
+                if (le == hipSuccess) le = e;
+                if (le == hipSuccess) le = hipGraphInstantiate(&n->xgraph_ex, n->xgraph, nullptr, nullptr, 0);
+                if (le != hipSuccess) {
+                    drop_graphs(n);
+                    return le;
+                }
+            }
+            hipError_t e = hipGraphLaunch(n->xgraph_ex, n->stream);
+            if (e != hipSuccess) return e;
+            n->xt += R;
+            left -= R;
+        } else {
+            hipError_t e = enqueue_exact_step(n, n->x, nullptr);
+            if (e != hipSuccess) return e;
+            --left;
+        }
+    }
+    return hipSuccess;
 }
 
 // Inputs dropped because an arrival slot's list was full (exact solver).
@@ -712,7 +758,11 @@ snn_status snn_step(snn_net* n, uint32_t n_ms)
     if (st) return st;
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
     if (n->exact) {
-        for (uint32_t i = 0; i < n_ms; ++i) HIPCHK(n, enqueue_exact_step(n, n->x, nullptr));
+        if (n->graph_chunk == 0) {
+            for (uint32_t i = 0; i < n_ms; ++i) HIPCHK(n, enqueue_exact_step(n, n->x, nullptr));
+        } else {
+            HIPCHK(n, step_exact(n, n_ms));
+        }
         return SNN_OK;
     }
     uint32_t left = n_ms;

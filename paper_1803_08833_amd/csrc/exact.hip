@@ -8,9 +8,12 @@
 //                external) in time order, Eq. (1)-(2) solved exactly between
 //                them, a spike at the input that crosses threshold; ordered
 //                spiker list per 256-neuron workgroup
-//   k_x_deliver  one wave per spike: AER history entry (step, id, offset) and
-//                fan-out of the row, one reservation per delay bucket in the
-//                arrival slot's list
+//   k_x_bscan    exclusive scan of the workgroups' spike counts (one workgroup)
+//   k_x_list     dense spike list of the step and its AER history entries
+//                (step, id, offset)
+//   k_x_deliver  one wave per (spike, 256-record row segment): fan-out into
+//                the arrival slots' lists, one reservation per delay bucket
+//                the segment touches
 //   k_x_finish   step counters
 //
 // Like the step kernels this is bound by memory traffic and atomics, not by
@@ -116,8 +119,9 @@ __device__ __forceinline__ void x_input(const XArgs& a, XNeuron& s, uint64_t t0,
     }
 }
 
-__global__ __launch_bounds__(256) void k_x_place(XArgs a, uint32_t t)
+__global__ __launch_bounds__(256) void k_x_place(XArgs a)
 {
+    const uint32_t t = a.ctrl->t0;   // the step in flight (k_x_finish advances it)
     const uint32_t slot = t % a.R;
     const uint64_t n0 = a.qn[slot];
     const uint64_t n = n0 < a.qcap ? n0 : a.qcap;
@@ -141,21 +145,33 @@ __global__ __launch_bounds__(256) void k_x_place(XArgs a, uint32_t t)
     if (bad) atomicAdd(a.dropped, bad);
 }
 
-__global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a, uint32_t t)
+__global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
 {
+    const uint32_t t = a.ctrl->t0;
     __shared__ uint2 ev_s[kXLocal * kXBlock];   // [input][thread]
     __shared__ uint32_t pois_s[kMaxPois];
     __shared__ uint32_t wcnt[kXBlock / 64];
     __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint32_t j = blockIdx.x * kXBlock + tid;
+    const bool live = j < a.N;
+    // the neuron's loads go out before the barrier, which then waits for them
+    // and for the table load together
+    uint64_t k0 = 0, k1 = 0, re0 = 0;
+    float V0 = 0.f, W0 = 0.f;
+    if (live) {
+        k0 = a.qoff[j];
+        k1 = a.qoff[j + 1];
+        V0 = a.V[j];
+        W0 = a.W[j];
+        re0 = a.rend[j];
+    }
     if (tid < a.npois) pois_s[tid] = a.poisc[tid];
     if (blockIdx.x == 0 && tid == 0) a.qn[t % a.R] = 0;   // the slot's list has been placed
     __syncthreads();
     const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
     uint32_t spiked = 0, next = 0, dis = 0;
-    if (j < a.N) {
-        uint64_t k0 = a.qoff[j], k1 = a.qoff[j + 1];
+    if (live) {
         k1 = k1 < a.qcap ? k1 : a.qcap;
         k0 = k0 < k1 ? k0 : k1;
         const uint32_t nrec = (uint32_t)(k1 - k0);
@@ -166,7 +182,7 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a, uint32_t t)
             for (uint32_t i = 0; i < a.npois; ++i) next += pois_s[i] <= u ? 1u : 0u;
         }
         const int32_t jext = a.ext_const ? a.ext_const_q : a.jext_q;
-        XNeuron s{a.V[j], a.W[j], a.rend[j], t0, 0u, 0u, 0u};
+        XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
         const bool exc = (j % a.M) < a.n_exc;
         const bool fj = a.forced ? a.forced[j] != 0 : false;
         const uint32_t ff = a.forced ? a.forced_f[j] : 0u;
@@ -259,103 +275,173 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a, uint32_t t)
     }
     if (spiked) a.blk_list[(size_t)blockIdx.x * kXBlock + off + x_mbcnt(m)] = j;
     if (tid == 0) {
+        // per-workgroup totals: k_x_bscan adds them up (no shared counter here)
         a.blk_cnt[blockIdx.x] = tot;
         unsigned long long ex = 0, ds = 0;
         for (uint32_t w = 0; w < kXBlock / 64; ++w) {
             ex += wext[w];
             ds += wdis[w];
         }
-        if (ex) atomicAdd((unsigned long long*)&a.ctrl->ext_events, ex);
-        if (ds) atomicAdd((unsigned long long*)&a.ctrl->disagree, ds);
+        a.blk_ext[blockIdx.x] = (uint32_t)ex;
+        if (ds) atomicAdd((unsigned long long*)&a.ctrl->disagree, ds);   // lock-step only
     }
 }
 
-__global__ __launch_bounds__(256) void k_x_deliver(XArgs a, uint32_t t)
+__global__ __launch_bounds__(1024) void k_x_bscan(XArgs a)
+{
+    __shared__ unsigned long long wsum[16], wext[16];
+    __shared__ unsigned long long carry_s;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    if (tid == 0) carry_s = 0;
+    if (tid < a.R) a.qn_prev[tid] = a.qn[tid];   // before this step's delivery appends
+    unsigned long long ext = 0;
+    __syncthreads();
+    for (uint32_t b0 = 0; b0 < a.nblk; b0 += 1024u) {
+        const uint32_t i = b0 + tid;
+        const unsigned long long v = i < a.nblk ? a.blk_cnt[i] : 0u;
+        ext += i < a.nblk ? a.blk_ext[i] : 0u;
+        unsigned long long x = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long u = __shfl_up(x, (unsigned)o);
+            if (lane >= (uint32_t)o) x += u;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        unsigned long long before = carry_s, total = 0;
+        for (uint32_t w = 0; w < 16; ++w) {
+            if (w < wv) before += wsum[w];
+            total += wsum[w];
+        }
+        if (i < a.nblk) a.blk_off[i] = before + x - v;
+        __syncthreads();
+        if (tid == 0) carry_s += total;
+        __syncthreads();
+    }
+    ext = x_wave_sum<unsigned long long>(ext);
+    if (lane == 0) wext[wv] = ext;
+    __syncthreads();
+    if (tid == 0) {
+        a.blk_off[a.nblk] = carry_s;
+        unsigned long long e = 0;
+        for (uint32_t w = 0; w < 16; ++w) e += wext[w];
+        a.ctrl->ext_events += e;
+    }
+}
+
+__global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)
+{
+    const uint32_t b = blockIdx.x, i = threadIdx.x;
+    if (i >= a.blk_cnt[b]) return;
+    const uint32_t t = a.ctrl->t0;
+    const uint64_t p = a.blk_off[b] + i;
+    const uint32_t gid = a.blk_list[(size_t)b * kXBlock + i];
+    const uint32_t f = a.fs[gid];
+    const uint64_t hb = a.ctrl->hist_n;
+    if (hb + p < a.hist_cap) {
+        a.hist[hb + p] = make_uint2(t, gid);
+        a.hist_f[hb + p] = f;
+    }
+    const uint64_t rb = a.row_ptr[gid];
+    a.spk[p] = make_uint4(gid, f, (uint32_t)rb, (uint32_t)(rb >> 32));
+}
+
+__global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
 {
     __shared__ int32_t cb_s[256];
     cb_s[threadIdx.x] = a.record ? a.cb[threadIdx.x] : 0;
     __syncthreads();
+    const uint32_t t = a.ctrl->t0;
     const uint32_t lane = threadIdx.x & 63u;
     const uint32_t wave = (blockIdx.x * 256u + threadIdx.x) >> 6;
     const uint32_t nw = gridDim.x * 4u;
-    const uint64_t nspk = a.blk_off[a.nblk];
-    const uint64_t hb = a.ctrl->hist_n;
-    unsigned long long ev = 0, drop = 0;
-    for (uint64_t p = wave; p < nspk; p += nw) {
-        // the workgroup list holding spike p: the last b with blk_off[b] <= p
-        uint32_t lo = 0, hi = a.nblk;
-        while (hi - lo > 1u) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (a.blk_off[mid] <= p) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t gid = a.blk_list[(size_t)lo * kXBlock + (uint32_t)(p - a.blk_off[lo])];
-        const uint32_t f = a.fs[gid];
-        if (lane == 0 && hb + p < a.hist_cap) {
-            a.hist[hb + p] = make_uint2(t, gid);
-            a.hist_f[hb + p] = f;
-        }
-        const uint64_t rb = a.row_ptr[gid];
-        const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
-        // lane d < D: delay bucket d of the row, [start, end), its arrival
-        // slot and its reservation in that slot's list
-        const uint32_t end = lane < a.D ? (uint32_t)a.bend[(size_t)gid * a.D + lane] : len;
+    const uint64_t items = a.blk_off[a.nblk] * a.smax;
+    unsigned long long drop = 0;
+    for (uint64_t it = wave; it < items; it += nw) {
+        const uint64_t p = it / a.smax;
+        const uint32_t s0 = (uint32_t)(it % a.smax) * 256u;
+        const uint4 sp = a.spk[p];
+        const uint32_t gid = sp.x, f = sp.y;
+        const uint64_t rb = (uint64_t)sp.z | ((uint64_t)sp.w << 32);
+        // lane d < D: delay bucket d of the row, [start, end); the last end is the row length
+        const uint32_t endv = lane < a.D ? (uint32_t)a.bend[(size_t)gid * a.D + lane] : 0u;
+        const uint32_t len = (uint32_t)__builtin_amdgcn_readlane((int)endv, (int)(a.D - 1u));
+        if (s0 >= len) continue;
+        const uint32_t s1 = len - s0 < 256u ? len : s0 + 256u;
+        const uint32_t end = lane < a.D ? endv : len;
         const uint32_t prev = __shfl_up(end, 1u);
         const uint32_t start = lane == 0 ? 0u : prev;
-        const uint32_t size = lane < a.D ? end - start : 0u;
+        // the part of bucket `lane` inside this segment, its slot and reservation
+        const uint32_t lo = start > s0 ? start : s0;
+        const uint32_t hi = end < s1 ? end : s1;
+        const uint32_t cnt = (lane < a.D && hi > lo) ? hi - lo : 0u;
         const uint32_t slot = (t + a.d_min + lane) % a.R;
         unsigned long long base = 0;
-        if (size) base = atomicAdd(a.qn + slot, (unsigned long long)size);
-        for (uint32_t c0 = 0; c0 < len; c0 += 64u) {
-            const uint32_t k = c0 + lane;
-            const uint32_t kk = k < len ? k : len - 1u;
-            uint32_t tgt;
-            int32_t wq;
+        if (cnt) base = atomicAdd(a.qn + slot, (unsigned long long)cnt);
+        // this lane's records k = s0 + 64 u + lane, u < 4: every load issued before any use
+        auto load = [&](uint32_t u, uint32_t& tgt, int32_t& wf) {
+            const uint32_t k = s0 + 64u * u + lane;
+            const uint32_t kk = k < s1 ? k : s1 - 1u;
             if (a.record) {
                 const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
                 tgt = v >> 8;
-                wq = cb_s[v & 255u];
+                wf = (int32_t)(v & 255u);
             } else {
                 const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
                 tgt = r.tgt;
-                wq = __float2int_rn(r.w * 65536.0f);
+                wf = __float2int_rn(r.w * 65536.0f);
             }
+        };
+        auto emit = [&](uint32_t u, uint32_t tgt, int32_t wf) {
+            if (s0 + 64u * u >= s1) return;   // (uniform) past the segment's end
+            const uint32_t k = s0 + 64u * u + lane;
+            const uint32_t kk = k < s1 ? k : s1 - 1u;
             uint32_t d = 0;
             for (uint32_t l = 0; l < a.D; ++l)
                 d += kk >= (uint32_t)__builtin_amdgcn_readlane((int)end, (int)l) ? 1u : 0u;
-            const uint32_t bs = __shfl(start, (int)d);
+            const uint32_t bl = __shfl(lo, (int)d);
             const uint32_t sl = __shfl(slot, (int)d);
             const unsigned long long bb = __shfl(base, (int)d);
-            if (k < len) {
-                const unsigned long long pos = bb + (kk - bs);
+            if (k < s1) {
+                const unsigned long long pos = bb + (kk - bl);
+                const int32_t w = a.record ? cb_s[wf] : wf;
                 if (pos < a.qcap && tgt < a.N) {
-                    a.qlist[(size_t)sl * a.qcap + pos] = make_uint4(tgt, f, (uint32_t)wq, 0u);
+                    a.qlist[(size_t)sl * a.qcap + pos] = make_uint4(tgt, f, (uint32_t)w, 0u);
                     atomicAdd(a.qcnt + (size_t)sl * a.N + tgt, 1u);
                 } else {
                     ++drop;
                 }
             }
-        }
-        if (lane == 0) ev += len;
+        };
+        uint32_t t0r, t1r, t2r, t3r;
+        int32_t w0r, w1r, w2r, w3r;
+        load(0, t0r, w0r);
+        load(1, t1r, w1r);
+        load(2, t2r, w2r);
+        load(3, t3r, w3r);
+        emit(0, t0r, w0r);
+        emit(1, t1r, w1r);
+        emit(2, t2r, w2r);
+        emit(3, t3r, w3r);
     }
-    ev = x_wave_sum<unsigned long long>(ev);
     drop = x_wave_sum<unsigned long long>(drop);
-    if (lane == 0) {
-        if (ev) atomicAdd((unsigned long long*)&a.ctrl->rec_events, ev);
-        if (drop) atomicAdd(a.dropped, drop);
-    }
+    if (lane == 0 && drop) atomicAdd(a.dropped, drop);
 }
 
 __global__ void k_x_finish(XArgs a)
 {
     if (threadIdx.x != 0) return;
     const uint64_t n = a.blk_off[a.nblk];
+    // the step's recurrent events: what delivery appended to the slots' lists
+    unsigned long long ev = 0;
+    for (uint32_t s = 0; s < a.R; ++s) ev += a.qn[s] - a.qn_prev[s];
+    a.ctrl->rec_events += ev;
     a.ctrl->hist_n += n;
     a.ctrl->spikes += n;
     a.ctrl->t0 += 1u;
 }
 
-constexpr uint32_t kXGrid = 2048;   // workgroups of the grid-stride kernels
+constexpr uint32_t kXGrid = 1024;   // workgroups of the grid-stride kernels
 
 }  // namespace
 
@@ -365,21 +451,28 @@ constexpr uint32_t kXGrid = 2048;   // workgroups of the grid-stride kernels
         else hipLaunchKernelGGL(kern, grid, block, 0, s, __VA_ARGS__);                                \
     } while (0)
 
-hipError_t launch_x_place(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev)
+hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 {
-    SNN_X_LAUNCH(ev, k_x_place, dim3(kXGrid), dim3(256), s, a, t);
+    SNN_X_LAUNCH(ev, k_x_place, dim3(kXGrid), dim3(256), s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_x_update(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev)
+hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 {
-    SNN_X_LAUNCH(ev, k_x_update, dim3(a.nblk), dim3(kXBlock), s, a, t);
+    SNN_X_LAUNCH(ev, k_x_update, dim3(a.nblk), dim3(kXBlock), s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_x_deliver(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev)
+hipError_t launch_x_list(const XArgs& a, hipStream_t s)
 {
-    SNN_X_LAUNCH(ev, k_x_deliver, dim3(kXGrid), dim3(256), s, a, t);
+    hipLaunchKernelGGL(k_x_bscan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_x_list, dim3(a.nblk), dim3(kXBlock), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_x_deliver(const XArgs& a, hipStream_t s, const LaunchEv* ev)
+{
+    SNN_X_LAUNCH(ev, k_x_deliver, dim3(kXGrid), dim3(256), s, a);
     return hipGetLastError();
 }
 

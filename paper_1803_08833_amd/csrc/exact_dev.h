@@ -17,7 +17,7 @@ namespace snn {
 
 constexpr uint32_t kStreamExtTime = 7u;   // offsets of the external inputs of a step
 constexpr uint32_t kXBlock = 256;          // neurons per update workgroup
-constexpr uint32_t kXLocal = 32;           // inputs per neuron sorted in LDS (more: slow path)
+constexpr uint32_t kXLocal = 16;           // inputs per neuron sorted in LDS (more: slow path)
 
 struct XArgs {
     uint32_t N, M, n_exc, sfa_on_inh;
@@ -26,6 +26,7 @@ struct XArgs {
     int32_t ext_const_q, jext_q;
     uint32_t key0, key1;
     uint32_t nblk;                         // update workgroups (kXBlock neurons each)
+    uint32_t smax;                         // 256-record segments of the longest row
     uint32_t tau_equal;                    // tau_w == tau_m
     uint64_t hist_cap;
     uint64_t qcap;                         // queued inputs per slot
@@ -39,12 +40,15 @@ struct XArgs {
     uint32_t* qcnt;                        // [R][N] queued inputs per target
     uint4* qlist;                          // [R][qcap] {target, offset, charge, 0}
     unsigned long long* qn;                // [R] entries appended per slot (may exceed qcap)
+    unsigned long long* qn_prev;           // [R] the same before the step's delivery
     unsigned long long* dropped;           // inputs that found their slot full
     uint64_t* qoff;                        // [N + 1] exclusive scan of this step's counts
     uint2* qsorted;                        // [qcap] {offset, charge} by target
     uint32_t* blk_cnt;                     // [nblk] spikers per update workgroup
+    uint32_t* blk_ext;                     // [nblk] external Poisson events per update workgroup
     uint32_t* blk_list;                    // [nblk * kXBlock] their ids, ascending
     uint64_t* blk_off;                     // [nblk + 1] exclusive scan of blk_cnt
+    uint4* spk;                            // [N] spikes of the step: {gid, offset, row start lo, hi}
     uint2* hist;                           // [hist_cap] (t, gid)
     uint32_t* hist_f;                      // [hist_cap] emission offsets
     Ctrl* ctrl;                            // counters shared with the step solver's reads
@@ -57,13 +61,15 @@ struct XArgs {
     const uint32_t* forced_f;              //            and their offsets
 };
 
-// One step t of the solver, after the caller has scanned qcnt[t mod R] into
-// qoff: place the slot's inputs by target, update every neuron, then (after
-// the caller has scanned blk_cnt into blk_off) record and deliver the spikes
-// and close the step.
-hipError_t launch_x_place(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
-hipError_t launch_x_update(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
-hipError_t launch_x_deliver(const XArgs& a, uint32_t t, hipStream_t s, const LaunchEv* ev = nullptr);
+// One step of the solver, the step index t read from ctrl->t0 on the device
+// (so that a captured sequence of steps can be replayed): after the caller
+// has scanned qcnt[t mod R] into qoff, place the slot's inputs by target,
+// update every neuron, scan the workgroups' spike counts, list the spikes
+// (with their history entries), deliver them, and close the step (t0 + 1).
+hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
+hipError_t launch_x_list(const XArgs& a, hipStream_t s);
+hipError_t launch_x_deliver(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_x_finish(const XArgs& a, hipStream_t s);
 
 }  // namespace snn

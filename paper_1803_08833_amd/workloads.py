@@ -113,6 +113,8 @@ WORKLOADS = {
     "grid48_exp_paper_code8": dict(net=make_paper(48, 48, PAPER_EXP, 8, w_inh=-5.3, ext_rate_hz=2.0,
                                                   record=REC_CODE8), steps=2000),
 }
+# The headline network under the exact-time event-driven solver.
+WORKLOADS["grid24_exp_exact"] = dict(net=dict(WORKLOADS["grid24_exp"]["net"], solver=SOLVER_EXACT), steps=10000)
 
 
 def workload(name, **over):
