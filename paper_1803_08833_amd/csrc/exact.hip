@@ -8,13 +8,13 @@
 //                external) in time order, Eq. (1)-(2) solved exactly between
 //                them, a spike at the input that crosses threshold; ordered
 //                spiker list per 256-neuron workgroup
-//   k_x_bscan    exclusive scan of the workgroups' spike counts (one workgroup)
-//   k_x_list     dense spike list of the step and its AER history entries
+//   k_x_list     dense spike list of the step (each workgroup's place from the
+//                counts of those before it) and its AER history entries
 //                (step, id, offset)
 //   k_x_deliver  one wave per (spike, 256-record row segment): fan-out into
 //                the arrival slots' lists, one reservation per delay bucket
 //                the segment touches
-//   k_x_finish   step counters
+//   k_x_finish   step counters (external events totalled over the workgroups)
 //
 // Like the step kernels this is bound by memory traffic and atomics, not by
 // arithmetic: no MFMA.
@@ -167,7 +167,10 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
         re0 = a.rend[j];
     }
     if (tid < a.npois) pois_s[tid] = a.poisc[tid];
-    if (blockIdx.x == 0 && tid == 0) a.qn[t % a.R] = 0;   // the slot's list has been placed
+    if (blockIdx.x == 0 && tid == 0) {
+        a.qn[t % a.R] = 0;   // the slot's list has been placed
+        for (uint32_t s = 0; s < a.R; ++s) a.qn_prev[s] = a.qn[s];   // before this step's delivery
+    }
     __syncthreads();
     const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
     uint32_t spiked = 0, next = 0, dis = 0;
@@ -275,7 +278,7 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
     }
     if (spiked) a.blk_list[(size_t)blockIdx.x * kXBlock + off + x_mbcnt(m)] = j;
     if (tid == 0) {
-        // per-workgroup totals: k_x_bscan adds them up (no shared counter here)
+        // per-workgroup totals, added up by k_x_list and k_x_finish (no shared counter here)
         a.blk_cnt[blockIdx.x] = tot;
         unsigned long long ex = 0, ds = 0;
         for (uint32_t w = 0; w < kXBlock / 64; ++w) {
@@ -287,54 +290,27 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
     }
 }
 
-__global__ __launch_bounds__(1024) void k_x_bscan(XArgs a)
-{
-    __shared__ unsigned long long wsum[16], wext[16];
-    __shared__ unsigned long long carry_s;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    if (tid == 0) carry_s = 0;
-    if (tid < a.R) a.qn_prev[tid] = a.qn[tid];   // before this step's delivery appends
-    unsigned long long ext = 0;
-    __syncthreads();
-    for (uint32_t b0 = 0; b0 < a.nblk; b0 += 1024u) {
-        const uint32_t i = b0 + tid;
-        const unsigned long long v = i < a.nblk ? a.blk_cnt[i] : 0u;
-        ext += i < a.nblk ? a.blk_ext[i] : 0u;
-        unsigned long long x = v;
-#pragma unroll
-        for (int o = 1; o < 64; o <<= 1) {
-            const unsigned long long u = __shfl_up(x, (unsigned)o);
-            if (lane >= (uint32_t)o) x += u;
-        }
-        if (lane == 63) wsum[wv] = x;
-        __syncthreads();
-        unsigned long long before = carry_s, total = 0;
-        for (uint32_t w = 0; w < 16; ++w) {
-            if (w < wv) before += wsum[w];
-            total += wsum[w];
-        }
-        if (i < a.nblk) a.blk_off[i] = before + x - v;
-        __syncthreads();
-        if (tid == 0) carry_s += total;
-        __syncthreads();
-    }
-    ext = x_wave_sum<unsigned long long>(ext);
-    if (lane == 0) wext[wv] = ext;
-    __syncthreads();
-    if (tid == 0) {
-        a.blk_off[a.nblk] = carry_s;
-        unsigned long long e = 0;
-        for (uint32_t w = 0; w < 16; ++w) e += wext[w];
-        a.ctrl->ext_events += e;
-    }
-}
-
 __global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)
 {
-    const uint32_t b = blockIdx.x, i = threadIdx.x;
-    if (i >= a.blk_cnt[b]) return;
+    __shared__ unsigned long long part[kXBlock / 64];
+    const uint32_t b = blockIdx.x, i = threadIdx.x, lane = i & 63u;
+    // this workgroup's first spike: the spike counts of the workgroups before it
+    // (a few thousand L2-resident words; no separate scan launch)
+    unsigned long long before = 0;
+    for (uint32_t k = i; k < b; k += kXBlock) before += a.blk_cnt[k];
+    before = x_wave_sum<unsigned long long>(before);
+    if (lane == 0) part[i >> 6] = before;
+    __syncthreads();
+    unsigned long long off = 0;
+    for (uint32_t w = 0; w < kXBlock / 64; ++w) off += part[w];
+    const uint32_t cnt = a.blk_cnt[b];
+    if (i == 0) {
+        a.blk_off[b] = off;
+        if (b + 1 == a.nblk) a.blk_off[a.nblk] = off + cnt;   // the step's spike total
+    }
+    if (i >= cnt) return;
     const uint32_t t = a.ctrl->t0;
-    const uint64_t p = a.blk_off[b] + i;
+    const uint64_t p = off + i;
     const uint32_t gid = a.blk_list[(size_t)b * kXBlock + i];
     const uint32_t f = a.fs[gid];
     const uint64_t hb = a.ctrl->hist_n;
@@ -428,9 +404,18 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
     if (lane == 0 && drop) atomicAdd(a.dropped, drop);
 }
 
-__global__ void k_x_finish(XArgs a)
+__global__ __launch_bounds__(1024) void k_x_finish(XArgs a)
 {
-    if (threadIdx.x != 0) return;
+    // the step's external events: the update workgroups' totals
+    __shared__ unsigned long long wext[16];
+    const uint32_t tid = threadIdx.x;
+    unsigned long long ext = 0;
+    for (uint32_t k = tid; k < a.nblk; k += 1024u) ext += a.blk_ext[k];
+    ext = x_wave_sum<unsigned long long>(ext);
+    if ((tid & 63u) == 0) wext[tid >> 6] = ext;
+    __syncthreads();
+    if (tid != 0) return;
+    for (uint32_t w = 0; w < 16; ++w) a.ctrl->ext_events += wext[w];
     const uint64_t n = a.blk_off[a.nblk];
     // the step's recurrent events: what delivery appended to the slots' lists
     unsigned long long ev = 0;
@@ -465,7 +450,6 @@ hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 
 hipError_t launch_x_list(const XArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_x_bscan, dim3(1), dim3(1024), 0, s, a);
     hipLaunchKernelGGL(k_x_list, dim3(a.nblk), dim3(kXBlock), 0, s, a);
     return hipGetLastError();
 }
@@ -478,7 +462,7 @@ hipError_t launch_x_deliver(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 
 hipError_t launch_x_finish(const XArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_x_finish, dim3(1), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_x_finish, dim3(1), dim3(1024), 0, s, a);
     return hipGetLastError();
 }
 

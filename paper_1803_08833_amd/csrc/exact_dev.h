@@ -64,8 +64,8 @@ struct XArgs {
 // One step of the solver, the step index t read from ctrl->t0 on the device
 // (so that a captured sequence of steps can be replayed): after the caller
 // has scanned qcnt[t mod R] into qoff, place the slot's inputs by target,
-// update every neuron, scan the workgroups' spike counts, list the spikes
-// (with their history entries), deliver them, and close the step (t0 + 1).
+// update every neuron, list the spikes (with their history entries), deliver
+// them, and close the step (t0 + 1).
 hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_x_list(const XArgs& a, hipStream_t s);

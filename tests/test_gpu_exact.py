@@ -8,7 +8,7 @@ against the oracle, through the C ABI.
   tolerance, the refractory steps exact and the counters equal.  Several
   256-neuron workgroups and a ragged tail; F32 and 8-bit-code records;
   Poisson and constant drive; a strong drive that sends neurons more inputs
-  in one step than the LDS sort holds (the slow path).
+  in one step than the LDS sort holds (16; the slow path).
 * Free run at the full 24x24 exponential size: every sampled spike happens
   at the exact time of one of its neuron's inputs (an external input, or a
   presynaptic spike plus the synapse's delay), no neuron fires twice within
@@ -100,7 +100,7 @@ def test_lockstep_exact(snn, oracle_mod, record, drive):
 
 def test_lockstep_exact_many_inputs(snn, oracle_mod):
     """Strong drive and in-degree: some neurons take more inputs in a step
-    than the LDS sort holds (32), which the slow path orders."""
+    than the LDS sort holds (16), up to 40 and more, which the slow path orders."""
     net = W.make(2, 2, W.GAUSS, 1.5, 400, 67, n_exc=160, n_inh=40, solver=W.SOLVER_EXACT, d_max=4,
                  ext_rate_hz=12.0, w_inh=-0.4)
     say(f"case: exact lock-step, many inputs per step, N {W.n_neurons(net)}")
