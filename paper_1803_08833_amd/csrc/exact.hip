@@ -119,6 +119,41 @@ __device__ __forceinline__ void x_input(const XArgs& a, XNeuron& s, uint64_t t0,
     }
 }
 
+// In-place heap sort of one neuron's placed inputs by offset (the segment
+// belongs to that neuron alone).  Every sift moves strictly down the heap, so
+// each loop ends.
+__device__ __forceinline__ void x_sift(uint2* v, uint32_t root, uint32_t n)
+{
+    const uint2 x = v[root];
+    for (;;) {
+        uint32_t c = 2u * root + 1u;
+        if (c >= n) break;
+        uint2 y = v[c];
+        if (c + 1u < n) {
+            const uint2 z = v[c + 1u];
+            if (z.x > y.x) {
+                ++c;
+                y = z;
+            }
+        }
+        if (y.x <= x.x) break;
+        v[root] = y;
+        root = c;
+    }
+    v[root] = x;
+}
+
+__device__ void x_heap_sort(uint2* v, uint32_t n)
+{
+    for (uint32_t r = n / 2u; r-- > 0u;) x_sift(v, r, n);
+    for (uint32_t end = n; end-- > 1u;) {
+        const uint2 top = v[0];
+        v[0] = v[end];
+        v[end] = top;
+        x_sift(v, 0u, end);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_x_place(XArgs a)
 {
     const uint32_t t = a.ctrl->t0;   // the step in flight (k_x_finish advances it)
@@ -217,8 +252,39 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
                 }
                 x_input(a, s, t0, f, J, exc, fj, ff);
             }
+        } else if (next <= kXLocal) {
+            // many queued inputs: heap-sort the neuron's placed segment in
+            // place, hold the (few) external ones sorted in LDS, merge the two
+            uint2* seg = a.qsorted + k0;
+            x_heap_sort(seg, nrec);
+            uint2* e = ev_s + tid;
+            for (uint32_t i = 0; i < next; i += 4) {
+                const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
+                                            : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
+                for (uint32_t q = 0; q < 4 && i + q < next; ++q) e[(i + q) * kXBlock] = make_uint2(word(r, q), (uint32_t)jext);
+            }
+            for (uint32_t i = 1; i < next; ++i) {
+                const uint2 x = e[i * kXBlock];
+                uint32_t p = i;
+                while (p > 0 && e[(p - 1) * kXBlock].x > x.x) {
+                    e[p * kXBlock] = e[(p - 1) * kXBlock];
+                    --p;
+                }
+                e[p * kXBlock] = x;
+            }
+            uint32_t ir = 0, ie = 0;
+            while (ir < nrec || ie < next) {
+                const uint64_t fr = ir < nrec ? (uint64_t)seg[ir].x : (1ull << 32);
+                const uint64_t fe = ie < next ? (uint64_t)e[ie * kXBlock].x : (1ull << 32);
+                const uint32_t f = (uint32_t)(fr < fe ? fr : fe);
+                int32_t J = 0;
+                while (ir < nrec && seg[ir].x == f) J += (int32_t)seg[ir++].y;
+                while (ie < next && e[ie * kXBlock].x == f) J += (int32_t)e[ie++ * kXBlock].y;
+                x_input(a, s, t0, f, J, exc, fj, ff);
+            }
         } else {
-            // many inputs: take the earliest remaining instant each time
+            // more external inputs than the LDS slots (a drive far above any
+            // workload's): take the earliest remaining instant each time
             uint64_t lo = 0;
             while (lo <= 0xFFFFFFFFull) {
                 uint64_t best = 1ull << 32;

@@ -86,11 +86,13 @@ def _lockstep(snn, oracle_mod, net, steps, check_every=1, qcap=0):
 
 
 @pytest.mark.parametrize("record,drive", [(W.REC_F32, "poisson"), (W.REC_CODE8, "poisson"),
-                                          (W.REC_F32, "const")])
+                                          (W.REC_F32, "const"), (W.REC_CODE8, "poisson-expdelay")])
 def test_lockstep_exact(snn, oracle_mod, record, drive):
     over = dict(n_exc=200, n_inh=52, record=record, solver=W.SOLVER_EXACT)
     if drive == "const":
         over.update(ext_mode=W.EXT_CONST, ext_const_q=round(1.3 * 65536))
+    if drive == "poisson-expdelay":
+        over.update(delay_dist=W.DELAY_EXP, delay_tau=4.0)
     net = W.make(3, 2, W.EXP, 2.0, 150, 61, **over)   # 1512 neurons: 5 full workgroups + a ragged one
     say(f"case: exact lock-step, record {record}, drive {drive}, N {W.n_neurons(net)}")
     st, nsp, _ = _lockstep(snn, oracle_mod, net, 120)
