@@ -1248,6 +1248,7 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         HIPCHK(n, hipStreamSynchronize(n->stream));
         HIPCHK(n, hipMemcpy((void*)n->a.poisc, tb.poisc.data(), tb.poisc.size() * 4, hipMemcpyHostToDevice));
         n->a.npois = (uint32_t)tb.poisc.size();
+        n->x.npois = n->a.npois;   // the exact solver reads the same table
         n->s.ext_rate_hz = tp.ext_rate_hz;
         break;
     }

@@ -134,6 +134,26 @@ def test_graph_replay_equals_single_launches(snn):
     assert a["rec_events"] == b["rec_events"] and a["ext_events"] == b["ext_events"]
 
 
+def test_drive_change_equals_fresh_network(snn):
+    """A run-time change of the external rate (SNN_OPT_EXT_RATE_UHZ) under the
+    exact solver gives the raster of a network built at the new rate."""
+    net = W.make(3, 2, W.EXP, 2.0, 150, 73, n_exc=200, n_inh=52, solver=W.SOLVER_EXACT, ext_rate_hz=3.0)
+    say("case: exact solver, run-time drive change vs fresh network")
+    out = []
+    with snn.Net(net) as g:
+        g.build_synapses()
+        g.set_option(snn.OPT_EXT_RATE_UHZ, 6_000_000)
+        g.step(100)
+        out.append(g.read_spike_times())
+    with snn.Net(dict(net, ext_rate_hz=6.0)) as g:
+        g.build_synapses()
+        g.step(100)
+        out.append(g.read_spike_times())
+    assert len(out[0][0]) > 100
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+
+
 def _ext_offsets(oracle_mod, net, poisc, g, t):
     key = [net["seed"] & 0xFFFFFFFF, net["seed"] >> 32]
     u = int(oracle_mod.philox([g >> 2, t, 3, 0], key)[g & 3])
