@@ -180,6 +180,61 @@ __global__ __launch_bounds__(256) void k_x_place(XArgs a)
     if (bad) atomicAdd(a.dropped, bad);
 }
 
+// A workgroup whose queued inputs average more than kXBusyPer per neuron is
+// updated by k_x_update_busy (its inputs are contiguous in qsorted); both
+// kernels take the same decision from the same two offsets.
+__device__ __forceinline__ uint64_t x_block_inputs(const XArgs& a)
+{
+    const uint32_t first = blockIdx.x * kXBlock;
+    const uint32_t last = first + kXBlock < a.N ? first + kXBlock : a.N;
+    uint64_t lo = a.qoff[first], hi = a.qoff[last];
+    hi = hi < a.qcap ? hi : a.qcap;
+    lo = lo < hi ? lo : hi;
+    return hi - lo;
+}
+
+__device__ __forceinline__ bool x_block_busy(const XArgs& a)
+{
+    return x_block_inputs(a) > (uint64_t)kXBusyPer * kXBlock;
+}
+
+// The end of an update workgroup: its spikers in ascending id, its spike and
+// external-event totals (added up later: no shared counter here).
+__device__ __forceinline__ void x_close_block(const XArgs& a, uint32_t j, uint32_t spiked, uint32_t next,
+                                              uint32_t dis, uint32_t* wcnt, unsigned long long* wext,
+                                              unsigned long long* wdis)
+{
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    // spikers of the workgroup in ascending id
+    const uint64_t m = __ballot(spiked != 0u);
+    // external events count Poisson inputs only (the constant drive is no event)
+    const unsigned long long we = x_wave_sum<unsigned long long>(a.ext_const ? 0u : next);
+    const unsigned long long wd = x_wave_sum<unsigned long long>(dis);
+    if (lane == 0) {
+        wcnt[wv] = (uint32_t)__popcll(m);
+        wext[wv] = we;
+        wdis[wv] = wd;
+    }
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+    for (uint32_t w = 0; w < kXBlock / 64; ++w) {
+        if (w < wv) off += wcnt[w];
+        tot += wcnt[w];
+    }
+    if (spiked) a.blk_list[(size_t)blockIdx.x * kXBlock + off + x_mbcnt(m)] = j;
+    if (tid == 0) {
+        // per-workgroup totals, added up by k_x_list and k_x_finish (no shared counter here)
+        a.blk_cnt[blockIdx.x] = tot;
+        unsigned long long ex = 0, ds = 0;
+        for (uint32_t w = 0; w < kXBlock / 64; ++w) {
+            ex += wext[w];
+            ds += wdis[w];
+        }
+        a.blk_ext[blockIdx.x] = (uint32_t)ex;
+        if (ds) atomicAdd((unsigned long long*)&a.ctrl->disagree, ds);   // lock-step only
+    }
+}
+
 __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
 {
     const uint32_t t = a.ctrl->t0;
@@ -187,9 +242,14 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
     __shared__ uint32_t pois_s[kMaxPois];
     __shared__ uint32_t wcnt[kXBlock / 64];
     __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t tid = threadIdx.x;
     const uint32_t j = blockIdx.x * kXBlock + tid;
     const bool live = j < a.N;
+    if (blockIdx.x == 0 && tid == 0) {
+        a.qn[t % a.R] = 0;   // the slot's list has been placed
+        for (uint32_t s = 0; s < a.R; ++s) a.qn_prev[s] = a.qn[s];   // before this step's delivery
+    }
+    if (x_block_busy(a)) return;   // (uniform) the workgroup is k_x_update_busy's
     // the neuron's loads go out before the barrier, which then waits for them
     // and for the table load together
     uint64_t k0 = 0, k1 = 0, re0 = 0;
@@ -202,10 +262,6 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
         re0 = a.rend[j];
     }
     if (tid < a.npois) pois_s[tid] = a.poisc[tid];
-    if (blockIdx.x == 0 && tid == 0) {
-        a.qn[t % a.R] = 0;   // the slot's list has been placed
-        for (uint32_t s = 0; s < a.R; ++s) a.qn_prev[s] = a.qn[s];   // before this step's delivery
-    }
     __syncthreads();
     const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
     uint32_t spiked = 0, next = 0, dis = 0;
@@ -326,34 +382,134 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
         spiked = s.spiked;
         dis = s.dis;
     }
-    // spikers of the workgroup in ascending id
-    const uint64_t m = __ballot(spiked != 0u);
-    // external events count Poisson inputs only (the constant drive is no event)
-    const unsigned long long we = x_wave_sum<unsigned long long>(a.ext_const ? 0u : next);
-    const unsigned long long wd = x_wave_sum<unsigned long long>(dis);
-    if (lane == 0) {
-        wcnt[wv] = (uint32_t)__popcll(m);
-        wext[wv] = we;
-        wdis[wv] = wd;
+    x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
+}
+
+// Busy workgroups: all of the workgroup's queued inputs (up to kXBusyCap) are
+// read into LDS in one coalesced pass; each neuron heap-sorts its own slice
+// there, holds its external inputs sorted in its LDS slots, and merges the
+// two.  A workgroup with more inputs sorts its slices in global memory.
+__global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
+{
+    __shared__ uint2 in_s[kXBusyCap];            // the workgroup's inputs, by target
+    __shared__ uint2 ev_s[kXLocal * kXBlock];    // external inputs [input][thread]
+    __shared__ uint32_t pois_s[kMaxPois];
+    __shared__ uint32_t wcnt[kXBlock / 64];
+    __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
+    if (!x_block_busy(a)) return;   // (uniform) the workgroup is k_x_update's
+    const uint32_t t = a.ctrl->t0;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t j = blockIdx.x * kXBlock + tid;
+    const bool live = j < a.N;
+    const uint32_t first = blockIdx.x * kXBlock;
+    uint64_t base = a.qoff[first];
+    base = base < a.qcap ? base : a.qcap;
+    const uint64_t T = x_block_inputs(a);
+    const bool in_lds = T <= kXBusyCap;
+    if (in_lds)
+        for (uint32_t i = tid; i < (uint32_t)T; i += kXBlock) in_s[i] = a.qsorted[base + i];
+    uint64_t k0 = 0, k1 = 0, re0 = 0;
+    float V0 = 0.f, W0 = 0.f;
+    if (live) {
+        k0 = a.qoff[j];
+        k1 = a.qoff[j + 1];
+        V0 = a.V[j];
+        W0 = a.W[j];
+        re0 = a.rend[j];
     }
+    if (tid < a.npois) pois_s[tid] = a.poisc[tid];
     __syncthreads();
-    uint32_t off = 0, tot = 0;
-    for (uint32_t w = 0; w < kXBlock / 64; ++w) {
-        if (w < wv) off += wcnt[w];
-        tot += wcnt[w];
-    }
-    if (spiked) a.blk_list[(size_t)blockIdx.x * kXBlock + off + x_mbcnt(m)] = j;
-    if (tid == 0) {
-        // per-workgroup totals, added up by k_x_list and k_x_finish (no shared counter here)
-        a.blk_cnt[blockIdx.x] = tot;
-        unsigned long long ex = 0, ds = 0;
-        for (uint32_t w = 0; w < kXBlock / 64; ++w) {
-            ex += wext[w];
-            ds += wdis[w];
+    const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
+    uint32_t spiked = 0, next = 0, dis = 0;
+    if (live) {
+        k1 = k1 < a.qcap ? k1 : a.qcap;
+        k0 = k0 < k1 ? k0 : k1;
+        k0 = k0 > base ? k0 : base;
+        k1 = k1 > k0 ? k1 : k0;
+        const uint32_t nrec = (uint32_t)(k1 - k0);
+        if (a.ext_const) {
+            next = 1;
+        } else {
+            const uint32_t u = word(x_philox(j >> 2, t, kStreamExt, 0u, a.key0, a.key1), j & 3u);
+            for (uint32_t i = 0; i < a.npois; ++i) next += pois_s[i] <= u ? 1u : 0u;
         }
-        a.blk_ext[blockIdx.x] = (uint32_t)ex;
-        if (ds) atomicAdd((unsigned long long*)&a.ctrl->disagree, ds);   // lock-step only
+        const int32_t jext = a.ext_const ? a.ext_const_q : a.jext_q;
+        XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
+        const bool exc = (j % a.M) < a.n_exc;
+        const bool fj = a.forced ? a.forced[j] != 0 : false;
+        const uint32_t ff = a.forced ? a.forced_f[j] : 0u;
+        uint2* seg = in_lds ? in_s + (k0 - base) : a.qsorted + k0;
+        if (next <= kXLocal) {
+            x_heap_sort(seg, nrec);
+            uint2* e = ev_s + tid;
+            for (uint32_t i = 0; i < next; i += 4) {
+                const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
+                                            : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
+                for (uint32_t q = 0; q < 4 && i + q < next; ++q) e[(i + q) * kXBlock] = make_uint2(word(r, q), (uint32_t)jext);
+            }
+            for (uint32_t i = 1; i < next; ++i) {
+                const uint2 x = e[i * kXBlock];
+                uint32_t p = i;
+                while (p > 0 && e[(p - 1) * kXBlock].x > x.x) {
+                    e[p * kXBlock] = e[(p - 1) * kXBlock];
+                    --p;
+                }
+                e[p * kXBlock] = x;
+            }
+            uint32_t ir = 0, ie = 0;
+            while (ir < nrec || ie < next) {
+                const uint64_t fr = ir < nrec ? (uint64_t)seg[ir].x : (1ull << 32);
+                const uint64_t fe = ie < next ? (uint64_t)e[ie * kXBlock].x : (1ull << 32);
+                const uint32_t f = (uint32_t)(fr < fe ? fr : fe);
+                int32_t J = 0;
+                while (ir < nrec && seg[ir].x == f) J += (int32_t)seg[ir++].y;
+                while (ie < next && e[ie * kXBlock].x == f) J += (int32_t)e[ie++ * kXBlock].y;
+                x_input(a, s, t0, f, J, exc, fj, ff);
+            }
+        } else {
+            // more external inputs than the LDS slots: earliest remaining instant each time
+            uint64_t lo = 0;
+            while (lo <= 0xFFFFFFFFull) {
+                uint64_t best = 1ull << 32;
+                int32_t J = 0;
+                for (uint32_t i = 0; i < nrec; ++i) {
+                    const uint2 x = seg[i];
+                    if (x.x < lo) continue;
+                    if (x.x < best) {
+                        best = x.x;
+                        J = (int32_t)x.y;
+                    } else if (x.x == best) {
+                        J += (int32_t)x.y;
+                    }
+                }
+                for (uint32_t i = 0; i < next; i += 4) {
+                    const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
+                                                : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
+                    for (uint32_t q = 0; q < 4 && i + q < next; ++q) {
+                        const uint32_t f = word(r, q);
+                        if (f < lo) continue;
+                        if (f < best) {
+                            best = f;
+                            J = jext;
+                        } else if (f == best) {
+                            J += jext;
+                        }
+                    }
+                }
+                if (best > 0xFFFFFFFFull) break;
+                x_input(a, s, t0, (uint32_t)best, J, exc, fj, ff);
+                lo = best + 1;
+            }
+        }
+        x_advance(a, s, t1);
+        a.V[j] = s.V;
+        a.W[j] = s.W;
+        a.rend[j] = s.re;
+        if (s.spiked) a.fs[j] = s.fsp;
+        spiked = s.spiked;
+        dis = s.dis;
     }
+    x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
 }
 
 __global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)
@@ -511,6 +667,7 @@ hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 {
     SNN_X_LAUNCH(ev, k_x_update, dim3(a.nblk), dim3(kXBlock), s, a);
+    hipLaunchKernelGGL(k_x_update_busy, dim3(a.nblk), dim3(kXBlock), 0, s, a);
     return hipGetLastError();
 }
 

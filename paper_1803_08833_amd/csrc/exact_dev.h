@@ -18,6 +18,8 @@ namespace snn {
 constexpr uint32_t kStreamExtTime = 7u;   // offsets of the external inputs of a step
 constexpr uint32_t kXBlock = 256;          // neurons per update workgroup
 constexpr uint32_t kXLocal = 16;           // inputs per neuron sorted in LDS (more: slow path)
+constexpr uint32_t kXBusyPer = 8;          // a workgroup averaging more inputs per neuron is busy
+constexpr uint32_t kXBusyCap = 15 * 1024;  // inputs of a busy workgroup held in LDS
 
 struct XArgs {
     uint32_t N, M, n_exc, sfa_on_inh;
