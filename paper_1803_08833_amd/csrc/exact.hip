@@ -180,6 +180,95 @@ __global__ __launch_bounds__(256) void k_x_place(XArgs a)
     if (bad) atomicAdd(a.dropped, bad);
 }
 
+// What one neuron's step takes besides its queued inputs.
+struct XIn {
+    uint32_t j, t, next;    // neuron, step, external inputs this step
+    int32_t jext;           // charge of one external input
+    bool exc, forced;       // excitatory; lock-step flag
+    uint32_t ff;            // lock-step offset
+    uint64_t t0;            // the step's start, 32.32 fixed point
+};
+
+// The external inputs of the step in the lane's LDS slots e[i * kXBlock],
+// i < next <= kXLocal, sorted by offset.
+__device__ __forceinline__ void x_ext_sorted(const XArgs& a, const XIn& in, uint2* e)
+{
+    for (uint32_t i = 0; i < in.next; i += 4) {
+        const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
+                                    : x_philox(in.j, in.t, kStreamExtTime, i >> 2, a.key0, a.key1);
+        for (uint32_t q = 0; q < 4 && i + q < in.next; ++q)
+            e[(i + q) * kXBlock] = make_uint2(word(r, q), (uint32_t)in.jext);
+    }
+    for (uint32_t i = 1; i < in.next; ++i) {
+        const uint2 x = e[i * kXBlock];
+        uint32_t p = i;
+        while (p > 0 && e[(p - 1) * kXBlock].x > x.x) {
+            e[p * kXBlock] = e[(p - 1) * kXBlock];
+            --p;
+        }
+        e[p * kXBlock] = x;
+    }
+}
+
+// Many queued inputs: heap-sort the neuron's own slice seg[0 .. nrec) in
+// place, hold its external inputs sorted in its LDS slots, and take the two
+// in time order, inputs of one instant together.
+__device__ __forceinline__ void x_take_merged(const XArgs& a, XNeuron& s, const XIn& in, uint2* seg,
+                                              uint32_t nrec, uint2* e)
+{
+    x_heap_sort(seg, nrec);
+    x_ext_sorted(a, in, e);
+    uint32_t ir = 0, ie = 0;
+    while (ir < nrec || ie < in.next) {
+        const uint64_t fr = ir < nrec ? (uint64_t)seg[ir].x : (1ull << 32);
+        const uint64_t fe = ie < in.next ? (uint64_t)e[ie * kXBlock].x : (1ull << 32);
+        const uint32_t f = (uint32_t)(fr < fe ? fr : fe);
+        int32_t J = 0;
+        while (ir < nrec && seg[ir].x == f) J += (int32_t)seg[ir++].y;
+        while (ie < in.next && e[ie * kXBlock].x == f) J += (int32_t)e[ie++ * kXBlock].y;
+        x_input(a, s, in.t0, f, J, in.exc, in.forced, in.ff);
+    }
+}
+
+// More external inputs than the LDS slots (a drive far above any workload's):
+// the earliest remaining instant each time.
+__device__ __forceinline__ void x_take_selected(const XArgs& a, XNeuron& s, const XIn& in, const uint2* seg,
+                                                uint32_t nrec)
+{
+    uint64_t lo = 0;
+    while (lo <= 0xFFFFFFFFull) {
+        uint64_t best = 1ull << 32;
+        int32_t J = 0;
+        for (uint32_t i = 0; i < nrec; ++i) {
+            const uint2 x = seg[i];
+            if (x.x < lo) continue;
+            if (x.x < best) {
+                best = x.x;
+                J = (int32_t)x.y;
+            } else if (x.x == best) {
+                J += (int32_t)x.y;
+            }
+        }
+        for (uint32_t i = 0; i < in.next; i += 4) {
+            const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
+                                        : x_philox(in.j, in.t, kStreamExtTime, i >> 2, a.key0, a.key1);
+            for (uint32_t q = 0; q < 4 && i + q < in.next; ++q) {
+                const uint32_t f = word(r, q);
+                if (f < lo) continue;
+                if (f < best) {
+                    best = f;
+                    J = in.jext;
+                } else if (f == best) {
+                    J += in.jext;
+                }
+            }
+        }
+        if (best > 0xFFFFFFFFull) break;
+        x_input(a, s, in.t0, (uint32_t)best, J, in.exc, in.forced, in.ff);
+        lo = best + 1;
+    }
+}
+
 // A workgroup whose queued inputs average more than kXBusyPer per neuron is
 // updated by k_x_update_busy (its inputs are contiguous in qsorted); both
 // kernels take the same decision from the same two offsets.
@@ -280,6 +369,7 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
         const bool exc = (j % a.M) < a.n_exc;
         const bool fj = a.forced ? a.forced[j] != 0 : false;
         const uint32_t ff = a.forced ? a.forced_f[j] : 0u;
+        const XIn in{j, t, next, jext, exc, fj, ff, t0};
         const uint32_t n = nrec + next;
         if (n <= kXLocal) {
             uint2* e = ev_s + tid;   // input i at e[i * kXBlock]
@@ -309,70 +399,9 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
                 x_input(a, s, t0, f, J, exc, fj, ff);
             }
         } else if (next <= kXLocal) {
-            // many queued inputs: heap-sort the neuron's placed segment in
-            // place, hold the (few) external ones sorted in LDS, merge the two
-            uint2* seg = a.qsorted + k0;
-            x_heap_sort(seg, nrec);
-            uint2* e = ev_s + tid;
-            for (uint32_t i = 0; i < next; i += 4) {
-                const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
-                                            : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
-                for (uint32_t q = 0; q < 4 && i + q < next; ++q) e[(i + q) * kXBlock] = make_uint2(word(r, q), (uint32_t)jext);
-            }
-            for (uint32_t i = 1; i < next; ++i) {
-                const uint2 x = e[i * kXBlock];
-                uint32_t p = i;
-                while (p > 0 && e[(p - 1) * kXBlock].x > x.x) {
-                    e[p * kXBlock] = e[(p - 1) * kXBlock];
-                    --p;
-                }
-                e[p * kXBlock] = x;
-            }
-            uint32_t ir = 0, ie = 0;
-            while (ir < nrec || ie < next) {
-                const uint64_t fr = ir < nrec ? (uint64_t)seg[ir].x : (1ull << 32);
-                const uint64_t fe = ie < next ? (uint64_t)e[ie * kXBlock].x : (1ull << 32);
-                const uint32_t f = (uint32_t)(fr < fe ? fr : fe);
-                int32_t J = 0;
-                while (ir < nrec && seg[ir].x == f) J += (int32_t)seg[ir++].y;
-                while (ie < next && e[ie * kXBlock].x == f) J += (int32_t)e[ie++ * kXBlock].y;
-                x_input(a, s, t0, f, J, exc, fj, ff);
-            }
+            x_take_merged(a, s, in, a.qsorted + k0, nrec, ev_s + tid);
         } else {
-            // more external inputs than the LDS slots (a drive far above any
-            // workload's): take the earliest remaining instant each time
-            uint64_t lo = 0;
-            while (lo <= 0xFFFFFFFFull) {
-                uint64_t best = 1ull << 32;
-                int32_t J = 0;
-                for (uint32_t i = 0; i < nrec; ++i) {
-                    const uint2 x = a.qsorted[k0 + i];
-                    if (x.x < lo) continue;
-                    if (x.x < best) {
-                        best = x.x;
-                        J = (int32_t)x.y;
-                    } else if (x.x == best) {
-                        J += (int32_t)x.y;
-                    }
-                }
-                for (uint32_t i = 0; i < next; i += 4) {
-                    const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
-                                                : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
-                    for (uint32_t q = 0; q < 4 && i + q < next; ++q) {
-                        const uint32_t f = word(r, q);
-                        if (f < lo) continue;
-                        if (f < best) {
-                            best = f;
-                            J = jext;
-                        } else if (f == best) {
-                            J += jext;
-                        }
-                    }
-                }
-                if (best > 0xFFFFFFFFull) break;
-                x_input(a, s, t0, (uint32_t)best, J, exc, fj, ff);
-                lo = best + 1;
-            }
+            x_take_selected(a, s, in, a.qsorted + k0, nrec);
         }
         x_advance(a, s, t1);
         a.V[j] = s.V;
@@ -438,69 +467,10 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
         const bool exc = (j % a.M) < a.n_exc;
         const bool fj = a.forced ? a.forced[j] != 0 : false;
         const uint32_t ff = a.forced ? a.forced_f[j] : 0u;
+        const XIn in{j, t, next, jext, exc, fj, ff, t0};
         uint2* seg = in_lds ? in_s + (k0 - base) : a.qsorted + k0;
-        if (next <= kXLocal) {
-            x_heap_sort(seg, nrec);
-            uint2* e = ev_s + tid;
-            for (uint32_t i = 0; i < next; i += 4) {
-                const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
-                                            : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
-                for (uint32_t q = 0; q < 4 && i + q < next; ++q) e[(i + q) * kXBlock] = make_uint2(word(r, q), (uint32_t)jext);
-            }
-            for (uint32_t i = 1; i < next; ++i) {
-                const uint2 x = e[i * kXBlock];
-                uint32_t p = i;
-                while (p > 0 && e[(p - 1) * kXBlock].x > x.x) {
-                    e[p * kXBlock] = e[(p - 1) * kXBlock];
-                    --p;
-                }
-                e[p * kXBlock] = x;
-            }
-            uint32_t ir = 0, ie = 0;
-            while (ir < nrec || ie < next) {
-                const uint64_t fr = ir < nrec ? (uint64_t)seg[ir].x : (1ull << 32);
-                const uint64_t fe = ie < next ? (uint64_t)e[ie * kXBlock].x : (1ull << 32);
-                const uint32_t f = (uint32_t)(fr < fe ? fr : fe);
-                int32_t J = 0;
-                while (ir < nrec && seg[ir].x == f) J += (int32_t)seg[ir++].y;
-                while (ie < next && e[ie * kXBlock].x == f) J += (int32_t)e[ie++ * kXBlock].y;
-                x_input(a, s, t0, f, J, exc, fj, ff);
-            }
-        } else {
-            // more external inputs than the LDS slots: earliest remaining instant each time
-            uint64_t lo = 0;
-            while (lo <= 0xFFFFFFFFull) {
-                uint64_t best = 1ull << 32;
-                int32_t J = 0;
-                for (uint32_t i = 0; i < nrec; ++i) {
-                    const uint2 x = seg[i];
-                    if (x.x < lo) continue;
-                    if (x.x < best) {
-                        best = x.x;
-                        J = (int32_t)x.y;
-                    } else if (x.x == best) {
-                        J += (int32_t)x.y;
-                    }
-                }
-                for (uint32_t i = 0; i < next; i += 4) {
-                    const uint4 r = a.ext_const ? make_uint4(0u, 0u, 0u, 0u)
-                                                : x_philox(j, t, kStreamExtTime, i >> 2, a.key0, a.key1);
-                    for (uint32_t q = 0; q < 4 && i + q < next; ++q) {
-                        const uint32_t f = word(r, q);
-                        if (f < lo) continue;
-                        if (f < best) {
-                            best = f;
-                            J = jext;
-                        } else if (f == best) {
-                            J += jext;
-                        }
-                    }
-                }
-                if (best > 0xFFFFFFFFull) break;
-                x_input(a, s, t0, (uint32_t)best, J, exc, fj, ff);
-                lo = best + 1;
-            }
-        }
+        if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid);
+        else x_take_selected(a, s, in, seg, nrec);
         x_advance(a, s, t1);
         a.V[j] = s.V;
         a.W[j] = s.W;
