@@ -62,8 +62,10 @@ enum { SNN_SOLVER_STEP = 0, SNN_SOLVER_EXACT = 1 };
 
 typedef struct snn_net snn_net;
 
-/* AER spike record (Sec. II.C): step index and neuron id.  Spike times are
- * quantised to the 1 ms step.  History is ordered by (t_ms, gid). */
+/* AER spike record (Sec. II.C): step index and neuron id.  Under the step
+ * solver spike times are quantised to the 1 ms step; under the exact solver
+ * snn_read_spike_times gives each spike's offset inside its step as well.
+ * History is ordered by (t_ms, gid). */
 typedef struct {
     uint32_t t_ms;
     uint32_t gid;
