@@ -302,6 +302,9 @@ def main():
         torch.cuda.synchronize()
         del x, y
     print(json.dumps(result), flush=True)
+    if result["served"] and result["served"]["failed"]:
+        print(f"# {result['served']['failed']} served jobs failed", file=sys.stderr, flush=True)
+        sys.exit(1)
 
 
 if __name__ == "__main__":

@@ -337,7 +337,9 @@ snn_status snn_batch_create(uint64_t hbm_budget, uint64_t max_neurons, void* hip
  * spike history with room for a 150 Hz mean rate) against the free budget,
  * reserves a slot, the estimated bytes and the job's update blocks, and queues
  * the build; returns at once with the job's slot in *slot.  SNN_E_NOMEM: not
- * now (budget, neurons or all 64 slots in use); SNN_E_INVAL: bad description.
+ * now (budget, neurons or all 64 slots in use by other jobs); SNN_E_INVAL: bad
+ * description, or a job that could never be admitted (more neurons than
+ * max_neurons, or a footprint estimate above hbm_budget).
  * A build that fails later is reported by snn_batch_poll as a finished slot
  * whose snn_batch_read_spikes returns the build's error and frees the slot. */
 snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_desc* s, uint32_t dur_ms,

@@ -115,6 +115,8 @@ def lib():
         L.or_net_rend.argtypes = [P, P]
         L.or_net_rend.restype = C.c_int
         L.or_net_stats.restype = None
+        L.or_net_ext_counts.argtypes = [P, U32, U32, P]
+        L.or_net_ext_counts.restype = C.c_int
         _lib = L
     return _lib
 
@@ -299,6 +301,14 @@ class Net:
         wq = np.zeros(max(n, 1), dtype=np.int32)
         lib().or_net_queue(self.h, slot, _p(tgt), _p(fr), _p(wq), n)
         return np.stack([tgt[:n].astype(np.int64), fr[:n].astype(np.int64), wq[:n].astype(np.int64)], axis=1)
+
+    def ext_counts(self, t0, t1):
+        """External Poisson counts u8[t1 - t0, N] of steps t0 .. t1-1."""
+        out = np.zeros((t1 - t0, self.N), dtype=np.uint8)
+        st = lib().or_net_ext_counts(self.h, t0, t1, _p(out))
+        if st != 0:
+            raise ValueError(f"oracle ext_counts: status {st}")
+        return out
 
     def rend(self):
         re = np.zeros(self.N, dtype=np.uint64)

@@ -893,6 +893,20 @@ static uint32_t ext_count(const or_net *n, uint32_t g, uint32_t t)
     return k;
 }
 
+/* External Poisson counts of every neuron for steps t0 .. t1-1, out[(t - t0)
+ * N + g] (saturated at 255); the same draw the simulation takes. */
+int or_net_ext_counts(void *h, uint32_t t0, uint32_t t1, uint8_t *out)
+{
+    or_net *n = (or_net *)h;
+    if (t1 < t0) return OR_E_INVAL;
+    for (uint32_t t = t0; t < t1; t++)
+        for (uint32_t g = 0; g < n->N; g++) {
+            uint32_t k = ext_count(n, g, t);
+            out[(size_t)(t - t0) * n->N + g] = (uint8_t)(k > 255u ? 255u : k);
+        }
+    return OR_OK;
+}
+
 static void hist_push(or_net *n, uint32_t t, uint32_t g, uint32_t f)
 {
     if (n->hist_n == n->hist_cap) {

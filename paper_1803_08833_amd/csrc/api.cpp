@@ -1638,6 +1638,9 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
     gd.hist_cap = (uint64_t)((double)N * dur_ms * 0.15) + 65536;   // room for a 150 Hz mean rate
     const uint64_t est = estimate_bytes(gd, *s, gd.hist_cap);
     std::lock_guard<std::mutex> lk(b->mu);
+    // a job that would not fit even in an empty batch is refused for good
+    if (nblk > b->blk_cap) return bfail(b, SNN_E_INVAL, "job larger than the batch's neuron capacity");
+    if (est > b->budget) return bfail(b, SNN_E_INVAL, "job footprint larger than the batch's HBM budget");
     int free_slot = -1;
     for (uint32_t j = 0; j < snn::kMaxJobs; ++j)
         if (b->jobs[j].state == snn_batch::kFree) {

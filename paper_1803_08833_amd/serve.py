@@ -44,14 +44,23 @@ def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chun
                 b.step(chunk_ms)
             while queue:
                 j = queue[0]
-                slot = b.admit(jobs[j]["net"], jobs[j]["steps"])
-                if slot is None:
+                try:
+                    slot = b.admit(jobs[j]["net"], jobs[j]["steps"])
+                except snn.SNNError as e:   # can never be admitted: fails, the queue moves on
+                    failed.append((j, str(e)))
+                    queue.pop(0)
+                    done_count += 1
+                    continue
+                if slot is None:            # no room now: wait for running jobs to finish
                     break
                 slot_job[slot] = j
                 queue.pop(0)
             if not stepped:
-                if not slot_job and nxt < n:
-                    time.sleep(max(0.0, min(arrivals[nxt] - (clock() - t0), 0.01)))
+                if not slot_job:
+                    # nothing running: wait for the next arrival, or for memory
+                    # of finished jobs to be handed back
+                    wait = arrivals[nxt] - (clock() - t0) if nxt < n else 0.01
+                    time.sleep(max(0.0, min(wait, 0.01)))
                 continue
             for slot in b.poll():
                 j = slot_job.pop(slot)
@@ -106,10 +115,16 @@ def poisson_arrivals(n, rate_per_s, seed=4):
 
 
 def summary(res, jobs):
+    """Throughput and latency of a served run.  Jobs that failed (never
+    admitted, or their build failed) have no latency and no simulated time:
+    they are counted in `failed` and left out of every other figure."""
     lat = res["latency"]
-    sim_s = sum(j["steps"] for j in jobs) * 1e-3
-    return dict(jobs=len(jobs), wall_s=res["wall"], jobs_per_s=len(jobs) / res["wall"],
-                p50_s=float(np.nanpercentile(lat, 50)), p99_s=float(np.nanpercentile(lat, 99)),
+    ok = ~np.isnan(lat)
+    n_ok = int(ok.sum())
+    sim_s = sum(j["steps"] for j, k in zip(jobs, ok) if k) * 1e-3
+    pct = (lambda q: float(np.percentile(lat[ok], q))) if n_ok else (lambda q: float("nan"))
+    return dict(jobs=len(jobs), failed=len(jobs) - n_ok, wall_s=res["wall"], jobs_per_s=n_ok / res["wall"],
+                p50_s=pct(50), p99_s=pct(99),
                 events_per_s=float(res["events"].sum() / res["wall"]), sim_s_per_wall_s=sim_s / res["wall"])
 
 
@@ -142,7 +157,8 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
                capacity_events_per_s=dict(batched=float(rc["events"].sum() / rc["wall"]),
                                           plain=float(rcp["events"].sum() / rcp["wall"])),
                p50_s=sb["p50_s"], p99_s=sb["p99_s"], jobs_per_s=sb["jobs_per_s"],
-               events_per_s=sb["events_per_s"], sim_s_per_wall_s=sb["sim_s_per_wall_s"])
+               events_per_s=sb["events_per_s"], sim_s_per_wall_s=sb["sim_s_per_wall_s"],
+               failed=sb["failed"] + summary(rc, cap_jobs)["failed"])
     if plain_jobs:
         pj = jobs[:plain_jobs]
         rp = serve_plain(pj, arrivals[:plain_jobs])
@@ -150,6 +166,7 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
         rb2 = serve_batched(pj, arrivals[:plain_jobs], hbm_budget, max_neurons, chunk_ms)
         sb2 = summary(rb2, pj)
         say(f"# first {plain_jobs} jobs: plain {sp} | batched {sb2}")
+        out["failed"] += sb2["failed"]
         out["same_stream_first_jobs"] = dict(
             jobs=plain_jobs,
             plain=dict(p50_s=sp["p50_s"], p99_s=sp["p99_s"], wall_s=sp["wall_s"], events_per_s=sp["events_per_s"]),
