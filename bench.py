@@ -45,9 +45,9 @@ def parse():
     p.add_argument("--ext-rate", type=float, default=None, help="override external Poisson rate (Hz)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--deliver-mode", type=int, default=None, help="0 direct atomics, 1 tile-binned")
-    p.add_argument("--serve-jobs", type=int, default=128, help="served-stream jobs (0: skip serving)")
-    p.add_argument("--serve-plain", type=int, default=32, help="first jobs also served one at a time")
-    p.add_argument("--serve-capacity", type=int, default=32, help="jobs of the closed-loop capacity run")
+    p.add_argument("--serve-jobs", type=int, default=512, help="served-stream jobs (0: skip serving)")
+    p.add_argument("--serve-plain", type=int, default=128, help="first jobs also served one at a time")
+    p.add_argument("--serve-capacity", type=int, default=64, help="jobs of the closed-loop capacity run")
     p.add_argument("--serve-gen", type=int, default=1,
                    help="synapse generator of the served jobs: 0 one trial per pair, 1 binomial + Floyd")
     p.add_argument("--graph-chunk", type=int, default=250,
@@ -98,10 +98,11 @@ def traffic_from_profile(args, steps):
 
 
 def cpu_baseline(net, spikes_per_step, seconds_budget=12.0):
-    """The FP64 oracle on a bounded sample of the same network: every neuron
-    of the full grid is updated each step, and each step delivers the
-    projections of `spikes_per_step` spikers (rows built beforehand by the
-    oracle, three disjoint groups in rotation so that no forced spiker is
+    """The FP64 oracle, built with OpenMP and run on all the host threads it
+    is given, on a bounded sample of the same network: every neuron of the
+    full grid is updated each step, and each step delivers the projections of
+    `spikes_per_step` spikers (the timed run's mean; rows built beforehand by
+    the oracle, three disjoint groups in rotation so that no forced spiker is
     refractory).  Value = recurrent events delivered / oracle wall time."""
     import multiprocessing as mp
 
@@ -111,16 +112,16 @@ def cpu_baseline(net, spikes_per_step, seconds_budget=12.0):
 
     N = net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
     D = net["d_max"] - net["d_min"] + 1
-    group = int(max(1, min(spikes_per_step, 1000)))
+    group = int(max(1, min(spikes_per_step, 8000)))
     # 3 * group consecutive rows starting at a module boundary, built by the
     # oracle in contiguous slices on the host cores (not timed)
     M = net["n_exc"] + net["n_inh"]
     r0 = (N // 2) // M * M
     rows = np.arange(r0, r0 + 3 * group, dtype=np.int64)
     workers = min(16, os.cpu_count() or 1)
-    cuts = np.linspace(0, rows.size, workers + 1).astype(np.int64)
+    cuts = np.linspace(0, rows.size, 4 * workers + 1).astype(np.int64)
     jobs = [(net, int(rows[a]), int(b - a)) for a, b in zip(cuts[:-1], cuts[1:]) if b > a]
-    with mp.get_context("fork").Pool(len(jobs)) as pool:
+    with mp.get_context("fork").Pool(workers) as pool:
         parts = pool.starmap(oracle.build_rows, jobs)
     lens = np.zeros(N, dtype=np.int64)
     bend = np.zeros((N, D), dtype=np.uint16)
@@ -136,24 +137,28 @@ def cpu_baseline(net, spikes_per_step, seconds_budget=12.0):
             dl.append((net["d_min"] + (be[r].astype(np.int64)[None, :] <= k[:, None]).sum(axis=1)).astype(np.uint32))
     row_ptr = np.zeros(N + 1, dtype=np.uint64)
     row_ptr[1:] = np.cumsum(lens)
-    o = oracle.Net(net)
-    o.set_csr(row_ptr, bend, np.concatenate(tg), np.concatenate(dl), np.concatenate(wq))
     groups = [rows[g::3] for g in range(3)]
-    t0 = time.perf_counter()
-    steps = 0
-    ev0 = o.stats()["rec_events"]
-    while True:
-        o.step_forced(groups[steps % 3].astype(np.uint32))
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > seconds_budget or steps >= 400:
-            break
-    events = o.stats()["rec_events"] - ev0
-    return dict(value=events / el, unit="synaptic events/s", cores=1, kind="oracle",
-                sample=(f"FP64 oracle, {net['gx']}x{net['gy']} grid ({N} neurons), {steps} forced 1 ms steps: "
-                        f"all neurons updated each step, {group} spikers delivered per step "
-                        f"(oracle-built projection rows), single thread"),
-                ms_per_step=1e3 * el / steps, sim_s_per_wall_s=steps * 1e-3 / el)
+    with oracle.library(oracle.build(openmp=True)):
+        threads = int(oracle.lib().or_threads())
+        o = oracle.Net(net)
+        o.set_csr(row_ptr, bend, np.concatenate(tg), np.concatenate(dl), np.concatenate(wq))
+        t0 = time.perf_counter()
+        steps = 0
+        ev0 = o.stats()["rec_events"]
+        while True:
+            o.step_forced(groups[steps % 3].astype(np.uint32))
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > seconds_budget or steps >= 2000:
+                break
+        events = o.stats()["rec_events"] - ev0
+        del o
+    return dict(value=events / el, unit="synaptic events/s", cores=threads, kind="oracle",
+                sample=(f"FP64 oracle (OpenMP build, {threads} threads; host nproc {os.cpu_count()}), "
+                        f"{net['gx']}x{net['gy']} grid ({N} neurons), {steps} forced 1 ms steps: all neurons "
+                        f"updated each step, {group} spikers delivered per step (the timed run's mean, "
+                        f"{events // max(1, steps)} events per step; oracle-built projection rows)"),
+                ms_per_step=1e3 * el / steps, sim_s_per_wall_s=steps * 1e-3 / el, nproc=os.cpu_count())
 
 
 def main():

@@ -149,6 +149,25 @@ typedef struct {
     double delay_tau;         /* exponential delays: scale in ms, > 0            */
     uint32_t solver;          /* SNN_SOLVER_STEP or SNN_SOLVER_EXACT              */
     uint32_t pad2_;
+    /* Spike-timing plasticity (stdp = 1; F32 records, step solver, no
+     * batches).  Synapses of excitatory sources only.  A synapse of delay d
+     * sees a presynaptic event at every arrival a = s + d of a spike of its
+     * source at step s, and a postsynaptic event at every spike of its target
+     * at step p.  Each pair within the window changes the weight by
+     * kp[p - a] = round(a_plus e^{-(p-a)/tau_plus} 2^16) when p >= a, and by
+     * -km[a - p] = -round(a_minus e^{-(a-p)/tau_minus} 2^16) when p < a
+     * (2^-16 mV; the window ends at the first lag where both round to zero,
+     * at most 255 steps).  A pair counts in the period of its later event;
+     * at the end of every ltp_period steps a synapse whose total is not
+     * zero takes weight + total, clipped to [0, w_max]; spikes use the
+     * weight in force when they are emitted.  The spikes come from the AER
+     * history, which must hold the period and the window before it
+     * (hist_cap): an overflow is reported as SNN_E_OVERFLOW. */
+    uint32_t stdp;            /* 0 off, 1 on                                      */
+    uint32_t ltp_period;      /* steps between long-term applications (1000 = 1 s) */
+    double a_plus, a_minus;   /* pair amplitudes at zero lag (mV), >= 0           */
+    double tau_plus, tau_minus; /* window time constants (ms), > 0                */
+    double w_max;             /* weight bound (mV), in (0, 65534 / 65536]          */
 } snn_syn_desc;
 
 typedef struct {
@@ -309,6 +328,21 @@ snn_status snn_set_option(snn_net* net, int key, int64_t value);
 snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32_t* T, int32_t* wtab,
                            int32_t* cb, uint32_t* poisc, uint32_t* npois, double* consts);
 
+/* Host-only: the plasticity tables of a description with stdp = 1: kp and km
+ * (win entries each, km[0] = 0; capacity 256), *win, and w_max in 2^-16 mV.
+ * Any output may be NULL. */
+snn_status snn_host_stdp_tables(const snn_grid_desc* g, const snn_syn_desc* s, int32_t* kp, int32_t* km,
+                                uint32_t* win, int32_t* wmax_q);
+
+/* Measurement aid, not part of the method: the rate of scattered
+ * device-scope int32 atomic adds (the unit of direct delivery) on this GPU.
+ * n_adds adds go to hashed words of a buffer of n_targets int32 (allocated
+ * and freed by the call); one untimed launch, then one timed with HIP events
+ * on hip_stream (NULL = default).  *adds_per_s receives the rate.
+ * Synchronises.  SNN_E_INVAL for zero sizes, SNN_E_NOMEM when the buffer
+ * cannot be allocated, SNN_E_HIP on a runtime error. */
+snn_status snn_probe_atomics(uint64_t n_targets, uint64_t n_adds, void* hip_stream, double* adds_per_s);
+
 /* Free every device buffer of the network (synchronises its stream). */
 void snn_destroy(snn_net* net);
 
@@ -364,6 +398,14 @@ snn_status snn_batch_read_spikes(snn_batch* b, int32_t slot, snn_spike* host_buf
 /* Counters of one running or finished job (synchronises the stepping
  * stream). */
 snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out);
+
+/* Parity hook: copy a running or finished job's neuron state and delay ring
+ * to host arrays (any may be NULL): v, w (n_neurons floats, mV), ref
+ * (n_neurons bytes, refractory steps left), ring (int32 [32][n_neurons],
+ * slot = arrival step mod 32), as snn_read_state / snn_read_ring give them
+ * for a network stepped alone.  A finished job keeps its state until its
+ * spikes are read.  Synchronises the stepping stream. */
+snn_status snn_batch_read_state(snn_batch* b, int32_t slot, float* v, float* w, uint8_t* ref, int32_t* ring);
 
 /* Device bytes held or reserved by the batch's jobs; number of admitted jobs
  * (building, running or finished and unread). */

@@ -12,6 +12,7 @@ statistics, delivery against brute force and charge conservation.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 import subprocess
@@ -24,14 +25,21 @@ LIB = os.path.join(HERE, "liboracle.so")
 RING = 32
 
 
-def build(force=False):
-    """Compile oracle.c with gcc (plain -O2, no fast-math)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-shared", "-fPIC",
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
+
+
+def build(force=False, openmp=False):
+    """Compile oracle.c with gcc (plain -O2, no fast-math).  openmp: the
+    multi-threaded build timed as the CPU baseline (same source; its OpenMP
+    loops are the neuron update and the delivery's integer adds)."""
+    lib_path = LIB_OMP if openmp else LIB
+    if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(SRC):
+        tmp = lib_path + ".tmp"
+        flags = ["-fopenmp"] if openmp else ["-Wno-unknown-pragmas"]
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", *flags, "-shared", "-fPIC",
                                "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 class Cfg(C.Structure):
@@ -52,10 +60,14 @@ class Cfg(C.Structure):
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
         ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
         ("solver", C.c_uint32), ("pad3_", C.c_uint32),
+        ("stdp", C.c_uint32), ("ltp_period", C.c_uint32),
+        ("a_plus", C.c_double), ("a_minus", C.c_double),
+        ("tau_plus", C.c_double), ("tau_minus", C.c_double), ("w_max", C.c_double),
     ]
 
 SOLVER_STEP, SOLVER_EXACT = 0, 1
-OPTIONAL = ("solver",)   # absent from a description: 0
+# absent from a description: 0
+OPTIONAL = ("solver", "stdp", "ltp_period", "a_plus", "a_minus", "tau_plus", "tau_minus", "w_max")
 
 
 def cfg(net: dict) -> Cfg:
@@ -69,56 +81,82 @@ def cfg(net: dict) -> Cfg:
 _lib = None
 
 
+def _load(path):
+    """Open a build of oracle.c and declare its entry points."""
+    L = C.CDLL(path)
+    P, U32, U64, I32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
+    L.or_philox.argtypes = [P, P, P]
+    L.or_philox.restype = None
+    L.or_make_tables.argtypes = [C.POINTER(Cfg), P, P, P, P, P, P, P]
+    L.or_make_tables.restype = C.c_int
+    L.or_net_create.argtypes = [C.POINTER(Cfg), C.c_int]
+    L.or_net_create.restype = P
+    L.or_net_free.argtypes = [P]
+    L.or_net_free.restype = None
+    L.or_net_build.argtypes = [P]
+    L.or_net_build.restype = C.c_int
+    L.or_build_rows.argtypes = [C.POINTER(Cfg), U32, U32, P, P, P, U64, C.POINTER(U64)]
+    L.or_build_rows.restype = C.c_int
+    L.or_col_input.argtypes = [C.POINTER(Cfg), U32, P, U64, P]
+    L.or_col_input.restype = C.c_int
+    L.or_col_pending.argtypes = [C.POINTER(Cfg), U32, P, P, U64, U32, P]
+    L.or_col_pending.restype = C.c_int
+    L.or_net_csr.argtypes = [P, P, P, P, U64]
+    L.or_net_csr.restype = C.c_int
+    L.or_net_nnz.argtypes = [P]
+    L.or_net_nnz.restype = U64
+    L.or_net_set_csr.argtypes = [P, P, P, P, P, P]
+    L.or_net_set_csr.restype = C.c_int
+    L.or_net_step.argtypes = [P, U32]
+    L.or_net_step.restype = C.c_int
+    L.or_net_step_forced.argtypes = [P, P, U64]
+    L.or_net_step_forced.restype = C.c_int
+    L.or_net_state.argtypes = [P, P, P, P]
+    L.or_net_state.restype = C.c_int
+    L.or_net_ring.argtypes = [P, P]
+    L.or_net_ring.restype = C.c_int
+    L.or_net_hist.argtypes = [P, P, U64]
+    L.or_net_hist.restype = U64
+    L.or_net_stats.argtypes = [P, P]
+    L.or_net_step_forced_exact.argtypes = [P, P, P, U64]
+    L.or_net_step_forced_exact.restype = C.c_int
+    L.or_net_hist_frac.argtypes = [P, P, U64]
+    L.or_net_hist_frac.restype = U64
+    L.or_net_queue.argtypes = [P, U32, P, P, P, U64]
+    L.or_net_queue.restype = U64
+    L.or_net_rend.argtypes = [P, P]
+    L.or_net_rend.restype = C.c_int
+    L.or_net_stats.restype = None
+    L.or_threads.argtypes = []
+    L.or_threads.restype = C.c_int
+    L.or_stdp_totals.argtypes = [C.POINTER(Cfg), P, P, U64, P, P, P, U64, U32, U32, P]
+    L.or_stdp_totals.restype = C.c_int
+    L.or_stdp_tables.argtypes = [C.POINTER(Cfg), P, P, P, P]
+    L.or_stdp_tables.restype = C.c_int
+    L.or_net_ext_counts.argtypes = [P, U32, U32, P]
+    L.or_net_ext_counts.restype = C.c_int
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         build()
-        L = C.CDLL(LIB)
-        P, U32, U64, I32 = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int32
-        L.or_philox.argtypes = [P, P, P]
-        L.or_philox.restype = None
-        L.or_make_tables.argtypes = [C.POINTER(Cfg), P, P, P, P, P, P, P]
-        L.or_make_tables.restype = C.c_int
-        L.or_net_create.argtypes = [C.POINTER(Cfg), C.c_int]
-        L.or_net_create.restype = P
-        L.or_net_free.argtypes = [P]
-        L.or_net_free.restype = None
-        L.or_net_build.argtypes = [P]
-        L.or_net_build.restype = C.c_int
-        L.or_build_rows.argtypes = [C.POINTER(Cfg), U32, U32, P, P, P, U64, C.POINTER(U64)]
-        L.or_build_rows.restype = C.c_int
-        L.or_col_input.argtypes = [C.POINTER(Cfg), U32, P, U64, P]
-        L.or_col_input.restype = C.c_int
-        L.or_net_csr.argtypes = [P, P, P, P, U64]
-        L.or_net_csr.restype = C.c_int
-        L.or_net_nnz.argtypes = [P]
-        L.or_net_nnz.restype = U64
-        L.or_net_set_csr.argtypes = [P, P, P, P, P, P]
-        L.or_net_set_csr.restype = C.c_int
-        L.or_net_step.argtypes = [P, U32]
-        L.or_net_step.restype = C.c_int
-        L.or_net_step_forced.argtypes = [P, P, U64]
-        L.or_net_step_forced.restype = C.c_int
-        L.or_net_state.argtypes = [P, P, P, P]
-        L.or_net_state.restype = C.c_int
-        L.or_net_ring.argtypes = [P, P]
-        L.or_net_ring.restype = C.c_int
-        L.or_net_hist.argtypes = [P, P, U64]
-        L.or_net_hist.restype = U64
-        L.or_net_stats.argtypes = [P, P]
-        L.or_net_step_forced_exact.argtypes = [P, P, P, U64]
-        L.or_net_step_forced_exact.restype = C.c_int
-        L.or_net_hist_frac.argtypes = [P, P, U64]
-        L.or_net_hist_frac.restype = U64
-        L.or_net_queue.argtypes = [P, U32, P, P, P, U64]
-        L.or_net_queue.restype = U64
-        L.or_net_rend.argtypes = [P, P]
-        L.or_net_rend.restype = C.c_int
-        L.or_net_stats.restype = None
-        L.or_net_ext_counts.argtypes = [P, U32, U32, P]
-        L.or_net_ext_counts.restype = C.c_int
-        _lib = L
+        _lib = _load(LIB)
     return _lib
+
+
+@contextlib.contextmanager
+def library(path):
+    """Route every oracle call inside the block to another build of
+    oracle.c (a planted-mistake variant compiled by a test)."""
+    global _lib
+    saved = lib()
+    _lib = _load(path)
+    try:
+        yield
+    finally:
+        _lib = saved
 
 
 def _p(a: np.ndarray):
@@ -156,6 +194,38 @@ def tables(net: dict):
                 nref=int(iconsts[0]), jext_q=int(iconsts[1]), winh_q=int(iconsts[2]))
 
 
+def stdp_tables(net: dict):
+    """Plasticity tables: kp[win], km[win] (2^-16 mV per pair at lag k), the
+    window and the weight bound w_max in 2^-16 mV."""
+    c = cfg(net)
+    kp = np.zeros(256, dtype=np.int32)
+    km = np.zeros(256, dtype=np.int32)
+    win = np.zeros(1, dtype=np.uint32)
+    wmax = np.zeros(1, dtype=np.int32)
+    st = lib().or_stdp_tables(C.byref(c), _p(kp), _p(km), _p(win), _p(wmax))
+    if st != 0:
+        raise ValueError(f"oracle stdp tables: status {st}")
+    w = int(win[0])
+    return dict(kp=kp[:w].copy(), km=km[:w].copy(), win=w, wmax_q=int(wmax[0]))
+
+
+def stdp_totals(net: dict, raster, pre, tgt, delay, T0: int, T1: int) -> np.ndarray:
+    """Plasticity change of a period [T0, T1) for the synapses (pre, tgt,
+    delay), summed pair by pair from the (step, gid) raster (unclipped)."""
+    c = cfg(net)
+    r = np.asarray(raster, dtype=np.uint32).reshape(-1, 2)
+    rs, rg = np.ascontiguousarray(r[:, 0]), np.ascontiguousarray(r[:, 1])
+    pre = np.ascontiguousarray(pre, dtype=np.uint32)
+    tgt = np.ascontiguousarray(tgt, dtype=np.uint32)
+    delay = np.ascontiguousarray(delay, dtype=np.uint32)
+    out = np.zeros(pre.size, dtype=np.int64)
+    st = lib().or_stdp_totals(C.byref(c), _p(rs), _p(rg), rs.size, _p(pre), _p(tgt), _p(delay), pre.size,
+                              T0, T1, _p(out))
+    if st != 0:
+        raise ValueError(f"oracle stdp_totals: status {st}")
+    return out
+
+
 def n_neurons(net):
     return net["gx"] * net["gy"] * (net["n_exc"] + net["n_inh"])
 
@@ -190,6 +260,21 @@ def build_rows(net: dict, pre0: int, cnt: int, cap: int | None = None):
             raise ValueError(f"oracle build_rows: status {st}")
         break
     return row_len, bend, recs[: int(n_out.value) * rec_bytes(net)].copy()
+
+
+def col_pending(net: dict, j: int, raster, T: int) -> np.ndarray:
+    """Charge in flight for target j after steps 0 .. T-1 of the (step, gid)
+    raster: int64[d_max], entry a arriving at step T + a."""
+    c = cfg(net)
+    r = np.ascontiguousarray(raster, dtype=np.uint32).reshape(-1, 2)
+    keep = r[:, 0].astype(np.int64) >= T - net["d_max"]
+    st_ = np.ascontiguousarray(r[keep, 0])
+    pr = np.ascontiguousarray(r[keep, 1])
+    out = np.zeros(net["d_max"], dtype=np.int64)
+    st = lib().or_col_pending(C.byref(c), j, _p(st_), _p(pr), pr.size, T, _p(out))
+    if st != 0:
+        raise ValueError(f"oracle col_pending: status {st}")
+    return out
 
 
 def col_input(net: dict, j: int, pres) -> np.ndarray:

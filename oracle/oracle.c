@@ -46,6 +46,9 @@
  * every spike of a recurrent network.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -83,6 +86,7 @@
 #define OR_SOLVER_STEP 0   /* charge summed per 1 ms step, one jump per step   */
 #define OR_SOLVER_EXACT 1  /* exact-time event-driven integration              */
 #define ST_EXT_TIME 7u     /* exact solver: arrival times of external events    */
+#define STDP_WIN_MAX 256   /* longest plasticity window, steps                  */
 
 /* Flat description of one network.  Times in ms, potentials in mV. */
 typedef struct {
@@ -111,6 +115,11 @@ typedef struct {
     double delay_tau;         /* exponential delays: scale (ms)               */
     uint32_t solver;          /* OR_SOLVER_STEP / OR_SOLVER_EXACT             */
     uint32_t pad3_;
+    uint32_t stdp;            /* 1: spike-timing plasticity of excitatory synapses */
+    uint32_t ltp_period;      /* steps between long-term applications (1000 = 1 s) */
+    double a_plus, a_minus;   /* pair amplitudes at zero lag (mV)             */
+    double tau_plus, tau_minus; /* window time constants (ms)                 */
+    double w_max;             /* upper bound of a plastic weight (mV)         */
 } or_cfg;
 
 /* ------------------------------------------------------------------------ */
@@ -202,6 +211,11 @@ typedef struct {
     double dm, dw, kappa;   /* one-step propagator constants                  */
     uint32_t nref;          /* refractory steps                               */
     int32_t jext_q, winh_q;
+    /* plasticity: weight change of one pair at lag k steps, 2^-16 mV */
+    int32_t kp[STDP_WIN_MAX];   /* potentiation, post k >= 0 steps after the arrival */
+    int32_t km[STDP_WIN_MAX];   /* depression, arrival k >= 1 steps after the post spike */
+    uint32_t win;               /* lags below win count                              */
+    int32_t wmax_q;
 } or_tables;
 
 static uint32_t module_size(const or_cfg *c) { return c->n_exc + c->n_inh; }
@@ -444,7 +458,42 @@ static int make_tables(const or_cfg *c, or_tables *tb)
     tb->nref = (uint32_t)llround(c->t_ref / h);
     tb->jext_q = fixq(c->ext_w);
     tb->winh_q = fixq(c->w_inh);
+    /* Spike-timing plasticity (Sec. II, Sec. II.A steps 1 and 4; pair-based
+     * with exponential windows, the family of the rules the paper cites).
+     * One pair of a presynaptic arrival and a postsynaptic spike k steps
+     * apart changes the weight by kp[k] = round(A+ e^{-k/tau+} 2^16) when
+     * the spike is not before the arrival, and by -km[k] = -round(A-
+     * e^{-k/tau-} 2^16) when the arrival is k >= 1 steps after it; the
+     * window ends at the first lag where both round to zero. */
+    tb->win = 0;
+    tb->wmax_q = 0;
+    if (c->stdp > 1) return OR_E_INVAL;
+    if (c->stdp) {
+        if (c->solver != OR_SOLVER_STEP || c->record != OR_REC_F32) return OR_E_INVAL;
+        if (!(c->a_plus >= 0.0) || !(c->a_minus >= 0.0) || !(c->tau_plus > 0.0) || !(c->tau_minus > 0.0) ||
+            !(c->w_max > 0.0) || c->ltp_period == 0)
+            return OR_E_INVAL;
+        uint32_t win = 0;
+        for (uint32_t k = 0; k < STDP_WIN_MAX; k++) {
+            tb->kp[k] = (int32_t)nearbyint(c->a_plus * exp(-(double)k / c->tau_plus) * 65536.0);
+            tb->km[k] = k ? (int32_t)nearbyint(c->a_minus * exp(-(double)k / c->tau_minus) * 65536.0) : 0;
+            if (tb->kp[k] || tb->km[k]) win = k + 1;
+        }
+        if (win == STDP_WIN_MAX) return OR_E_INVAL;   /* window longer than the table */
+        tb->win = win;
+        tb->wmax_q = fixq(c->w_max);
+    }
     return OR_OK;
+}
+
+/* Host threads the oracle's step uses (1 unless built with OpenMP). */
+int or_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* Exported for the table pins. */
@@ -462,6 +511,24 @@ int or_make_tables(const or_cfg *c, uint32_t *T, int32_t *wtab, int32_t *cb,
         if (npois) *npois = tb->npois;
         if (consts) { consts[0] = tb->dm; consts[1] = tb->dw; consts[2] = tb->kappa; }
         if (iconsts) { iconsts[0] = (int32_t)tb->nref; iconsts[1] = tb->jext_q; iconsts[2] = tb->winh_q; }
+    }
+    free_tables(tb);
+    free(tb);
+    return st;
+}
+
+/* Plasticity tables: kp[win], km[win] (km[0] unused, 0), the window and the
+ * weight bound in 2^-16 mV.  Exported for the table pins. */
+int or_stdp_tables(const or_cfg *c, int32_t *kp, int32_t *km, uint32_t *win, int32_t *wmax_q)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    if (st == OR_OK) {
+        if (kp) memcpy(kp, tb->kp, sizeof(int32_t) * tb->win);
+        if (km) memcpy(km, tb->km, sizeof(int32_t) * tb->win);
+        if (win) *win = tb->win;
+        if (wmax_q) *wmax_q = tb->wmax_q;
     }
     free_tables(tb);
     free(tb);
@@ -672,6 +739,13 @@ typedef struct {
     struct or_ev *q[RING];  /* per arrival slot: queued events, unsorted                 */
     size_t qn[RING], qcap[RING];
     uint32_t *hist_f;       /* emission offset of each history entry                     */
+    /* spike-timing plasticity */
+    int64_t *acc;           /* [nnz] weight change of the running period, 2^-16 mV */
+    uint64_t *in_ptr;       /* [N+1] incoming synapses grouped by target            */
+    uint64_t *in_syn;       /* [nnz] index in syn[] of each incoming synapse         */
+    uint32_t *in_pre;       /* [nnz] its presynaptic neuron                          */
+    uint32_t **spk;         /* [N] spike steps of each neuron, ascending            */
+    uint32_t *spk_n, *spk_cap;
 } or_net;
 
 void or_net_free(void *h)
@@ -683,6 +757,10 @@ void or_net_free(void *h)
     free(n->flag); free(n->hist);
     free(n->rend); free(n->fs); free(n->hist_f);
     for (int k = 0; k < RING; k++) free(n->q[k]);
+    free(n->acc); free(n->in_ptr); free(n->in_syn); free(n->in_pre);
+    if (n->spk)
+        for (uint32_t i = 0; i < n->N; i++) free(n->spk[i]);
+    free(n->spk); free(n->spk_n); free(n->spk_cap);
     free(n);
 }
 
@@ -835,6 +913,31 @@ int or_col_input(const or_cfg *c, uint32_t j, const uint32_t *pres, uint64_t np,
     return st;
 }
 
+/* Charge queued for target j after steps 0 .. T-1 (delay ring in flight):
+ * out[a], a < d_max, is the fixed-point charge arriving at step T + a from
+ * the spikes (steps[k], pres[k]), each reaching j at its step plus the
+ * synapse's delay (Sec. II.A steps 2-4). */
+int or_col_pending(const or_cfg *c, uint32_t j, const uint32_t *steps, const uint32_t *pres, uint64_t np,
+                   uint32_t T, int64_t *out)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    for (uint32_t a = 0; a < c->d_max; a++) out[a] = 0;
+    for (uint64_t k = 0; st == OR_OK && k < np; k++) {
+        uint32_t i = pres[k];
+        if (!connects(c, tb, i, j)) continue;
+        uint32_t delay, code;
+        int32_t wq;
+        attributes(c, tb, i, j, &delay, &wq, &code);
+        uint64_t arr = (uint64_t)steps[k] + delay;
+        if (arr >= T && arr < (uint64_t)T + c->d_max) out[arr - T] += wq;
+    }
+    free_tables(tb);
+    free(tb);
+    return st;
+}
+
 int or_net_csr(void *h, uint64_t *row_ptr, uint16_t *bend, void *recs, uint64_t rec_cap)
 {
     or_net *n = (or_net *)h;
@@ -875,6 +978,8 @@ int or_net_set_csr(void *h, const uint64_t *row_ptr, const uint16_t *bend, const
     }
     n->nnz = nnz;
     n->built = 1;
+    free(n->in_ptr); free(n->in_syn); free(n->in_pre); free(n->acc);
+    n->in_ptr = NULL; n->in_syn = NULL; n->in_pre = NULL; n->acc = NULL;
     return OR_OK;
 }
 
@@ -925,6 +1030,177 @@ static void hist_push(or_net *n, uint32_t t, uint32_t g, uint32_t f)
     n->hist_n++;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Spike-timing plasticity (Sec. II, Sec. II.A steps 1 and 4, long-term    */
+/* application every period)                                                */
+/* ------------------------------------------------------------------------ */
+/* A synapse i -> j of delay d sees a presynaptic event at every arrival
+ * a = s + d of a spike of i at step s, and a postsynaptic event at every
+ * spike of j at step p.  Each pair of the two within the window contributes
+ * once, when its later event happens: at a postsynaptic spike (step 1 of the
+ * step loop: the step's spikers are identified) every arrival a <= p adds
+ * kp[p - a]; at an arrival (step 4: the synapse injects its current) every
+ * earlier postsynaptic spike p < a adds -km[a - p].  An arrival and a spike
+ * in the same step form a potentiating pair (the input is applied before the
+ * threshold test).  Only synapses of excitatory sources are plastic.  At the
+ * end of every period of ltp_period steps a synapse whose accumulated change
+ * is not zero gets its weight plus the change, clipped to [0, w_max] (the
+ * others keep theirs), and the accumulator is cleared; spikes use the weight
+ * in force when they are emitted. */
+static int stdp_prepare(or_net *n)
+{
+    const uint32_t N = n->N;
+    if (!n->spk) {
+        n->spk = (uint32_t **)calloc(N, sizeof(uint32_t *));
+        n->spk_n = (uint32_t *)calloc(N, sizeof(uint32_t));
+        n->spk_cap = (uint32_t *)calloc(N, sizeof(uint32_t));
+        if (!n->spk || !n->spk_n || !n->spk_cap) return OR_E_NOMEM;
+    }
+    if (n->in_ptr || !n->built) return OR_OK;
+    const uint64_t nnz = n->nnz;
+    n->in_ptr = (uint64_t *)calloc((size_t)N + 1, sizeof(uint64_t));
+    n->in_syn = (uint64_t *)malloc((nnz ? nnz : 1) * sizeof(uint64_t));
+    n->in_pre = (uint32_t *)malloc((nnz ? nnz : 1) * sizeof(uint32_t));
+    n->acc = (int64_t *)calloc(nnz ? nnz : 1, sizeof(int64_t));
+    if (!n->in_ptr || !n->in_syn || !n->in_pre || !n->acc) return OR_E_NOMEM;
+    for (uint64_t k = 0; k < nnz; k++) n->in_ptr[n->syn[k].tgt + 1]++;
+    for (uint32_t j = 0; j < N; j++) n->in_ptr[j + 1] += n->in_ptr[j];
+    uint64_t *fill = (uint64_t *)malloc(((size_t)N + 1) * sizeof(uint64_t));
+    if (!fill) return OR_E_NOMEM;
+    memcpy(fill, n->in_ptr, ((size_t)N + 1) * sizeof(uint64_t));
+    for (uint32_t i = 0; i < N; i++)
+        for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
+            uint64_t e = fill[n->syn[k].tgt]++;
+            n->in_syn[e] = k;
+            n->in_pre[e] = i;
+        }
+    free(fill);
+    return OR_OK;
+}
+
+static int spike_log(or_net *n, uint32_t i, uint32_t t)
+{
+    if (n->spk_n[i] == n->spk_cap[i]) {
+        uint32_t nc = n->spk_cap[i] ? 2 * n->spk_cap[i] : 16;
+        uint32_t *p = (uint32_t *)realloc(n->spk[i], nc * sizeof(uint32_t));
+        if (!p) return OR_E_NOMEM;
+        n->spk[i] = p;
+        n->spk_cap[i] = nc;
+    }
+    n->spk[i][n->spk_n[i]++] = t;
+    return OR_OK;
+}
+
+/* First history entry of step s (the history is ordered by step). */
+static size_t hist_lower(const or_net *n, uint32_t s)
+{
+    size_t lo = 0, hi = n->hist_n;
+    while (lo < hi) {
+        size_t mid = (lo + hi) / 2;
+        if (n->hist[2 * mid] < s) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+/* Contributions of the pairs whose later event falls in step t. */
+static void stdp_events(or_net *n, uint32_t t)
+{
+    const or_cfg *c = &n->c;
+    const or_tables *tb = &n->tb;
+    const uint32_t M = module_size(c), win = tb->win;
+    /* postsynaptic spikes of step t: potentiation against arrivals a <= t */
+    for (uint32_t j = 0; j < n->N; j++) {
+        if (!n->flag[j]) continue;
+        for (uint64_t e = n->in_ptr[j]; e < n->in_ptr[j + 1]; e++) {
+            uint32_t i = n->in_pre[e];
+            if (i % M >= c->n_exc) continue;
+            uint64_t k = n->in_syn[e];
+            uint32_t d = n->syn[k].delay;
+            for (uint32_t q = 0; q < n->spk_n[i]; q++) {
+                uint32_t a = n->spk[i][q] + d;
+                if (a > t) break;
+                if (t - a < win) n->acc[k] += tb->kp[t - a];
+            }
+        }
+    }
+    /* arrivals at step t (spikes of step t - d through delay-d synapses):
+     * depression against postsynaptic spikes p < t */
+    for (uint32_t d = c->d_min; d <= c->d_max && d <= t; d++) {
+        uint32_t s = t - d;
+        for (size_t h = hist_lower(n, s); h < n->hist_n && n->hist[2 * h] == s; h++) {
+            uint32_t i = n->hist[2 * h + 1];
+            if (i % M >= c->n_exc) continue;
+            uint64_t r0 = n->row_ptr[i];
+            uint64_t b0 = r0 + (d > c->d_min ? n->bend[(size_t)i * n->D + (d - c->d_min - 1)] : 0);
+            uint64_t b1 = r0 + n->bend[(size_t)i * n->D + (d - c->d_min)];
+            for (uint64_t k = b0; k < b1; k++) {
+                uint32_t j = n->syn[k].tgt;
+                for (uint32_t q = n->spk_n[j]; q-- > 0;) {
+                    uint32_t p = n->spk[j][q];
+                    if (p >= t) continue;
+                    if (t - p >= win) break;
+                    n->acc[k] -= tb->km[t - p];
+                }
+            }
+        }
+    }
+}
+
+/* The change of a period for given synapses, straight from the definition:
+ * for synapse k (pre[k] -> tgt[k], delay[k]) the sum over every pair of a
+ * spike s of the source and a spike p of the target in the raster, with
+ * arrival a = s + delay, max(a, p) in [T0, T1) and |p - a| < win, of
+ * kp[p - a] (p >= a) or -km[a - p] (p < a).  Unclipped; 0 for inhibitory
+ * sources.  The raster is (step, gid) pairs in any order. */
+int or_stdp_totals(const or_cfg *c, const uint32_t *r_step, const uint32_t *r_gid, uint64_t nr,
+                   const uint32_t *pre, const uint32_t *tgt, const uint32_t *delay, uint64_t ns,
+                   uint32_t T0, uint32_t T1, int64_t *out)
+{
+    or_tables *tb = (or_tables *)calloc(1, sizeof(or_tables));
+    if (!tb) return OR_E_NOMEM;
+    int st = make_tables(c, tb);
+    const uint32_t M = module_size(c);
+    for (uint64_t k = 0; st == OR_OK && k < ns; k++) {
+        int64_t acc = 0;
+        if (c->stdp && pre[k] % M < c->n_exc) {
+            for (uint64_t x = 0; x < nr; x++) {
+                if (r_gid[x] != pre[k]) continue;
+                int64_t a = (int64_t)r_step[x] + delay[k];
+                for (uint64_t y = 0; y < nr; y++) {
+                    if (r_gid[y] != tgt[k]) continue;
+                    int64_t p = r_step[y], later = p > a ? p : a, lag = p - a;
+                    if (later < T0 || later >= T1) continue;
+                    if (lag >= 0 && lag < (int64_t)tb->win) acc += tb->kp[lag];
+                    if (lag < 0 && -lag < (int64_t)tb->win) acc -= tb->km[-lag];
+                }
+            }
+        }
+        out[k] = acc;
+    }
+    free_tables(tb);
+    free(tb);
+    return st;
+}
+
+/* Long-term application at the end of a period. */
+static void stdp_apply(or_net *n)
+{
+    const uint32_t M = module_size(&n->c);
+    for (uint32_t i = 0; i < n->N; i++) {
+        if (i % M >= n->c.n_exc) continue;
+        for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
+            if (n->acc[k] == 0) continue;   /* no net change: the weight is kept as it is */
+            int64_t w = (int64_t)n->syn[k].wq + n->acc[k];
+            if (w < 0) w = 0;
+            if (w > n->tb.wmax_q) w = n->tb.wmax_q;
+            n->syn[k].wq = (int32_t)w;
+            n->syn[k].wf = (double)w / 65536.0;
+            n->acc[k] = 0;
+        }
+    }
+}
+
 /* One 1 ms step.  Every neuron first takes the charge queued for this step
  * (recurrent, from the delay queue, plus external), then integrates
  * Eq. (1)-(2); the spikers, in ascending id, are recorded and their
@@ -936,6 +1212,10 @@ static int step_once(or_net *n, const uint8_t *forced)
 {
     const or_cfg *c = &n->c;
     uint32_t t = n->t, slot = t % RING, N = n->N;
+    uint64_t ext_ev = 0, rec_ev = 0;
+    /* each neuron's update reads and writes only its own state (the OpenMP
+     * build of the CPU baseline splits this loop over the host cores) */
+#pragma omp parallel for schedule(static) reduction(+ : ext_ev)
     for (uint32_t j = 0; j < N; j++) {
         size_t s = (size_t)slot * N + j;
         int64_t in64 = n->ring64[s];
@@ -950,7 +1230,7 @@ static int step_once(or_net *n, const uint8_t *forced)
             eq = c->ext_const_q;
         } else {
             uint32_t k = ext_count(n, j, t);
-            n->ext_events += k;
+            ext_ev += k;
             eq = (int32_t)k * n->tb.jext_q;
         }
         double J = n->fp64_weights ? inf + (double)eq / 65536.0 : (double)(iq + eq) / 65536.0;
@@ -977,19 +1257,41 @@ static int step_once(or_net *n, const uint8_t *forced)
         }
         n->w[j] = n->w[j] - n->w[j] * n->tb.dw;
     }
+    n->ext_events += ext_ev;
+    if (c->stdp) {
+        int st = stdp_prepare(n);
+        if (st) return st;
+    }
+    /* the step's spikers, in ascending id, into the AER history */
     for (uint32_t i = 0; i < N; i++) {
         if (!n->flag[i]) continue;
         hist_push(n, t, i, 0u);
         n->n_spikes++;
-        if (!n->built) continue;
-        for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
-            const or_syn *s = &n->syn[k];
-            size_t a = (size_t)((t + s->delay) % RING) * N + s->tgt;
-            n->ring[a] = (int32_t)((uint32_t)n->ring[a] + (uint32_t)s->wq);
-            n->ring64[a] += s->wq;
-            n->ringf[a] += s->wf;
-            n->rec_events++;
+        if (c->stdp && spike_log(n, i, t)) return OR_E_NOMEM;
+    }
+    /* each spiker's projection into the delay ring at step t + delay (integer
+     * sums commute: the OpenMP build adds from several cores at once) */
+    if (n->built) {
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : rec_ev)
+        for (uint32_t i = 0; i < N; i++) {
+            if (!n->flag[i]) continue;
+            for (uint64_t k = n->row_ptr[i]; k < n->row_ptr[i + 1]; k++) {
+                const or_syn *s = &n->syn[k];
+                size_t a = (size_t)((t + s->delay) % RING) * N + s->tgt;
+#pragma omp atomic
+                ((uint32_t *)n->ring)[a] += (uint32_t)s->wq;
+#pragma omp atomic
+                n->ring64[a] += s->wq;
+#pragma omp atomic
+                n->ringf[a] += s->wf;
+                rec_ev++;
+            }
         }
+        n->rec_events += rec_ev;
+    }
+    if (c->stdp && n->built) {
+        stdp_events(n, t);
+        if ((t + 1) % c->ltp_period == 0) stdp_apply(n);
     }
     n->t = t + 1;
     return n->overflow ? OR_E_OVERFLOW : OR_OK;

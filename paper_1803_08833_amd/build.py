@@ -13,7 +13,7 @@ LIB = os.path.join(PKG, "libsnn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["kernels.hip", "exact.hip", "api.cpp", "tables.cpp"]
+SOURCES = ["kernels.hip", "exact.hip", "stdp.hip", "probe.hip", "api.cpp", "tables.cpp"]
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", f"-I{INCLUDE}", f"-I{CSRC}"]
 # packed FP32 VALU forms stay off for every device compile
 DEVICE = [f"--offload-arch={ARCH}", "-mcode-object-version=5", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -21,6 +21,7 @@
 #include "snn.h"
 #include "exact_dev.h"
 #include "snn_dev.h"
+#include "stdp_dev.h"
 #include "tables.h"
 
 using snn::Ctrl;
@@ -78,6 +79,11 @@ struct snn_net {
     uint32_t* xforced_f = nullptr;
     hipGraph_t xgraph = nullptr;      // R captured steps from a step t with t mod R = 0
     hipGraphExec_t xgraph_ex = nullptr;
+    // spike-timing plasticity (s.stdp)
+    bool stdp = false;
+    snn::StdpArgs sa{};
+    uint64_t* stdp_tsum = nullptr;    // scan scratch of the long-term application
+    uint64_t stdp_t = 0;              // steps taken (the period's position)
 };
 
 namespace {
@@ -303,6 +309,12 @@ snn::TableParams table_params(const snn_grid_desc& g, const snn_syn_desc& s)
     tp.tau_m = g.tau_m;
     tp.tau_w = g.tau_w;
     tp.t_ref = g.t_ref;
+    tp.stdp = s.stdp;
+    tp.a_plus = s.a_plus;
+    tp.a_minus = s.a_minus;
+    tp.tau_plus = s.tau_plus;
+    tp.tau_minus = s.tau_minus;
+    tp.w_max = s.w_max;
     return tp;
 }
 
@@ -550,8 +562,84 @@ static hipError_t step_exact(snn_net* n, uint32_t n_ms)
 }
 
 // Inputs dropped because an arrival slot's list was full (exact solver).
+// Buffers of the long-term plasticity application: per-neuron counters,
+// list offsets, the window's spike steps (at most one spike per refractory
+// period and neuron, and never more than the history holds), the rows to
+// visit, and the lag tables.
+static snn_status setup_stdp(snn_net* n, const snn::HostTables& tb)
+{
+    snn::StdpArgs& sa = n->sa;
+    const StepArgs& a = n->a;
+    sa.N = n->N;
+    sa.M = n->M;
+    sa.n_exc = n->g.n_exc;
+    sa.D = n->D;
+    sa.d_min = n->s.d_min;
+    sa.win = tb.stdp_win;
+    sa.wmax_q = tb.wmax_q;
+    sa.smax = n->max_len ? (n->max_len + 255u) / 256u : 1u;
+    sa.hist = a.hist;
+    sa.hist_cap = a.hist_cap;
+    sa.ctrl = a.ctrl;
+    sa.row_ptr = a.row_ptr;
+    sa.bend = a.bend;
+    sa.recs = reinterpret_cast<snn::Rec8*>(const_cast<void*>(a.recs));
+    const uint64_t span = (uint64_t)n->s.ltp_period + tb.stdp_win + n->s.d_max;
+    const uint64_t per = (span + tb.nref) / (tb.nref + 1u);   // spikes a neuron can have in the span
+    sa.times_cap = std::max<uint64_t>(1, std::min<uint64_t>(a.hist_cap, (uint64_t)n->N * per));
+    int32_t* kp = nullptr;
+    int32_t* km = nullptr;
+    hipError_t e = dalloc(n, &sa.range, 2);
+    if (e == hipSuccess) e = dalloc(n, &sa.cnt, n->N);
+    if (e == hipSuccess) e = dalloc(n, &sa.fill, n->N);
+    if (e == hipSuccess) e = dalloc(n, &sa.off, (size_t)n->N + 1);
+    if (e == hipSuccess) e = dalloc(n, &sa.times, sa.times_cap);
+    if (e == hipSuccess) e = dalloc(n, &sa.act, n->N);
+    if (e == hipSuccess) e = dalloc(n, &sa.nact, 1);
+    if (e == hipSuccess) e = dalloc(n, &kp, tb.kp.size());
+    if (e == hipSuccess) e = dalloc(n, &km, tb.km.size());
+    if (e == hipSuccess) e = dalloc(n, &n->stdp_tsum, snn::scan_tiles(n->N) + 1);
+    if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (plasticity)");
+    HIPCHK(n, hipMemcpyAsync(kp, tb.kp.data(), tb.kp.size() * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, hipMemcpyAsync(km, tb.km.data(), tb.km.size() * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    sa.kp = kp;
+    sa.km = km;
+    n->stdp = true;
+    n->stdp_t = 0;
+    return SNN_OK;
+}
+
+// The long-term application that ends the period just stepped.
+static hipError_t enqueue_ltp(snn_net* n)
+{
+    snn::StdpArgs sa = n->sa;
+    const uint64_t P = n->s.ltp_period;
+    sa.T1 = (uint32_t)n->stdp_t;
+    sa.T0 = (uint32_t)(n->stdp_t - P);
+    const uint64_t back = (uint64_t)sa.win + n->s.d_max;
+    sa.W0 = (uint64_t)sa.T0 + 1 >= back ? (uint32_t)(sa.T0 + 1 - back) : 0u;
+    return snn::launch_stdp_period(sa, n->stdp_tsum, n->stream);
+}
+
+// Book `count` steps just enqueued on a plastic network (never past the end
+// of a period) and apply the period when they end it.
+static hipError_t stdp_after(snn_net* n, uint32_t count)
+{
+    if (!n->stdp) return hipSuccess;
+    n->stdp_t += count;
+    return n->stdp_t % n->s.ltp_period == 0 ? enqueue_ltp(n) : hipSuccess;
+}
+
 static snn_status check_dropped(snn_net* n)
 {
+    if (n->stdp) {
+        Ctrl hc{};
+        HIPCHK(n, hipMemcpy(&hc, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+        if (hc.err & 8u)
+            return fail(n, SNN_E_OVERFLOW, "plasticity: the spike history overflowed its capacity, so pairs were "
+                                           "missed (raise hist_cap)");
+    }
     if (!n->exact) return SNN_OK;
     unsigned long long d = 0;
     HIPCHK(n, hipMemcpy(&d, n->x.dropped, 8, hipMemcpyDeviceToHost));
@@ -585,6 +673,14 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     snn::HostTables tb;
     std::string why = snn::build_tables(tp, tb);
     if (!why.empty()) return fail(n, SNN_E_INVAL, why);
+    if (s->stdp) {
+        if (s->solver != SNN_SOLVER_STEP) return fail(n, SNN_E_INVAL, "plasticity runs under the step solver only");
+        if (s->record != SNN_REC_F32) return fail(n, SNN_E_INVAL, "plasticity needs F32 records");
+        if (s->ltp_period == 0) return fail(n, SNN_E_INVAL, "ltp_period must be at least one step");
+        // a plastic weight must keep the binned delivery's 17-bit weight field
+        if (!(s->w_max > 0.0) || tb.wmax_q > 65534)
+            return fail(n, SNN_E_INVAL, "w_max must be in (0, 65534/65536] mV");
+    }
     n->s = *s;
     n->D = s->d_max - s->d_min + 1;
     StepArgs& a = n->a;
@@ -747,6 +843,10 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     }
     n->mode = mode;
     a.grp_atomic = n->mode == 1 ? 0u : 1u;
+    if (s->stdp) {
+        st = setup_stdp(n, tb);
+        if (st) return st;
+    }
     n->built = true;
     n->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t_start).count();
     return SNN_OK;
@@ -765,18 +865,30 @@ snn_status snn_step(snn_net* n, uint32_t n_ms)
         }
         return SNN_OK;
     }
-    uint32_t left = n_ms;
-    if (n->graph_chunk > 0) {
-        while (left >= n->graph_chunk) {
-            hipGraphExec_t ex = nullptr;
-            HIPCHK(n, get_graph(n, n->graph_chunk, &ex));
-            HIPCHK(n, hipGraphLaunch(ex, n->stream));
-            left -= n->graph_chunk;
+    uint32_t todo = n_ms;
+    while (todo) {
+        // a plastic network stops at the end of each period for its long-term
+        // application
+        uint32_t run = todo;
+        if (n->stdp) {
+            const uint64_t to_end = n->s.ltp_period - n->stdp_t % n->s.ltp_period;
+            run = to_end < run ? (uint32_t)to_end : run;
         }
-    }
-    if (left) {
-        HIPCHK(n, enqueue_steps(n, 0, left));
-        HIPCHK(n, snn::launch_advance(n->a.ctrl, left, n->stream));
+        uint32_t left = run;
+        if (n->graph_chunk > 0) {
+            while (left >= n->graph_chunk) {
+                hipGraphExec_t ex = nullptr;
+                HIPCHK(n, get_graph(n, n->graph_chunk, &ex));
+                HIPCHK(n, hipGraphLaunch(ex, n->stream));
+                left -= n->graph_chunk;
+            }
+        }
+        if (left) {
+            HIPCHK(n, enqueue_steps(n, 0, left));
+            HIPCHK(n, snn::launch_advance(n->a.ctrl, left, n->stream));
+        }
+        HIPCHK(n, stdp_after(n, run));
+        todo -= run;
     }
     return SNN_OK;
 }
@@ -797,6 +909,7 @@ snn_status snn_step_forced(snn_net* n, const uint32_t* gids, size_t cnt)
     HIPCHK(n, enqueue_step(n, a, 0));
     HIPCHK(n, snn::launch_advance(a.ctrl, 1, n->stream));
     HIPCHK(n, snn::launch_set_flags(n->forced, n->forced_ids, (uint32_t)cnt, 0, n->stream));
+    HIPCHK(n, stdp_after(n, 1));
     HIPCHK(n, hipStreamSynchronize(n->stream));
     return SNN_OK;
 }
@@ -1061,6 +1174,7 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
     if (!out) return fail(n, SNN_E_INVAL, "null output");
     if (n->exact) return time_exact(n, n_ms, out);
+    if (n->stdp) return fail(n, SNN_E_STATE, "per-launch timing is not available for plastic networks");
     if (check_items(n) != hipSuccess) return fail(n, SNN_E_INVAL, "spike items exceed 32 bits");
     std::memset(out, 0, sizeof(*out));
     // The steps are the ones snn_step enqueues (same kernels, same order), each
@@ -1166,6 +1280,7 @@ snn_status snn_reset(snn_net* n)
     if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride, n->stream));
     if (a.sbin_fill) HIPCHK(n, hipMemsetAsync(a.sbin_fill, 0, 4 * (size_t)a.nsuper * snn::kFillStride, n->stream));
     HIPCHK(n, snn::launch_init(a, n->stream));
+    n->stdp_t = 0;   // a plastic network keeps the weights it has learned
     if (n->exact) {
         const snn::XArgs& x = n->x;
         HIPCHK(n, hipMemsetAsync(x.rend, 0, 8 * (size_t)n->N, n->stream));
@@ -1288,6 +1403,23 @@ snn_status snn_host_tables(const snn_grid_desc* g, const snn_syn_desc* s, uint32
         consts[1] = tb.dw;
         consts[2] = tb.kappa;
     }
+    return SNN_OK;
+}
+
+snn_status snn_host_stdp_tables(const snn_grid_desc* g, const snn_syn_desc* s, int32_t* kp, int32_t* km,
+                                uint32_t* win, int32_t* wmax_q)
+{
+    if (!g || !s) return fail(nullptr, SNN_E_INVAL, "null argument");
+    if (s->stdp != 1) return fail(nullptr, SNN_E_INVAL, "the description has no plasticity");
+    std::string why;
+    if (!valid_grid(g, why)) return fail(nullptr, SNN_E_INVAL, why);
+    snn::HostTables tb;
+    why = snn::build_tables(table_params(*g, *s), tb);
+    if (!why.empty()) return fail(nullptr, SNN_E_INVAL, why);
+    if (kp) std::memcpy(kp, tb.kp.data(), tb.kp.size() * 4);
+    if (km) std::memcpy(km, tb.km.data(), tb.km.size() * 4);
+    if (win) *win = tb.stdp_win;
+    if (wmax_q) *wmax_q = tb.wmax_q;
     return SNN_OK;
 }
 
@@ -1629,6 +1761,7 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
     if (st) return st;
     if (!g || !s || !slot || dur_ms == 0) return bfail(b, SNN_E_INVAL, "bad job arguments");
     if (s->solver != SNN_SOLVER_STEP) return bfail(b, SNN_E_INVAL, "batches run the step solver only");
+    if (s->stdp) return bfail(b, SNN_E_INVAL, "batches run networks without plasticity");
     *slot = -1;
     std::string why;
     if (!valid_grid(g, why)) return bfail(b, SNN_E_INVAL, why);
@@ -1792,6 +1925,23 @@ snn_status snn_batch_job_stats(snn_batch* b, int32_t slot, snn_stats_t* out)
     Ctrl hc{};
     BHIPCHK(b, hipMemcpy(&hc, J.net->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
     fill_stats(J.net, hc, out);
+    return SNN_OK;
+}
+
+snn_status snn_batch_read_state(snn_batch* b, int32_t slot, float* v, float* w, uint8_t* ref, int32_t* ring)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    if (slot < 0 || slot >= (int32_t)snn::kMaxJobs) return bfail(b, SNN_E_INVAL, "no job in this slot");
+    std::lock_guard<std::mutex> lk(b->mu);
+    const snn_batch::Job& J = b->jobs[slot];
+    if (J.state != snn_batch::kActive) return bfail(b, SNN_E_INVAL, "no running or finished job in this slot");
+    BHIPCHK(b, hipStreamSynchronize(b->stream));
+    const size_t N = J.net->N;
+    if (v) BHIPCHK(b, hipMemcpy(v, J.net->a.V, N * 4, hipMemcpyDeviceToHost));
+    if (w) BHIPCHK(b, hipMemcpy(w, J.net->a.W, N * 4, hipMemcpyDeviceToHost));
+    if (ref) BHIPCHK(b, hipMemcpy(ref, J.net->a.ref, N, hipMemcpyDeviceToHost));
+    if (ring) BHIPCHK(b, hipMemcpy(ring, J.net->a.ring, (size_t)snn::kRing * N * 4, hipMemcpyDeviceToHost));
     return SNN_OK;
 }
 

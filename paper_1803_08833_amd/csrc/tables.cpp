@@ -256,6 +256,29 @@ std::string build_tables(const TableParams& p, HostTables& out)
     else
         out.kappa = (h / p.tau_m) * std::exp(-h / p.tau_m);
     out.nref = (uint32_t)std::llround(p.t_ref / h);
+    // --- plasticity: one pair k steps apart, potentiating (spike not before
+    // the arrival) or depressing (arrival after the spike), rounded to 2^-16 mV
+    out.kp.clear();
+    out.km.clear();
+    out.stdp_win = 0;
+    out.wmax_q = 0;
+    if (p.stdp > 1) return "unknown plasticity mode";
+    if (p.stdp) {
+        if (!(p.a_plus >= 0.0 && p.a_minus >= 0.0)) return "plasticity amplitudes must be >= 0";
+        if (!(p.tau_plus > 0.0 && p.tau_minus > 0.0)) return "plasticity time constants must be > 0";
+        std::vector<int32_t> kp(256), km(256);
+        uint32_t win = 0;
+        for (uint32_t k = 0; k < 256; ++k) {
+            kp[k] = to_fixed(p.a_plus * std::exp(-(double)k / p.tau_plus));
+            km[k] = k == 0 ? 0 : to_fixed(p.a_minus * std::exp(-(double)k / p.tau_minus));
+            if (kp[k] != 0 || km[k] != 0) win = k + 1;
+        }
+        if (win >= 256) return "plasticity window longer than 255 steps";
+        out.kp.assign(kp.begin(), kp.begin() + win);
+        out.km.assign(km.begin(), km.begin() + win);
+        out.stdp_win = win;
+        out.wmax_q = to_fixed(p.w_max);
+    }
     return std::string();
 }
 

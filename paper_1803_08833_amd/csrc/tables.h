@@ -21,6 +21,10 @@ struct HostTables {
     double dm = 0.0, dw = 0.0, kappa = 0.0;  // one-step propagator constants
     uint32_t nref = 0;           // refractory steps
     int32_t jext_q = 0, winh_q = 0;
+    // spike-timing plasticity: change per pair at lag k (2^-16 mV), window, bound
+    std::vector<int32_t> kp, km; // [win]; km[0] = 0
+    uint32_t stdp_win = 0;
+    int32_t wmax_q = 0;
 };
 
 struct TableParams {
@@ -38,6 +42,8 @@ struct TableParams {
     uint32_t ext_poisson;
     double ext_n, ext_rate_hz, ext_w;
     double tau_m, tau_w, t_ref;
+    uint32_t stdp;               // 1: pair-based plasticity of excitatory synapses
+    double a_plus, a_minus, tau_plus, tau_minus, w_max;
 };
 
 // Returns an empty string on success, else the reason the description is invalid.

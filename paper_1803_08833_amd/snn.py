@@ -34,6 +34,7 @@ EXPORTS = [
     "snn_batch_create", "snn_batch_admit", "snn_batch_step", "snn_batch_poll", "snn_batch_read_spikes",
     "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
     "snn_set_allocator", "snn_step_forced_exact", "snn_read_spike_times", "snn_read_queue",
+    "snn_batch_read_state", "snn_host_stdp_tables", "snn_probe_atomics",
 ]
 
 # snn_set_allocator's function types: alloc(bytes, ctx) -> pointer, free(ptr, ctx)
@@ -64,6 +65,9 @@ class SynDesc(C.Structure):
         ("p_local", C.c_double), ("amp", C.c_double), ("p_cut", C.c_double),
         ("gen", C.c_uint32), ("delay_dist", C.c_uint32), ("delay_tau", C.c_double),
         ("solver", C.c_uint32), ("pad2_", C.c_uint32),
+        ("stdp", C.c_uint32), ("ltp_period", C.c_uint32),
+        ("a_plus", C.c_double), ("a_minus", C.c_double),
+        ("tau_plus", C.c_double), ("tau_minus", C.c_double), ("w_max", C.c_double),
     ]
 
 
@@ -124,6 +128,9 @@ def lib():
             "snn_batch_read_spikes": ([P, C.c_int32, P, SZ, C.POINTER(SZ)], C.c_int),
             "snn_batch_job_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
             "snn_batch_usage": ([P, C.POINTER(U64), C.POINTER(U32)], C.c_int),
+            "snn_batch_read_state": ([P, C.c_int32, P, P, P, P], C.c_int),
+            "snn_host_stdp_tables": ([C.POINTER(GridDesc), C.POINTER(SynDesc), P, P, P, P], C.c_int),
+            "snn_probe_atomics": ([U64, U64, P, C.POINTER(C.c_double)], C.c_int),
             "snn_batch_destroy": ([P], None),
             "snn_batch_last_error": ([P], C.c_char_p),
             "snn_destroy": ([P], None),
@@ -159,7 +166,8 @@ def syn_desc(net: dict) -> SynDesc:
     for k in ("kernel", "record", "range", "k_in", "d_min", "d_max", "w_exc", "w_exc_sd", "w_inh",
               "ext_mode", "ext_const_q", "ext_n", "ext_rate_hz", "ext_w"):
         setattr(s, k, net[k])
-    for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau", "solver"):   # absent: defaults
+    for k in ("preset", "p_local", "amp", "p_cut", "gen", "delay_dist", "delay_tau", "solver",
+              "stdp", "ltp_period", "a_plus", "a_minus", "tau_plus", "tau_minus", "w_max"):   # absent: defaults
         setattr(s, k, net.get(k, 0))
     return s
 
@@ -207,6 +215,28 @@ def current_stream_handle():
     if torch.cuda.is_available():
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
     return None
+
+
+def probe_atomics(n_targets: int, n_adds: int, stream=None) -> float:
+    """Scattered int32 device-scope atomic adds per second (snn_probe_atomics)."""
+    r = C.c_double(0.0)
+    st = lib().snn_probe_atomics(n_targets, n_adds, stream, C.byref(r))
+    if st != SNN_OK:
+        raise SNNError(st, "snn_probe_atomics failed")
+    return r.value
+
+
+def host_stdp_tables(net: dict) -> dict:
+    """The library's plasticity tables for a description with stdp = 1."""
+    g, s = grid_desc(net), syn_desc(net)
+    kp = np.zeros(256, dtype=np.int32)
+    km = np.zeros(256, dtype=np.int32)
+    win = C.c_uint32(0)
+    wmax = C.c_int32(0)
+    st = lib().snn_host_stdp_tables(C.byref(g), C.byref(s), _p(kp), _p(km), C.byref(win), C.byref(wmax))
+    if st != SNN_OK:
+        raise SNNError(st, lib().snn_last_error(None).decode())
+    return dict(kp=kp[: win.value].copy(), km=km[: win.value].copy(), win=win.value, wmax_q=wmax.value)
 
 
 def host_tables(net: dict) -> dict:
@@ -431,6 +461,18 @@ class Batch:
         self._check(lib().snn_batch_read_spikes(self.h, slot, _p(out), n.value, C.byref(n)))
         self._descs.pop(slot, None)
         return out[: n.value]
+
+    def read_state(self, slot: int, ring: bool = True):
+        """A running or finished job's (V, w, refractory steps, ring [32][N])."""
+        g, _ = self._descs[slot]
+        N = g.gx * g.gy * (g.n_exc + g.n_inh)
+        V = np.zeros(N, dtype=np.float32)
+        Wf = np.zeros(N, dtype=np.float32)
+        R = np.zeros(N, dtype=np.uint8)
+        rg = np.zeros((RING, N), dtype=np.int32) if ring else None
+        self._check(lib().snn_batch_read_state(self.h, slot, _p(V), _p(Wf), _p(R),
+                                               _p(rg) if ring else None))
+        return V, Wf, R, rg
 
     def usage(self):
         b = C.c_uint64(0)

@@ -48,6 +48,10 @@ SYNAPSE = dict(
     delay_dist=0, delay_tau=0.0,
     # neuron solver: charge summed per 1 ms step, or exact-time event-driven
     solver=0,
+    # spike-timing plasticity of excitatory synapses (off in every workload of
+    # the paper's measurements): pair amplitudes at zero lag (mV), window time
+    # constants (ms), weight bound (mV), steps between long-term applications
+    stdp=0, a_plus=0.004, a_minus=0.0042, tau_plus=20.0, tau_minus=20.0, w_max=0.8, ltp_period=1000,
 )
 SOLVER_STEP = 0
 SOLVER_EXACT = 1

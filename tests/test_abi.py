@@ -105,3 +105,24 @@ def test_invalid_descriptions_are_rejected_on_the_host(snn):
     for over in (dict(p_local=1.0), dict(amp=-0.1), dict(p_cut=0.0)):
         with pytest.raises(snn.SNNError):
             snn.host_tables(dict(paper, **over))
+
+
+@pytest.mark.parametrize("over", [dict(), dict(a_plus=0.01, a_minus=0.012, tau_plus=16.8, tau_minus=33.7),
+                                  dict(a_plus=0.0, a_minus=0.005, tau_minus=5.0, w_max=0.999969),
+                                  dict(a_plus=0.05, a_minus=0.0, tau_plus=25.0)])
+def test_library_stdp_tables_equal_oracle_tables(snn, oracle_mod, over):
+    net = dict(W.workload("grid4_gauss")["net"], stdp=1, **over)
+    lt = snn.host_stdp_tables(net)
+    ot = oracle_mod.stdp_tables(net)
+    assert lt["win"] == ot["win"] and lt["wmax_q"] == ot["wmax_q"]
+    np.testing.assert_array_equal(lt["kp"], ot["kp"])
+    np.testing.assert_array_equal(lt["km"], ot["km"])
+
+
+def test_invalid_plasticity_is_rejected_on_the_host(snn):
+    base = dict(W.workload("grid4_gauss")["net"], stdp=1)
+    for over in (dict(tau_plus=0.0), dict(a_minus=-0.001), dict(tau_plus=200.0, a_plus=0.5), dict(stdp=2)):
+        with pytest.raises(snn.SNNError):
+            snn.host_stdp_tables(dict(base, **over))
+    with pytest.raises(snn.SNNError):
+        snn.host_stdp_tables(dict(base, stdp=0))

@@ -15,13 +15,14 @@
 * Closed-form interspike intervals under constant drive; free-running
   population rate within 2 % of the oracle's.
 """
-import os
 import sys
 
 import numpy as np
 import pytest
 
 from paper_1803_08833_amd import workloads as W
+from parity_helpers import compare_state as _compare_state
+from parity_helpers import pending_charge as _pending_charge
 
 pytestmark = pytest.mark.gpu
 
@@ -92,20 +93,6 @@ def test_build_sampled_rows_full_size_exp(snn, oracle_mod):
             np.testing.assert_array_equal(rl, orl)
             np.testing.assert_array_equal(be, obe)
             np.testing.assert_array_equal(rc, orc)
-
-
-def _compare_state(net, gs, os_, t):
-    """Relative error 1e-5 of V against max(|V|, V_th - E) (the threshold
-    distance is the voltage scale near 0 mV), of w against max(|w|, alpha)."""
-    Vg, Wg, Rg = gs
-    Vo, Wo, Ro = os_
-    tolV = 1e-5 * np.maximum(np.abs(Vo), net["v_th"] - net["e_rest"])
-    dv = np.abs(Vg.astype(np.float64) - Vo)
-    assert np.all(dv <= tolV), f"step {t}: V error {dv.max()} at {dv.argmax()} (V={Vo[dv.argmax()]})"
-    tolw = 1e-5 * np.maximum(np.abs(Wo), net["alpha_w"])
-    dw = np.abs(Wg.astype(np.float64) - Wo)
-    assert np.all(dw <= tolw), f"step {t}: w error {dw.max()}"
-    np.testing.assert_array_equal(Rg.astype(np.int32), Ro)
 
 
 def test_lockstep_small(snn, oracle_mod):
@@ -182,24 +169,6 @@ def test_step0_full_size_exp(snn, oracle_mod):
             want = oracle_mod.col_input(net, int(j), pres)
             got = ring[net["d_min"]:net["d_max"] + 1, j].astype(np.int64)
             np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
-
-
-def _pending_charge(oracle_mod, net, raster, T, j):
-    """Charge queued for target j after steps 0..T-1, by arrival time T ..
-    T - 1 + d_max: the oracle's per-delay column sums of each recent step's
-    spike set, placed at step + delay."""
-    dmin, dmax = net["d_min"], net["d_max"]
-    out = np.zeros(dmax, dtype=np.int64)          # arrival T + i, i < d_max
-    for s in range(max(0, T - dmax), T):
-        pres = np.sort(raster[raster[:, 0] == s, 1]).astype(np.uint32)
-        if pres.size == 0:
-            continue
-        col = oracle_mod.col_input(net, int(j), pres)   # delays d_min .. d_max
-        for d in range(dmin, dmax + 1):
-            a = s + d - T
-            if 0 <= a < dmax:
-                out[a] += col[d - dmin]
-    return out
 
 
 def test_full_size_burst_in_flight_bench_schedule(snn, oracle_mod):
@@ -413,7 +382,7 @@ def test_two_level_lockstep_code8(snn, oracle_mod):
         assert g.stats()["rec_events"] == o.stats()["rec_events"]
 
 
-def test_two_level_matches_direct_over_super_tiles(snn):
+def test_two_level_matches_direct_over_super_tiles(snn, oracle_mod):
     """A 12x12 grid (178,560 neurons: three super tiles, the last partial):
     two-level binned delivery, fused and unfused, with ample and with tiny
     bins (fallback), gives the direct schedule's ring and raster."""
@@ -441,16 +410,28 @@ def test_two_level_matches_direct_over_super_tiles(snn):
     say("max spikes per step:", int(per_step.max()), "overflow events:", out[3][2]["bin_overflow"])
     if per_step.max() * 300 > 3 * 65536:   # some step overfilled a super tile's 65,536-event bin
         assert out[3][2]["bin_overflow"] > 0
+    # against the oracle: charge in flight at step 150 for targets in each of
+    # the three super tiles (ample bins, and tiny bins that overflow)
+    rng = np.random.default_rng(21)
+    picks = [0, 65535, 65536, 131071, 131072, 178559]
+    picks += [int(x) for x in rng.integers(0, 65536, 2)] + [int(x) for x in rng.integers(65536, 131072, 2)]
+    picks += [int(x) for x in rng.integers(131072, 178560, 2)]
+    for j in picks:
+        want = _pending_charge(oracle_mod, net, sp, 150, j)
+        for ring, _, _ in (out[2], out[3]):
+            got = np.array([ring[(150 + a) % ring.shape[0], j] for a in range(net["d_max"])], dtype=np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
 
 
-@pytest.mark.skipif(os.environ.get("SNN_FULL_SCALE") != "1",
-                    reason="full-scale 96x96 run (about 190 GB of HBM, 1-2 minutes): set SNN_FULL_SCALE=1")
 def test_full_scale_96x96_code8(snn, oracle_mod):
     """The 96x96 exponential grid with 8-bit codes (11.4 M neurons, 29.7 G
     synapses) at full size, in the configuration bench.py times (two-level
-    binned delivery): sampled rows bit-exact, step 0 (about 3 % of the neurons
-    fire from their initial state and drive) with every neuron's state and the
-    charge queued for sampled targets against the oracle."""
+    binned delivery, graph-replayed steps): sampled rows bit-exact; step 0
+    (about 3 % of the neurons fire from their initial state and drive) with
+    every neuron's state and the charge queued for sampled targets against the
+    oracle; then free-running to step 40, the charge in flight for sampled
+    targets in every super tile equals the oracle's column sums over the GPU's
+    own spike sets of the last d_max steps."""
     wl = W.workload("grid96_exp_code8")
     net = wl["net"]
     say("case: grid96_exp_code8 full-size build (about one minute)")
@@ -459,7 +440,7 @@ def test_full_scale_96x96_code8(snn, oracle_mod):
     o.step(1)
     Vo, Wo, Ro = o.state()
     s0 = o.spikes()[:, 1]
-    with snn.Net(net) as g:
+    with snn.Net(net, hist_cap=1 << 28) as g:     # room for the start-up burst (~1 M spikes per step)
         g.build_synapses()
         st = g.stats()
         say("built:", st["nnz"], "synapses, mode", st["deliver_mode"])
@@ -490,3 +471,24 @@ def test_full_scale_96x96_code8(snn, oracle_mod):
             want = oracle_mod.col_input(net, int(j), pres)
             got = ring[net["d_min"]:net["d_max"] + 1, j].astype(np.int64)
             np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
+        del ring
+        # free run in the bench's schedule: graphs of 13 steps and a remainder
+        g.set_option(snn.OPT_GRAPH_CHUNK, 13)
+        T = 40
+        g.step(T - 1)
+        raster = g.read_spikes()
+        counts = np.bincount(raster[:, 0].astype(np.int64), minlength=T)
+        st = g.stats()
+        say(f"steps 0..{T - 1}: spikes per step min {counts.min()} max {counts.max()}; "
+            f"events {st['rec_events']}, overflow {st['bin_overflow']}")
+        assert st["t"] == T and counts.size == T
+        ring = g.read_ring()
+        # two targets in each of the 175 super tiles' first, middle and last thirds
+        nsup = (g.N + 65535) // 65536
+        picks = [int(x) for x in rng.integers(0, g.N, 12)]
+        picks += [0, g.N - 1, 65535, 65536, (nsup - 1) * 65536]
+        for j in picks:
+            want = _pending_charge(oracle_mod, net, raster, T, j)
+            got = np.array([ring[(T + a) % ring.shape[0], j] for a in range(net["d_max"])], dtype=np.int64)
+            np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
+        say(f"in-flight charge of {len(picks)} targets bit-exact at step {T}")

@@ -109,21 +109,38 @@ def test_single_job_batch_equals_alone(snn):
 
 
 def test_admission_by_budget(snn):
+    """A job that could never fit (footprint above the whole budget, or more
+    neurons than the batch's capacity) is refused for good (SNN_E_INVAL); one
+    that does not fit beside the running jobs is refused for now (None) and
+    admitted once they have finished."""
     jobs = mix(3, seed=5)
-    with snn.Batch(1 << 20, 1 << 20) as b:   # 1 MiB: nothing fits
-        assert b.admit(jobs[0]["net"], 50) is None
+    with snn.Batch(1 << 20, 1 << 20) as b:   # 1 MiB: nothing can ever fit
+        with pytest.raises(snn.SNNError, match="budget"):
+            b.admit(jobs[0]["net"], 50)
     with snn.Batch(6 << 30, 4096) as b:      # neuron capacity of four 1024-neuron blocks
         big = W.make(2, 2, W.EXP, 3.0, 300, 1)   # 4960 neurons: five blocks
-        assert b.admit(big, 50) is None
-        small = W.make(1, 1, W.EXP, 3.0, 300, 2)
+        with pytest.raises(snn.SNNError, match="capacity"):
+            b.admit(big, 50)
+        small = W.make(1, 1, W.EXP, 3.0, 300, 2)   # 1240 neurons: two blocks
         s = b.admit(small, 20)
         assert s is not None
+        s2 = b.admit(dict(small, seed=3), 20)      # two blocks more: still fits
+        assert s2 is not None
+        assert b.admit(dict(small, seed=4), 20) is None   # not beside the two running jobs
         used, n = b.usage()
-        assert n == 1 and used > 0
+        assert n == 2 and used > 0
+        done = []
+        while len(done) < 2:
+            b.step(10)
+            done += b.poll()
+        b.read_spikes(s)
+        b.read_spikes(s2)
+        assert b.usage() == (0, 0)
+        s3 = b.admit(dict(small, seed=4), 20)       # room again
+        assert s3 is not None
         while not b.poll():
             b.step(10)
-        b.read_spikes(s)
-        assert b.usage() == (0, 0)
+        b.read_spikes(s3)
 
 
 def test_serving_loop_matches_plain(snn):

@@ -95,3 +95,20 @@ def test_forced_step_matches_free_run(oracle_mod):
     for x, y in zip(a.state(), b.state()):
         np.testing.assert_array_equal(x, y)
     np.testing.assert_array_equal(a.ring(), b.ring())
+
+
+def test_col_pending_is_the_ring_in_flight(oracle_mod):
+    """col_pending (the charge in flight for one target, regenerated from the
+    pair draws of a raster's recent spikers) equals what the oracle's own
+    delay ring holds after the same steps, for every target and every arrival
+    step ahead; the ring is pinned to the dense brute force above."""
+    net = W.make(2, 1, W.EXP, 2.0, 120, 23, n_exc=160, n_inh=40, ext_rate_hz=4.0)
+    o = oracle_mod.Net(net).build()
+    for T in (37, 90):
+        o.step(T - o.stats()["t"])
+        raster = o.spikes()
+        assert (raster[:, 0] >= T - net["d_max"]).sum() > 50
+        ring = o.ring()
+        for j in range(0, o.N, 23):
+            want = np.array([ring[(T + a) % oracle_mod.RING, j] for a in range(net["d_max"])], dtype=np.int64)
+            np.testing.assert_array_equal(oracle_mod.col_pending(net, j, raster, T), want, err_msg=f"target {j}")

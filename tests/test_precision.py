@@ -1,47 +1,55 @@
 """Precision statement of the compressed synapse records (8-bit weight codes),
-made entirely with the FP64 oracle: the same network is simulated with
+made entirely with the FP64 oracle at the size of the 4x4 parity workload
+(19,840 neurons, Gaussian sigma 1, 1100 synapses per neuron, 3 Hz drive,
+1 s), over several seeds.  Each seed's network is simulated with
   (a) the 255-bin codebook weights (what the 8-bit records deliver exactly),
   (b) the 65536-bin weight table (F32 records),
   (c) the uncompressed FP64 weights mu + sd * Phi^-1((u + 1/2) / 2^32) of the
       same draws.
-It reports the firing-rate differences and, with (c) forced onto (a)'s spike
-raster, the membrane-potential differences caused by weight quantisation
-alone.  The figures are stated, not bounded; the loose assertions only catch
-a broken comparison.
+Same connectivity, delays and drive in all three; only the weight values
+differ.  Firing rates: at these parameters one trajectory's rate moves by
+tens of per cent under any perturbation (the start of each ~55 Hz up-state
+shifts), as (b) against (c) shows with weights that differ by less than
+2^-16 mV.  So the rate error of the codes is stated as the mean and spread
+of the paired per-seed differences next to the table's and next to the
+seed-to-seed spread of the rate itself, and the assertion is statistical:
+the mean paired difference is within 2 % plus three standard errors of zero.
+Membrane potential: with (c) forced onto (a)'s raster the difference is the
+quantisation alone, deterministic and bounded.
 """
 import json
-import os
+import multiprocessing as mp
 
 import numpy as np
 import pytest
 
 from paper_1803_08833_amd import workloads as W
 
-STEPS = 600
+STEPS = 1000
+SEEDS = (101, 102, 103, 104)
 
 
-def _net(record):
-    return W.make(2, 1, W.EXP, 2.0, 600, 41, record=record, ext_rate_hz=2.5)
+def _net(seed, record):
+    return W.make(4, 4, W.GAUSS, 1.0, 1100, seed, record=record, ext_rate_hz=3.0)
 
 
-def _run(oracle_mod, net, fp64):
-    o = oracle_mod.Net(net, fp64_weights=fp64).build()
+def _rate(args):
+    import oracle
+
+    seed, variant = args
+    rec = W.REC_F32 if variant == "f32" else W.REC_CODE8
+    o = oracle.Net(_net(seed, rec), fp64_weights=(variant == "fp64")).build()
     o.step(STEPS)
-    return o
+    return seed, variant, o.stats()["spikes"] / o.N / (STEPS * 1e-3)
 
 
-@pytest.mark.slow
-def test_code8_precision_statement(oracle_mod):
-    code = _run(oracle_mod, _net(W.REC_CODE8), False)
-    f32 = _run(oracle_mod, _net(W.REC_F32), False)
-    exact = _run(oracle_mod, _net(W.REC_CODE8), True)
-    N = code.N
-    r = {name: o.stats()["spikes"] / N / (STEPS * 1e-3) for name, o in
-         (("code8", code), ("f32", f32), ("fp64", exact))}
-    # membrane error from weight quantisation alone: the uncompressed network
-    # is forced onto the 8-bit-code network's spike raster
-    forced = oracle_mod.Net(_net(W.REC_CODE8), fp64_weights=True).build()
-    ref = oracle_mod.Net(_net(W.REC_CODE8), fp64_weights=False).build()
+def _vm_error(seed):
+    """(max, rms) of |V_fp64 - V_code8| over live neurons, the FP64 network
+    forced onto the code network's raster."""
+    import oracle
+
+    ref = oracle.Net(_net(seed, W.REC_CODE8), fp64_weights=False).build()
+    forced = oracle.Net(_net(seed, W.REC_CODE8), fp64_weights=True).build()
     dv_max, dv_sq, cnt = 0.0, 0.0, 0
     for t in range(STEPS):
         ref.step(1)
@@ -52,16 +60,39 @@ def test_code8_precision_statement(oracle_mod):
         live = (ra == 0) & (rb == 0)
         d = np.abs(Va - Vb)[live]
         dv_max = max(dv_max, float(d.max(initial=0.0)))
-        dv_sq += float((d**2).sum())
+        dv_sq += float((d ** 2).sum())
         cnt += int(d.size)
+    return dv_max, (dv_sq / max(cnt, 1)) ** 0.5
+
+
+@pytest.mark.slow
+def test_code8_precision_statement(oracle_mod):
+    jobs = [(s, v) for s in SEEDS for v in ("fp64", "code8", "f32")]
+    with mp.get_context("fork").Pool(min(8, len(jobs) + 1)) as pool:
+        vm = pool.apply_async(_vm_error, (SEEDS[0],))
+        res = pool.map(_rate, jobs)
+        dv_max, dv_rms = vm.get()
+    r = {}
+    for s, v, rate in res:
+        r.setdefault(v, {})[s] = rate
+    fp = np.array([r["fp64"][s] for s in SEEDS])
+    c8 = np.array([r["code8"][s] for s in SEEDS])
+    f32 = np.array([r["f32"][s] for s in SEEDS])
+    d8, d32 = (c8 - fp) / fp, (f32 - fp) / fp
+    n = len(SEEDS)
     stmt = dict(
-        network="2x1 modules of 992+248 neurons, exponential lambda 2, k_in 600, 2.5 Hz drive, 600 ms",
-        rate_hz=r,
-        rate_rel_err_code8_vs_fp64=(r["code8"] - r["fp64"]) / r["fp64"],
-        rate_rel_err_f32_vs_fp64=(r["f32"] - r["fp64"]) / r["fp64"],
-        vm_err_code8_vs_fp64_mV=dict(max=dv_max, rms=(dv_sq / max(cnt, 1)) ** 0.5),
+        network="4x4 modules of 992+248 neurons, Gaussian sigma 1, k_in 1100, 3 Hz drive, 1 s; seeds "
+                + ",".join(map(str, SEEDS)),
+        rate_fp64_hz=dict(mean=float(fp.mean()), sd_between_seeds=float(fp.std(ddof=1))),
+        rate_rel_diff_code8_vs_fp64=dict(mean=float(d8.mean()), sd=float(d8.std(ddof=1)),
+                                         se=float(d8.std(ddof=1) / np.sqrt(n))),
+        rate_rel_diff_table_vs_fp64=dict(mean=float(d32.mean()), sd=float(d32.std(ddof=1))),
+        vm_err_code8_vs_fp64_mV=dict(seed=SEEDS[0], max=dv_max, rms=dv_rms),
     )
     print("PRECISION", json.dumps(stmt), flush=True)
-    assert r["fp64"] > 0
-    assert abs(stmt["rate_rel_err_code8_vs_fp64"]) < 0.5
-    assert stmt["vm_err_code8_vs_fp64_mV"]["rms"] < 1.0
+    assert fp.min() > 0
+    # no codebook bias beyond the 2 % tolerance that these seeds can resolve
+    assert abs(d8.mean()) <= 0.02 + 3.0 * d8.std(ddof=1) / np.sqrt(n)
+    # the quantisation alone moves the membrane by far less than the 5 mV
+    # between reset and threshold
+    assert dv_rms < 0.05 and dv_max < 1.0
