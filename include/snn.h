@@ -256,6 +256,20 @@ snn_status snn_step(snn_net* net, uint32_t n_ms);
  * solver only (SNN_E_STATE under the exact solver). */
 snn_status snn_step_forced(snn_net* net, const uint32_t* gids, size_t n);
 
+/* snn_step_forced without device allocation, for callers that cannot
+ * allocate device memory (code running under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result and
+ * synchronisation as snn_step_forced; the forced ids and per-neuron forced
+ * flags are staged in a library-owned static device array (20 MiB per device,
+ * held until the process ends) instead of the network's buffers, so the call
+ * allocates nothing.  Limits: at most 2^20 ids per call and networks of at
+ * most 2^24 neurons (SNN_E_INVAL beyond them, before any device work).  The
+ * array is shared by every call on one device and keeps the last call's
+ * contents (each call clears its own range first): calls that overlap on one
+ * device, from several threads or streams, race and must not be issued.
+ * Call with the network's device current, as every call. */
+snn_status snn_step_forced_noalloc(snn_net* net, const uint32_t* gids, size_t n);
+
 /* Exact solver, lock-step mode (Sec. II.C): neuron gids[k] spikes this step
  * at offset frac[k] (2^-32 ms) -- at its input of that instant, if it is not
  * refractory then -- and no other neuron spikes; each neuron's own threshold

@@ -914,6 +914,78 @@ snn_status snn_step_forced(snn_net* n, const uint32_t* gids, size_t cnt)
     return SNN_OK;
 }
 
+}  // extern "C"
+
+// Lock-step without allocation.  snn_step_forced_noalloc stages the forced
+// spike ids and the per-neuron forced flags in this file-scope device array
+// instead of the network's buffers: the flags of up to kNoAllocMaxNeurons
+// neurons (one byte each), then up to kNoAllocMaxIds staged ids.  Each device
+// the library runs on holds its own copy until the process ends; every call
+// on a device shares it.
+constexpr size_t kNoAllocMaxNeurons = size_t(1) << 24;
+constexpr size_t kNoAllocMaxIds = size_t(1) << 20;
+static __device__ __align__(256) uint8_t scratch[kNoAllocMaxNeurons + 4 * kNoAllocMaxIds];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_ptr[kMaxDevices] = {};   // device address of `scratch`, per device
+
+// Device address of this device's copy of `scratch`, looked up once per
+// device with that device current.  In host code the array's name is only a
+// stand-in: kernels and copies get this address.
+hipError_t scratch_for_current_device(uint8_t** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<uint8_t*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+snn_status snn_step_forced_noalloc(snn_net* n, const uint32_t* gids, size_t cnt)
+{
+    snn_status st = check_usable(n);
+    if (st) return st;
+    if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before stepping");
+    if (n->exact) return fail(n, SNN_E_STATE, "the exact solver takes spike times: use snn_step_forced_exact");
+    if (cnt > kNoAllocMaxIds)
+        return fail(n, SNN_E_INVAL, "forced spike set larger than the allocation-free maximum of 2^20 ids");
+    if (n->N > kNoAllocMaxNeurons)
+        return fail(n, SNN_E_INVAL, "network larger than the allocation-free maximum of 2^24 neurons");
+    if (cnt > n->N || (cnt && !gids)) return fail(n, SNN_E_INVAL, "bad forced spike set");
+    for (size_t i = 0; i < cnt; ++i)
+        if (gids[i] >= n->N) return fail(n, SNN_E_INVAL, "forced spike id out of range");
+    uint8_t* scr = nullptr;
+    HIPCHK(n, scratch_for_current_device(&scr));
+    uint8_t* flags = scr;
+    uint32_t* ids = reinterpret_cast<uint32_t*>(scr + kNoAllocMaxNeurons);
+    // the array keeps the last call's flags (any network's): clear this one's range
+    HIPCHK(n, snn::launch_fill_u8(flags, n->N, 0, n->stream));
+    if (cnt) HIPCHK(n, hipMemcpyAsync(ids, gids, cnt * 4, hipMemcpyHostToDevice, n->stream));
+    HIPCHK(n, snn::launch_set_flags(flags, ids, (uint32_t)cnt, 1, n->stream));
+    StepArgs a = n->a;
+    a.forced = flags;
+    HIPCHK(n, enqueue_step(n, a, 0));
+    HIPCHK(n, snn::launch_advance(a.ctrl, 1, n->stream));
+    HIPCHK(n, stdp_after(n, 1));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    return SNN_OK;
+}
+
 static snn_status read_history(snn_net* n, uint64_t t0, uint64_t t1, snn_spike* buf, uint32_t* frac, size_t cap,
                         size_t* n_out)
 {

@@ -1767,6 +1767,11 @@ __global__ __launch_bounds__(256) void k_set_flags(uint8_t* flags, const uint32_
     if (i < n) flags[ids[i]] = v;
 }
 
+__global__ __launch_bounds__(256) void k_fill_u8(uint8_t* p, uint64_t n, uint8_t v)
+{
+    for (uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256u) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -1938,6 +1943,14 @@ hipError_t launch_batch_advance(const JobDesc* jobs, uint32_t n, hipStream_t s)
 hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, c, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(k_fill_u8, dim3((uint32_t)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, p, n, v);
     return hipGetLastError();
 }
 

@@ -166,6 +166,8 @@ hipError_t launch_batch_advance(const JobDesc* jobs, uint32_t n, hipStream_t s);
 hipError_t launch_advance(Ctrl* c, uint32_t n, hipStream_t s);
 hipError_t launch_set_flags(uint8_t* flags, const uint32_t* ids, uint32_t n, uint8_t v,
                             hipStream_t s);
+// p[0 .. n) = v (a kernel, so that it may be recorded in a captured graph)
+hipError_t launch_fill_u8(uint8_t* p, uint64_t n, uint8_t v, hipStream_t s);
 uint32_t scan_tiles(uint32_t N);
 
 }  // namespace snn

@@ -34,7 +34,7 @@ EXPORTS = [
     "snn_batch_create", "snn_batch_admit", "snn_batch_step", "snn_batch_poll", "snn_batch_read_spikes",
     "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
     "snn_set_allocator", "snn_step_forced_exact", "snn_read_spike_times", "snn_read_queue",
-    "snn_batch_read_state", "snn_host_stdp_tables", "snn_probe_atomics",
+    "snn_batch_read_state", "snn_step_forced_noalloc", "snn_host_stdp_tables", "snn_probe_atomics",
 ]
 
 # snn_set_allocator's function types: alloc(bytes, ctx) -> pointer, free(ptr, ctx)
@@ -112,6 +112,7 @@ def lib():
             "snn_build_synapses": ([P, C.POINTER(SynDesc)], C.c_int),
             "snn_step": ([P, U32], C.c_int),
             "snn_step_forced": ([P, P, SZ], C.c_int),
+            "snn_step_forced_noalloc": ([P, P, SZ], C.c_int),
             "snn_read_spikes": ([P, U64, U64, P, SZ, C.POINTER(SZ)], C.c_int),
             "snn_read_state": ([P, P, P, P], C.c_int),
             "snn_read_ring": ([P, P], C.c_int),
@@ -302,6 +303,11 @@ class Net:
     def step_forced(self, gids):
         g = np.ascontiguousarray(gids, dtype=np.uint32)
         self._check(lib().snn_step_forced(self.h, _p(g), g.size))
+
+    def step_forced_noalloc(self, gids):
+        """step_forced staged in the library's static device array (no device allocation)."""
+        g = np.ascontiguousarray(gids, dtype=np.uint32)
+        self._check(lib().snn_step_forced_noalloc(self.h, _p(g), g.size))
 
     def read_spikes(self, t0=0, t1=2**63):
         n = C.c_size_t(0)
