@@ -846,7 +846,7 @@ __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint3
 
 constexpr uint32_t kScatterThreads = 1024;
 constexpr uint32_t kScatterWaves = kScatterThreads / 64;
-constexpr uint32_t kSegPerWave = kChunkItems / kScatterWaves;   // 7 row segments per wave
+constexpr uint32_t kSegPerWave = kChunkItems / kScatterWaves;   // 5 row segments per wave
 // Lanes that write one bin's run in the last scatter phase: a chunk puts a few
 // dozen events in a typical bin, and the phase is bound by the latency of its
 // per-bin steps, so four bins go at once per wave.
@@ -1112,7 +1112,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
 // those tiles' bins, stages the events sorted by tile with the tile code
 // (target & 1023 | bucket << 10 | code << 15) and writes the runs.  Events
 // beyond a tile bin's capacity take the direct atomic path.
-constexpr uint32_t kSubPerThread = kStage / kScatterThreads;   // 28 codes per thread
+constexpr uint32_t kSubPerThread = kStage / kScatterThreads;   // 20 codes per thread
 __global__ __launch_bounds__(kScatterThreads) void k_sub(StepArgs a, uint32_t k)
 {
     constexpr uint32_t NSUB = 1u << (kSuperBits - kTileBits);   // tiles per super tile

@@ -19,7 +19,7 @@ constexpr uint32_t kTileBits = 10;
 constexpr uint32_t kTile = 1u << kTileBits;
 static_assert(kTile == kNeuronsPerBlock, "a delivery tile is an update block");
 constexpr uint32_t kMaxTiles = 2048;          // binned delivery needs N <= 2M neurons
-constexpr uint32_t kChunkItems = 112;       // row segments (256 records) per scatter chunk: 16 waves x 7
+constexpr uint32_t kChunkItems = 80;        // row segments (256 records) per scatter chunk: 16 waves x 5
 constexpr uint32_t kStage = kChunkItems * 256;
 constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for the inhibitory weight
 // Bin fill counters sit one per 128-byte line: every scatter workgroup reserves

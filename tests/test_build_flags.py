@@ -1,6 +1,7 @@
-"""The library's device code, as build.py compiles it, contains no packed FP32
-VALU instructions (the build turns that target feature off), and the flag
-does what it says: the same probe kernel compiled without it does get them."""
+"""Build checks of the library's device code as build.py compiles it: no
+packed FP32 VALU instructions (the build turns that target feature off, and
+the flag does what it says: the same probe kernel compiled without it does
+get them), and no kernel spills vector registers to scratch memory."""
 import os
 import re
 import subprocess
@@ -51,3 +52,21 @@ def test_library_device_code_has_no_packed_fp32(hipcc, tmp_path, src):
     asm = _device_asm(os.path.join(B.CSRC, src), str(tmp_path / (src + ".s")), B.DEVICE + B.COMMON)
     found = sorted(set(m.group(0) for m in PACKED.finditer(asm)))
     assert not found, f"{src}: {found}"
+
+
+@pytest.mark.parametrize("src", [s for s in B.SOURCES if s.endswith(".hip")])
+def test_no_vgpr_spills(hipcc, tmp_path, src):
+    """Every kernel keeps its vector registers within the hardware budget of
+    its launch shape: no VGPR spills to scratch memory (as build.py compiles)."""
+    cmd = [B.HIPCC, "--cuda-device-only", "-c", *B.DEVICE, *B.COMMON, "-Rpass-analysis=kernel-resource-usage",
+           os.path.join(B.CSRC, src), "-o", str(tmp_path / "k.o")]
+    out = subprocess.run(cmd, check=True, capture_output=True, text=True).stderr
+    found = {}
+    for block in out.split("Function Name: ")[1:]:
+        name = block.split()[0]
+        m = re.search(r"VGPRs Spill: (\d+)", block)
+        assert m, f"{src}: no spill figure for {name}"
+        found[name] = int(m.group(1))
+    assert found, f"{src}: no kernel resource report"
+    spilled = {k: v for k, v in found.items() if v}
+    assert not spilled, f"{src}: VGPR spills {spilled}"
