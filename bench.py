@@ -39,8 +39,8 @@ BYTES_EXACT_PER_NEURON_STEP = 52
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10, help="timed seconds of biological time")
-    p.add_argument("--warmup", type=int, default=1, help="untimed seconds of biological time")
+    p.add_argument("--steps", type=int, default=20, help="timed seconds of biological time")
+    p.add_argument("--warmup", type=int, default=5, help="untimed seconds of biological time")
     p.add_argument("--workload", default="grid24_exp")
     p.add_argument("--ext-rate", type=float, default=None, help="override external Poisson rate (Hz)")
     p.add_argument("--no-cpu-baseline", action="store_true")
@@ -79,13 +79,15 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(args, steps):
-    """HBM bytes per step (the two step kernels) from the committed rocprofv3
-    counter summary of this workload: FETCH_SIZE and WRITE_SIZE summed over the
-    replayed steps' dispatches, each divided by the same counter's reading per
-    byte of a plain device copy of known size, per step.  None when there is
-    no summary for this exact workload, or when it was taken on other kernel
-    sources than the ones built now."""
+def counters_from_profile(args):
+    """Per-step counter figures of the step kernels from the committed
+    rocprofv3 summary of this workload (profiles/<workload>_hbm_counters.json):
+    HBM bytes (FETCH_SIZE and WRITE_SIZE summed over the replayed steps'
+    dispatches, each divided by the same counter's reading per byte of a plain
+    device copy of known size) and atomic requests at the L2 (TCC_ATOMIC), per
+    step.  None when there is no summary for this exact window (workload,
+    drive, steps, warm-up) or it was taken on other kernel sources than the
+    ones built now."""
     path = os.path.join(ROOT, "profiles", f"{args.workload}_hbm_counters.json")
     if not os.path.exists(path):
         return None
@@ -94,7 +96,7 @@ def traffic_from_profile(args, steps):
     same = (prof.get("kernel_source_sha256_16") == kernel_source_hash()
             and prof.get("ext_rate_hz") == workload(args)["net"]["ext_rate_hz"]
             and prof.get("steps") == args.steps and prof.get("warmup") == args.warmup)
-    return prof.get("hbm_bytes_per_step") if same else None
+    return prof if same else None
 
 
 def cpu_baseline(net, spikes_per_step, seconds_budget=12.0):
@@ -245,10 +247,19 @@ def main():
         ms = kt["update_ms"] + kt["compact_ms"] + kt["deliver_ms"]
     step_bytes = ev_per_step * bpe + N * bpn
     achieved = step_bytes / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+    prof = None if exact else counters_from_profile(args)
+    # scattered int32 atomic adds per second on this GPU (the unit of direct
+    # delivery), from the library's own probe: the peak atomics are read against
+    atomic_peak = snn.probe_atomics(1 << 26, 1 << 28, stream)
+    atomics = {"probe_peak_per_s": atomic_peak,
+               "requests_per_step": prof.get("atomic_requests_per_step") if prof else None,
+               "achieved_per_s": (prof["atomic_requests_per_step"] / (ms * 1e-3)
+                                  if prof and prof.get("atomic_requests_per_step") and ms > 0 else None)}
     roofline = {"bound": "hbm", "kernel": name,
                 "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if exact else traffic_from_profile(args, steps_k),
+                "traffic": prof.get("hbm_bytes_per_step") if prof else None,
+                "atomics": atomics,
                 "bytes_per_launch": round(step_bytes, 1), "avg_launch_ms": round(ms, 6),
                 "events_per_launch": round(ev_per_step, 1),
                 "bytes_per_event": bpe, "bytes_per_neuron_step": bpn,

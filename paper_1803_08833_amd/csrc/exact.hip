@@ -414,29 +414,30 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
     x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
 }
 
-// Busy workgroups: all of the workgroup's queued inputs (up to kXBusyCap) are
-// read into LDS in one coalesced pass; each neuron heap-sorts its own slice
-// there, holds its external inputs sorted in its LDS slots, and merges the
-// two.  A workgroup with more inputs sorts its slices in global memory.
+// Busy workgroups: the workgroup's queued inputs are read into LDS in
+// windows of up to kXBusyCap entries, coalesced; a neuron whose whole slice
+// lies in the window heap-sorts it there, holds its external inputs sorted in
+// its LDS slots, merges the two and integrates.  The next window starts at
+// the first neuron not yet done, so every pass finishes at least that neuron;
+// only a slice longer than a whole window is sorted where it lies, in global
+// memory.
 __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
 {
-    __shared__ uint2 in_s[kXBusyCap];            // the workgroup's inputs, by target
+    __shared__ uint2 in_s[kXBusyCap];            // one window of the workgroup's inputs, by target
     __shared__ uint2 ev_s[kXLocal * kXBlock];    // external inputs [input][thread]
     __shared__ uint32_t pois_s[kMaxPois];
     __shared__ uint32_t wcnt[kXBlock / 64];
     __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
+    __shared__ unsigned long long wlo[kXBlock / 64];
     if (!x_block_busy(a)) return;   // (uniform) the workgroup is k_x_update's
     const uint32_t t = a.ctrl->t0;
-    const uint32_t tid = threadIdx.x;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
     const uint32_t j = blockIdx.x * kXBlock + tid;
     const bool live = j < a.N;
     const uint32_t first = blockIdx.x * kXBlock;
     uint64_t base = a.qoff[first];
     base = base < a.qcap ? base : a.qcap;
-    const uint64_t T = x_block_inputs(a);
-    const bool in_lds = T <= kXBusyCap;
-    if (in_lds)
-        for (uint32_t i = tid; i < (uint32_t)T; i += kXBlock) in_s[i] = a.qsorted[base + i];
+    const uint64_t end = base + x_block_inputs(a);
     uint64_t k0 = 0, k1 = 0, re0 = 0;
     float V0 = 0.f, W0 = 0.f;
     if (live) {
@@ -450,34 +451,60 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
     __syncthreads();
     const uint64_t t0 = (uint64_t)t << 32, t1 = t0 + (1ull << 32);
     uint32_t spiked = 0, next = 0, dis = 0;
+    k1 = k1 < a.qcap ? k1 : a.qcap;
+    k0 = k0 < k1 ? k0 : k1;
+    k0 = k0 > base ? k0 : base;
+    k1 = k1 > k0 ? k1 : k0;
+    const uint32_t nrec = (uint32_t)(k1 - k0);
     if (live) {
-        k1 = k1 < a.qcap ? k1 : a.qcap;
-        k0 = k0 < k1 ? k0 : k1;
-        k0 = k0 > base ? k0 : base;
-        k1 = k1 > k0 ? k1 : k0;
-        const uint32_t nrec = (uint32_t)(k1 - k0);
         if (a.ext_const) {
             next = 1;
         } else {
             const uint32_t u = word(x_philox(j >> 2, t, kStreamExt, 0u, a.key0, a.key1), j & 3u);
             for (uint32_t i = 0; i < a.npois; ++i) next += pois_s[i] <= u ? 1u : 0u;
         }
-        const int32_t jext = a.ext_const ? a.ext_const_q : a.jext_q;
-        XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
-        const bool exc = (j % a.M) < a.n_exc;
-        const bool fj = a.forced ? a.forced[j] != 0 : false;
-        const uint32_t ff = a.forced ? a.forced_f[j] : 0u;
-        const XIn in{j, t, next, jext, exc, fj, ff, t0};
-        uint2* seg = in_lds ? in_s + (k0 - base) : a.qsorted + k0;
-        if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid);
-        else x_take_selected(a, s, in, seg, nrec);
-        x_advance(a, s, t1);
-        a.V[j] = s.V;
-        a.W[j] = s.W;
-        a.rend[j] = s.re;
-        if (s.spiked) a.fs[j] = s.fsp;
-        spiked = s.spiked;
-        dis = s.dis;
+    }
+    const int32_t jext = a.ext_const ? a.ext_const_q : a.jext_q;
+    const bool exc = (j % a.M) < a.n_exc;
+    const bool fj = (live && a.forced) ? a.forced[j] != 0 : false;
+    const uint32_t ff = (live && a.forced) ? a.forced_f[j] : 0u;
+    const XIn in{j, t, next, jext, exc, fj, ff, t0};
+    bool done = !live;
+    uint64_t lo = base;
+    for (;;) {
+        const uint64_t hi = (end - lo) < kXBusyCap ? end : lo + kXBusyCap;
+        for (uint64_t i = lo + tid; i < hi; i += kXBlock) in_s[i - lo] = a.qsorted[i];
+        __syncthreads();
+        const bool whole = k0 >= lo && k1 <= hi;          // the slice lies in this window
+        const bool huge = nrec > kXBusyCap;                 // no window holds it
+        if (!done && (whole || huge)) {
+            XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
+            uint2* seg = whole ? in_s + (k0 - lo) : a.qsorted + k0;
+            if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid);
+            else x_take_selected(a, s, in, seg, nrec);
+            x_advance(a, s, t1);
+            a.V[j] = s.V;
+            a.W[j] = s.W;
+            a.rend[j] = s.re;
+            if (s.spiked) a.fs[j] = s.fsp;
+            spiked = s.spiked;
+            dis = s.dis;
+            done = true;
+        }
+        // the next window starts at the slice of the first neuron not done
+        unsigned long long m = done ? ~0ull : (unsigned long long)k0;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long y = __shfl_xor(m, o);
+            m = y < m ? y : m;
+        }
+        if (lane == 0) wlo[wv] = m;
+        __syncthreads();   // also: every lane is done with this window's LDS copy
+        unsigned long long nlo = ~0ull;
+        for (uint32_t w = 0; w < kXBlock / 64; ++w) nlo = wlo[w] < nlo ? wlo[w] : nlo;
+        __syncthreads();   // wlo is rewritten by the next pass
+        if (nlo == ~0ull) break;
+        lo = nlo;
     }
     x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
 }

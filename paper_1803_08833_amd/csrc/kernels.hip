@@ -397,6 +397,21 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* x, const uin
 // Poisson count (one Philox EXT call per quad), integrate the LIF+SFA exact
 // one-step map in fp32, and compact the block's spikers in ascending id.
 // ---------------------------------------------------------------------------
+
+// streaming stores: written once per step and read by the next kernel from
+// memory, so they need not stay dirty in this XCD's L2 until the kernel ends
+typedef int v4i_nt __attribute__((ext_vector_type(4)));
+typedef float v4f_nt __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u_nt __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(float4* p, float4 v) { __builtin_nontemporal_store((v4f_nt){v.x, v.y, v.z, v.w}, reinterpret_cast<v4f_nt*>(p)); }
+__device__ __forceinline__ void st_nt(int4* p, int4 v) { __builtin_nontemporal_store((v4i_nt){v.x, v.y, v.z, v.w}, reinterpret_cast<v4i_nt*>(p)); }
+__device__ __forceinline__ void st_nt(uint4* p, uint4 v) { __builtin_nontemporal_store((v4u_nt){v.x, v.y, v.z, v.w}, reinterpret_cast<v4u_nt*>(p)); }
+__device__ __forceinline__ void st_nt(uchar4* p, uchar4 v)
+{
+    const uint32_t w = (uint32_t)v.x | ((uint32_t)v.y << 8) | ((uint32_t)v.z << 16) | ((uint32_t)v.w << 24);
+    __builtin_nontemporal_store(w, reinterpret_cast<uint32_t*>(p));
+}
+
 __device__ __forceinline__ bool neuron_step(const StepArgs& a, uint32_t gid, bool exc, int32_t iq,
                                             float& V, float& W, uint8_t& R, uint32_t& dis)
 {
@@ -465,9 +480,9 @@ __device__ __forceinline__ uint32_t update_quad(const StepArgs& a, const uint32_
     flags |= neuron_step(a, g0 + 1u, loc + 1u < a.n_exc, add(in.y, e1), V.y, W.y, R.y, dis) ? 2u : 0u;
     flags |= neuron_step(a, g0 + 2u, loc + 2u < a.n_exc, add(in.z, e2), V.z, W.z, R.z, dis) ? 4u : 0u;
     flags |= neuron_step(a, g0 + 3u, loc + 3u < a.n_exc, add(in.w, e3), V.w, W.w, R.w, dis) ? 8u : 0u;
-    reinterpret_cast<float4*>(a.V)[q] = V;
-    reinterpret_cast<float4*>(a.W)[q] = W;
-    reinterpret_cast<uchar4*>(a.ref)[q] = R;
+    st_nt(reinterpret_cast<float4*>(a.V) + q, V);
+    st_nt(reinterpret_cast<float4*>(a.W) + q, W);
+    st_nt(reinterpret_cast<uchar4*>(a.ref) + q, R);
     return flags;
 }
 
@@ -516,7 +531,7 @@ __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, u
                 const uint32_t gid = 4u * q + s;
                 const uint64_t rb = a.row_ptr[gid];
                 const uint32_t len = (uint32_t)(a.row_ptr[gid + 1] - rb);
-                *dst++ = make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32));
+                st_nt(dst++, make_uint4(gid, len, (uint32_t)rb, (uint32_t)(rb >> 32)));
                 ev += len;
             }
         }
@@ -533,7 +548,7 @@ __device__ __forceinline__ void block_compact(const StepArgs& a, uint32_t blk, u
             bv += wev[i];
         }
         // events: <= 1024 rows of < 2^16 records; external: <= 1024 x kMaxPois
-        a.blk_stat[blk] = make_uint4(btot, (uint32_t)bv, (uint32_t)be, 0u);
+        st_nt(a.blk_stat + blk, make_uint4(btot, (uint32_t)bv, (uint32_t)be, 0u));
         if (a.grp_atomic && btot) atomicAdd(&a.grp_cnt[(t & 1u) * a.ngrp + blk / kGroup], btot);
         if (bd) atomicAdd((unsigned long long*)&a.ctrl->disagree, (unsigned long long)bd);
     }
@@ -555,7 +570,7 @@ __global__ __launch_bounds__(256) void k_update(StepArgs a, uint32_t k)
     if (q < a.nq) {
         int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
         const int4 in = *rp;
-        *rp = make_int4(0, 0, 0, 0);
+        st_nt(rp, make_int4(0, 0, 0, 0));
         flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
     }
     block_compact<4>(a, blockIdx.x, t, q, flags, ext_tot, dis, threadIdx.x, true, wtot, wext, wdis, wev);
@@ -1355,7 +1370,7 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
             } else {
                 int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)((t + 1u) & (kRing - 1u)) * a.N) + q;
                 in = *rp;
-                *rp = make_int4(0, 0, 0, 0);
+                st_nt(rp, make_int4(0, 0, 0, 0));
             }
         }
         __syncthreads();
@@ -1369,7 +1384,7 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
             if (4u * qq < nn) {
                 const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
                 const int4 v = (do_upd && b == 0u) ? make_int4(0, 0, 0, 0) : reinterpret_cast<const int4*>(acc)[idx];
-                reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0)[qq] = v;
+                st_nt(reinterpret_cast<int4*>(a.ring + (size_t)slot * a.N + g0) + qq, v);
             }
         }
         if (tid == 0) a.bin_fill[(size_t)tt * kFillStride] = 0u;
@@ -1407,7 +1422,7 @@ __device__ __forceinline__ void update_groups(const StepArgs& a, uint32_t t, uin
         if (live && q < a.nq) {
             int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
             const int4 in = *rp;
-            *rp = make_int4(0, 0, 0, 0);
+            st_nt(rp, make_int4(0, 0, 0, 0));
             flags = update_quad(a, scr, q, t, in, ext_tot, dis);
         }
         block_compact<4>(a, blk, t, q, flags, ext_tot, dis, gtid, live, gs, reinterpret_cast<unsigned long long*>(gs + 8),
@@ -1475,7 +1490,7 @@ __global__ __launch_bounds__(256) void k_batch_update(const JobDesc* __restrict_
     if (q < a.nq) {
         int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)(t & (kRing - 1u)) * a.N) + q;
         const int4 in = *rp;
-        *rp = make_int4(0, 0, 0, 0);
+        st_nt(rp, make_int4(0, 0, 0, 0));
         flags = update_quad(a, pois_s, q, t, in, ext_tot, dis);
     }
     block_append<4>(a, t, q, flags, ext_tot, threadIdx.x, true, wtot, wext, wev, &sbase);
@@ -1735,7 +1750,7 @@ __global__ __launch_bounds__(kTileThreads) void k_btile(const JobDesc* __restric
             if (q < a.nq) {
                 int4* rp = reinterpret_cast<int4*>(a.ring + (size_t)((t + 1u) & (kRing - 1u)) * a.N) + q;
                 const int4 in = *rp;
-                *rp = make_int4(0, 0, 0, 0);
+                st_nt(rp, make_int4(0, 0, 0, 0));
                 flags = update_quad(a, pois, q, t + 1u, in, ext_tot, dis);
             }
         }

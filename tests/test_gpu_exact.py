@@ -254,3 +254,44 @@ def test_solver_specific_calls(snn):
     with snn.Batch(1 << 30, 1 << 16) as b:
         with pytest.raises(snn.SNNError):
             b.admit(exact_net, 10)
+
+
+def test_busy_workgroups_taken_in_windows(snn, oracle_mod):
+    """Workgroups whose queued inputs in one step exceed the busy kernel's LDS
+    window (15,360 inputs) are taken in several windows: a 1000-neuron module
+    with 300 synapses per neuron, all of delay 1, where every neuron is forced
+    to fire in step 0 (at its constant-drive input, offset 0), so that each
+    256-neuron workgroup receives ~77 K inputs in step 1 (six windows); then
+    some neurons fire again.  Lock-step against the oracle: history with offsets, every queued
+    input and the state after each step."""
+    net = W.make(1, 1, W.GAUSS, 1.0, 300, 77, n_exc=800, n_inh=200, d_min=1, d_max=1, t_ref=1.0,
+                 solver=W.SOLVER_EXACT, ext_mode=W.EXT_CONST, ext_const_q=round(0.3 * 65536))
+    say("case: exact solver, workgroups with more inputs than one LDS window")
+    o = oracle_mod.Net(net).build()
+    rng = np.random.default_rng(5)
+    R = net["d_max"] + 1
+    with snn.Net(net) as g:
+        g.set_option(snn.OPT_QUEUE_CAP, 1 << 19)   # a step's 300 K inputs in one arrival slot
+        g.build_synapses()
+        for t in range(6):
+            if t == 0:
+                gids = np.arange(o.N, dtype=np.uint32)
+            elif t == 3:
+                gids = np.sort(rng.choice(o.N, 700, replace=False)).astype(np.uint32)
+            else:
+                gids = np.zeros(0, dtype=np.uint32)
+            fr = np.zeros(gids.size, dtype=np.uint32)   # the instant of the constant drive
+            o.step_forced_exact(gids, fr)
+            g.step_forced_exact(gids, fr)
+            gsp, gfr = g.read_spike_times()
+            np.testing.assert_array_equal(gsp, o.spikes(), err_msg=f"spikes after step {t}")
+            np.testing.assert_array_equal(gfr, o.spike_fracs(), err_msg=f"offsets after step {t}")
+            for k in range(R):
+                q = o.queue((t + 1 + k) % oracle_mod.RING)
+                np.testing.assert_array_equal(g.read_queue(k), q, err_msg=f"queue {k} ahead after step {t}")
+                if t in (0, 3) and k == 0:
+                    per_wg = np.bincount(q[:, 0] // 256)
+                    say(f"  step {t}: inputs per workgroup next step {per_wg.tolist()}")
+                    if t == 0:
+                        assert per_wg.max() > 2 * 15 * 1024
+            _compare_state(net, g.read_state(), o.state(), t)
