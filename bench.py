@@ -48,6 +48,8 @@ def parse():
     p.add_argument("--serve-jobs", type=int, default=512, help="served-stream jobs (0: skip serving)")
     p.add_argument("--serve-plain", type=int, default=128, help="first jobs also served one at a time")
     p.add_argument("--serve-capacity", type=int, default=64, help="jobs of the closed-loop capacity run")
+    p.add_argument("--serve-tune", type=int, default=16,
+                   help="jobs the batch autotuner serves per candidate schedule (0: default schedule)")
     p.add_argument("--serve-gen", type=int, default=1,
                    help="synapse generator of the served jobs: 0 one trial per pair, 1 binomial + Floyd")
     p.add_argument("--graph-chunk", type=int, default=250,
@@ -304,7 +306,7 @@ def main():
 
         say = lambda *a: print(*a, file=sys.stderr, flush=True)
         result["served"] = serve.bench_served(args.serve_jobs, args.serve_plain, args.serve_capacity, log=say,
-                                              gen=args.serve_gen)
+                                              gen=args.serve_gen, tune_jobs=args.serve_tune)
         result["served"]["generator"] = "binomial + Floyd" if args.serve_gen else "one trial per pair"
     if not args.no_cpu_baseline and not exact:
         sps = spikes / max(1, args.steps * 1000)

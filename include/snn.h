@@ -229,11 +229,16 @@ enum {
                                     (0 = always binned)                             */
     SNN_OPT_EXT_RATE_UHZ = 8,    /* after snn_build_synapses: external Poisson rate
                                     in micro-hertz (rebuilds the CDF thresholds)    */
-    SNN_OPT_QUEUE_CAP = 9        /* before snn_build_synapses, exact solver: inputs
+    SNN_OPT_QUEUE_CAP = 9,       /* before snn_build_synapses, exact solver: inputs
                                     one arrival slot holds (0 = automatic: a step's
                                     events at a 150 Hz mean rate + 65536); inputs
                                     beyond it are dropped and reported as
                                     SNN_E_OVERFLOW by the reads and snn_stats       */
+    SNN_OPT_BIN_THRESHOLD_PPM = 10 /* batches only (snn_batch_set_option): a binned
+                                    job's steps with fewer recurrent events than
+                                    value * 1e-6 * neurons * delay rows are
+                                    delivered directly (0 = each job's own
+                                    threshold, 0.039 * neurons * delay rows)      */
 };
 
 /* Create the grid (Sec. III.B) and the initial neuron state: V uniform in
@@ -397,6 +402,18 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
  * has finished join first).  With no running job but builds in progress it
  * waits for a build to finish; with nothing to run it returns at once. */
 snn_status snn_batch_step(snn_batch* b, uint32_t chunk_ms);
+
+/* Set a knob of the batched schedule (what the batch autotuner chooses; the
+ * results do not depend on it: integer delivery is order-free):
+ *   SNN_OPT_SCATTER_BLOCKS     workgroups of the batched scatter kernel,
+ *                              64 .. 4096 (waits for the enqueued steps and
+ *                              drops the captured chunks);
+ *   SNN_OPT_DELIVER_MODE       0: every job by direct ring atomics; 1: tile-
+ *                              binned for the jobs that allow it (default);
+ *   SNN_OPT_BIN_THRESHOLD_PPM  see the enum above.
+ * The running jobs take the change from the next snn_batch_step on.
+ * SNN_E_INVAL for an unknown option or a value out of range. */
+snn_status snn_batch_set_option(snn_batch* b, int opt, int64_t value);
 
 /* Finished jobs (and failed builds) whose spikes have not been read yet
  * (synchronises the stepping stream). */

@@ -1,13 +1,21 @@
-"""Schedule autotuner for the single-network path.
+"""Schedule autotuners.
 
-Candidates are the delivery schedules and their knobs exposed by the C ABI
-(direct atomics vs tile-binned delivery, the per-step binning threshold, the
-scatter grid, the number of steps per captured HIP graph).  Every candidate is
-timed on the identical workload: the network is reset to its initial state
-(snn_reset), stepped through a warm-up, then timed; all candidates give
-bit-identical results (integer delivery is order-free), so the choice affects
-speed only.  The winner is cached in a JSON file keyed by the network
-description and applied with snn_set_option.
+Single network: the candidates are the delivery schedules and their knobs
+exposed by the C ABI (direct atomics vs tile-binned delivery, the per-step
+binning threshold, the scatter grid, the number of steps per captured HIP
+graph).  Every candidate is timed on the identical workload: the network is
+reset to its initial state (snn_reset), stepped through a warm-up, then timed;
+all candidates give bit-identical results (integer delivery is order-free), so
+the choice affects speed only.  The winner is cached in a JSON file keyed by
+the network description and applied with snn_set_option.
+
+Batches (continuous batching of many jobs): the candidates are the steps per
+batched call (the length of a captured chunk, which is also the admission
+granularity), the batched scatter grid, binned vs direct delivery and the
+binning threshold (snn_batch_set_option).  Each is timed on the same closed
+loop, a sample of the job mix all queued at once and served to completion, so
+construction overlap and admission granularity count as they do when serving;
+the schedule with the highest jobs/s wins.  Rasters do not depend on it.
 """
 from __future__ import annotations
 
@@ -93,3 +101,80 @@ def load(g: "snn.Net", cache: str = DEFAULT_CACHE) -> bool:
         return False
     apply(g, {int(k): v for k, v in ent["options"].items()})
     return True
+
+
+def batch_key(jobs) -> str:
+    """Key of a job mix: its jobs' descriptions without seeds, drives and
+    durations (the shapes the batched kernels see)."""
+    shapes = sorted(json.dumps(sorted((k, v) for k, v in j["net"].items() if k not in ("seed", "ext_rate_hz")))
+                    for j in jobs)
+    return "batch-" + hashlib.sha1(json.dumps(shapes).encode()).hexdigest()[:16]
+
+
+def batch_candidates():
+    """Batch schedules to try: {"chunk_ms": steps per call, "options": {...}}.
+    The default (50 ms chunks, 256 scatter workgroups, binned where the job
+    allows it, each job's own threshold) comes first."""
+    out = [dict(chunk_ms=50, options={snn.OPT_SCATTER_BLOCKS: 256, snn.OPT_DELIVER_MODE: 1,
+                                      snn.OPT_BIN_THRESHOLD_PPM: 0})]
+    for chunk in (25, 50, 100):
+        for blocks, mode, ppm in ((256, 1, 0), (512, 1, 0), (256, 0, 0), (256, 1, 19500), (256, 1, 78000)):
+            c = dict(chunk_ms=chunk, options={snn.OPT_SCATTER_BLOCKS: blocks, snn.OPT_DELIVER_MODE: mode,
+                                              snn.OPT_BIN_THRESHOLD_PPM: ppm})
+            if c not in out:
+                out.append(c)
+    return out
+
+
+def tune_batch(jobs, hbm_budget: int, max_neurons: int, candidates=None, finalists: int = 3,
+               cache: str | None = DEFAULT_CACHE, log=None) -> dict:
+    """Serve `jobs` (all queued at once) with every candidate schedule, time
+    the best `finalists` once more, and return {"schedule": fastest by mean
+    jobs/s, "trials": [...]}; cached under batch_key(jobs) when cache is set."""
+    import numpy as np
+
+    from . import serve
+
+    say = log or (lambda *a: None)
+    cands = list(candidates or batch_candidates())
+    arrivals = np.zeros(len(jobs))
+    walls = [[] for _ in cands]
+
+    def trial(i):
+        r = serve.serve_batched(jobs, arrivals, hbm_budget, max_neurons, schedule=cands[i])
+        if r["failed"]:
+            raise RuntimeError(f"batch autotuner: {len(r['failed'])} jobs failed under {cands[i]}")
+        walls[i].append(r["wall"])
+
+    for i in range(len(cands)):
+        trial(i)
+    order = sorted(range(len(cands)), key=lambda i: walls[i][0])
+    for i in order[:finalists]:
+        trial(i)
+    mean = [sum(w) / len(w) for w in walls]
+    best = min(order[:finalists] if finalists else order, key=lambda i: mean[i])
+    trials = [dict(chunk_ms=c["chunk_ms"], options={str(k): v for k, v in c["options"].items()},
+                   jobs_per_s=[len(jobs) / w for w in walls[i]]) for i, c in enumerate(cands)]
+    schedule = dict(chunk_ms=cands[best]["chunk_ms"], options={str(k): v for k, v in cands[best]["options"].items()})
+    say(f"# batch autotuner ({len(jobs)} jobs, {len(cands)} schedules): {schedule}, "
+        f"{len(jobs) / mean[best]:.2f} jobs/s (default {len(jobs) / mean[0]:.2f})")
+    if cache:
+        os.makedirs(os.path.dirname(cache), exist_ok=True)
+        data = {}
+        if os.path.exists(cache):
+            with open(cache) as f:
+                data = json.load(f)
+        data[batch_key(jobs)] = dict(schedule=schedule, jobs_per_s=len(jobs) / mean[best])
+        with open(cache + ".tmp", "w") as f:
+            json.dump(data, f, indent=1)
+        os.replace(cache + ".tmp", cache)
+    return dict(schedule=schedule, trials=trials)
+
+
+def load_batch(jobs, cache: str = DEFAULT_CACHE):
+    """The cached schedule for this job mix, or None."""
+    if not os.path.exists(cache):
+        return None
+    with open(cache) as f:
+        ent = json.load(f).get(batch_key(jobs))
+    return ent["schedule"] if ent else None

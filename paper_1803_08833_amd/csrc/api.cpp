@@ -1520,6 +1520,8 @@ struct snn_batch {
     uint32_t blk_cap = 0, blk_used = 0;   // blk_used: blocks of the jobs in the device table
     uint32_t blk_reserved = 0;            // blocks of every admitted job (building included)
     uint32_t scatter_blocks = 256;        // one 1024-thread workgroup per CU (its LDS use allows no more)
+    uint32_t deliver_mode = 1;            // 0: every job direct; 1: tile-binned where the job allows it
+    uint64_t thr_ppm = 0;                 // binned steps from ppm * N * D events (0: each job's own)
     enum State { kFree, kBuilding, kActive, kFailed };
     struct Job {
         snn_net* net = nullptr;
@@ -1643,7 +1645,8 @@ hipError_t batch_upload(snn_batch* b)
         d.active = 1;
         d.blk_base = base;
         d.smax = J.net->max_len ? (J.net->max_len + 255) / 256 : 1;
-        d.binned = (J.binned && J.net->binned_ok && d.a.bins) ? 1u : 0u;
+        d.binned = (b->deliver_mode == 1 && J.binned && J.net->binned_ok && d.a.bins) ? 1u : 0u;
+        if (b->thr_ppm) d.a.bin_threshold = (uint64_t)((double)b->thr_ppm * 1e-6 * J.net->N * J.net->D);
         base += J.nblk;
     }
     b->blk_used = base;
@@ -1866,6 +1869,38 @@ snn_status snn_batch_admit(snn_batch* b, const snn_grid_desc* g, const snn_syn_d
     b->todo.push_back(snn_batch::BuildReq{free_slot, gd, *s});
     b->cv.notify_all();
     *slot = free_slot;
+    return SNN_OK;
+}
+
+snn_status snn_batch_set_option(snn_batch* b, int opt, int64_t value)
+{
+    snn_status st = batch_check(b);
+    if (st) return st;
+    std::lock_guard<std::mutex> lk(b->mu);
+    switch (opt) {
+    case SNN_OPT_SCATTER_BLOCKS:
+        if (value < 64 || value > 4096) return bfail(b, SNN_E_INVAL, "scatter blocks out of range (64 .. 4096)");
+        if ((uint32_t)value != b->scatter_blocks) {
+            // the grid is part of the captured chunks: none may still be pending
+            BHIPCHK(b, hipStreamSynchronize(b->stream));
+            batch_drop_graphs(b);
+            b->scatter_blocks = (uint32_t)value;
+        }
+        return SNN_OK;
+    case SNN_OPT_DELIVER_MODE:
+        if (value != 0 && value != 1) return bfail(b, SNN_E_INVAL, "batch delivery mode must be 0 or 1");
+        b->deliver_mode = (uint32_t)value;
+        break;
+    case SNN_OPT_BIN_THRESHOLD_PPM:
+        if (value < 0 || value > 1000000000) return bfail(b, SNN_E_INVAL, "threshold out of range");
+        b->thr_ppm = (uint64_t)value;
+        break;
+    default:
+        return bfail(b, SNN_E_INVAL, "unknown batch option");
+    }
+    // the running jobs' table entries change from the next chunk on (the
+    // copy is ordered after the chunks already enqueued)
+    BHIPCHK(b, batch_upload(b));
     return SNN_OK;
 }
 

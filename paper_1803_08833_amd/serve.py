@@ -17,10 +17,14 @@ class Result(dict):
 
 
 def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chunk_ms=50,
-                  keep_spikes=False, clock=time.perf_counter):
+                  keep_spikes=False, clock=time.perf_counter, schedule=None):
     """Continuous batching.  jobs: list of {"net": desc, "steps": duration};
-    arrivals: seconds after start (sorted).  Returns per-job latency and
-    events, wall time, and the rasters when keep_spikes."""
+    arrivals: seconds after start (sorted).  schedule: a batch schedule
+    {"chunk_ms": steps per batched call, "options": {option: value}} (the
+    batch autotuner's choice), which replaces chunk_ms.  Returns per-job
+    latency and events, wall time, and the rasters when keep_spikes."""
+    if schedule:
+        chunk_ms = int(schedule["chunk_ms"])
     n = len(jobs)
     lat = np.full(n, np.nan)
     events = np.zeros(n, dtype=np.int64)
@@ -31,6 +35,8 @@ def serve_batched(jobs, arrivals, hbm_budget=96 << 30, max_neurons=4 << 20, chun
     queue = []
     t0 = clock()
     with snn.Batch(hbm_budget, max_neurons, stream=snn.current_stream_handle()) as b:
+        for opt, v in ((schedule or {}).get("options") or {}).items():
+            b.set_option(int(opt), int(v))
         done_count = 0
         while done_count < n:
             now = clock() - t0
@@ -129,27 +135,35 @@ def summary(res, jobs):
 
 
 def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4, log=None,
-                 hbm_budget=160 << 30, max_neurons=6 << 20, chunk_ms=50, gen=0):
+                 hbm_budget=160 << 30, max_neurons=6 << 20, chunk_ms=50, gen=0, tune_jobs=16):
     """The served workload: the seeded stream of simulation jobs (grids
     2x2..16x16, Gaussian/exponential, 0.5-5 s), Poisson arrivals at `load`
     times the capacity measured by a saturated closed-loop batched run, served
     with continuous batching; the plain one-job-at-a-time server is run on the
     first `plain_jobs` jobs of the same stream with the same arrival process,
     and both servers' closed-loop capacities (throughput with every job
-    queued at once) are measured on the first `capacity_jobs` jobs."""
+    queued at once) are measured on the first `capacity_jobs` jobs.  With
+    tune_jobs > 0 the batch schedule is first chosen by the batch autotuner on
+    the stream's first tune_jobs jobs (otherwise chunk_ms and the defaults)."""
     from . import workloads as W
 
     say = log or (lambda *a: None)
     jobs = W.serving_stream(n_jobs, seed=seed, gen=gen)
+    schedule, tuning = None, None
+    if tune_jobs:
+        from . import autotune
+
+        tuning = autotune.tune_batch(jobs[:tune_jobs], hbm_budget, max_neurons, cache=None, log=say)
+        schedule = tuning["schedule"]
     cap_jobs = jobs[:capacity_jobs]
-    rc = serve_batched(cap_jobs, np.zeros(len(cap_jobs)), hbm_budget, max_neurons, chunk_ms)
+    rc = serve_batched(cap_jobs, np.zeros(len(cap_jobs)), hbm_budget, max_neurons, chunk_ms, schedule=schedule)
     capacity = len(cap_jobs) / rc["wall"]
     rcp = serve_plain(cap_jobs, np.zeros(len(cap_jobs)))
     capacity_plain = len(cap_jobs) / rcp["wall"]
     say(f"# capacity (closed loop, {len(cap_jobs)} jobs): batched {capacity:.2f} jobs/s, "
         f"plain {capacity_plain:.2f} jobs/s")
     arrivals = poisson_arrivals(n_jobs, load * capacity, seed=seed)
-    rb = serve_batched(jobs, arrivals, hbm_budget, max_neurons, chunk_ms)
+    rb = serve_batched(jobs, arrivals, hbm_budget, max_neurons, chunk_ms, schedule=schedule)
     sb = summary(rb, jobs)
     say(f"# served batched: {sb}")
     out = dict(jobs=n_jobs, arrival_rate_jobs_per_s=load * capacity, capacity_jobs_per_s=capacity,
@@ -158,12 +172,15 @@ def bench_served(n_jobs=512, plain_jobs=128, capacity_jobs=64, load=0.8, seed=4,
                                           plain=float(rcp["events"].sum() / rcp["wall"])),
                p50_s=sb["p50_s"], p99_s=sb["p99_s"], jobs_per_s=sb["jobs_per_s"],
                events_per_s=sb["events_per_s"], sim_s_per_wall_s=sb["sim_s_per_wall_s"],
-               failed=sb["failed"] + summary(rc, cap_jobs)["failed"])
+               failed=sb["failed"] + summary(rc, cap_jobs)["failed"],
+               schedule=schedule or dict(chunk_ms=chunk_ms, options={}))
+    if tuning:
+        out["tuning"] = dict(jobs=tune_jobs, trials=tuning["trials"])
     if plain_jobs:
         pj = jobs[:plain_jobs]
         rp = serve_plain(pj, arrivals[:plain_jobs])
         sp = summary(rp, pj)
-        rb2 = serve_batched(pj, arrivals[:plain_jobs], hbm_budget, max_neurons, chunk_ms)
+        rb2 = serve_batched(pj, arrivals[:plain_jobs], hbm_budget, max_neurons, chunk_ms, schedule=schedule)
         sb2 = summary(rb2, pj)
         say(f"# first {plain_jobs} jobs: plain {sp} | batched {sb2}")
         out["failed"] += sb2["failed"]

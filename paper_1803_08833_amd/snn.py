@@ -24,6 +24,7 @@ OPT_BIN_FRAC_PPM = 6
 OPT_BIN_THRESHOLD = 7
 OPT_EXT_RATE_UHZ = 8
 OPT_QUEUE_CAP = 9
+OPT_BIN_THRESHOLD_PPM = 10
 SOLVER_STEP, SOLVER_EXACT = 0, 1
 RING = 32
 
@@ -35,6 +36,7 @@ EXPORTS = [
     "snn_batch_job_stats", "snn_batch_usage", "snn_batch_destroy", "snn_batch_last_error",
     "snn_set_allocator", "snn_step_forced_exact", "snn_read_spike_times", "snn_read_queue",
     "snn_batch_read_state", "snn_step_forced_noalloc", "snn_host_stdp_tables", "snn_probe_atomics",
+    "snn_batch_set_option",
 ]
 
 # snn_set_allocator's function types: alloc(bytes, ctx) -> pointer, free(ptr, ctx)
@@ -125,6 +127,7 @@ def lib():
             "snn_batch_create": ([U64, U64, P, C.POINTER(P)], C.c_int),
             "snn_batch_admit": ([P, C.POINTER(GridDesc), C.POINTER(SynDesc), U32, C.POINTER(C.c_int32)], C.c_int),
             "snn_batch_step": ([P, U32], C.c_int),
+            "snn_batch_set_option": ([P, C.c_int, C.c_int64], C.c_int),
             "snn_batch_poll": ([P, P, SZ, C.POINTER(SZ)], C.c_int),
             "snn_batch_read_spikes": ([P, C.c_int32, P, SZ, C.POINTER(SZ)], C.c_int),
             "snn_batch_job_stats": ([P, C.c_int32, C.POINTER(Stats)], C.c_int),
@@ -441,6 +444,11 @@ class Batch:
 
     def step(self, chunk_ms: int):
         self._check(lib().snn_batch_step(self.h, chunk_ms))
+
+    def set_option(self, opt: int, value: int):
+        """A knob of the batched schedule (OPT_SCATTER_BLOCKS,
+        OPT_DELIVER_MODE, OPT_BIN_THRESHOLD_PPM)."""
+        self._check(lib().snn_batch_set_option(self.h, int(opt), int(value)))
 
     def poll(self):
         out = np.zeros(64, dtype=np.int32)
