@@ -57,6 +57,8 @@ def parse():
     p.add_argument("--queue-cap", type=float, default=0.3,
                    help="exact solver: queued inputs per arrival slot, as a mean rate in kHz "
                         "times neurons times synapses per neuron")
+    p.add_argument("--gen", type=int, default=None,
+                   help="synapse generator of the workload: 0 one trial per pair, 1 binomial + Floyd")
     p.add_argument("--copy-mib", type=int, default=0,
                    help="end with one plain device copy of this size (reference kernel for HBM counters)")
     return p.parse_args()
@@ -68,6 +70,8 @@ def workload(args):
     over = {}
     if args.ext_rate is not None:
         over["ext_rate_hz"] = args.ext_rate
+    if args.gen is not None:
+        over["gen"] = args.gen
     return W.workload(args.workload, **over)
 
 
@@ -97,7 +101,8 @@ def counters_from_profile(args):
         prof = json.load(f)
     same = (prof.get("kernel_source_sha256_16") == kernel_source_hash()
             and prof.get("ext_rate_hz") == workload(args)["net"]["ext_rate_hz"]
-            and prof.get("steps") == args.steps and prof.get("warmup") == args.warmup)
+            and prof.get("steps") == args.steps and prof.get("warmup") == args.warmup
+            and args.gen is None)
     return prof if same else None
 
 
@@ -241,7 +246,7 @@ def main():
         name = "k_scatter+k_tile (one 1 ms step: compaction, delivery, fused neuron update)"
         ms = kt["scatter_ms"] + kt["tile_ms"]
     elif stf["deliver_mode"] == 2:
-        name = ("k_compact+k_scatter+k_sub+k_tile (one 1 ms step: compaction, two-level binned "
+        name = ("k_compact+k_seg_emit+k_seg_bin+k_tile (one 1 ms step: compaction, two-level binned "
                 "delivery, fused neuron update)")
         ms = kt["compact_ms"] + kt["scatter_ms"] + kt["sub_ms"] + kt["tile_ms"]
     else:
@@ -290,6 +295,7 @@ def main():
         "mean_rate_hz": rate_hz,
         "build_s": build_s,
         "solver": "exact-time event-driven" if exact else "1 ms step",
+        # two-level networks: the scatter slot is k_seg_emit, the second pass k_seg_bin
         "kernels_avg_ms": {"k_update": round(kt["update_ms"], 6), "k_compact": round(kt["compact_ms"], 6),
                            "k_scatter": round(kt["scatter_ms"], 6), "k_sub": round(kt["sub_ms"], 6),
                            "k_tile": round(kt["tile_ms"], 6),

@@ -183,7 +183,8 @@ typedef struct {
     uint64_t bin_overflow;    /* binned delivery: events that took the fallback  */
     uint32_t deliver_mode;    /* delivery schedule in use (SNN_OPT_DELIVER_MODE) */
     uint32_t binned_ok;       /* bit 0: single-level binned delivery possible;
-                                 bit 1: two-level binned delivery possible     */
+                                 bit 1: two-level binned delivery built (rows
+                                 laid out by super tile)                       */
     uint64_t bin_threshold;   /* per-step switch to direct delivery (events)     */
     double build_ms;          /* wall time of snn_build_synapses                 */
 } snn_stats_t;
@@ -216,7 +217,10 @@ enum {
     SNN_OPT_DELIVER_MODE = 4,    /* 0: direct ring atomics; 1: tile-binned (default
                                     when the network allows it, see snn_stats);
                                     2: two-level tile-binned (8-bit-code records;
-                                    default when the tiles exceed one level).
+                                    default when the tiles exceed one level; the
+                                    rows are then laid out by super tile of 2^19
+                                    targets, and mode 0 is the two-level kernels'
+                                    direct branch at every step).
                                     Before snn_build_synapses it selects which bins
                                     are allocated; afterwards it switches between
                                     direct delivery and the mode built for.     */
@@ -314,7 +318,9 @@ snn_status snn_read_ring(snn_net* net, int32_t* host_ring);
  * row_len[n] (u64), bucket ends bend[n][d_max-d_min+1] (u16, row-relative end
  * of each delay), and the records back to back in rec_buf (8 B
  * {u32 target, f32 weight mV} for SNN_REC_F32; 4 B (target << 8 | code) for
- * SNN_REC_CODE8).  rec_cap is in records; *n_out = records in the range. */
+ * SNN_REC_CODE8), each row in (delay, target) order: rows that two-level
+ * delivery holds laid out by super tile are converted back on the host.
+ * rec_cap is in records; *n_out = records in the range. */
 snn_status snn_export_rows(snn_net* net, uint32_t pre0, uint32_t n, uint64_t* row_len,
                            uint16_t* bend, void* rec_buf, size_t rec_cap, size_t* n_out);
 

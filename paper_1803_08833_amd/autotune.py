@@ -40,10 +40,11 @@ def candidates(stats: dict):
     auto_thr = stats["bin_threshold"]
     for chunk in (32, 64, 128):
         out.append({snn.OPT_DELIVER_MODE: 0, snn.OPT_GRAPH_CHUNK: chunk})
-    if stats["binned_ok"]:
+    binned = 1 if stats["binned_ok"] & 1 else (2 if stats["binned_ok"] & 2 else 0)
+    if binned:
         for thr in (auto_thr // 2, auto_thr, auto_thr * 2):
             for blocks in (256, 512):
-                out.append({snn.OPT_DELIVER_MODE: 1, snn.OPT_BIN_THRESHOLD: int(thr),
+                out.append({snn.OPT_DELIVER_MODE: binned, snn.OPT_BIN_THRESHOLD: int(thr),
                             snn.OPT_SCATTER_BLOCKS: blocks, snn.OPT_GRAPH_CHUNK: 64})
     return out
 

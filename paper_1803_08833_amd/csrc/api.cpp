@@ -68,6 +68,7 @@ struct snn_net {
     double bin_frac = 0.5;      // bin capacity as a fraction of the tile's in-synapses
     bool bin_threshold_set = false;
     uint64_t bin_threshold_opt = 0;
+    uint64_t bin_threshold_auto = 0;   // the build's default (0.039 D N events)
     std::map<uint32_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     // exact-time solver (SNN_SOLVER_EXACT)
     bool exact = false;
@@ -190,25 +191,38 @@ snn_status check_usable(snn_net* n)
     return SNN_OK;
 }
 
+// Kernel sequence of a network: one whose rows are laid out by super tile
+// always steps through the two-level kernels (its direct delivery, mode 0, is
+// their direct branch at every step); otherwise the selected mode's.
+uint32_t seq(const snn_net* n) { return n->a.nsuper ? 2u : n->mode; }
+
+// Binning threshold in force: mode 0 of a two-level network delivers every
+// step directly.
+uint64_t threshold_in_force(const snn_net* n)
+{
+    if (n->a.nsuper && n->mode == 0) return ~0ull;
+    return n->bin_threshold_set ? n->bin_threshold_opt : n->bin_threshold_auto;
+}
+
 // Enqueue step k (0-based within the current chunk) of the plain path.
 // Binned delivery of step k (tile kernel without the next step's update).
 hipError_t enqueue_binned(snn_net* n, const StepArgs& a, uint32_t k, bool update_next)
 {
     hipError_t e = snn::launch_scatter(a, k, n->max_len, n->scatter_blocks, n->stream);
-    if (e == hipSuccess && n->mode == 2) e = snn::launch_sub(a, k, n->scatter_blocks, n->stream);
+    if (e == hipSuccess && seq(n) == 2) e = snn::launch_sub(a, k, n->scatter_blocks, n->stream);
     if (e == hipSuccess) e = snn::launch_tile(a, k, update_next, n->stream);
     return e;
 }
 
 hipError_t enqueue_deliver(snn_net* n, const StepArgs& a, uint32_t k)
 {
-    if (n->mode != 0) return enqueue_binned(n, a, k, false);
+    if (seq(n) != 0) return enqueue_binned(n, a, k, false);
     return snn::launch_deliver(a, k, n->deliver_waves, n->unroll, n->max_len, n->stream);
 }
 
 hipError_t check_items(snn_net* n)
 {
-    const uint64_t seg = 64ull * (n->mode != 0 ? 4 : n->unroll);
+    const uint64_t seg = 64ull * (seq(n) != 0 ? 4 : n->unroll);
     const uint64_t smax = n->max_len ? (n->max_len + seg - 1) / seg : 1;
     return ((uint64_t)n->N * smax >= (1ull << 32)) ? hipErrorInvalidValue : hipSuccess;
 }
@@ -220,7 +234,7 @@ hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
     if (e != hipSuccess) return e;
     e = snn::launch_update(a, k, n->stream);
     if (e != hipSuccess) return e;
-    if (n->mode != 1) {   // single-level binned delivery compacts inside its scatter kernel
+    if (seq(n) != 1) {   // single-level binned delivery compacts inside its scatter kernel
         e = snn::launch_compact(a, k, n->stream);
         if (e != hipSuccess) return e;
     }
@@ -236,7 +250,7 @@ hipError_t enqueue_step(snn_net* n, const StepArgs& a, uint32_t k)
 hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
 {
     if (count == 0) return hipSuccess;
-    if (n->mode == 0 || n->a.d_min != 1) {
+    if (seq(n) == 0 || n->a.d_min != 1) {
         for (uint32_t k = k0; k < k0 + count; ++k) {
             hipError_t e = enqueue_step(n, n->a, k);
             if (e != hipSuccess) return e;
@@ -246,7 +260,7 @@ hipError_t enqueue_steps(snn_net* n, uint32_t k0, uint32_t count)
     hipError_t e = check_items(n);
     if (e == hipSuccess) e = snn::launch_update(n->a, k0, n->stream);
     for (uint32_t k = k0; k < k0 + count && e == hipSuccess; ++k) {
-        if (n->mode == 2) e = snn::launch_compact(n->a, k, n->stream);
+        if (seq(n) == 2) e = snn::launch_compact(n->a, k, n->stream);
         if (e == hipSuccess) e = enqueue_binned(n, n->a, k, k + 1 < k0 + count);
     }
     return e;
@@ -753,6 +767,32 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     b.rowlen = rowlen;
     b.row_ptr = row_ptr;
     b.ctrl = a.ctrl;
+    // Delivery schedule, chosen before the rows are written (two levels lay
+    // the rows out by super tile).  Single level: the tiles fit the scatter
+    // kernel's LDS tables and every weight has a 17-bit event field (code, or
+    // w_q + 65536 in range).  Two levels (8-bit codes): networks with more
+    // tiles than one LDS table.
+    a.ntiles = (n->N + snn::kTile - 1) / snn::kTile;
+    a.winh_q = tb.winh_q;
+    bool ok1 = a.ntiles <= snn::kMaxTiles;
+    if (s->record != SNN_REC_CODE8)
+        for (int32_t w : tb.wtab)
+            if (w != tb.winh_q && (w < -65536 || w > 65534)) ok1 = false;
+    const uint32_t nsuper = (uint32_t)(((uint64_t)n->N + (1u << snn::kSegBits) - 1) >> snn::kSegBits);
+    const bool ok2 = s->record == SNN_REC_CODE8 && nsuper <= snn::kMaxSuper;
+    uint32_t mode = 0;
+    if (s->solver == SNN_SOLVER_EXACT) {
+        ok1 = false;   // the exact solver has its own queues
+    } else if (n->mode_pref == 2) mode = ok2 ? 2 : 0;
+    else if (n->mode_pref == 1) mode = ok1 ? 1 : 0;
+    else if (n->mode_pref < 0) mode = ok1 ? 1 : (ok2 ? 2 : 0);
+    uint16_t* sstart = nullptr;
+    if (mode == 2) {
+        if (dalloc(n, &sstart, (size_t)n->N * nsuper) != hipSuccess)
+            return fail(n, SNN_E_NOMEM, "device allocation failed (segment starts)");
+        b.nsuper = nsuper;
+        b.sstart = sstart;
+    }
     // Rows are built in slices so that no single launch runs for long: the
     // slice's rows are generated into a buffer of slab_cap hits per row
     // (8 standard deviations above the busiest source type's expected row
@@ -796,50 +836,43 @@ snn_status snn_build_synapses(snn_net* n, const snn_syn_desc* s)
     a.recs = recs;
     dfree(n, rowlen);
     dfree(n, tsum);
-    // Tile-binned delivery.  Single level: the tiles fit the scatter kernel's
-    // LDS tables and every weight has a 17-bit event field (code, or w_q +
-    // 65536 in range).  Two levels (8-bit codes): first by super tile of 65536
-    // targets, then by tile; for networks with more tiles than one LDS table.
-    a.ntiles = (n->N + snn::kTile - 1) / snn::kTile;
-    a.winh_q = tb.winh_q;
-    bool ok1 = a.ntiles <= snn::kMaxTiles;
-    if (s->record != SNN_REC_CODE8)
-        for (int32_t w : tb.wtab)
-            if (w != tb.winh_q && (w < -65536 || w > 65534)) ok1 = false;
-    const uint32_t nsuper = (uint32_t)(((uint64_t)n->N + (1u << snn::kSuperBits) - 1) >> snn::kSuperBits);
-    const bool ok2 = s->record == SNN_REC_CODE8 && nsuper <= snn::kMaxTiles;
+    // Tile-binned delivery (mode chosen above).
     n->binned_ok = ok1;
-    n->two_level_ok = ok2;
-    uint32_t mode = 0;
+    n->two_level_ok = mode == 2;   // two levels need rows laid out for them
     if (s->solver == SNN_SOLVER_EXACT) {
-        n->binned_ok = n->two_level_ok = false;   // the exact solver has its own queues
+        n->binned_ok = n->two_level_ok = false;
         st = setup_exact(n, tb);
         if (st) return st;
-    } else if (n->mode_pref == 2) mode = ok2 ? 2 : 0;
-    else if (n->mode_pref == 1) mode = ok1 ? 1 : 0;
-    else if (n->mode_pref < 0) mode = ok1 ? 1 : (ok2 ? 2 : 0);
+    }
     if (mode) {
         HIPCHK(n, snn::setup_kernels());
         // the expected in-degree equals the mean row length (every module alike)
         const double kin = tb.mean_out + 6.0 * std::sqrt(tb.mean_out + 1.0);
-        const double frac = mode == 2 ? 0.5 * n->bin_frac : n->bin_frac;   // two levels hold every event twice
+        // two-level networks are the largest: their bins hold half as much
+        // (a quarter of every row firing in one step by default)
+        const double frac = mode == 2 ? 0.5 * n->bin_frac : n->bin_frac;
         a.bin_cap_tile = (uint32_t)std::min(frac * (double)snn::kTile * kin + 4096.0, 1.0e9);
         e = dalloc(n, &a.bin_fill, (size_t)a.ntiles * snn::kFillStride);
         if (e == hipSuccess) e = dalloc(n, &a.bins, (size_t)a.ntiles * a.bin_cap_tile);
         if (e == hipSuccess && mode == 2) {
+            // segment lists: a row touches a super tile in one segment, cut in
+            // pieces of 256 records; capacity for the same fraction of every
+            // row firing at once (pieces beyond it are delivered directly)
             a.nsuper = nsuper;
-            a.sbin_cap = (uint32_t)std::min(frac * (double)(1u << snn::kSuperBits) * kin + 65536.0, 4.0e9);
-            e = dalloc(n, &a.sbin_fill, (size_t)nsuper * snn::kFillStride);
-            if (e == hipSuccess) e = dalloc(n, &a.sbins, (size_t)nsuper * a.sbin_cap);
+            a.sstart = sstart;
+            const double pieces = (double)n->N * (std::min<double>(nsuper, kin) + kin / 256.0) / nsuper;
+            a.dcap = (uint32_t)std::min(frac * pieces + 65536.0, 2.0e9);
+            e = dalloc(n, &a.dfill, (size_t)nsuper * snn::kFillStride);
+            if (e == hipSuccess) e = dalloc(n, &a.dsc, (size_t)nsuper * a.dcap);
         }
         if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (delivery bins)");
         HIPCHK(n, hipMemset(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride));
-        if (mode == 2) HIPCHK(n, hipMemset(a.sbin_fill, 0, 4 * (size_t)nsuper * snn::kFillStride));
+        if (mode == 2) HIPCHK(n, hipMemset(a.dfill, 0, 4 * (size_t)nsuper * snn::kFillStride));
         // Per-step switch: binning costs about one read and one write of every
         // future ring row (8 D N bytes at ~5.5 TB/s); direct delivery about one
         // global atomic per event (~27 G/s).  Equal at ~0.039 D N events.
-        if (n->bin_threshold_set) a.bin_threshold = n->bin_threshold_opt;
-        else a.bin_threshold = (uint64_t)(0.039 * n->D * (double)n->N);
+        n->bin_threshold_auto = (uint64_t)(0.039 * n->D * (double)n->N);
+        a.bin_threshold = n->bin_threshold_set ? n->bin_threshold_opt : n->bin_threshold_auto;
     }
     n->mode = mode;
     a.grp_atomic = n->mode == 1 ? 0u : 1u;
@@ -1144,6 +1177,34 @@ snn_status snn_export_rows(snn_net* n, uint32_t pre0, uint32_t cnt, uint64_t* ro
     const size_t rb = n->s.record == SNN_REC_CODE8 ? 4 : 8;
     if (m && rec_buf)
         HIPCHK(n, hipMemcpy(rec_buf, (const uint8_t*)n->a.recs + rp[0] * rb, m * rb, hipMemcpyDeviceToHost));
+    if (m && rec_buf && n->a.nsuper) {
+        // rows laid out by super tile: back to (delay, target) order, records
+        // target << 8 | code (within a (super tile, delay) run the targets
+        // ascend, and the super tiles come in order)
+        const uint32_t ns = n->a.nsuper;
+        std::vector<uint16_t> ss((size_t)cnt * ns);
+        HIPCHK(n, hipMemcpy(ss.data(), n->a.sstart + (size_t)pre0 * ns, ss.size() * 2, hipMemcpyDeviceToHost));
+        uint32_t* r = static_cast<uint32_t*>(rec_buf);
+        std::vector<uint32_t> row, out;
+        for (uint32_t i = 0; i < cnt; ++i) {
+            const uint64_t o = rp[i] - rp[0], len = rp[i + 1] - rp[i];
+            row.assign(r + o, r + o + len);
+            out.clear();
+            for (uint32_t b = 0; b < n->D; ++b)
+                for (uint32_t sp = 0; sp < ns; ++sp) {
+                    const uint32_t s0 = ss[(size_t)i * ns + sp];
+                    const uint32_t s1 = sp + 1 < ns ? ss[(size_t)i * ns + sp + 1] : (uint32_t)len;
+                    for (uint32_t k = s0; k < s1; ++k) {
+                        const uint32_t v = row[k];
+                        if (((v >> snn::kSegBits) & 31u) != b) continue;
+                        const uint32_t tgt = (sp << snn::kSegBits) | (v & ((1u << snn::kSegBits) - 1u));
+                        out.push_back((tgt << 8) | (v >> (snn::kSegBits + 5)));
+                    }
+                }
+            if (out.size() != len) return fail(n, SNN_E_STATE, "segmented row does not decode");
+            std::copy(out.begin(), out.end(), r + o);
+        }
+    }
     return SNN_OK;
 }
 
@@ -1272,7 +1333,7 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     Ctrl c0{}, c1{};
     e = hipStreamSynchronize(n->stream);
     if (e == hipSuccess) e = hipMemcpy(&c0, n->a.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost);
-    const bool fused = n->mode != 0 && n->a.d_min == 1;
+    const bool fused = seq(n) != 0 && n->a.d_min == 1;
     // kind of each launch slot: 0 update, 1 compact, 2 direct deliver, 3 scatter, 4 tile, 5 second pass
     double sum[6] = {0, 0, 0, 0, 0, 0};
     uint32_t cnt[6] = {0, 0, 0, 0, 0, 0};
@@ -1288,14 +1349,14 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
                 kind[i * kL] = 0;
             }
             if (e != hipSuccess) break;
-            if (n->mode != 0) {
-                if (n->mode == 2) {
+            if (seq(n) != 0) {
+                if (seq(n) == 2) {
                     e = snn::launch_compact(n->a, k, n->stream, &x[3]);
                     kind[i * kL + 3] = 1;
                 }
                 if (e == hipSuccess) e = snn::launch_scatter(n->a, k, n->max_len, n->scatter_blocks, n->stream, &x[1]);
                 kind[i * kL + 1] = 3;
-                if (e == hipSuccess && n->mode == 2) {
+                if (e == hipSuccess && seq(n) == 2) {
                     e = snn::launch_sub(n->a, k, n->scatter_blocks, n->stream, &x[4]);
                     kind[i * kL + 4] = 5;
                 }
@@ -1333,7 +1394,7 @@ snn_status snn_time_kernels(snn_net* n, uint32_t n_ms, snn_kernel_times* out)
     out->scatter_ms = avg(3);
     out->tile_ms = avg(4);
     out->sub_ms = avg(5);
-    out->deliver_ms = n->mode != 0 ? avg(3) + avg(4) + avg(5) : avg(2);
+    out->deliver_ms = seq(n) != 0 ? avg(3) + avg(4) + avg(5) : avg(2);
     out->step_ms = (sum[0] + sum[1] + sum[2] + sum[3] + sum[4] + sum[5]) / steps;
     out->steps = n_ms;
     out->rec_events = c1.rec_events - c0.rec_events;
@@ -1350,7 +1411,7 @@ snn_status snn_reset(snn_net* n)
     HIPCHK(n, hipMemsetAsync(a.grp_cnt, 0, sizeof(uint32_t) * 2 * a.ngrp, n->stream));
     HIPCHK(n, hipMemsetAsync(a.ctrl, 0, sizeof(Ctrl), n->stream));
     if (a.bin_fill) HIPCHK(n, hipMemsetAsync(a.bin_fill, 0, 4 * (size_t)a.ntiles * snn::kFillStride, n->stream));
-    if (a.sbin_fill) HIPCHK(n, hipMemsetAsync(a.sbin_fill, 0, 4 * (size_t)a.nsuper * snn::kFillStride, n->stream));
+    if (a.dfill) HIPCHK(n, hipMemsetAsync(a.dfill, 0, 4 * (size_t)a.nsuper * snn::kFillStride, n->stream));
     HIPCHK(n, snn::launch_init(a, n->stream));
     n->stdp_t = 0;   // a plastic network keeps the weights it has learned
     if (n->exact) {
@@ -1404,6 +1465,7 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
                 return fail(n, SNN_E_INVAL, "this delivery mode was not selected when the synapses were built");
         }
         n->mode = (uint32_t)value;
+        n->a.bin_threshold = threshold_in_force(n);
         HIPCHK(n, hipStreamSynchronize(n->stream));
         HIPCHK(n, hipMemset(reinterpret_cast<char*>(n->a.ctrl) + offsetof(Ctrl, step_ev), 0, sizeof(uint64_t) * 2));
         // direct delivery's compaction reads the group counts, which the
@@ -1421,7 +1483,7 @@ snn_status snn_set_option(snn_net* n, int key, int64_t value)
         if (value < 0) return fail(n, SNN_E_INVAL, "threshold must be >= 0");
         n->bin_threshold_set = true;
         n->bin_threshold_opt = (uint64_t)value;
-        n->a.bin_threshold = (uint64_t)value;
+        n->a.bin_threshold = threshold_in_force(n);
         break;
     case SNN_OPT_EXT_RATE_UHZ: {
         if (!n->built) return fail(n, SNN_E_STATE, "build the synapses before changing the drive");

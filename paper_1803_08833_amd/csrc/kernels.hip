@@ -4,12 +4,17 @@
 //   k_syn_gen     projection generation: per-pair Bernoulli trials, hits per row
 //   k_scan_*      row offsets (exclusive scan of row lengths)
 //   k_syn_out     projection write-out: delay buckets, records ordered by (delay, target)
+//   k_syn_out_seg the same for two-level networks, records ordered by (super tile,
+//                 delay, target), with each row's super-tile segment starts
 //   k_update      fused neuron step: ring read+clear, Poisson drive, LIF+SFA, ordered
 //                 block-local spike compaction
 //   k_compact     ordered global spike list + AER history
 //   k_deliver     wave-per-row-segment fan-out into the delay ring (int32 atomics)
 //   k_scatter     tile-binned delivery, phase A: events binned by target tile
 //   k_tile        tile-binned delivery, phase B: LDS accumulation, ring write-back
+//   k_seg_emit    two-level networks: the step's record segments listed per super tile
+//   k_seg_bin     two-level networks: each super tile's segments binned by tile
+//                 (or delivered directly in a step below the binning threshold)
 //
 // Nothing here is a dense contraction: the path is bound by HBM/L2 traffic and
 // atomics (update, delivery) or by 32-bit integer multiplies (Philox), so no MFMA.
@@ -114,6 +119,19 @@ __global__ __launch_bounds__(256) void k_init(StepArgs a)
 // (delay, target) order.  syn_flush counts (lane b: hits of bucket b) or, with
 // FILL, writes (lane b: the next free offset of bucket b).
 // ---------------------------------------------------------------------------
+// Delay bucket and weight draw of the synapse row -> j (ATTR stream).
+__device__ __forceinline__ void hit_attr(const BuildArgs& a, uint32_t row, uint32_t j, uint32_t& b, uint32_t& wsel)
+{
+    const uint4 r = philox(row, j, kStreamAttr, 0u, a.key0, a.key1);
+    if (a.delay_exp) {
+        b = 0;
+        for (uint32_t k = 0; k + 1u < a.D; ++k) b += a.dthr[k] <= r.x ? 1u : 0u;
+    } else {
+        b = __umulhi(r.x, a.D);
+    }
+    wsel = r.y;
+}
+
 template <bool FILL>
 __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q, uint32_t n,
                                           uint32_t row, bool exc, uint32_t lane, uint32_t& pos,
@@ -126,14 +144,7 @@ __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q,
         uint32_t j = 0, b = 0xFFFFFFFFu, wsel = 0;
         if (valid) {
             j = q[e];
-            const uint4 r = philox(row, j, kStreamAttr, 0u, a.key0, a.key1);
-            if (a.delay_exp) {
-                b = 0;
-                for (uint32_t k = 0; k + 1u < a.D; ++k) b += a.dthr[k] <= r.x ? 1u : 0u;
-            } else {
-                b = __umulhi(r.x, a.D);
-            }
-            wsel = r.y;
+            hit_attr(a, row, j, b, wsel);
         }
         for (uint32_t bb = 0; bb < a.D; ++bb) {
             const uint64_t mb = __ballot(b == bb);
@@ -322,6 +333,99 @@ __global__ __launch_bounds__(256) void k_syn_out(BuildArgs a)
     if (lane < a.D) a.bend[(size_t)row * a.D + lane] = (uint16_t)(v > 65535u ? 65535u : v);
     pos = v - (lane < a.D ? pos : 0u);   // lane b: start of bucket b
     syn_flush<true>(a, hits, n, row, exc, lane, pos, rbase);
+}
+
+// Write-out of a two-level network's row (8-bit codes; one wave per row), laid
+// out by super tile of 2^kSegBits targets: every hit's delay bucket from its
+// ATTR draw (as above), counts per (super tile, bucket) in the wave's LDS
+// table, whose exclusive scan in (super tile, bucket) order gives each super
+// tile's segment start and each (super tile, bucket) run's first slot; the
+// hits, taken in target order, then go to their run's cursor, so a run keeps
+// its targets ascending.  Record: target & (2^kSegBits - 1) | bucket <<
+// kSegBits | code << (kSegBits + 5).  The bucket ends of the whole row (the
+// (delay, target) order every other layout uses) are written too.
+__global__ __launch_bounds__(256) void k_syn_out_seg(BuildArgs a)
+{
+    constexpr uint32_t KB = 32;   // table entries per super tile (>= kMaxD)
+    __shared__ uint32_t tab_s[4][kMaxSuper * KB];
+    const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
+    const uint32_t rl = blockIdx.x * 4u + wv;
+    if (rl >= a.nrows) return;   // no workgroup barrier below: each wave works alone
+    uint32_t* const tab = tab_s[wv];
+    const uint32_t row = a.row0 + rl;
+    const uint32_t* const hits = a.slab + (size_t)rl * a.slab_cap;
+    const bool exc = (row % a.M) < a.n_exc;
+    uint32_t n = a.rowlen[row];
+    n = n < a.slab_cap ? n : a.slab_cap;
+    const uint64_t rbase = a.row_ptr[row];
+    if (rbase + n > a.rec_cap) {
+        if (lane == 0) atomicOr(&a.ctrl->err, 4u);
+        return;
+    }
+    const uint32_t ns = a.nsuper;
+    for (uint32_t i = lane; i < ns * KB; i += 64u) tab[i] = 0;
+    wave_sync();
+    for (uint32_t base = 0; base < n; base += 64u) {
+        const uint32_t e = base + lane;
+        if (e < n) {
+            const uint32_t j = hits[e];
+            uint32_t b, wsel;
+            hit_attr(a, row, j, b, wsel);
+            atomicAdd(&tab[(j >> kSegBits) * KB + b], 1u);
+        }
+    }
+    wave_sync();
+    // bucket ends of the whole row: lane b totals bucket b over the super tiles
+    {
+        uint32_t c = 0;
+        if (lane < a.D)
+            for (uint32_t sp = 0; sp < ns; ++sp) c += tab[sp * KB + lane];
+        const uint32_t v = wave_incl_scan<uint32_t>(lane < a.D ? c : 0u, lane);
+        if (lane < a.D) a.bend[(size_t)row * a.D + lane] = (uint16_t)(v > 65535u ? 65535u : v);
+    }
+    // lane s: super tile s's segment length, its start, then its runs' cursors
+    uint32_t seg = 0;
+    if (lane < ns)
+        for (uint32_t b = 0; b < a.D; ++b) seg += tab[lane * KB + b];
+    const uint32_t incl = wave_incl_scan<uint32_t>(seg, lane);
+    wave_sync();
+    if (lane < ns) {
+        uint32_t at = incl - seg;
+        a.sstart[(size_t)row * ns + lane] = (uint16_t)at;
+        for (uint32_t b = 0; b < a.D; ++b) {
+            const uint32_t c = tab[lane * KB + b];
+            tab[lane * KB + b] = at;
+            at += c;
+        }
+    }
+    wave_sync();
+    uint32_t* const out = reinterpret_cast<uint32_t*>(a.recs);
+    for (uint32_t base = 0; base < n; base += 64u) {
+        const uint32_t e = base + lane;
+        const bool valid = e < n;
+        uint32_t j = 0, b = 0, wsel = 0, key = 0;
+        if (valid) {
+            j = hits[e];
+            hit_attr(a, row, j, b, wsel);
+            key = (j >> kSegBits) * KB + b;
+        }
+        // the chunk's distinct (super tile, bucket) runs in turn; within a run
+        // the lanes keep their (target) order
+        uint64_t pend = __ballot(valid);
+        while (pend) {
+            const uint32_t k0 = readlane(key, (uint32_t)__builtin_ctzll(pend));
+            const uint64_t m = __ballot(valid && key == k0);
+            const uint32_t c0 = tab[k0];
+            if (valid && key == k0) {
+                const uint32_t code = exc ? __umulhi(wsel, 255u) : 255u;
+                out[rbase + c0 + mbcnt(m)] = (j & ((1u << kSegBits) - 1u)) | (b << kSegBits) | (code << (kSegBits + 5u));
+            }
+            wave_sync();
+            if (lane == 0) tab[k0] = c0 + popc(m);
+            wave_sync();
+            pend &= ~m;
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -823,8 +927,7 @@ __device__ __forceinline__ void seg_decode(const StepArgs& a, SegLoad& L)
     }
 }
 
-// A bin covers 2^SHIFT targets: 1024-target tiles (SHIFT = kTileBits) or, for
-// two-level binning, 65536-target super tiles (SHIFT = kSuperBits).  The event
+// A bin covers the 2^SHIFT targets of a tile (SHIFT = kTileBits).  The event
 // code keeps the target's low SHIFT bits, the delay bucket and the weight
 // field: target & (2^SHIFT - 1) | bucket << SHIFT | weight field << (SHIFT + 5).
 template <uint32_t SHIFT>
@@ -911,20 +1014,15 @@ __device__ __forceinline__ void write_history(const StepArgs& a, const uint32_t*
 // spike records in the per-block lists; the workgroups write the AER history
 // in ascending order; workgroup 0 publishes the spike count and the step's
 // event totals.
-//
-// TWO (two-level binning, 8-bit-code records, networks with more update blocks
-// than one LDS scan covers): the spike list, history and totals come from the
-// compaction kernel before, and the events are binned by 65536-target super
-// tile; k_sub then splits each super tile's bin into its tiles' bins.
-template <bool CODE8, bool TWO>
+template <bool CODE8>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
 {
-    constexpr uint32_t SHIFT = TWO ? kSuperBits : kTileBits;
+    constexpr uint32_t SHIFT = kTileBits;
     __shared__ uint32_t stage[kStage];
     __shared__ uint32_t tcnt2[2][kMaxTiles];   // counts, then fill cursor (by chunk parity)
     __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
-    __shared__ uint32_t boff[TWO ? 1 : kMaxTiles + 1];
+    __shared__ uint32_t boff[kMaxTiles + 1];
     __shared__ uint4 info_s[kChunkItems + kScatterWaves];  // spike records of the chunk whose segments load next
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
@@ -933,14 +1031,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));   // uniform: scalar registers
     if (CODE8 && tid < 256u) cb_s[tid] = a.cb[tid];
     const uint32_t t = a.ctrl->t0 + k;
-    const uint32_t nb = a.nblk;          // single level: <= kMaxTiles
+    const uint32_t nb = a.nblk;          // <= kMaxTiles
     bool binned;
     uint32_t n;
-    if (TWO) {
-        if (CODE8) __syncthreads();
-        binned = step_binned(a, t);
-        n = a.ctrl->nspk;
-    } else {
+    {
         // exclusive scan of the update blocks' spike counts (two blocks per
         // thread) and the step's recurrent and external event totals: the
         // event total decides binned vs direct; workgroup 0 books the totals
@@ -984,20 +1078,20 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         }
     }
     // spike s of the step (wave-uniform s)
-    auto spike = [&](uint32_t s) { return TWO ? a.spk[s] : spike_rec(a, boff, nb, s); };
+    auto spike = [&](uint32_t s) { return spike_rec(a, boff, nb, s); };
     if (!binned) {
         const uint32_t items = n * smax;    // host guarantees N * smax < 2^32
         const uint32_t nw = gridDim.x * kScatterWaves;
         for (uint32_t it = blockIdx.x * kScatterWaves + wv; it < items; it += nw)
             deliver_item<4, CODE8>(a, t, spike(it / smax), it % smax, lane, cb_s);
-        if (!TWO) write_history(a, boff, nb, n, t);
+        write_history(a, boff, nb, n, t);
         return;
     }
     const uint32_t items = n * smax;
-    const uint32_t nt = TWO ? a.nsuper : a.ntiles;
-    const uint32_t cap = TWO ? a.sbin_cap : a.bin_cap_tile;
-    uint32_t* const fill = TWO ? a.sbin_fill : a.bin_fill;
-    uint32_t* const bins = TWO ? a.sbins : a.bins;
+    const uint32_t nt = a.ntiles;
+    const uint32_t cap = a.bin_cap_tile;
+    uint32_t* const fill = a.bin_fill;
+    uint32_t* const bins = a.bins;
     // chunk size: large chunks bin better, but every workgroup should get work
     uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
     per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
@@ -1015,7 +1109,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     auto fetch_info = [&](uint32_t c0, uint32_t c1) {
         const uint32_t it = c0 + wv + kScatterWaves * lane;
         if (lane < kSegPerWave && it < c1)
-            nxt = TWO ? a.spk[it / smax] : spike_rec<false>(a, boff, nb, it / smax);
+            nxt = spike_rec<false>(a, boff, nb, it / smax);
         else
             nxt = make_uint4(0, 0, 0, 0);
     };
@@ -1118,117 +1212,349 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     }
     spill = wave_sum<unsigned long long>(spill);
     if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
-    if (!TWO) write_history(a, boff, nb, n, t);
+    write_history(a, boff, nb, n, t);
 }
 
-// Two-level binning, second pass: every super tile's bin (codes of 65536
-// targets) is cut into chunks of up to kStage events; a workgroup takes a
-// chunk, counts its events by tile (64 tiles per super tile), reserves room in
-// those tiles' bins, stages the events sorted by tile with the tile code
-// (target & 1023 | bucket << 10 | code << 15) and writes the runs.  Events
-// beyond a tile bin's capacity take the direct atomic path.
-constexpr uint32_t kSubPerThread = kStage / kScatterThreads;   // 20 codes per thread
-__global__ __launch_bounds__(kScatterThreads) void k_sub(StepArgs a, uint32_t k)
+// ---------------------------------------------------------------------------
+// Two-level delivery: 8-bit-code networks with more tiles than one LDS table,
+// rows laid out by super tile (k_syn_out_seg).  The step's spike list,
+// history and event totals come from k_compact.
+//
+// k_seg_emit cuts every spike's row at its super tiles' segment starts and
+// lists each nonempty segment, in pieces of at most 256 records, in its super
+// tile's segment list.  A workgroup takes kEmitPass spikes per pass (each wave
+// kEmitPerWave of them; lane s of a wave handles super tile s): the pieces are
+// counted per super tile in LDS, one global atomic per super tile reserves the
+// pass's room, and the pieces are written.  A piece beyond its list's
+// capacity is delivered on the spot by one lane (a fallback, counted as
+// overflow like a full bin).
+// ---------------------------------------------------------------------------
+constexpr uint32_t kEmitThreads = 1024;
+constexpr uint32_t kEmitPerWave = 4;
+constexpr uint32_t kEmitPass = kEmitThreads / 64 * kEmitPerWave;
+
+// Record v of super tile `sup` (segmented layout) as a ring atomic.
+__device__ __forceinline__ void seg_atomic(const StepArgs& a, uint32_t t, uint32_t sup, uint32_t v, const int32_t* cb)
 {
-    constexpr uint32_t NSUB = 1u << (kSuperBits - kTileBits);   // tiles per super tile
-    __shared__ uint32_t stage[kStage];
-    __shared__ uint32_t cpre[kMaxTiles + 1];   // chunks before each super tile
-    __shared__ uint32_t scnt[kMaxTiles];       // events held by each super tile's bin
-    __shared__ uint32_t tcnt[NSUB], toff[NSUB], tres[NSUB];
+    const uint32_t tgt = (sup << kSegBits) | (v & ((1u << kSegBits) - 1u));
+    const uint32_t slot = (t + a.d_min + ((v >> kSegBits) & 31u)) & (kRing - 1u);
+    __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, cb[v >> (kSegBits + 5u)], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ __launch_bounds__(kEmitThreads) void k_seg_emit(StepArgs a, uint32_t k)
+{
+    __shared__ uint32_t cnt[kMaxSuper];   // pieces of the pass per super tile
+    __shared__ uint32_t res[kMaxSuper];   // their reserved start in the list
     __shared__ int32_t cb_s[256];
-    __shared__ uint32_t wsum[kScatterWaves];
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint32_t t = a.ctrl->t0 + k;
-    if (!step_binned(a, t)) return;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
     if (tid < 256u) cb_s[tid] = a.cb[tid];
-    const uint32_t ns = a.nsuper;   // <= kMaxTiles
-    {
-        const uint32_t i0 = 2u * tid, i1 = 2u * tid + 1u;
-        uint32_t f0 = i0 < ns ? a.sbin_fill[(size_t)i0 * kFillStride] : 0u;
-        uint32_t f1 = i1 < ns ? a.sbin_fill[(size_t)i1 * kFillStride] : 0u;
-        f0 = f0 < a.sbin_cap ? f0 : a.sbin_cap;
-        f1 = f1 < a.sbin_cap ? f1 : a.sbin_cap;
-        if (i0 < ns) scnt[i0] = f0;
-        if (i1 < ns) scnt[i1] = f1;
-        const uint32_t c0 = (f0 + kStage - 1u) / kStage, c1 = (f1 + kStage - 1u) / kStage;
-        const uint32_t sum = c0 + c1;
-        const uint32_t inc = wave_incl_scan<uint32_t>(sum, lane);
-        if (lane == 63u) wsum[wv] = inc;
-        __syncthreads();
-        uint32_t off = inc - sum;
-        for (uint32_t i = 0; i < wv; ++i) off += wsum[i];
-        if (i0 <= ns) cpre[i0] = off;
-        if (i1 <= ns) cpre[i1] = off + c0;
-        if (i1 + 1u == ns) cpre[ns] = off + sum;
-        __syncthreads();
-    }
-    const uint32_t total = cpre[ns];
+    const uint32_t t = a.ctrl->t0 + k;
+    const uint32_t n = a.ctrl->nspk;
+    const uint32_t ns = a.nsuper;
+    const uint32_t* const recs = reinterpret_cast<const uint32_t*>(a.recs);
     unsigned long long spill = 0;
-    for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
-        uint32_t lo = 0, hi = ns;   // cpre[lo] <= c < cpre[hi]
-        while (hi - lo > 1u) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (cpre[mid] <= c) lo = mid;
-            else hi = mid;
-        }
-        const uint32_t sup = lo;
-        const uint32_t e0 = (c - cpre[sup]) * kStage;
-        const uint32_t cnt = (scnt[sup] - e0) < kStage ? scnt[sup] - e0 : kStage;
-        const uint32_t* src = a.sbins + (size_t)sup * a.sbin_cap + e0;
-        uint32_t code[kSubPerThread];
+    for (uint32_t p0 = blockIdx.x * kEmitPass; p0 < n; p0 += gridDim.x * kEmitPass) {
+        if (tid < kMaxSuper) cnt[tid] = 0;
+        __syncthreads();
+        uint32_t st[kEmitPerWave], len[kEmitPerWave], off[kEmitPerWave];
+        uint64_t rb[kEmitPerWave];
 #pragma unroll
-        for (uint32_t i = 0; i < kSubPerThread; ++i) {
-            const uint32_t p = i * kScatterThreads + tid;
-            code[i] = p < cnt ? src[p] : 0xFFFFFFFFu;
-        }
-        if (tid < NSUB) tcnt[tid] = 0;
-        __syncthreads();
-#pragma unroll
-        for (uint32_t i = 0; i < kSubPerThread; ++i)
-            if (code[i] != 0xFFFFFFFFu) atomicAdd(&tcnt[(code[i] & 0xFFFFu) >> kTileBits], 1u);
-        __syncthreads();
-        if (wv == 0) {   // NSUB == 64: one wave scans and reserves
-            const uint32_t v = tcnt[lane];
-            const uint32_t inc = wave_incl_scan<uint32_t>(v, lane);
-            const uint32_t tile = sup * NSUB + lane;
-            toff[lane] = inc - v;
-            tcnt[lane] = inc - v;
-            tres[lane] = v ? atomicAdd(&a.bin_fill[(size_t)tile * kFillStride], v) : 0u;
-        }
-        __syncthreads();
-#pragma unroll
-        for (uint32_t i = 0; i < kSubPerThread; ++i) {
-            if (code[i] == 0xFFFFFFFFu) continue;
-            const uint32_t c16 = code[i] & 0xFFFFu;
-            const uint32_t p = atomicAdd(&tcnt[c16 >> kTileBits], 1u);
-            const uint32_t bucket = (code[i] >> kSuperBits) & 31u, wf = code[i] >> (kSuperBits + 5u);
-            stage[p] = (c16 & (kTile - 1u)) | (bucket << kTileBits) | (wf << 15);
-        }
-        __syncthreads();
-        const uint32_t cap = a.bin_cap_tile;
-        for (uint32_t st = wv; st < NSUB; st += kScatterWaves) {
-            const uint32_t o0 = toff[st];
-            const uint32_t m = tcnt[st] - o0;
-            if (m == 0) continue;
-            const uint32_t tile = sup * NSUB + st;
-            const uint32_t r0 = tres[st];
-            uint32_t* dst = a.bins + (size_t)tile * cap;
-            for (uint32_t e = lane; e < m; e += 64u) {
-                const uint32_t cd = stage[o0 + e];
-                const uint32_t pos = r0 + e;
-                if (pos < cap) {
-                    dst[pos] = cd;
-                } else {
-                    const uint32_t tgt = (tile << kTileBits) | (cd & (kTile - 1u));
-                    const uint32_t b = (cd >> kTileBits) & 31u;
-                    const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
-                    __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, decode_weight(cd >> 15, true, cb_s, 0),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    spill += 1;
+        for (uint32_t i = 0; i < kEmitPerWave; ++i) {
+            const uint32_t sp = p0 + wv * kEmitPerWave + i;   // wave-uniform
+            st[i] = 0;
+            len[i] = 0;
+            off[i] = 0;
+            rb[i] = 0;
+            if (sp < n) {
+                const uint4 r = a.spk[sp];   // {gid, row length, row start lo, hi}
+                rb[i] = (uint64_t)r.z | ((uint64_t)r.w << 32);
+                const uint32_t s0 = lane < ns ? (uint32_t)a.sstart[(size_t)r.x * ns + lane] : r.y;
+                const uint32_t nx = (uint32_t)__shfl_down((int)s0, 1);
+                const uint32_t s1 = lane + 1u < ns ? nx : r.y;
+                if (lane < ns) {
+                    st[i] = s0;
+                    len[i] = s1 - s0;
                 }
+                if (len[i]) off[i] = atomicAdd(&cnt[lane], (len[i] + 255u) >> 8);
             }
         }
         __syncthreads();
+        if (tid < ns) {
+            const uint32_t c = cnt[tid];
+            res[tid] = c ? atomicAdd(&a.dfill[(size_t)tid * kFillStride], c) : 0u;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t i = 0; i < kEmitPerWave; ++i) {
+            if (!len[i]) continue;
+            uint32_t pos = res[lane] + off[i];
+            uint64_t r0 = rb[i] + st[i];
+            for (uint32_t q = 0; q < len[i]; q += 256u, ++pos, r0 += 256u) {
+                const uint32_t pl = (len[i] - q) < 256u ? len[i] - q : 256u;
+                if (pos < a.dcap) {
+                    a.dsc[(size_t)lane * a.dcap + pos] = make_uint2((uint32_t)r0, (uint32_t)(r0 >> 32) | (pl << 8));
+                } else {
+                    for (uint32_t e = 0; e < pl; ++e) seg_atomic(a, t, lane, recs[r0 + e], cb_s);
+                    spill += pl;
+                }
+            }
+        }
+        __syncthreads();   // cnt and res are reused by the next pass
+    }
+    spill = wave_sum<unsigned long long>(spill);
+    if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
+}
+
+// k_seg_bin: the super tiles' segment lists are cut into chunks of up to
+// kBinDesc pieces, all of one super tile.  A workgroup takes a chunk: its
+// pieces' descriptors and the exclusive scan of their lengths go to LDS, and
+// the chunk's records, read as one concatenated sequence, are binned in rounds
+// of up to kStage records.  A round is 80 slots of 256 records, five per
+// wave; a wave holds the pieces of a slot in registers (lane l: piece f + l)
+// and each record finds its own piece by comparing its position with their
+// starts.  The records are counted by tile (kSegTiles tiles per super tile;
+// the returned count is the record's rank in its tile), one global atomic per
+// tile reserves room in its bin, the tile codes (target & 1023 | bucket << 10
+// | code << 15) are staged in LDS at their tile's offset plus their rank, and
+// each tile's run is written into its bin while the next round's records are
+// being read.  Pieces are short (a row reaches most super tiles with a few
+// dozen to a few hundred records), so a wave does not take one piece per
+// 256-record slot.  Events beyond a tile bin's capacity take a direct ring
+// atomic.  In a step below the binning threshold every piece is delivered
+// directly instead, one wave per piece.
+constexpr uint32_t kBinDesc = kScatterThreads;   // pieces per chunk
+// lanes per tile run in the write phase (16 measured faster than 8 or 4 on the
+// 96x96 grid: 512 tiles of ~40 events per round)
+constexpr uint32_t kSegRunLanes = 16;
+constexpr uint32_t kGather = kStage / kScatterThreads;   // records per lane and round
+
+__global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_t k)
+{
+    __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t tcnt[kSegTiles];       // records of the round per tile
+    __shared__ uint32_t toff[kSegTiles];       // start of each tile's run in `stage`
+    __shared__ uint32_t tres[kSegTiles];       // reserved offset in the tile's bin
+    __shared__ uint32_t cpre[kMaxSuper + 1];   // work units (chunks, or pieces) before each super tile
+    __shared__ uint32_t pcnt[kMaxSuper];       // pieces listed per super tile
+    __shared__ uint2 dsc_s[kBinDesc];          // the chunk's pieces
+    __shared__ uint32_t pref[kBinDesc + 1];    // exclusive scan of their lengths
+    __shared__ uint32_t first[kChunkItems];    // piece holding each slot's first record
+    __shared__ int32_t cb_s[256];
+    __shared__ uint32_t wsum[kScatterWaves];
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+    if (tid < 256u) cb_s[tid] = a.cb[tid];
+    const uint32_t t = a.ctrl->t0 + k;
+    const bool binned = step_binned(a, t);
+    const uint32_t ns = a.nsuper;
+    const uint32_t unit = binned ? kBinDesc : 1u;
+    if (wv == 0) {
+        uint32_t f = lane < ns ? a.dfill[(size_t)lane * kFillStride] : 0u;
+        f = f < a.dcap ? f : a.dcap;
+        const uint32_t c = (f + unit - 1u) / unit;
+        const uint32_t inc = wave_incl_scan<uint32_t>(c, lane);
+        if (lane < ns) {
+            pcnt[lane] = f;
+            cpre[lane + 1u] = inc;
+        }
+        if (lane == 0) cpre[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t total = cpre[ns];
+    const uint32_t* const recs = reinterpret_cast<const uint32_t*>(a.recs);
+    auto super_of = [&](uint32_t u) {   // cpre[s] <= u < cpre[s + 1] (u wave-uniform)
+        uint32_t lo = 0, hi = ns;
+        while (hi - lo > 1u) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (cpre[mid] <= u) lo = mid;
+            else hi = mid;
+        }
+        return (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+    };
+    if (!binned) {
+        const uint32_t nw = gridDim.x * kScatterWaves;
+        for (uint32_t it = blockIdx.x * kScatterWaves + wv; it < total; it += nw) {
+            const uint32_t sup = super_of(it);
+            const uint2 d = a.dsc[(size_t)sup * a.dcap + (it - cpre[sup])];
+            const uint64_t r0 = (uint64_t)d.x | ((uint64_t)(d.y & 255u) << 32);
+            const uint32_t len = d.y >> 8;
+            uint32_t v[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u) {
+                const uint32_t e = 64u * u + lane;
+                v[u] = recs[r0 + (e < len ? e : len - 1u)];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4u; ++u)
+                if (64u * u + lane < len) seg_atomic(a, t, sup, v[u], cb_s);
+        }
+        return;
+    }
+    unsigned long long spill = 0;
+    const uint32_t nt = kSegTiles;
+    const uint32_t cap = a.bin_cap_tile;
+    for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
+        const uint32_t sup = super_of(c);
+        const uint32_t d0 = (c - cpre[sup]) * kBinDesc;
+        const uint32_t nd = (pcnt[sup] - d0) < kBinDesc ? pcnt[sup] - d0 : kBinDesc;
+        // the chunk's descriptors and the exclusive scan of their lengths
+        // (one piece per thread)
+        if (tid < kBinDesc) {
+            const uint2 d = tid < nd ? a.dsc[(size_t)sup * a.dcap + d0 + tid] : make_uint2(0, 0);
+            const uint32_t len = d.y >> 8;
+            const uint32_t inc = wave_incl_scan<uint32_t>(len, lane);
+            dsc_s[tid] = d;
+            pref[tid + 1u] = inc;   // within the wave; waves' totals added below
+            if (lane == 63u) wsum[wv] = inc;
+        }
+        if (tid < nt) tcnt[tid] = 0;
+        __syncthreads();
+        if (tid < kBinDesc) {
+            uint32_t add = 0;
+            for (uint32_t i = 0; i < wv; ++i) add += wsum[i];
+            pref[tid + 1u] += add;
+            if (tid == 0) pref[0] = 0;
+        }
+        __syncthreads();
+        const uint32_t R = pref[kBinDesc];   // records of the chunk
+        // slot j of a round: records q0 + 256 j .. + 255 of the chunk's
+        // concatenated pieces, taken by wave j mod 16; the piece holding its
+        // first record is found by one thread per slot
+        auto find_first = [&](uint32_t q0) {
+            if (tid < kChunkItems) {
+                const uint32_t P = q0 + 256u * tid;
+                uint32_t lo = 0, hi = kBinDesc;   // pref[lo] <= P < pref[hi]
+                while (hi - lo > 1u) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (pref[mid] <= P) lo = mid;
+                    else hi = mid;
+                }
+                first[tid] = lo;
+            }
+        };
+        // the round's records into v: a slot's pieces (one per lane: start,
+        // length prefix) sit in registers, and each record finds its piece by
+        // comparing its position with the prefixes
+        uint32_t v[kGather], rk[kGather];
+        auto gather = [&](uint32_t q0) {
+#pragma unroll
+            for (uint32_t j = 0; j < kSegPerWave; ++j) {
+                const uint32_t P = q0 + 256u * (wv + kScatterWaves * j);
+                const uint32_t f = first[wv + kScatterWaves * j];
+                const uint32_t fl = f + lane < kBinDesc ? f + lane : kBinDesc - 1u;
+                const uint32_t pf = pref[fl];
+                const uint2 dd = dsc_s[fl];
+                // the window: pieces f .. f + 63, ending where piece f + 64 starts
+                const uint32_t wend = pref[f + 64u < kBinDesc ? f + 64u : kBinDesc];
+                // window pieces starting inside the slot, besides the first (uniform)
+                const uint64_t inside = __ballot(lane >= 1u && f + lane < kBinDesc && pf < P + 256u && pf < R);
+                const uint32_t np = 1u + popc(inside);
+#pragma unroll
+                for (uint32_t u = 0; u < 4u; ++u) {
+                    const uint32_t p = P + 64u * u + lane;
+                    uint32_t k = 0;
+                    for (uint32_t l = 1; l < np; ++l) k += readlane(pf, l) <= p ? 1u : 0u;
+                    uint32_t lo32 = 0, hi8 = 0, st = 0;
+                    for (uint32_t l = 0; l < np; ++l)
+                        if (k == l) {
+                            lo32 = readlane(dd.x, l);
+                            hi8 = readlane(dd.y, l) & 255u;
+                            st = readlane(pf, l);
+                        }
+                    if (p >= wend && p < R) {
+                        // past the window (more than 64 pieces in 256 records):
+                        // the piece from the scanned lengths
+                        uint32_t lo = f + 64u, hi = kBinDesc;   // pref[lo] <= p < pref[hi]
+                        while (hi - lo > 1u) {
+                            const uint32_t mid = (lo + hi) >> 1;
+                            if (pref[mid] <= p) lo = mid;
+                            else hi = mid;
+                        }
+                        lo32 = dsc_s[lo].x;
+                        hi8 = dsc_s[lo].y & 255u;
+                        st = pref[lo];
+                    }
+                    const uint64_t at = ((uint64_t)hi8 << 32 | lo32) + (p - st);
+                    v[4u * j + u] = p < R ? recs[at] : 0u;
+                }
+            }
+        };
+        find_first(0);
+        __syncthreads();
+        gather(0);
+        for (uint32_t q0 = 0; q0 < R; q0 += kStage) {
+            // 1. histogram by tile; the returned count is the record's rank
+            //    among the round's records of its tile
+#pragma unroll
+            for (uint32_t i = 0; i < kGather; ++i) {
+                const uint32_t p = q0 + 256u * (wv + kScatterWaves * (i >> 2)) + 64u * (i & 3u) + lane;
+                rk[i] = p < R ? atomicAdd(&tcnt[(v[i] >> kTileBits) & (kSegTiles - 1u)], 1u) : 0u;
+            }
+            __syncthreads();
+            // 2. exclusive scan of the counts (one tile per thread)
+            //    and reservation in the bins
+            if (tid < nt) {
+                const uint32_t cn = tcnt[tid];
+                const uint32_t inc = wave_incl_scan<uint32_t>(cn, lane);
+                if (lane == 63u) wsum[wv] = inc;
+                toff[tid] = inc - cn;   // within the wave for now
+                tres[tid] = cn ? atomicAdd(&a.bin_fill[(size_t)(sup * kSegTiles + tid) * kFillStride], cn) : 0u;
+            }
+            __syncthreads();
+            if (tid < nt) {
+                uint32_t add = 0;
+                for (uint32_t i = 0; i < wv; ++i) add += wsum[i];
+                toff[tid] += add;
+            }
+            __syncthreads();
+            // 3. tile codes staged sorted by tile, each at its tile's start
+            //    plus its rank
+#pragma unroll
+            for (uint32_t i = 0; i < kGather; ++i) {
+                const uint32_t p = q0 + 256u * (wv + kScatterWaves * (i >> 2)) + 64u * (i & 3u) + lane;
+                if (p < R) {
+                    const uint32_t x = v[i];
+                    stage[toff[(x >> kTileBits) & (kSegTiles - 1u)] + rk[i]] =
+                        (x & (kTile - 1u)) | (((x >> kSegBits) & 31u) << kTileBits) | ((x >> (kSegBits + 5u)) << 15);
+                }
+            }
+            __syncthreads();
+            // the next round's records are read while this round's runs are
+            // written
+            const bool more = q0 + kStage < R;
+            if (more) find_first(q0 + kStage);
+            __syncthreads();
+            if (more) gather(q0 + kStage);
+            // 4. contiguous runs into the bins: each group of kSegRunLanes lanes
+            // writes one tile's run at a time
+            const uint32_t rl = tid % kSegRunLanes;
+            for (uint32_t tt = tid / kSegRunLanes; tt < nt; tt += kScatterThreads / kSegRunLanes) {
+                const uint32_t o0 = toff[tt];
+                const uint32_t cnt = tcnt[tt];
+                const uint32_t r0 = tres[tt];
+                const uint32_t tile = sup * kSegTiles + tt;
+                uint32_t* dst = a.bins + (size_t)tile * cap;
+                for (uint32_t e = rl; e < cnt; e += kSegRunLanes) {
+                    const uint32_t code = stage[o0 + e];
+                    const uint32_t pos = r0 + e;
+                    if (pos < cap) {
+                        dst[pos] = code;
+                    } else {
+                        const uint32_t tgt = (tile << kTileBits) | (code & (kTile - 1u));
+                        const uint32_t b = (code >> kTileBits) & 31u;
+                        const uint32_t slot = (t + a.d_min + b) & (kRing - 1u);
+                        __hip_atomic_fetch_add(a.ring + (size_t)slot * a.N + tgt, cb_s[code >> 15], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        spill += 1;
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid < nt) tcnt[tid] = 0;   // the next round's histogram
+            __syncthreads();
+        }
     }
     spill = wave_sum<unsigned long long>(spill);
     if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
@@ -1440,9 +1766,9 @@ __global__ __launch_bounds__(kTileThreads) void k_tile(StepArgs a, uint32_t k)
     extern __shared__ int32_t acc[];      // [D][1024]
     const uint32_t t = a.ctrl->t0 + k;
     if (blockIdx.x == 0 && threadIdx.x == 0) a.ctrl->hist_n += a.ctrl->nspk;   // step t's history is complete
+    if (blockIdx.x == 0 && threadIdx.x < a.nsuper)
+        a.dfill[(size_t)threadIdx.x * kFillStride] = 0u;   // two levels: the second pass has consumed the lists
     if (step_binned(a, t)) {
-        for (uint32_t i = blockIdx.x * kTileThreads + threadIdx.x; i < a.nsuper; i += gridDim.x * kTileThreads)
-            a.sbin_fill[(size_t)i * kFillStride] = 0u;   // the second pass has consumed them
         for (uint32_t tt = blockIdx.x; tt < a.ntiles; tt += gridDim.x) {
             tile_work<CODE8, UPD, false>(a, tt, t, true, true, acc);
             __syncthreads();   // the LDS rows are reloaded for the next tile
@@ -1808,7 +2134,8 @@ hipError_t launch_syn_gen(const BuildArgs& a, hipStream_t s)
 hipError_t launch_syn_out(const BuildArgs& a, hipStream_t s)
 {
     if (a.nrows == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_syn_out, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    if (a.nsuper) hipLaunchKernelGGL(k_syn_out_seg, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_syn_out, dim3(cdiv(a.nrows, 4)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1871,15 +2198,15 @@ hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint3
                           hipStream_t s, const LaunchEv* ev)
 {
     const uint32_t smax = max_len ? cdiv(max_len, 256) : 1u;
-    if (a.nsuper) SNN_LAUNCH(ev, (k_scatter<true, true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
-    else if (a.record == 1u) SNN_LAUNCH(ev, (k_scatter<true, false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
-    else SNN_LAUNCH(ev, (k_scatter<false, false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    if (a.nsuper) SNN_LAUNCH(ev, k_seg_emit, dim3(blocks), dim3(kEmitThreads), 0, s, a, k);
+    else if (a.record == 1u) SNN_LAUNCH(ev, (k_scatter<true>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
+    else SNN_LAUNCH(ev, (k_scatter<false>), dim3(blocks), dim3(kScatterThreads), 0, s, a, k, smax);
     return hipGetLastError();
 }
 
 hipError_t launch_sub(const StepArgs& a, uint32_t k, uint32_t blocks, hipStream_t s, const LaunchEv* ev)
 {
-    SNN_LAUNCH(ev, k_sub, dim3(blocks), dim3(kScatterThreads), 0, s, a, k);
+    SNN_LAUNCH(ev, k_seg_bin, dim3(blocks), dim3(kScatterThreads), 0, s, a, k);
     return hipGetLastError();
 }
 

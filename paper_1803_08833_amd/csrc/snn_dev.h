@@ -25,9 +25,13 @@ constexpr uint32_t kWInhField = 0x1FFFFu;     // weight field that stands for th
 // Bin fill counters sit one per 128-byte line: every scatter workgroup reserves
 // in every tile's bin each chunk, and counters sharing a line serialise there.
 constexpr uint32_t kFillStride = 32;
-// Two-level binning (networks whose update blocks exceed one LDS scan): first
-// by super tile of 2^kSuperBits targets, then by tile.
-constexpr uint32_t kSuperBits = 16;
+// Two-level binning (8-bit-code networks with more tiles than one LDS table):
+// the records of every row are laid out by super tile of 2^kSegBits targets
+// at construction, a step lists the (spike, super tile) record segments per
+// super tile, and a second pass bins each super tile's segments by tile.
+constexpr uint32_t kSegBits = 19;
+constexpr uint32_t kSegTiles = 1u << (kSegBits - kTileBits);   // tiles per super tile
+constexpr uint32_t kMaxSuper = 32;                             // N <= 2^24 neurons
 
 // Philox stream identifiers (third counter word).
 constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamInit = 4u;
@@ -91,11 +95,15 @@ struct StepArgs {
     uint32_t* bin_fill;       // [ntiles * kFillStride] events binned this step (one counter per line)
     uint32_t* bins;           // [ntiles][bin_cap_tile] event codes:
                               //   target & 1023 | bucket << 10 | weight field << 15
-    // two-level binning (nsuper > 0; 8-bit-code records only)
-    uint32_t nsuper;          // super tiles of 65536 targets
-    uint32_t sbin_cap;        // capacity of every super tile's bin (events)
-    uint32_t* sbin_fill;      // [nsuper * kFillStride]
-    uint32_t* sbins;          // [nsuper][sbin_cap] codes: target & 0xFFFF | bucket << 16 | code << 21
+    // two-level binning (nsuper > 0; 8-bit-code records laid out by super
+    // tile: each row's records sorted by (super tile, delay bucket, target),
+    // record = target & (2^kSegBits - 1) | bucket << kSegBits | code << (kSegBits + 5))
+    uint32_t nsuper;          // super tiles of 2^kSegBits targets (<= kMaxSuper)
+    const uint16_t* sstart;   // [N][nsuper] start of each super tile's segment in the row
+    uint32_t dcap;            // capacity of every super tile's segment list
+    uint32_t* dfill;          // [nsuper * kFillStride] segments listed this step
+    uint2* dsc;               // [nsuper][dcap] segments of at most 256 records:
+                              //   {record index lo, record index hi | length << 8}
 };
 
 // One job of a batch: the job network's step arguments plus its schedule.
@@ -132,6 +140,8 @@ struct BuildArgs {
     uint32_t dthr[kMaxD];      //    (D - 1 of them); 0: mulhi(draw, D)
     const uint4* btab;         // gen 1: [2][gy][gx] {k0, len, at lo, at hi} count tables
     const uint32_t* bthr;      // gen 1: their thresholds
+    uint32_t nsuper;           // > 0: write the rows laid out by super tile (8-bit codes)
+    uint16_t* sstart;          //      [N][nsuper] segment starts
 };
 
 // ---- launchers (kernels.hip) ----
@@ -155,6 +165,9 @@ hipError_t launch_deliver(const StepArgs& a, uint32_t k, uint32_t waves, uint32_
 hipError_t launch_scatter(const StepArgs& a, uint32_t k, uint32_t max_len, uint32_t blocks,
                           hipStream_t s,
                           const LaunchEv* ev = nullptr);
+// Two-level networks (a.nsuper > 0): launch_scatter lists the step's record
+// segments per super tile (k_seg_emit), launch_sub bins them by tile or, in a
+// step below the binning threshold, delivers them directly (k_seg_bin).
 hipError_t launch_sub(const StepArgs& a, uint32_t k, uint32_t blocks, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_tile(const StepArgs& a, uint32_t k, bool update_next, hipStream_t s,
                        const LaunchEv* ev = nullptr);

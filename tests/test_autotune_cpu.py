@@ -18,6 +18,7 @@ def test_candidates_cover_both_schedules():
     assert modes == {0, 1}
     assert all(o.get(snn.OPT_BIN_THRESHOLD, 1) >= 0 for o in c)
     assert {o[snn.OPT_DELIVER_MODE] for o in autotune.candidates(dict(bin_threshold=0, binned_ok=0))} == {0}
+    assert {o[snn.OPT_DELIVER_MODE] for o in autotune.candidates(dict(bin_threshold=9, binned_ok=2))} == {0, 2}
 
 
 def test_batch_candidates_default_first_and_distinct():

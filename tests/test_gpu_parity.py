@@ -369,7 +369,13 @@ def test_two_level_lockstep_code8(snn, oracle_mod):
         g.set_option(snn.OPT_DELIVER_MODE, 2)
         g.build_synapses()
         g.set_option(snn.OPT_BIN_THRESHOLD, 0)
-        assert g.stats()["deliver_mode"] == 2
+        assert g.stats()["deliver_mode"] == 2 and g.stats()["binned_ok"] & 2
+        for r in (0, 5, g.N // 2, g.N - 1):   # rows laid out by super tile read back in (delay, target) order
+            rl, be, rc = g.export_rows(r, 1)
+            orl, obe, orc = oracle_mod.build_rows(net, r, 1)
+            np.testing.assert_array_equal(rl, orl)
+            np.testing.assert_array_equal(be, obe)
+            np.testing.assert_array_equal(rc, orc, err_msg=f"row {r}")
         for t in range(300):
             o.step(1)
             sp = o.spikes()
@@ -382,21 +388,41 @@ def test_two_level_lockstep_code8(snn, oracle_mod):
         assert g.stats()["rec_events"] == o.stats()["rec_events"]
 
 
+SUPER = 1 << 19   # targets per super tile of two-level delivery
+
+
 def test_two_level_matches_direct_over_super_tiles(snn, oracle_mod):
-    """A 12x12 grid (178,560 neurons: three super tiles, the last partial):
-    two-level binned delivery, fused and unfused, with ample and with tiny
-    bins (fallback), gives the direct schedule's ring and raster."""
-    net = W.make(12, 12, W.EXP, 4.0, 400, 21, record=W.REC_CODE8, ext_rate_hz=3.0)
-    say("case: 12x12 exp CODE8, two-level vs direct, 150 steps")
+    """A 21x21 grid (546,840 neurons: two super tiles of 2^19 targets, the
+    second partial), rows laid out by super tile: sampled rows read back equal
+    to the oracle's (delay, target) rows; two-level binned delivery, fused and
+    unfused, with ample and with tiny bins (fallback), its direct branch at
+    every step (mode 0 after a two-level build), and a plain direct build all
+    give the same ring and raster, and the charge in flight equals the
+    oracle's column sums."""
+    net = W.make(21, 21, W.EXP, 4.0, 400, 21, record=W.REC_CODE8, ext_rate_hz=3.0)
+    N = W.n_neurons(net)
+    say("case: 21x21 exp CODE8, two-level vs direct, 150 steps")
     out = []
-    for pref, ppm, chunk in ((0, 500000, 64), (2, 500000, 64), (2, 500000, 0), (2, 2000, 16)):
+    rng = np.random.default_rng(21)
+    rows = sorted(set([0, 1, N - 1] + [int(x) for x in rng.integers(0, N, 6)]))
+    for pref, mode, ppm, chunk in ((0, 0, 500000, 64), (2, 2, 500000, 64), (2, 2, 500000, 0), (2, 2, 2000, 16),
+                                   (2, 0, 500000, 64)):
         with snn.Net(net) as g:
             g.set_option(snn.OPT_DELIVER_MODE, pref)
             g.set_option(snn.OPT_BIN_FRAC_PPM, ppm)
             g.build_synapses()
             assert g.stats()["deliver_mode"] == pref
-            if pref:
+            if pref == 2 and chunk == 64 and mode == 2:
+                for r in rows:
+                    rl, be, rc = g.export_rows(r, 1)
+                    orl, obe, orc = oracle_mod.build_rows(net, r, 1)
+                    np.testing.assert_array_equal(rl, orl)
+                    np.testing.assert_array_equal(be, obe)
+                    np.testing.assert_array_equal(rc, orc, err_msg=f"row {r}")
+            g.set_option(snn.OPT_DELIVER_MODE, mode)
+            if mode:
                 g.set_option(snn.OPT_BIN_THRESHOLD, 0)
+            assert g.stats()["deliver_mode"] == mode
             g.set_option(snn.OPT_GRAPH_CHUNK, chunk)
             g.step(150)
             out.append((g.read_ring(), g.read_spikes(), g.stats()))
@@ -408,17 +434,17 @@ def test_two_level_matches_direct_over_super_tiles(snn, oracle_mod):
     assert len(sp) > 1000
     per_step = np.bincount(sp[:, 0].astype(np.int64), minlength=150)
     say("max spikes per step:", int(per_step.max()), "overflow events:", out[3][2]["bin_overflow"])
-    if per_step.max() * 300 > 3 * 65536:   # some step overfilled a super tile's 65,536-event bin
+    # 2000 ppm bins hold about 4,700 events per tile: a step whose events
+    # average twice that over the 535 tiles overflows some of them
+    if per_step.max() * net["k_in"] > 2 * 4700 * 535:
         assert out[3][2]["bin_overflow"] > 0
-    # against the oracle: charge in flight at step 150 for targets in each of
-    # the three super tiles (ample bins, and tiny bins that overflow)
-    rng = np.random.default_rng(21)
-    picks = [0, 65535, 65536, 131071, 131072, 178559]
-    picks += [int(x) for x in rng.integers(0, 65536, 2)] + [int(x) for x in rng.integers(65536, 131072, 2)]
-    picks += [int(x) for x in rng.integers(131072, 178560, 2)]
+    # against the oracle: charge in flight at step 150 for targets in both
+    # super tiles (ample bins, tiny bins that overflow, direct branch)
+    picks = [0, SUPER - 1, SUPER, N - 1]
+    picks += [int(x) for x in rng.integers(0, SUPER, 3)] + [int(x) for x in rng.integers(SUPER, N, 3)]
     for j in picks:
         want = _pending_charge(oracle_mod, net, sp, 150, j)
-        for ring, _, _ in (out[2], out[3]):
+        for ring, _, _ in (out[2], out[3], out[4]):
             got = np.array([ring[(150 + a) % ring.shape[0], j] for a in range(net["d_max"])], dtype=np.int64)
             np.testing.assert_array_equal(got, want, err_msg=f"target {j}")
 
@@ -483,10 +509,10 @@ def test_full_scale_96x96_code8(snn, oracle_mod):
             f"events {st['rec_events']}, overflow {st['bin_overflow']}")
         assert st["t"] == T and counts.size == T
         ring = g.read_ring()
-        # two targets in each of the 175 super tiles' first, middle and last thirds
-        nsup = (g.N + 65535) // 65536
+        # random targets, and both ends of the first and the last super tile
+        nsup = (g.N + SUPER - 1) // SUPER
         picks = [int(x) for x in rng.integers(0, g.N, 12)]
-        picks += [0, g.N - 1, 65535, 65536, (nsup - 1) * 65536]
+        picks += [0, g.N - 1, SUPER - 1, SUPER, (nsup - 1) * SUPER]
         for j in picks:
             want = _pending_charge(oracle_mod, net, raster, T, j)
             got = np.array([ring[(T + a) % ring.shape[0], j] for a in range(net["d_max"])], dtype=np.int64)
