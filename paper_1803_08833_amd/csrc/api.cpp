@@ -527,7 +527,9 @@ static hipError_t enqueue_exact_step(snn_net* n, const snn::XArgs& x, const snn:
 {
     const uint32_t t = n->xt;
     const uint32_t slot = t % x.R;
-    hipError_t e = snn::launch_scan_rows(x.qcnt + (size_t)slot * n->N, x.qoff, n->xtsum, n->N, n->stream);
+    // the arriving slot's counts are zeroed as they are scanned (the slot is
+    // next filled R steps later)
+    hipError_t e = snn::launch_scan_rows(x.qcnt + (size_t)slot * n->N, x.qoff, n->xtsum, n->N, n->stream, true);
     if (e == hipSuccess) e = snn::launch_x_place(x, n->stream, ev ? &ev[0] : nullptr);
     if (e == hipSuccess) e = snn::launch_x_update(x, n->stream, ev ? &ev[1] : nullptr);
     if (e == hipSuccess) e = snn::launch_x_list(x, n->stream);

@@ -2,8 +2,8 @@
 // (Sec. II.A, Sec. II.C).
 //
 //   k_x_place    the arriving slot's queued inputs, counting-sorted by target
-//                (positions from the scanned per-target counts, which count
-//                back down to zero for the slot's next use)
+//                (position: the target's scanned offset plus the input's rank
+//                among the target's inputs, taken when it was delivered)
 //   k_x_update   one thread per neuron: this step's inputs (queued and
 //                external) in time order, Eq. (1)-(2) solved exactly between
 //                them, a spike at the input that crosses threshold; ordered
@@ -161,17 +161,15 @@ __global__ __launch_bounds__(256) void k_x_place(XArgs a)
     const uint64_t n0 = a.qn[slot];
     const uint64_t n = n0 < a.qcap ? n0 : a.qcap;
     const uint4* L = a.qlist + (size_t)slot * a.qcap;
-    uint32_t* cnt = a.qcnt + (size_t)slot * a.N;
     unsigned long long bad = 0;
     for (uint64_t e = (uint64_t)blockIdx.x * 256u + threadIdx.x; e < n; e += (uint64_t)gridDim.x * 256u) {
-        const uint4 v = L[e];
+        const uint4 v = L[e];   // {target, offset, charge, rank}
         if (v.x >= a.N) {
             ++bad;
             continue;
         }
-        const uint32_t c = atomicSub(cnt + v.x, 1u);
-        const uint64_t pos = a.qoff[v.x] + (uint64_t)c - 1u;
-        if (c == 0 || pos >= a.qcap) {   // cannot happen while counts and lists agree
+        const uint64_t pos = a.qoff[v.x] + (uint64_t)v.w;
+        if (pos >= a.qoff[v.x + 1] || pos >= a.qcap) {   // cannot happen while counts and lists agree
             ++bad;
             continue;
         }
@@ -601,8 +599,9 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
                 const unsigned long long pos = bb + (kk - bl);
                 const int32_t w = a.record ? cb_s[wf] : wf;
                 if (pos < a.qcap && tgt < a.N) {
-                    a.qlist[(size_t)sl * a.qcap + pos] = make_uint4(tgt, f, (uint32_t)w, 0u);
-                    atomicAdd(a.qcnt + (size_t)sl * a.N + tgt, 1u);
+                    // the input's rank among its target's inputs of the slot
+                    const uint32_t r = atomicAdd(a.qcnt + (size_t)sl * a.N + tgt, 1u);
+                    a.qlist[(size_t)sl * a.qcap + pos] = make_uint4(tgt, f, (uint32_t)w, r);
                 } else {
                     ++drop;
                 }

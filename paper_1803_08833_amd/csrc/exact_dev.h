@@ -39,8 +39,8 @@ struct XArgs {
     float* W;
     uint64_t* rend;                        // [N] end of the refractory period
     uint32_t* fs;                          // [N] offset of the neuron's last spike
-    uint32_t* qcnt;                        // [R][N] queued inputs per target
-    uint4* qlist;                          // [R][qcap] {target, offset, charge, 0}
+    uint32_t* qcnt;                        // [R][N] queued inputs per target (zeroed when scanned)
+    uint4* qlist;                          // [R][qcap] {target, offset, charge, rank among the target's inputs}
     unsigned long long* qn;                // [R] entries appended per slot (may exceed qcap)
     unsigned long long* qn_prev;           // [R] the same before the step's delivery
     unsigned long long* dropped;           // inputs that found their slot full

@@ -475,7 +475,7 @@ __global__ __launch_bounds__(256) void k_scan_tiles(uint64_t* tsum, uint32_t nt)
 }
 
 __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* x, const uint64_t* toff,
-                                                    uint64_t* out, uint32_t N)
+                                                    uint64_t* out, uint32_t N, uint32_t* clear)
 {
     __shared__ uint64_t ws[4];
     const uint32_t i0 = blockIdx.x * 1024u + threadIdx.x * 4u;
@@ -485,6 +485,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(const uint32_t* x, const uin
         v[u] = (i0 + u < N) ? x[i0 + u] : 0u;
         s += v[u];
     }
+    if (clear)   // the counts are consumed: zero them for their next use
+        for (uint32_t u = 0; u < 4u; ++u)
+            if (i0 + u < N && v[u]) clear[i0 + u] = 0u;
     uint64_t tot;
     const uint64_t base = out[0];   // offset of the first row (set before; rewritten unchanged)
     uint64_t o = base + toff[blockIdx.x] + block_excl_scan(s, ws, tot);
@@ -1311,8 +1314,8 @@ __global__ __launch_bounds__(kEmitThreads) void k_seg_emit(StepArgs a, uint32_t 
 // kBinDesc pieces, all of one super tile.  A workgroup takes a chunk: its
 // pieces' descriptors and the exclusive scan of their lengths go to LDS, and
 // the chunk's records, read as one concatenated sequence, are binned in rounds
-// of up to kStage records.  A round is 80 slots of 256 records, five per
-// wave; a wave holds the pieces of a slot in registers (lane l: piece f + l)
+// of up to kSegStage records.  A round is kSegSlots slots of 256 records,
+// kSegSlotsPerWave per wave; a wave holds the pieces of a slot in registers (lane l: piece f + l)
 // and each record finds its own piece by comparing its position with their
 // starts.  The records are counted by tile (kSegTiles tiles per super tile;
 // the returned count is the record's rank in its tile), one global atomic per
@@ -1328,11 +1331,15 @@ constexpr uint32_t kBinDesc = kScatterThreads;   // pieces per chunk
 // lanes per tile run in the write phase (16 measured faster than 8 or 4 on the
 // 96x96 grid: 512 tiles of ~40 events per round)
 constexpr uint32_t kSegRunLanes = 16;
-constexpr uint32_t kGather = kStage / kScatterThreads;   // records per lane and round
+// 256-record slots per wave and round (six or more spill registers)
+constexpr uint32_t kSegSlotsPerWave = 5;
+constexpr uint32_t kSegSlots = kScatterWaves * kSegSlotsPerWave;
+constexpr uint32_t kSegStage = kSegSlots * 256u;                 // records per round
+constexpr uint32_t kGather = kSegSlotsPerWave * 4u;               // records per lane and round
 
 __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_t k)
 {
-    __shared__ uint32_t stage[kStage];
+    __shared__ uint32_t stage[kSegStage];
     __shared__ uint32_t tcnt[kSegTiles];       // records of the round per tile
     __shared__ uint32_t toff[kSegTiles];       // start of each tile's run in `stage`
     __shared__ uint32_t tres[kSegTiles];       // reserved offset in the tile's bin
@@ -1340,7 +1347,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
     __shared__ uint32_t pcnt[kMaxSuper];       // pieces listed per super tile
     __shared__ uint2 dsc_s[kBinDesc];          // the chunk's pieces
     __shared__ uint32_t pref[kBinDesc + 1];    // exclusive scan of their lengths
-    __shared__ uint32_t first[kChunkItems];    // piece holding each slot's first record
+    __shared__ uint32_t first[kSegSlots];      // piece holding each slot's first record
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
@@ -1423,7 +1430,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
         // concatenated pieces, taken by wave j mod 16; the piece holding its
         // first record is found by one thread per slot
         auto find_first = [&](uint32_t q0) {
-            if (tid < kChunkItems) {
+            if (tid < kSegSlots) {
                 const uint32_t P = q0 + 256u * tid;
                 uint32_t lo = 0, hi = kBinDesc;   // pref[lo] <= P < pref[hi]
                 while (hi - lo > 1u) {
@@ -1440,7 +1447,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
         uint32_t v[kGather], rk[kGather];
         auto gather = [&](uint32_t q0) {
 #pragma unroll
-            for (uint32_t j = 0; j < kSegPerWave; ++j) {
+            for (uint32_t j = 0; j < kSegSlotsPerWave; ++j) {
                 const uint32_t P = q0 + 256u * (wv + kScatterWaves * j);
                 const uint32_t f = first[wv + kScatterWaves * j];
                 const uint32_t fl = f + lane < kBinDesc ? f + lane : kBinDesc - 1u;
@@ -1484,7 +1491,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
         find_first(0);
         __syncthreads();
         gather(0);
-        for (uint32_t q0 = 0; q0 < R; q0 += kStage) {
+        for (uint32_t q0 = 0; q0 < R; q0 += kSegStage) {
             // 1. histogram by tile; the returned count is the record's rank
             //    among the round's records of its tile
 #pragma unroll
@@ -1523,10 +1530,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
             __syncthreads();
             // the next round's records are read while this round's runs are
             // written
-            const bool more = q0 + kStage < R;
-            if (more) find_first(q0 + kStage);
+            const bool more = q0 + kSegStage < R;
+            if (more) find_first(q0 + kSegStage);
             __syncthreads();
-            if (more) gather(q0 + kStage);
+            if (more) gather(q0 + kSegStage);
             // 4. contiguous runs into the bins: each group of kSegRunLanes lanes
             // writes one tile's run at a time
             const uint32_t rl = tid % kSegRunLanes;
@@ -2142,12 +2149,13 @@ hipError_t launch_syn_out(const BuildArgs& a, hipStream_t s)
 uint32_t scan_tiles(uint32_t N) { return cdiv(N, 1024); }
 
 hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
-                            uint32_t N, hipStream_t s)
+                            uint32_t N, hipStream_t s, bool clear)
 {
     const uint32_t nt = scan_tiles(N);
     hipLaunchKernelGGL(k_scan_reduce, dim3(nt), dim3(256), 0, s, rowlen, tile_sums, N);
     hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(256), 0, s, tile_sums, nt);
-    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, s, rowlen, tile_sums, row_ptr, N);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(256), 0, s, rowlen, tile_sums, row_ptr, N,
+                       clear ? const_cast<uint32_t*>(rowlen) : nullptr);
     return hipGetLastError();
 }
 

@@ -149,9 +149,10 @@ hipError_t launch_init(const StepArgs& a, hipStream_t s);
 hipError_t launch_syn_gen(const BuildArgs& a, hipStream_t s);
 hipError_t launch_syn_out(const BuildArgs& a, hipStream_t s);
 // row_ptr[i] = row_ptr[0] + sum of rowlen[0 .. i) for i <= N (row_ptr[0] is
-// the offset of the first row, set before).
+// the offset of the first row, set before); with clear, rowlen is zeroed as
+// it is consumed.
 hipError_t launch_scan_rows(const uint32_t* rowlen, uint64_t* row_ptr, uint64_t* tile_sums,
-                            uint32_t N, hipStream_t s);
+                            uint32_t N, hipStream_t s, bool clear = false);
 // Optional per-launch timing: the launch records the kernel's start and end
 // in these events (both created with timing enabled).
 struct LaunchEv {
