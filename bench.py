@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--ext-rate", type=float, default=None, help="override external Poisson rate (Hz)")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--deliver-mode", type=int, default=None, help="0 direct atomics, 1 tile-binned")
+    p.add_argument("--bin-threshold", type=float, default=None,
+                   help="binned steps from this many recurrent events, as a multiple of the library's default")
     p.add_argument("--serve-jobs", type=int, default=512, help="served-stream jobs (0: skip serving)")
     p.add_argument("--serve-plain", type=int, default=128, help="first jobs also served one at a time")
     p.add_argument("--serve-capacity", type=int, default=64, help="jobs of the closed-loop capacity run")
@@ -196,6 +198,8 @@ def main():
     build_s = time.perf_counter() - tb
     if args.deliver_mode is not None and not exact:
         g.set_option(snn.OPT_DELIVER_MODE, args.deliver_mode)
+    if args.bin_threshold is not None and not exact:
+        g.set_option(snn.OPT_BIN_THRESHOLD, int(args.bin_threshold * g.stats()["bin_threshold"]))
     g.set_option(snn.OPT_GRAPH_CHUNK, args.graph_chunk)   # default: a bench step (1000 ms) is four graphs
     st0 = g.stats()
     print(f"# built {args.workload}: {N} neurons, {st0['nnz']} synapses in {build_s:.2f} s", file=sys.stderr,

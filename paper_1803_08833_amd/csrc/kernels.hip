@@ -1315,14 +1315,15 @@ __global__ __launch_bounds__(kEmitThreads) void k_seg_emit(StepArgs a, uint32_t 
 // pieces' descriptors and the exclusive scan of their lengths go to LDS, and
 // the chunk's records, read as one concatenated sequence, are binned in rounds
 // of up to kSegStage records.  A round is kSegSlots slots of 256 records,
-// kSegSlotsPerWave per wave; a wave holds the pieces of a slot in registers (lane l: piece f + l)
-// and each record finds its own piece by comparing its position with their
-// starts.  The records are counted by tile (kSegTiles tiles per super tile;
-// the returned count is the record's rank in its tile), one global atomic per
-// tile reserves room in its bin, the tile codes (target & 1023 | bucket << 10
-// | code << 15) are staged in LDS at their tile's offset plus their rank, and
-// each tile's run is written into its bin while the next round's records are
-// being read.  Pieces are short (a row reaches most super tiles with a few
+// kSegSlotsPerWave per wave; a wave holds the pieces of a slot in registers
+// (lane l: piece f + l) and each record finds its own piece by comparing its
+// position with their starts.  The records are counted by tile (kSegTiles
+// tiles per super tile; the returned count is the record's rank in its
+// tile), one global atomic per tile reserves room in its bin, the tile codes
+// (target & 1023 | bucket << 10 | code << 15) are staged in LDS at their
+// tile's offset plus their rank, and each tile's run is written into its bin
+// while the next round's records are being read (at a chunk's last round the
+// next chunk's descriptors go to the other LDS buffer first).  Pieces are short (a row reaches most super tiles with a few
 // dozen to a few hundred records), so a wave does not take one piece per
 // 256-record slot.  Events beyond a tile bin's capacity take a direct ring
 // atomic.  In a step below the binning threshold every piece is delivered
@@ -1331,8 +1332,9 @@ constexpr uint32_t kBinDesc = kScatterThreads;   // pieces per chunk
 // lanes per tile run in the write phase (16 measured faster than 8 or 4 on the
 // 96x96 grid: 512 tiles of ~40 events per round)
 constexpr uint32_t kSegRunLanes = 16;
-// 256-record slots per wave and round (six or more spill registers)
-constexpr uint32_t kSegSlotsPerWave = 5;
+// 256-record slots per wave and round: 28,672 records per round, the most
+// the LDS holds next to the tables (147 KB); 5 slots measured 6 % slower
+constexpr uint32_t kSegSlotsPerWave = 7;
 constexpr uint32_t kSegSlots = kScatterWaves * kSegSlotsPerWave;
 constexpr uint32_t kSegStage = kSegSlots * 256u;                 // records per round
 constexpr uint32_t kGather = kSegSlotsPerWave * 4u;               // records per lane and round
@@ -1345,8 +1347,8 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
     __shared__ uint32_t tres[kSegTiles];       // reserved offset in the tile's bin
     __shared__ uint32_t cpre[kMaxSuper + 1];   // work units (chunks, or pieces) before each super tile
     __shared__ uint32_t pcnt[kMaxSuper];       // pieces listed per super tile
-    __shared__ uint2 dsc_s[kBinDesc];          // the chunk's pieces
-    __shared__ uint32_t pref[kBinDesc + 1];    // exclusive scan of their lengths
+    __shared__ uint2 dsc_s[2][kBinDesc];       // a chunk's pieces (two buffers: this chunk, the next)
+    __shared__ uint32_t pref[2][kBinDesc + 1]; // exclusive scan of their lengths
     __shared__ uint32_t first[kSegSlots];      // piece holding each slot's first record
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
@@ -1402,96 +1404,106 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
     unsigned long long spill = 0;
     const uint32_t nt = kSegTiles;
     const uint32_t cap = a.bin_cap_tile;
-    for (uint32_t c = blockIdx.x; c < total; c += gridDim.x) {
+    // Descriptors of chunk c into buffer b (one piece per thread) and the
+    // exclusive scan of their lengths; two barriers.
+    auto load_chunk = [&](uint32_t c, uint32_t b) {
         const uint32_t sup = super_of(c);
         const uint32_t d0 = (c - cpre[sup]) * kBinDesc;
         const uint32_t nd = (pcnt[sup] - d0) < kBinDesc ? pcnt[sup] - d0 : kBinDesc;
-        // the chunk's descriptors and the exclusive scan of their lengths
-        // (one piece per thread)
+        uint2* const ds = dsc_s[b];
+        uint32_t* const pf = pref[b];
         if (tid < kBinDesc) {
             const uint2 d = tid < nd ? a.dsc[(size_t)sup * a.dcap + d0 + tid] : make_uint2(0, 0);
             const uint32_t len = d.y >> 8;
             const uint32_t inc = wave_incl_scan<uint32_t>(len, lane);
-            dsc_s[tid] = d;
-            pref[tid + 1u] = inc;   // within the wave; waves' totals added below
+            ds[tid] = d;
+            pf[tid + 1u] = inc;   // within the wave; waves' totals added below
             if (lane == 63u) wsum[wv] = inc;
         }
-        if (tid < nt) tcnt[tid] = 0;
         __syncthreads();
         if (tid < kBinDesc) {
             uint32_t add = 0;
             for (uint32_t i = 0; i < wv; ++i) add += wsum[i];
-            pref[tid + 1u] += add;
-            if (tid == 0) pref[0] = 0;
+            pf[tid + 1u] += add;
+            if (tid == 0) pf[0] = 0;
         }
         __syncthreads();
-        const uint32_t R = pref[kBinDesc];   // records of the chunk
-        // slot j of a round: records q0 + 256 j .. + 255 of the chunk's
-        // concatenated pieces, taken by wave j mod 16; the piece holding its
-        // first record is found by one thread per slot
-        auto find_first = [&](uint32_t q0) {
-            if (tid < kSegSlots) {
-                const uint32_t P = q0 + 256u * tid;
-                uint32_t lo = 0, hi = kBinDesc;   // pref[lo] <= P < pref[hi]
-                while (hi - lo > 1u) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (pref[mid] <= P) lo = mid;
-                    else hi = mid;
-                }
-                first[tid] = lo;
+    };
+    // slot j of a round: records q0 + 256 j .. + 255 of the chunk's
+    // concatenated pieces, taken by wave j mod 16; the piece holding its
+    // first record is found by one thread per slot
+    auto find_first = [&](uint32_t q0, uint32_t b) {
+        if (tid < kSegSlots) {
+            const uint32_t* const pf = pref[b];
+            const uint32_t P = q0 + 256u * tid;
+            uint32_t lo = 0, hi = kBinDesc;   // pf[lo] <= P < pf[hi]
+            while (hi - lo > 1u) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (pf[mid] <= P) lo = mid;
+                else hi = mid;
             }
-        };
-        // the round's records into v: a slot's pieces (one per lane: start,
-        // length prefix) sit in registers, and each record finds its piece by
-        // comparing its position with the prefixes
-        uint32_t v[kGather], rk[kGather];
-        auto gather = [&](uint32_t q0) {
+            first[tid] = lo;
+        }
+    };
+    // the round's records into v: a slot's pieces (one per lane: start,
+    // length prefix) sit in registers, and each record finds its piece by
+    // comparing its position with the prefixes
+    uint32_t v[kGather], rk[kGather];
+    auto gather = [&](uint32_t q0, uint32_t b) {
+        const uint2* const ds = dsc_s[b];
+        const uint32_t* const pfa = pref[b];
+        const uint32_t R = pfa[kBinDesc];
 #pragma unroll
-            for (uint32_t j = 0; j < kSegSlotsPerWave; ++j) {
-                const uint32_t P = q0 + 256u * (wv + kScatterWaves * j);
-                const uint32_t f = first[wv + kScatterWaves * j];
-                const uint32_t fl = f + lane < kBinDesc ? f + lane : kBinDesc - 1u;
-                const uint32_t pf = pref[fl];
-                const uint2 dd = dsc_s[fl];
-                // the window: pieces f .. f + 63, ending where piece f + 64 starts
-                const uint32_t wend = pref[f + 64u < kBinDesc ? f + 64u : kBinDesc];
-                // window pieces starting inside the slot, besides the first (uniform)
-                const uint64_t inside = __ballot(lane >= 1u && f + lane < kBinDesc && pf < P + 256u && pf < R);
-                const uint32_t np = 1u + popc(inside);
+        for (uint32_t j = 0; j < kSegSlotsPerWave; ++j) {
+            const uint32_t P = q0 + 256u * (wv + kScatterWaves * j);
+            const uint32_t f = first[wv + kScatterWaves * j];
+            const uint32_t fl = f + lane < kBinDesc ? f + lane : kBinDesc - 1u;
+            const uint32_t pf = pfa[fl];
+            const uint2 dd = ds[fl];
+            // the window: pieces f .. f + 63, ending where piece f + 64 starts
+            const uint32_t wend = pfa[f + 64u < kBinDesc ? f + 64u : kBinDesc];
+            // window pieces starting inside the slot, besides the first (uniform)
+            const uint64_t inside = __ballot(lane >= 1u && f + lane < kBinDesc && pf < P + 256u && pf < R);
+            const uint32_t np = 1u + popc(inside);
 #pragma unroll
-                for (uint32_t u = 0; u < 4u; ++u) {
-                    const uint32_t p = P + 64u * u + lane;
-                    uint32_t k = 0;
-                    for (uint32_t l = 1; l < np; ++l) k += readlane(pf, l) <= p ? 1u : 0u;
-                    uint32_t lo32 = 0, hi8 = 0, st = 0;
-                    for (uint32_t l = 0; l < np; ++l)
-                        if (k == l) {
-                            lo32 = readlane(dd.x, l);
-                            hi8 = readlane(dd.y, l) & 255u;
-                            st = readlane(pf, l);
-                        }
-                    if (p >= wend && p < R) {
-                        // past the window (more than 64 pieces in 256 records):
-                        // the piece from the scanned lengths
-                        uint32_t lo = f + 64u, hi = kBinDesc;   // pref[lo] <= p < pref[hi]
-                        while (hi - lo > 1u) {
-                            const uint32_t mid = (lo + hi) >> 1;
-                            if (pref[mid] <= p) lo = mid;
-                            else hi = mid;
-                        }
-                        lo32 = dsc_s[lo].x;
-                        hi8 = dsc_s[lo].y & 255u;
-                        st = pref[lo];
+            for (uint32_t u = 0; u < 4u; ++u) {
+                const uint32_t p = P + 64u * u + lane;
+                uint32_t k = 0;
+                for (uint32_t l = 1; l < np; ++l) k += readlane(pf, l) <= p ? 1u : 0u;
+                uint32_t lo32 = 0, hi8 = 0, st = 0;
+                for (uint32_t l = 0; l < np; ++l)
+                    if (k == l) {
+                        lo32 = readlane(dd.x, l);
+                        hi8 = readlane(dd.y, l) & 255u;
+                        st = readlane(pf, l);
                     }
-                    const uint64_t at = ((uint64_t)hi8 << 32 | lo32) + (p - st);
-                    v[4u * j + u] = p < R ? recs[at] : 0u;
+                if (p >= wend && p < R) {
+                    // past the window (more than 64 pieces in 256 records):
+                    // the piece from the scanned lengths
+                    uint32_t lo = f + 64u, hi = kBinDesc;   // pfa[lo] <= p < pfa[hi]
+                    while (hi - lo > 1u) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (pfa[mid] <= p) lo = mid;
+                        else hi = mid;
+                    }
+                    lo32 = ds[lo].x;
+                    hi8 = ds[lo].y & 255u;
+                    st = pfa[lo];
                 }
+                const uint64_t at = ((uint64_t)hi8 << 32 | lo32) + (p - st);
+                v[4u * j + u] = p < R ? recs[at] : 0u;
             }
-        };
-        find_first(0);
-        __syncthreads();
-        gather(0);
-        for (uint32_t q0 = 0; q0 < R; q0 += kSegStage) {
+        }
+    };
+    if (tid < nt) tcnt[tid] = 0;
+    // The workgroup's rounds in turn (chunks c = blockIdx.x, + gridDim.x, ...;
+    // rounds q0 = 0, kSegStage, ... of each).  Each pass finishes the current
+    // round and reads the next one's records before writing the current runs;
+    // the first pass only reads.
+    bool cur = false;                 // a current round (records in v)
+    uint32_t c = 0, q0 = 0, buf = 0, R = 0, sup = 0;
+    for (;;) {
+        if (cur) {
             // 1. histogram by tile; the returned count is the record's rank
             //    among the round's records of its tile
 #pragma unroll
@@ -1499,23 +1511,29 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
                 const uint32_t p = q0 + 256u * (wv + kScatterWaves * (i >> 2)) + 64u * (i & 3u) + lane;
                 rk[i] = p < R ? atomicAdd(&tcnt[(v[i] >> kTileBits) & (kSegTiles - 1u)], 1u) : 0u;
             }
-            __syncthreads();
-            // 2. exclusive scan of the counts (one tile per thread)
-            //    and reservation in the bins
-            if (tid < nt) {
-                const uint32_t cn = tcnt[tid];
-                const uint32_t inc = wave_incl_scan<uint32_t>(cn, lane);
-                if (lane == 63u) wsum[wv] = inc;
-                toff[tid] = inc - cn;   // within the wave for now
-                tres[tid] = cn ? atomicAdd(&a.bin_fill[(size_t)(sup * kSegTiles + tid) * kFillStride], cn) : 0u;
-            }
-            __syncthreads();
+        }
+        __syncthreads();
+        // 2. exclusive scan of the counts (one tile per thread) and
+        //    reservation in the bins; the reservations' results are first
+        //    needed in phase 4, so they stay in flight while phase 3 stages
+        uint32_t res = 0;
+        if (cur && tid < nt) {
+            const uint32_t cnt = tcnt[tid];
+            const uint32_t inc = wave_incl_scan<uint32_t>(cnt, lane);
+            if (lane == 63u) wsum[wv] = inc;
+            toff[tid] = inc - cnt;   // within the wave for now
+            if (cnt) res = atomicAdd(&a.bin_fill[(size_t)(sup * kSegTiles + tid) * kFillStride], cnt);
+        }
+        __syncthreads();
+        if (cur) {
             if (tid < nt) {
                 uint32_t add = 0;
                 for (uint32_t i = 0; i < wv; ++i) add += wsum[i];
                 toff[tid] += add;
             }
-            __syncthreads();
+        }
+        __syncthreads();
+        if (cur) {
             // 3. tile codes staged sorted by tile, each at its tile's start
             //    plus its rank
 #pragma unroll
@@ -1527,15 +1545,31 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
                         (x & (kTile - 1u)) | (((x >> kSegBits) & 31u) << kTileBits) | ((x >> (kSegBits + 5u)) << 15);
                 }
             }
+            if (tid < nt) tres[tid] = res;
+        }
+        __syncthreads();
+        // the next round: of this chunk, or the workgroup's next chunk (its
+        // descriptors into the other buffer); its records are read while this
+        // round's runs are written
+        bool nxt = false, load = false;
+        uint32_t nc = c, nq = q0 + kSegStage, nb = buf;
+        if (cur && nq < R) {
+            nxt = true;
+        } else {
+            nc = cur ? c + gridDim.x : blockIdx.x;
+            nq = 0;
+            nb = cur ? buf ^ 1u : 0u;
+            nxt = load = nc < total;
+        }
+        if (nxt) {
+            if (load) load_chunk(nc, nb);
+            find_first(nq, nb);
             __syncthreads();
-            // the next round's records are read while this round's runs are
-            // written
-            const bool more = q0 + kSegStage < R;
-            if (more) find_first(q0 + kSegStage);
-            __syncthreads();
-            if (more) gather(q0 + kSegStage);
-            // 4. contiguous runs into the bins: each group of kSegRunLanes lanes
-            // writes one tile's run at a time
+            gather(nq, nb);
+        }
+        if (cur) {
+            // 4. contiguous runs into the bins: each group of kSegRunLanes
+            // lanes writes one tile's run at a time
             const uint32_t rl = tid % kSegRunLanes;
             for (uint32_t tt = tid / kSegRunLanes; tt < nt; tt += kScatterThreads / kSegRunLanes) {
                 const uint32_t o0 = toff[tt];
@@ -1558,10 +1592,16 @@ __global__ __launch_bounds__(kScatterThreads) void k_seg_bin(StepArgs a, uint32_
                     }
                 }
             }
-            __syncthreads();
-            if (tid < nt) tcnt[tid] = 0;   // the next round's histogram
-            __syncthreads();
         }
+        __syncthreads();
+        if (tid < nt) tcnt[tid] = 0;   // the next round's histogram
+        if (!nxt) break;
+        cur = true;
+        c = nc;
+        q0 = nq;
+        buf = nb;
+        R = pref[buf][kBinDesc];
+        sup = super_of(c);
     }
     spill = wave_sum<unsigned long long>(spill);
     if (lane == 0 && spill) atomicAdd((unsigned long long*)&a.ctrl->bin_overflow, spill);
@@ -1673,14 +1713,22 @@ __device__ __forceinline__ void tile_work(const StepArgs& a, uint32_t tt, uint32
         const uint32_t cap = a.bin_cap_tile;
         const uint32_t n = fill < cap ? fill : cap;
         const uint32_t* ev = a.bins + (size_t)tt * cap;
+        // U codes per thread and pass; the next pass's codes are read while
+        // this pass's are added
         constexpr uint32_t U = 8;
-        for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
-            uint32_t code[U];
+        uint32_t code[U], nxt[U];
+        auto fetch = [&](uint32_t e0, uint32_t* c) {
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 const uint32_t e = e0 + u * kTileThreads + tid;
-                code[u] = e < n ? ev[e] : 0xFFFFFFFFu;
+                c[u] = e < n ? ev[e] : 0xFFFFFFFFu;
             }
+        };
+        fetch(0, nxt);
+        for (uint32_t e0 = 0; e0 < n; e0 += U * kTileThreads) {
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) code[u] = nxt[u];
+            if (e0 + U * kTileThreads < n) fetch(e0 + U * kTileThreads, nxt);
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u) {
                 if (code[u] != 0xFFFFFFFFu) {
