@@ -28,12 +28,12 @@ HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E peak
 BYTES_PER_EVENT = {0: 16, 1: 12}      # record + ring slot read + write (F32 / 8-bit code records)
 BYTES_PER_NEURON_STEP = 26            # V 4+4, w 4+4, ref 1+1, ring slot 4+4
 # Exact-time solver: per event the record (8 / 4 B), the queue entry written
-# (16) and read back (16), its count raised (4) and lowered (4), the placed
+# (16) and read back (16), its target's count raised (4), the placed
 # {offset, charge} pair written (8) and read by the update (8); per neuron and
 # step V, w and the refractory end read and written (32), the input count
-# scanned (4 read, 8 written) and the neuron's offset read (8).
-BYTES_EXACT_PER_EVENT = {0: 64, 1: 60}
-BYTES_EXACT_PER_NEURON_STEP = 52
+# scanned and zeroed (4 read, 4 written), its offset written (8) and read (8).
+BYTES_EXACT_PER_EVENT = {0: 60, 1: 56}
+BYTES_EXACT_PER_NEURON_STEP = 56
 
 
 def parse():
