@@ -1179,6 +1179,11 @@ snn_status snn_export_rows(snn_net* n, uint32_t pre0, uint32_t cnt, uint64_t* ro
     const size_t rb = n->s.record == SNN_REC_CODE8 ? 4 : 8;
     if (m && rec_buf)
         HIPCHK(n, hipMemcpy(rec_buf, (const uint8_t*)n->a.recs + rp[0] * rb, m * rb, hipMemcpyDeviceToHost));
+    if (m && rec_buf && n->s.record != SNN_REC_CODE8) {
+        // 8-byte records: the target without the delay bucket it carries
+        uint32_t* r = static_cast<uint32_t*>(rec_buf);
+        for (uint64_t i = 0; i < m; ++i) r[2 * i] &= snn::kTgtMask;
+    }
     if (m && rec_buf && n->a.nsuper) {
         // rows laid out by super tile: back to (delay, target) order, records
         // target << 8 | code (within a (super tile, delay) run the targets

@@ -581,7 +581,7 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
                 wf = (int32_t)(v & 255u);
             } else {
                 const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
-                tgt = r.tgt;
+                tgt = r.tgt & kTgtMask;
                 wf = __float2int_rn(r.w * 65536.0f);
             }
         };

@@ -159,7 +159,7 @@ __device__ __forceinline__ void syn_flush(const BuildArgs& a, const uint32_t* q,
                     } else {
                         const int32_t wq = exc ? a.wtab[wsel >> 16] : a.winh_q;
                         Rec8 r8;
-                        r8.tgt = j;
+                        r8.tgt = j | (b << kTgtBits);
                         r8.w = (float)wq * 0x1p-16f;
                         reinterpret_cast<Rec8*>(a.recs)[at] = r8;
                     }
@@ -776,7 +776,9 @@ __device__ __forceinline__ void deliver_item(const StepArgs& a, uint32_t t, uint
                         ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)info.w) << 32);
     const uint32_t c0 = seg * SEG;
     if (c0 >= len) return;
-    const uint32_t be = lane < a.D ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
+    // 8-bit codes: the row's bucket ends, one per lane (8-byte records carry
+    // their bucket)
+    const uint32_t be = (CODE8 && lane < a.D) ? (uint32_t)a.bend[(size_t)pre * a.D + lane] : 0xFFFFFFFFu;
     uint32_t tg[U];
     int32_t wq[U];
 #pragma unroll
@@ -798,12 +800,18 @@ __device__ __forceinline__ void deliver_item(const StepArgs& a, uint32_t t, uint
         const uint32_t c = c0 + 64u * u;
         if (c >= len) break;
         const uint32_t kk = c + lane;
-        uint32_t bl = popc(__ballot(be <= c));
-        uint64_t inm = __ballot(be > c && be < c + 64u);
-        while (inm) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(inm);
-            inm &= inm - 1u;
-            bl += (kk >= readlane(be, l)) ? 1u : 0u;
+        uint32_t bl;
+        if (CODE8) {
+            bl = popc(__ballot(be <= c));
+            uint64_t inm = __ballot(be > c && be < c + 64u);
+            while (inm) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+                inm &= inm - 1u;
+                bl += (kk >= readlane(be, l)) ? 1u : 0u;
+            }
+        } else {
+            bl = tg[u] >> kTgtBits;
+            tg[u] &= kTgtMask;
         }
         if (kk < len) {
             const int32_t w = CODE8 ? cb[wq[u]] : wq[u];
@@ -895,7 +903,7 @@ __device__ __forceinline__ void seg_load(const StepArgs& a, uint4 info, uint32_t
     L.s0 = seg * 256u;
     L.be = 0xFFFFFFFFu;
     if (L.s0 >= L.len) return;
-    if (lane < a.D) L.be = (uint32_t)a.bend[(size_t)pre * a.D + lane];
+    if (CODE8 && lane < a.D) L.be = (uint32_t)a.bend[(size_t)pre * a.D + lane];   // 8-byte records carry their bucket
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         uint32_t kk = L.s0 + 64u * u + lane;
@@ -924,8 +932,10 @@ __device__ __forceinline__ void seg_decode(const StepArgs& a, SegLoad& L)
             L.tg[u] = v >> 8;
             L.wf[u] = v & 255u;
         } else {
+            // weight field (17 bits) and, above it, the record's bucket
             const int32_t wq = __float2int_rn(__uint_as_float(L.wf[u]) * 65536.0f);
-            L.wf[u] = wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536);
+            L.wf[u] = (wq == a.winh_q ? kWInhField : (uint32_t)(wq + 65536)) | ((L.tg[u] >> kTgtBits) << 17);
+            L.tg[u] &= kTgtMask;
         }
     }
 }
@@ -942,7 +952,9 @@ __device__ __forceinline__ void seg_count(const SegLoad& L, uint32_t lane, uint3
         if (L.s0 + 64u * u + lane < L.len) atomicAdd(&tcnt[L.tg[u] >> SHIFT], 1u);
 }
 
-template <uint32_t SHIFT>
+// CODE8: the bucket from the row's bucket ends (L.be); 8-byte records: from
+// the weight field's top bits (seg_decode).
+template <uint32_t SHIFT, bool CODE8>
 __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint32_t* tcnt, uint32_t* stage)
 {
     if (L.s0 >= L.len) return;
@@ -951,16 +963,23 @@ __device__ __forceinline__ void seg_stage(const SegLoad& L, uint32_t lane, uint3
         const uint32_t c = L.s0 + 64u * u;
         if (c >= L.len) break;
         const uint32_t kk = c + lane;
-        uint32_t bl = popc(__ballot(L.be <= c));
-        uint64_t inm = __ballot(L.be > c && L.be < c + 64u);
-        while (inm) {
-            const uint32_t l = (uint32_t)__builtin_ctzll(inm);
-            inm &= inm - 1u;
-            bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
+        uint32_t bl, wf;
+        if (CODE8) {
+            bl = popc(__ballot(L.be <= c));
+            uint64_t inm = __ballot(L.be > c && L.be < c + 64u);
+            while (inm) {
+                const uint32_t l = (uint32_t)__builtin_ctzll(inm);
+                inm &= inm - 1u;
+                bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
+            }
+            wf = L.wf[u];
+        } else {
+            bl = L.wf[u] >> 17;
+            wf = L.wf[u] & 0x1FFFFu;
         }
         if (kk < L.len) {
             const uint32_t p = atomicAdd(&tcnt[L.tg[u] >> SHIFT], 1u);
-            stage[p] = (L.tg[u] & ((1u << SHIFT) - 1u)) | (bl << SHIFT) | (L.wf[u] << (SHIFT + 5u));
+            stage[p] = (L.tg[u] & ((1u << SHIFT) - 1u)) | (bl << SHIFT) | (wf << (SHIFT + 5u));
         }
     }
 }
@@ -1021,12 +1040,16 @@ template <bool CODE8>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_t k, uint32_t smax)
 {
     constexpr uint32_t SHIFT = kTileBits;
-    __shared__ uint32_t stage[kStage];
+    // row segments per wave and chunk: 8-byte records carry their bucket, so
+    // a segment holds no bucket ends and six fit the registers (8-bit codes: five)
+    constexpr uint32_t SPW = CODE8 ? kSegPerWave : kSegPerWave + 1u;
+    constexpr uint32_t CHUNK = kScatterWaves * SPW;
+    __shared__ uint32_t stage[CHUNK * 256u];
     __shared__ uint32_t tcnt2[2][kMaxTiles];   // counts, then fill cursor (by chunk parity)
     __shared__ uint32_t toff[kMaxTiles];   // start of each bin's run in `stage`
     __shared__ uint32_t tres[kMaxTiles];   // reserved offset in the bin
     __shared__ uint32_t boff[kMaxTiles + 1];
-    __shared__ uint4 info_s[kChunkItems + kScatterWaves];  // spike records of the chunk whose segments load next
+    __shared__ uint4 info_s[CHUNK + kScatterWaves];  // spike records of the chunk whose segments load next
     __shared__ int32_t cb_s[256];
     __shared__ uint32_t wsum[kScatterWaves];
     __shared__ unsigned long long red[2 * kScatterWaves + 1];
@@ -1097,7 +1120,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     uint32_t* const bins = a.bins;
     // chunk size: large chunks bin better, but every workgroup should get work
     uint32_t per = (items + gridDim.x - 1u) / gridDim.x;
-    per = per < kScatterWaves ? kScatterWaves : (per > kChunkItems ? kChunkItems : per);
+    per = per < kScatterWaves ? kScatterWaves : (per > CHUNK ? CHUNK : per);
     unsigned long long spill = 0;
     // this wave's row segments of chunk [c0, c1): items c0 + wv + 16 j, all
     // loads issued before use; the next chunk's segments are loaded while the
@@ -1107,21 +1130,21 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
     // earlier still: lane j of a wave fetches its segment j's record (a
     // register while phase 4 runs), the top of the next chunk parks it in
     // info_s, and the segments' loads read it there.
-    SegLoad S[kSegPerWave];
+    SegLoad S[SPW];
     uint4 nxt = make_uint4(0, 0, 0, 0);
     auto fetch_info = [&](uint32_t c0, uint32_t c1) {
         const uint32_t it = c0 + wv + kScatterWaves * lane;
-        if (lane < kSegPerWave && it < c1)
+        if (lane < SPW && it < c1)
             nxt = spike_rec<false>(a, boff, nb, it / smax);
         else
             nxt = make_uint4(0, 0, 0, 0);
     };
     auto park_info = [&]() {   // every lane stores (lanes past the segments to a spare slot)
-        info_s[lane < kSegPerWave ? wv + kScatterWaves * lane : kChunkItems + wv] = nxt;
+        info_s[lane < SPW ? wv + kScatterWaves * lane : CHUNK + wv] = nxt;
     };
     auto load_chunk = [&](uint32_t c0, uint32_t c1) {
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) {
+        for (uint32_t j = 0; j < SPW; ++j) {
             const uint32_t it = c0 + wv + kScatterWaves * j;
             seg_load<CODE8>(a, info_s[wv + kScatterWaves * j], it < c1 ? it % smax : 0u, lane, S[j]);
         }
@@ -1144,10 +1167,10 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         uint32_t* const tcnt = tcnt2[par];
         park_info();   // the next chunk's spike records (zeros past the end)
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_decode<CODE8>(a, S[j]);
+        for (uint32_t j = 0; j < SPW; ++j) seg_decode<CODE8>(a, S[j]);
         // 1. histogram of targets by bin
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_count<SHIFT>(S[j], lane, tcnt);
+        for (uint32_t j = 0; j < SPW; ++j) seg_count<SHIFT>(S[j], lane, tcnt);
         __syncthreads();
         // 2. exclusive scan of the counts (2 bins per thread) and reservation
         // in the bins; the reservations' results are first needed in phase 4,
@@ -1177,7 +1200,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(StepArgs a, uint32_
         __syncthreads();
         // 3. encode and stage sorted by bin
 #pragma unroll
-        for (uint32_t j = 0; j < kSegPerWave; ++j) seg_stage<SHIFT>(S[j], lane, tcnt, stage);
+        for (uint32_t j = 0; j < SPW; ++j) seg_stage<SHIFT, CODE8>(S[j], lane, tcnt, stage);
         if (t0i < nt) tres[t0i] = res0;
         if (t1i < nt) tres[t1i] = res1;
         __syncthreads();
@@ -2034,16 +2057,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_bscatter(const JobDesc* __r
                 const uint32_t c = L.s0 + 64u * u;
                 if (c >= L.len) break;
                 const uint32_t kk = c + lane;
-                uint32_t bl = popc(__ballot(L.be <= c));
-                uint64_t inm = __ballot(L.be > c && L.be < c + 64u);
-                while (inm) {
-                    const uint32_t l = (uint32_t)__builtin_ctzll(inm);
-                    inm &= inm - 1u;
-                    bl += (kk >= readlane(L.be, l)) ? 1u : 0u;
-                }
                 if (kk < L.len) {
+                    // 8-byte records: the bucket above the weight field (seg_decode)
+                    const uint32_t bl = L.wf[u] >> 17, wf = L.wf[u] & 0x1FFFFu;
                     const uint32_t p = atomicAdd(&tcnt[wb + (L.tg[u] >> kTileBits)], 1u);
-                    stage[p] = (L.tg[u] & (kTile - 1u)) | (bl << kTileBits) | (L.wf[u] << 15);
+                    stage[p] = (L.tg[u] & (kTile - 1u)) | (bl << kTileBits) | (wf << 15);
                 }
             }
         }

@@ -39,9 +39,14 @@ constexpr uint32_t kStreamConn = 1u, kStreamAttr = 2u, kStreamExt = 3u, kStreamI
 constexpr uint32_t kStreamCount = 5u, kStreamPick = 6u;
 
 struct Rec8 {        // 8-byte record: target and weight in mV (an exact multiple of 2^-16)
-    uint32_t tgt;
+    uint32_t tgt;    // target | delay bucket << kTgtBits
     float w;
 };
+// The target word of an 8-byte record also carries the synapse's delay bucket
+// in its top bits (a network has fewer than 2^27 neurons: 32 N < 2^32), so a
+// kernel reading the record needs no search of the row's bucket ends.
+constexpr uint32_t kTgtBits = 27;
+constexpr uint32_t kTgtMask = (1u << kTgtBits) - 1u;
 
 // Device-side control block, one per network.
 struct Ctrl {

@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kThreads) void k_stdp_apply(StdpArgs a)
             }
             if (kk < len) {
                 Rec8& r = a.recs[rb + kk];
-                const uint32_t j = r.tgt;
+                const uint32_t j = r.tgt & kTgtMask;   // (bl comes from the bucket ends)
                 const uint64_t q0 = a.off[j];
                 uint64_t q1 = a.off[j + 1];
                 q1 = q1 < a.times_cap ? q1 : a.times_cap;
