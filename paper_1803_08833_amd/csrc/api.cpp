@@ -1750,9 +1750,13 @@ void batch_worker(snn_batch* b, int w)
             const snn_batch::Retired r = b->retired.front();
             b->retired.pop_front();
             lk.unlock();
-            (void)hipEventSynchronize(r.after);   // no kernel still reads the job's descriptor
             {
+                // the event was recorded on the stepping stream: waiting for it
+                // while that stream is being captured would invalidate the
+                // capture, so the wait holds the capture lock too (the event
+                // completes with work already enqueued: the capture only waits)
                 std::shared_lock<std::shared_mutex> cap(b->capture_mu);
+                (void)hipEventSynchronize(r.after);   // no kernel still reads the job's descriptor
                 (void)hipEventDestroy(r.after);
                 snn_destroy(r.net);
             }
