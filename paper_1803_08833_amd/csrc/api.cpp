@@ -471,6 +471,13 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
     x.inv_tau_m = (float)(1.0 / g.tau_m);
     x.inv_tau_w = (float)(1.0 / g.tau_w);
     x.ck = x.tau_equal ? 0.0f : (float)(g.tau_w / (g.tau_w - g.tau_m));
+    x.dinv_tau_m = 1.0 / g.tau_m;
+    x.dinv_tau_w = 1.0 / g.tau_w;
+    x.dck = x.tau_equal ? 0.0 : g.tau_w / (g.tau_w - g.tau_m);
+    x.dv_th = g.v_th;
+    x.dv_reset = g.v_reset;
+    x.de_rest = g.e_rest;
+    x.dalpha = g.alpha_w;
     // inputs queued per slot: a step's events at a 150 Hz mean rate, or the option
     const double qc = n->qcap_opt ? (double)n->qcap_opt : (double)n->N * (tb.mean_out + 1.0) * 0.15 + 65536.0;
     x.qcap = (uint64_t)std::min(qc, 4.0e9);

@@ -154,6 +154,64 @@ __device__ void x_heap_sort(uint2* v, uint32_t n)
     }
 }
 
+// Compare-exchange at distance JJ * 64 (pairs within a lane) of the bitonic
+// merge of size k.
+template <uint32_t K, uint32_t JJ>
+__device__ __forceinline__ void x_cx_in_lane(uint64_t* v, uint32_t k)
+{
+    if constexpr (JJ < K) {
+#pragma unroll
+        for (uint32_t r = 0; r < K; ++r) {
+            if (r & JJ) continue;
+            const bool asc = ((r * 64u) & k) == 0u;
+            const uint64_t x = v[r], y = v[r | JJ];
+            const bool swap = (y < x) == asc;
+            v[r] = swap ? y : x;
+            v[r | JJ] = swap ? x : y;
+        }
+    }
+}
+
+// Bitonic sort (ascending) of 64 K 64-bit keys held by one wave, element
+// r * 64 + lane in the lane's register r.  Distances below 64 exchange across
+// lanes, larger ones within a lane.  The stages are loops, not unrolled, so
+// that the code stays small enough for the instruction cache.
+template <uint32_t K>
+__device__ __forceinline__ void x_bitonic(uint64_t* v, uint32_t lane)
+{
+#pragma unroll 1
+    for (uint32_t k = 2; k <= 64u * K; k <<= 1) {
+#pragma unroll 1
+        for (uint32_t jj = k >> 7; jj > 0; jj >>= 1) {
+            if (jj == 1u) x_cx_in_lane<K, 1>(v, k);
+            else if (jj == 2u) x_cx_in_lane<K, 2>(v, k);
+            else if (jj == 4u) x_cx_in_lane<K, 4>(v, k);
+            else x_cx_in_lane<K, 8>(v, k);
+        }
+#pragma unroll 1
+        for (uint32_t j = (k >> 1) < 32u ? (k >> 1) : 32u; j > 0; j >>= 1) {
+            // every partner is fetched before any is used, so the exchanges'
+            // LDS round trips overlap instead of following one another
+            const uint32_t src = (lane ^ j) << 2;
+            uint32_t ylo[K], yhi[K];
+#pragma unroll
+            for (uint32_t r = 0; r < K; ++r) {
+                ylo[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)src, (int)(uint32_t)v[r]);
+                yhi[r] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)src, (int)(uint32_t)(v[r] >> 32));
+            }
+            const bool low = (lane & j) == 0u;
+#pragma unroll
+            for (uint32_t r = 0; r < K; ++r) {
+                const uint64_t x = v[r], y = ((uint64_t)yhi[r] << 32) | ylo[r];
+                const bool asc = ((r * 64u + lane) & k) == 0u;
+                // keep the smaller of the two where this lane's element is the
+                // lower one of an ascending pair or the upper one of a descending pair
+                v[r] = ((x < y) == (asc == low)) ? x : y;
+            }
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_x_place(XArgs a)
 {
     const uint32_t t = a.ctrl->t0;   // the step in flight (k_x_finish advances it)
@@ -162,18 +220,33 @@ __global__ __launch_bounds__(256) void k_x_place(XArgs a)
     const uint64_t n = n0 < a.qcap ? n0 : a.qcap;
     const uint4* L = a.qlist + (size_t)slot * a.qcap;
     unsigned long long bad = 0;
-    for (uint64_t e = (uint64_t)blockIdx.x * 256u + threadIdx.x; e < n; e += (uint64_t)gridDim.x * 256u) {
-        const uint4 v = L[e];   // {target, offset, charge, rank}
-        if (v.x >= a.N) {
-            ++bad;
-            continue;
+    // four entries per thread and round, each step's loads all in flight together
+    const uint64_t S = (uint64_t)gridDim.x * 256u;
+    for (uint64_t e0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; e0 < n; e0 += 4u * S) {
+        uint4 v[4];   // {target, offset, charge, rank}
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t e = e0 + u * S;
+            v[u] = e < n ? L[e] : make_uint4(~0u, 0u, 0u, 0u);
         }
-        const uint64_t pos = a.qoff[v.x] + (uint64_t)v.w;
-        if (pos >= a.qoff[v.x + 1] || pos >= a.qcap) {   // cannot happen while counts and lists agree
-            ++bad;
-            continue;
+        uint64_t lo[4], hi[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t x = v[u].x < a.N ? v[u].x : 0u;
+            lo[u] = a.qoff[x];
+            hi[u] = a.qoff[x + 1];
         }
-        a.qsorted[pos] = make_uint2(v.y, v.z);
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            if (e0 + u * S >= n) continue;
+            const uint64_t pos = lo[u] + (uint64_t)v[u].w;
+            // cannot happen while counts and lists agree
+            if (v[u].x >= a.N || pos >= hi[u] || pos >= a.qcap) {
+                ++bad;
+                continue;
+            }
+            a.qsorted[pos] = make_uint2(v[u].y, v[u].z);
+        }
     }
     if (bad) atomicAdd(a.dropped, bad);
 }
@@ -209,12 +282,13 @@ __device__ __forceinline__ void x_ext_sorted(const XArgs& a, const XIn& in, uint
 }
 
 // Many queued inputs: heap-sort the neuron's own slice seg[0 .. nrec) in
-// place, hold its external inputs sorted in its LDS slots, and take the two
-// in time order, inputs of one instant together.
+// place (unless a wave has sorted it already), hold its external inputs
+// sorted in its LDS slots, and take the two in time order, inputs of one
+// instant together.
 __device__ __forceinline__ void x_take_merged(const XArgs& a, XNeuron& s, const XIn& in, uint2* seg,
-                                              uint32_t nrec, uint2* e)
+                                              uint32_t nrec, uint2* e, bool sorted)
 {
-    x_heap_sort(seg, nrec);
+    if (!sorted) x_heap_sort(seg, nrec);
     x_ext_sorted(a, in, e);
     uint32_t ir = 0, ie = 0;
     while (ir < nrec || ie < in.next) {
@@ -265,6 +339,174 @@ __device__ __forceinline__ void x_take_selected(const XArgs& a, XNeuron& s, cons
         x_input(a, s, in.t0, (uint32_t)best, J, in.exc, in.forced, in.ff);
         lo = best + 1;
     }
+}
+
+// What a wave's update of one neuron hands back (the same in every lane).
+struct XWaveOut {
+    float V, W;
+    uint64_t re;
+    uint32_t spiked, fsp, dis;
+};
+
+// One neuron's step by a whole wave, in closed form (Eq. (1)-(2)).  Its n
+// queued inputs (seg, in LDS) and its external inputs are sorted together
+// by offset (a bitonic network over {offset, charge} packed as 64-bit keys;
+// padding sorts last and is never taken).  From the start Ts (the step's
+// start, or the end of a refractory period inside the step; earlier inputs
+// are discarded) until the neuron spikes, w decays freely and u = V - E is
+// linear in the inputs: after the inputs up to instant T_k,
+//   u_k = e^{-h_k/tau_m} (u_s + sum_{i<=k} J_i e^{(T_i - Ts)/tau_m}) - kappa(h_k) w_s,
+// h_k = T_k - Ts, kappa(h) = ck (e^{-h/tau_w} - e^{-h/tau_m}) (h/tau_m e^{-h/tau_m}
+// when tau_w = tau_m), so every instant is evaluated at once from a prefix sum
+// over the sorted inputs (summed in double; the per-input decay factors in
+// single precision, the end-of-step state in double).  Inputs of one instant
+// are summed before the threshold test, which takes place at the last input
+// of each instant.
+// The spike is the first instant above threshold (lock-step: the forced
+// instant; disagreements are counted up to it); the refractory period (at
+// least 1 ms) then covers the rest of the step.
+template <uint32_t K>
+__device__ __forceinline__ void x_wave_neuron(const XArgs& a, const uint2* seg, uint32_t n, const XIn& in,
+                                              float V0, float W0, uint64_t re0, uint32_t lane, XWaveOut& o)
+{
+    const uint32_t nall = n + in.next;
+    uint64_t v[K];
+#pragma unroll
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint32_t i = r * 64u + lane;
+        uint2 x = make_uint2(~0u, ~0u);
+        if (i < n) {
+            x = seg[i];
+        } else if (i < nall) {
+            const uint32_t e = i - n;
+            const uint32_t f =
+                a.ext_const ? 0u : word(x_philox(in.j, in.t, kStreamExtTime, e >> 2, a.key0, a.key1), e & 3u);
+            x = make_uint2(f, (uint32_t)in.jext);
+        }
+        v[r] = ((uint64_t)x.x << 32) | x.y;
+    }
+    x_bitonic<K>(v, lane);
+
+    const uint64_t t0 = in.t0, t1 = t0 + (1ull << 32);
+    const double dt = 0x1p-32;   // ms per unit of the 32.32 times
+    const bool held = re0 > t0;
+    const uint64_t Ts = held ? (re0 < t1 ? re0 : t1) : t0;
+    const double us = held ? a.dv_reset - a.de_rest : (double)V0 - a.de_rest;
+    const double ws = held ? (double)W0 * exp(-(double)(Ts - t0) * dt * a.dinv_tau_w) : (double)W0;
+    o.re = re0;
+    o.spiked = 0u;
+    o.fsp = 0u;
+    o.dis = 0u;
+    if (Ts >= t1) {   // (uniform) refractory for the whole step: every input is discarded
+        o.V = a.v_reset;
+        o.W = (float)ws;
+        return;
+    }
+    // the decay factors of one input or instant (h in ms, at most 1) in
+    // single precision: each multiplies a term that is then summed in double
+    const float fm = a.inv_tau_m, fw = a.inv_tau_w, fck = a.ck;
+    auto kappa = [&](float h, float em) {
+        return a.tau_equal ? h * fm * em : fck * (expf(-h * fw) - em);
+    };
+    // prefix sums of the decay-weighted charges, in sorted order: a wave scan
+    // of every register at once (their shuffles overlap), then the carries
+    double P[K];
+    uint32_t F[K];
+#pragma unroll
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint32_t i = r * 64u + lane;
+        F[r] = (uint32_t)(v[r] >> 32);
+        const uint64_t T = t0 | F[r];
+        const bool valid = i < nall && T >= Ts;
+        const float g = expf((float)(T - Ts) * 0x1p-32f * fm);
+        P[r] = valid ? (double)(int32_t)(uint32_t)v[r] * 0x1p-16 * (double)g : 0.0;
+    }
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        double y[K];
+#pragma unroll
+        for (uint32_t r = 0; r < K; ++r) y[r] = __shfl_up(P[r], d);
+#pragma unroll
+        for (uint32_t r = 0; r < K; ++r)
+            if (lane >= d) P[r] += y[r];
+    }
+    double carry = 0.0;
+#pragma unroll
+    for (uint32_t r = 0; r < K; ++r) {
+        P[r] += carry;
+        carry = __shfl(P[r], 63);
+    }
+    // threshold tests at the last input of each instant
+    bool found = false, ffound = false;
+    uint32_t fstar = 0u, fidx = ~0u;
+    bool own[K], test[K];
+#pragma unroll
+    for (uint32_t r = 0; r < K; ++r) {
+        const uint32_t i = r * 64u + lane;
+        const uint64_t T = t0 | F[r];
+        uint32_t fn = __shfl_down(F[r], 1u);
+        const uint32_t f0 = r + 1u < K ? (uint32_t)__builtin_amdgcn_readlane((int)F[r + 1u < K ? r + 1u : r], 0) : 0u;
+        if (lane == 63u) fn = f0;
+        test[r] = i < nall && T >= Ts && (i + 1u >= nall || fn != F[r]);
+        const float h = (float)(T - Ts) * 0x1p-32f;
+        const float em = expf(-h * fm);
+        const double u = (double)em * (us + P[r]) - (double)kappa(h, em) * ws;
+        own[r] = test[r] && a.de_rest + u > a.dv_th;
+        const uint64_t m = __ballot(own[r]);
+        if (!found && m) {
+            found = true;
+            const int l = __builtin_ctzll(m);
+            fstar = (uint32_t)__builtin_amdgcn_readlane((int)F[r], l);
+        }
+        if (a.forced) {
+            const uint64_t mf = __ballot(test[r] && in.forced && F[r] == in.ff);
+            if (!ffound && mf) {
+                ffound = true;
+                fidx = r * 64u + (uint32_t)__builtin_ctzll(mf);
+            }
+        }
+    }
+    if (a.forced) {
+        // lock-step: the spike is the forced instant; an instant up to it
+        // whose own decision differs from the forced one is a disagreement
+        uint32_t dis = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < K; ++r) {
+            const uint32_t i = r * 64u + lane;
+            dis += (uint32_t)__popcll(__ballot(test[r] && i <= fidx && own[r] != (i == fidx)));
+        }
+        o.dis = dis;
+        found = ffound;
+        fstar = in.ff;
+    }
+    if (found) {
+        const uint64_t Tsp = t0 | fstar;
+        double w = ws * exp(-(double)(Tsp - Ts) * dt * a.dinv_tau_w);
+        if (in.exc || a.sfa_on_inh) w += a.dalpha;
+        o.spiked = 1u;
+        o.fsp = fstar;
+        o.re = Tsp + a.tref_q;   // >= t1: held to the end of the step
+        o.V = a.v_reset;
+        o.W = (float)(w * exp(-(double)(t1 - Tsp) * dt * a.dinv_tau_w));
+    } else {
+        const double h = (double)(t1 - Ts) * dt;
+        const double em = exp(-h * a.dinv_tau_m), ew = exp(-h * a.dinv_tau_w);
+        const double kap = a.tau_equal ? h * a.dinv_tau_m * em : a.dck * (ew - em);
+        o.V = (float)(a.de_rest + em * (us + carry) - kap * ws);
+        o.W = (float)(ws * ew);
+    }
+}
+
+// (n + next wave-uniform, at most kXWaveSort)
+__device__ __forceinline__ void x_wave_neuron_any(const XArgs& a, const uint2* seg, uint32_t n, const XIn& in,
+                                                  float V0, float W0, uint64_t re0, uint32_t lane, XWaveOut& o)
+{
+    const uint32_t nall = n + in.next;
+    if (nall <= 64u) x_wave_neuron<1>(a, seg, n, in, V0, W0, re0, lane, o);
+    else if (nall <= 128u) x_wave_neuron<2>(a, seg, n, in, V0, W0, re0, lane, o);
+    else if (nall <= 256u) x_wave_neuron<4>(a, seg, n, in, V0, W0, re0, lane, o);
+    else if (nall <= 512u) x_wave_neuron<8>(a, seg, n, in, V0, W0, re0, lane, o);
+    else x_wave_neuron<16>(a, seg, n, in, V0, W0, re0, lane, o);
 }
 
 // A workgroup whose queued inputs average more than kXBusyPer per neuron is
@@ -397,7 +639,7 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
                 x_input(a, s, t0, f, J, exc, fj, ff);
             }
         } else if (next <= kXLocal) {
-            x_take_merged(a, s, in, a.qsorted + k0, nrec, ev_s + tid);
+            x_take_merged(a, s, in, a.qsorted + k0, nrec, ev_s + tid, false);
         } else {
             x_take_selected(a, s, in, a.qsorted + k0, nrec);
         }
@@ -413,12 +655,17 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
 }
 
 // Busy workgroups: the workgroup's queued inputs are read into LDS in
-// windows of up to kXBusyCap entries, coalesced; a neuron whose whole slice
-// lies in the window heap-sorts it there, holds its external inputs sorted in
-// its LDS slots, merges the two and integrates.  The next window starts at
-// the first neuron not yet done, so every pass finishes at least that neuron;
-// only a slice longer than a whole window is sorted where it lies, in global
-// memory.
+// windows of up to kXBusyCap entries, coalesced.  Lane l takes neuron
+// (l mod 64) * 4 + l / 64 of the workgroup, so that the run of consecutive
+// neurons a window holds keeps every wave busy.  Each wave updates its own
+// neurons whose slices lie whole in the window one at a time with all its
+// lanes, in closed form (x_wave_neuron; at most kXWaveSort inputs with the
+// external ones); a neuron with more inputs is updated by its own lane, which
+// heap-sorts its slice, holds its external inputs sorted in its LDS slots,
+// merges the two and integrates input by input.  The next window starts at
+// the first neuron not yet done, so every pass finishes at least that
+// neuron; only a slice longer than a whole window is sorted where it lies,
+// in global memory.
 __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
 {
     __shared__ uint2 in_s[kXBusyCap];            // one window of the workgroup's inputs, by target
@@ -427,12 +674,16 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
     __shared__ uint32_t wcnt[kXBlock / 64];
     __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
     __shared__ unsigned long long wlo[kXBlock / 64];
+    __shared__ uint32_t spk_s[kXBlock];
     if (!x_block_busy(a)) return;   // (uniform) the workgroup is k_x_update's
     const uint32_t t = a.ctrl->t0;
     const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint32_t j = blockIdx.x * kXBlock + tid;
-    const bool live = j < a.N;
     const uint32_t first = blockIdx.x * kXBlock;
+    // neighbouring neurons go to different waves: a window holds a run of
+    // consecutive neurons, which then keeps every wave busy
+    const uint32_t jl = lane * (kXBlock / 64u) + wv;
+    const uint32_t j = first + jl;
+    const bool live = j < a.N;
     uint64_t base = a.qoff[first];
     base = base < a.qcap ? base : a.qcap;
     const uint64_t end = base + x_block_inputs(a);
@@ -475,10 +726,39 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
         __syncthreads();
         const bool whole = k0 >= lo && k1 <= hi;          // the slice lies in this window
         const bool huge = nrec > kXBusyCap;                 // no window holds it
-        if (!done && (whole || huge)) {
+        const bool take = !done && (whole || huge);
+        const bool coop = take && whole && nrec + next <= kXWaveSort;
+        const uint32_t off = whole ? (uint32_t)(k0 - lo) : 0u;
+        // (uniform) this wave's neurons whose slices lie in the window, one at
+        // a time with every lane
+        for (uint64_t m = __ballot(coop); m; m &= m - 1ull) {
+            const int l = __builtin_ctzll(m);
+            const uint64_t re_l = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(re0 >> 32), l) << 32) |
+                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)re0, l);
+            const XIn in_l{(uint32_t)__builtin_amdgcn_readlane((int)j, l), t,
+                           (uint32_t)__builtin_amdgcn_readlane((int)next, l), jext,
+                           __builtin_amdgcn_readlane((int)exc, l) != 0, __builtin_amdgcn_readlane((int)fj, l) != 0,
+                           (uint32_t)__builtin_amdgcn_readlane((int)ff, l), t0};
+            XWaveOut o;
+            x_wave_neuron_any(a, in_s + __builtin_amdgcn_readlane((int)off, l),
+                              (uint32_t)__builtin_amdgcn_readlane((int)nrec, l), in_l,
+                              __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, V0), l)),
+                              __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, W0), l)),
+                              re_l, lane, o);
+            if (lane == (uint32_t)l) {
+                a.V[j] = o.V;
+                a.W[j] = o.W;
+                a.rend[j] = o.re;
+                if (o.spiked) a.fs[j] = o.fsp;
+                spiked = o.spiked;
+                dis = o.dis;
+                done = true;
+            }
+        }
+        if (take && !coop) {
             XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
-            uint2* seg = whole ? in_s + (k0 - lo) : a.qsorted + k0;
-            if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid);
+            uint2* seg = whole ? in_s + off : a.qsorted + k0;
+            if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid, false);
             else x_take_selected(a, s, in, seg, nrec);
             x_advance(a, s, t1);
             a.V[j] = s.V;
@@ -504,7 +784,10 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
         if (nlo == ~0ull) break;
         lo = nlo;
     }
-    x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
+    // the spiker list is built in ascending id: lane tid closes neuron first + tid
+    spk_s[jl] = spiked;
+    __syncthreads();
+    x_close_block(a, first + tid, spk_s[tid], next, dis, wcnt, wext, wdis);
 }
 
 __global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)
@@ -572,51 +855,68 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
         unsigned long long base = 0;
         if (cnt) base = atomicAdd(a.qn + slot, (unsigned long long)cnt);
         // this lane's records k = s0 + 64 u + lane, u < 4: every load issued before any use
-        auto load = [&](uint32_t u, uint32_t& tgt, int32_t& wf) {
-            const uint32_t k = s0 + 64u * u + lane;
-            const uint32_t kk = k < s1 ? k : s1 - 1u;
-            if (a.record) {
-                const uint32_t v = reinterpret_cast<const uint32_t*>(a.recs)[rb + kk];
-                tgt = v >> 8;
-                wf = (int32_t)(v & 255u);
-            } else {
-                const Rec8 r = reinterpret_cast<const Rec8*>(a.recs)[rb + kk];
-                tgt = r.tgt & kTgtMask;
-                wf = __float2int_rn(r.w * 65536.0f);
+        uint32_t tg[4], bk[4];
+        int32_t wq[4];
+        if (a.record) {   // (uniform)
+            uint32_t v[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t k = s0 + 64u * u + lane;
+                v[u] = reinterpret_cast<const uint32_t*>(a.recs)[rb + (k < s1 ? k : s1 - 1u)];
             }
-        };
-        auto emit = [&](uint32_t u, uint32_t tgt, int32_t wf) {
-            if (s0 + 64u * u >= s1) return;   // (uniform) past the segment's end
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                tg[u] = v[u] >> 8;
+                wq[u] = (int32_t)(v[u] & 255u);
+                bk[u] = 0u;
+            }
+        } else {
+            Rec8 r[4];
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                const uint32_t k = s0 + 64u * u + lane;
+                r[u] = reinterpret_cast<const Rec8*>(a.recs)[rb + (k < s1 ? k : s1 - 1u)];
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < 4; ++u) {
+                tg[u] = r[u].tgt & kTgtMask;
+                bk[u] = r[u].tgt >> kTgtBits;   // 8-byte records carry their delay bucket
+                wq[u] = __float2int_rn(r[u].w * 65536.0f);
+            }
+        }
+        // each record's bucket, that bucket's reservation and the record's
+        // place in it
+        unsigned long long pos[4];
+        uint32_t sl[4];
+        bool ok[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
             const uint32_t k = s0 + 64u * u + lane;
             const uint32_t kk = k < s1 ? k : s1 - 1u;
-            uint32_t d = 0;
-            for (uint32_t l = 0; l < a.D; ++l)
-                d += kk >= (uint32_t)__builtin_amdgcn_readlane((int)end, (int)l) ? 1u : 0u;
+            uint32_t d = bk[u];
+            if (a.record) {   // (uniform) 8-bit codes: the bucket from the row's bucket ends
+                d = 0;
+                for (uint32_t l = 0; l < a.D; ++l)
+                    d += kk >= (uint32_t)__builtin_amdgcn_readlane((int)end, (int)l) ? 1u : 0u;
+            }
             const uint32_t bl = __shfl(lo, (int)d);
-            const uint32_t sl = __shfl(slot, (int)d);
-            const unsigned long long bb = __shfl(base, (int)d);
-            if (k < s1) {
-                const unsigned long long pos = bb + (kk - bl);
-                const int32_t w = a.record ? cb_s[wf] : wf;
-                if (pos < a.qcap && tgt < a.N) {
-                    // the input's rank among its target's inputs of the slot
-                    const uint32_t r = atomicAdd(a.qcnt + (size_t)sl * a.N + tgt, 1u);
-                    a.qlist[(size_t)sl * a.qcap + pos] = make_uint4(tgt, f, (uint32_t)w, r);
-                } else {
-                    ++drop;
-                }
-            }
-        };
-        uint32_t t0r, t1r, t2r, t3r;
-        int32_t w0r, w1r, w2r, w3r;
-        load(0, t0r, w0r);
-        load(1, t1r, w1r);
-        load(2, t2r, w2r);
-        load(3, t3r, w3r);
-        emit(0, t0r, w0r);
-        emit(1, t1r, w1r);
-        emit(2, t2r, w2r);
-        emit(3, t3r, w3r);
+            sl[u] = __shfl(slot, (int)d);
+            pos[u] = __shfl(base, (int)d) + (kk - bl);
+            ok[u] = k < s1 && pos[u] < a.qcap && tg[u] < a.N;
+            if (k < s1 && !ok[u]) ++drop;
+        }
+        // every count increment goes out before any entry is written: the
+        // increment returns the input's rank among its target's inputs of the slot
+        uint32_t rk[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) rk[u] = ok[u] ? atomicAdd(a.qcnt + (size_t)sl[u] * a.N + tg[u], 1u) : 0u;
+        // one wait for the four ranks (else each store waits for the stores before it)
+        __builtin_amdgcn_s_waitcnt(0);
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+            if (ok[u])
+                a.qlist[(size_t)sl[u] * a.qcap + pos[u]] =
+                    make_uint4(tg[u], f, (uint32_t)(a.record ? cb_s[wq[u]] : wq[u]), rk[u]);
     }
     drop = x_wave_sum<unsigned long long>(drop);
     if (lane == 0 && drop) atomicAdd(a.dropped, drop);

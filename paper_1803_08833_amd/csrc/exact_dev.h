@@ -20,6 +20,7 @@ constexpr uint32_t kXBlock = 256;          // neurons per update workgroup
 constexpr uint32_t kXLocal = 16;           // inputs per neuron sorted in LDS (more: slow path)
 constexpr uint32_t kXBusyPer = 8;          // a workgroup averaging more inputs per neuron is busy
 constexpr uint32_t kXBusyCap = 15 * 1024;  // inputs of a busy workgroup held in LDS
+constexpr uint32_t kXWaveSort = 1024;      // longest slice a busy workgroup's wave sorts together
 
 struct XArgs {
     uint32_t N, M, n_exc, sfa_on_inh;
@@ -35,6 +36,8 @@ struct XArgs {
     uint64_t tref_q;                       // refractory period, 2^-32 ms
     float v_th, v_reset, e_rest, alpha;
     float inv_tau_m, inv_tau_w, ck;        // ck = tau_w / (tau_w - tau_m)
+    double dinv_tau_m, dinv_tau_w, dck;    // the same in double (closed-form update of busy workgroups)
+    double dv_th, dv_reset, de_rest, dalpha;
     float* V;
     float* W;
     uint64_t* rend;                        // [N] end of the refractory period

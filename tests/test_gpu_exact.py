@@ -111,6 +111,27 @@ def test_lockstep_exact_many_inputs(snn, oracle_mod):
     assert st["disagree"] <= max(2, nsp // 1000)
 
 
+@pytest.mark.parametrize("case", ["upto512", "past1024"])
+def test_lockstep_exact_busy_sorted_by_waves(snn, oracle_mod, case):
+    """A 12 Hz drive bursts the network within a few steps, so that every
+    update workgroup is busy and its neurons' slices, at hundreds of distinct
+    offsets with ties, span each width the busy kernel's waves sort together
+    (2-64 ... 513-1024 inputs) and, past 1024, the single-lane heap sort, over
+    many LDS windows per workgroup.  Lock-step against the oracle's free run."""
+    if case == "upto512":
+        net = W.make(2, 1, W.GAUSS, 1.0, 1100, 71, n_exc=960, n_inh=240, solver=W.SOLVER_EXACT, d_max=2,
+                     ext_rate_hz=12.0)
+        steps, want = 8, 256
+    else:
+        net = W.make(2, 1, W.GAUSS, 1.0, 2200, 71, n_exc=1920, n_inh=480, solver=W.SOLVER_EXACT, d_max=1,
+                     ext_rate_hz=12.0)
+        steps, want = 6, 1024
+    say(f"case: exact lock-step, busy workgroups sorted by waves ({case}), N {W.n_neurons(net)}")
+    st, nsp, big = _lockstep(snn, oracle_mod, net, steps, qcap=1 << 23)
+    assert big > want, big
+    assert st["disagree"] <= max(2, nsp // 1000)
+
+
 def test_graph_replay_equals_single_launches(snn):
     """Free runs stepped through captured R-step graphs (from any phase) and
     launched step by step give bitwise identical rasters, offsets and state."""
