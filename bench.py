@@ -28,12 +28,12 @@ HBM_PEAK_GBS = 8000.0                 # MI355X HBM3E peak
 BYTES_PER_EVENT = {0: 16, 1: 12}      # record + ring slot read + write (F32 / 8-bit code records)
 BYTES_PER_NEURON_STEP = 26            # V 4+4, w 4+4, ref 1+1, ring slot 4+4
 # Exact-time solver: per event the record (8 / 4 B), the queue entry written
-# (16) and read back (16), its target's count raised (4), the placed
-# {offset, charge} pair written (8) and read by the update (8); per neuron and
-# step V, w and the refractory end read and written (32), the input count
-# scanned and zeroed (4 read, 4 written), its offset written (8) and read (8).
-BYTES_EXACT_PER_EVENT = {0: 60, 1: 56}
-BYTES_EXACT_PER_NEURON_STEP = 56
+# (16) and read back (16), the placed {offset, charge} pair written (8) and
+# read by the update (8); per neuron and step V, w and the refractory end read
+# and written (32), its input offset written (8) and read (8).  The arrival
+# sort's group pass (each entry written and read once more) is not counted.
+BYTES_EXACT_PER_EVENT = {0: 56, 1: 52}
+BYTES_EXACT_PER_NEURON_STEP = 48
 
 
 def parse():
@@ -239,9 +239,9 @@ def main():
     bpn = BYTES_PER_NEURON_STEP
     ev_per_step = kt["rec_events"] / steps_k
     if exact:
-        # one step: count scan, k_x_place, k_x_update, spike scan, k_x_deliver, k_x_finish
-        name = ("k_x_place+k_x_update+k_x_deliver with their scans (one 1 ms step of the exact-time "
-                "solver)")
+        # one step: arrival sort (k_xs_*), k_x_update(_busy), k_x_list, k_x_offsets, k_x_deliver, k_x_finish
+        name = ("k_xs_*+k_x_update+k_x_offsets+k_x_deliver and the rest of one 1 ms step of the "
+                "exact-time solver")
         ms = kt["step_ms"]
         bpe, bpn = BYTES_EXACT_PER_EVENT[net["record"]], BYTES_EXACT_PER_NEURON_STEP
     elif stf["deliver_mode"] == 1:

@@ -75,7 +75,6 @@ struct snn_net {
     snn::XArgs x{};
     uint32_t xt = 0;                  // steps taken
     uint64_t qcap_opt = 0;            // SNN_OPT_QUEUE_CAP, set before the build (0: automatic)
-    uint64_t* xtsum = nullptr;        // scan scratch: per-target counts
     uint8_t* xforced = nullptr;       // lock-step flags and offsets
     uint32_t* xforced_f = nullptr;
     hipGraph_t xgraph = nullptr;      // R captured steps from a step t with t mod R = 0
@@ -481,12 +480,17 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
     // inputs queued per slot: a step's events at a 150 Hz mean rate, or the option
     const double qc = n->qcap_opt ? (double)n->qcap_opt : (double)n->N * (tb.mean_out + 1.0) * 0.15 + 65536.0;
     x.qcap = (uint64_t)std::min(qc, 4.0e9);
+    // arrival sort: targets in at most kXGroups groups of 2^gbits >= 256 neurons
+    x.gbits = 8;
+    while (((uint64_t)n->N + (1ull << x.gbits) - 1) >> x.gbits > snn::kXGroups) ++x.gbits;
+    if (x.gbits > snn::kXGroupBitsMax)
+        return fail(n, SNN_E_INVAL, "the exact solver takes at most 2^24 neurons");
+    x.ngroups = (uint32_t)(((uint64_t)n->N + (1ull << x.gbits) - 1) >> x.gbits);
     hipError_t e = hipSuccess;
 #define XALLOC(p, cnt) \
     if (e == hipSuccess) e = dalloc(n, &(p), (size_t)(cnt))
     XALLOC(x.rend, n->N);
     XALLOC(x.fs, n->N);
-    XALLOC(x.qcnt, (size_t)x.R * n->N);
     XALLOC(x.qlist, (size_t)x.R * x.qcap);
     XALLOC(x.qn, x.R);
     XALLOC(x.qn_prev, x.R);
@@ -494,18 +498,22 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
     XALLOC(x.dropped, 1);
     XALLOC(x.qoff, (size_t)n->N + 1);
     XALLOC(x.qsorted, x.qcap);
+    XALLOC(x.qtmp, x.qcap);
+    XALLOC(x.gcnt, x.ngroups);
+    XALLOC(x.goff, (size_t)x.ngroups + 1);
+    XALLOC(x.gcur, x.ngroups);
+    XALLOC(x.xpref, (size_t)n->N * x.D);
     XALLOC(x.blk_cnt, x.nblk);
     XALLOC(x.blk_list, (size_t)x.nblk * snn::kXBlock);
     XALLOC(x.blk_off, (size_t)x.nblk + 1);
     XALLOC(x.spk, n->N);
     XALLOC(x.hist_f, g.hist_cap);
-    XALLOC(n->xtsum, snn::scan_tiles(n->N) + 1);
     XALLOC(n->xforced, n->N);
     XALLOC(n->xforced_f, n->N);
 #undef XALLOC
     if (e != hipSuccess) return fail(n, SNN_E_NOMEM, "device allocation failed (exact-solver queues)");
     HIPCHK(n, hipMemsetAsync(x.rend, 0, 8 * (size_t)n->N, n->stream));
-    HIPCHK(n, hipMemsetAsync(x.qcnt, 0, 4 * (size_t)x.R * n->N, n->stream));
+    HIPCHK(n, hipMemsetAsync(x.gcnt, 0, 4 * (size_t)x.ngroups, n->stream));
     HIPCHK(n, hipMemsetAsync(x.qn, 0, 8 * (size_t)x.R, n->stream));
     HIPCHK(n, hipMemsetAsync(x.dropped, 0, 8, n->stream));
     HIPCHK(n, hipMemsetAsync(x.qoff, 0, 8, n->stream));      // offset of the first target
@@ -533,11 +541,7 @@ static snn_status setup_exact(snn_net* n, const snn::HostTables& tb)
 static hipError_t enqueue_exact_step(snn_net* n, const snn::XArgs& x, const snn::LaunchEv* ev)
 {
     const uint32_t t = n->xt;
-    const uint32_t slot = t % x.R;
-    // the arriving slot's counts are zeroed as they are scanned (the slot is
-    // next filled R steps later)
-    hipError_t e = snn::launch_scan_rows(x.qcnt + (size_t)slot * n->N, x.qoff, n->xtsum, n->N, n->stream, true);
-    if (e == hipSuccess) e = snn::launch_x_place(x, n->stream, ev ? &ev[0] : nullptr);
+    hipError_t e = snn::launch_x_place(x, n->stream, ev ? &ev[0] : nullptr);
     if (e == hipSuccess) e = snn::launch_x_update(x, n->stream, ev ? &ev[1] : nullptr);
     if (e == hipSuccess) e = snn::launch_x_list(x, n->stream);
     if (e == hipSuccess) e = snn::launch_x_deliver(x, n->stream, ev ? &ev[2] : nullptr);
@@ -547,8 +551,8 @@ static hipError_t enqueue_exact_step(snn_net* n, const snn::XArgs& x, const snn:
 }
 
 // Exact solver, n_ms steps: whenever the step index is a multiple of R and R
-// steps are left, the R steps are replayed from a captured graph (the scans'
-// slot pointers are fixed in it, the kernels read the step from the device);
+// steps are left, the R steps are replayed from a captured graph (the kernels
+// read the step from the device, so one capture serves every such sequence);
 // other steps are launched one by one.
 static hipError_t step_exact(snn_net* n, uint32_t n_ms)
 {
@@ -1431,7 +1435,7 @@ snn_status snn_reset(snn_net* n)
     if (n->exact) {
         const snn::XArgs& x = n->x;
         HIPCHK(n, hipMemsetAsync(x.rend, 0, 8 * (size_t)n->N, n->stream));
-        HIPCHK(n, hipMemsetAsync(x.qcnt, 0, 4 * (size_t)x.R * n->N, n->stream));
+        HIPCHK(n, hipMemsetAsync(x.gcnt, 0, 4 * (size_t)x.ngroups, n->stream));
         HIPCHK(n, hipMemsetAsync(x.qn, 0, 8 * (size_t)x.R, n->stream));
         HIPCHK(n, hipMemsetAsync(x.dropped, 0, 8, n->stream));
         n->xt = 0;

@@ -212,43 +212,203 @@ __device__ __forceinline__ void x_bitonic(uint64_t* v, uint32_t lane)
     }
 }
 
-__global__ __launch_bounds__(256) void k_x_place(XArgs a)
+// Arrival sort of the step's slot (its inputs in delivery order) by target,
+// in three passes and no device atomic per input.  1: each workgroup counts
+// its contiguous chunk of the list per target group in LDS and adds the
+// nonzero counts to the group totals.  2: one workgroup scans the totals.
+// 3: each workgroup counts its chunk again, reserves each group's share at
+// the group's cursor and writes every input there (its place among the
+// chunk's inputs of the group from an LDS counter).  4: one workgroup per
+// group counts the group's inputs per neuron in LDS, writes the neurons'
+// offsets and places the {offset, charge} pairs by neuron.  Within one
+// target the order is arbitrary: the update sorts by offset.
+__device__ __forceinline__ void x_chunk(const XArgs& a, uint64_t& c0, uint64_t& c1, const uint4*& L)
 {
-    const uint32_t t = a.ctrl->t0;   // the step in flight (k_x_finish advances it)
-    const uint32_t slot = t % a.R;
+    const uint32_t slot = a.ctrl->t0 % a.R;   // the step in flight (k_x_finish advances it)
     const uint64_t n0 = a.qn[slot];
     const uint64_t n = n0 < a.qcap ? n0 : a.qcap;
-    const uint4* L = a.qlist + (size_t)slot * a.qcap;
+    // chunks of at least kXChunkMin inputs: a short list leaves most
+    // workgroups idle instead of each sweeping its LDS histogram
+    uint64_t per = (n + gridDim.x - 1u) / gridDim.x;
+    per = per < kXChunkMin ? kXChunkMin : per;
+    c0 = (uint64_t)blockIdx.x * per;
+    c0 = c0 < n ? c0 : n;
+    c1 = c0 + per < n ? c0 + per : n;
+    L = a.qlist + (size_t)slot * a.qcap;
+}
+
+__global__ __launch_bounds__(256) void k_xs_count(XArgs a)
+{
+    __shared__ uint32_t h[kXGroups];
+    uint64_t c0, c1;
+    const uint4* L;
+    x_chunk(a, c0, c1, L);
+    if (c0 >= c1) return;   // (uniform) an empty chunk
+    for (uint32_t i = threadIdx.x; i < a.ngroups; i += 256u) h[i] = 0u;
+    __syncthreads();
+    for (uint64_t e0 = c0 + threadIdx.x; e0 < c1; e0 += 4u * 256u) {
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {   // every load in flight before any count
+            const uint64_t e = e0 + 256u * u;
+            x[u] = e < c1 ? L[e].x : ~0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+            if (x[u] < a.N) atomicAdd(&h[x[u] >> a.gbits], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.ngroups; i += 256u)
+        if (h[i]) atomicAdd(a.gcnt + i, h[i]);
+}
+
+__global__ __launch_bounds__(1024) void k_xs_scan(XArgs a)
+{
+    __shared__ uint64_t wsum[16];
+    // thread i holds groups 4i .. 4i + 3 (ngroups <= kXGroups = 4 x 1024)
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    uint32_t c[4];
+    uint64_t sum = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t g = 4u * tid + u;
+        c[u] = g < a.ngroups ? a.gcnt[g] : 0u;
+        sum += c[u];
+    }
+    uint64_t inc = sum;
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint64_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63u) wsum[wv] = inc;
+    __syncthreads();
+    uint64_t off = inc - sum;
+    for (uint32_t w = 0; w < wv; ++w) off += wsum[w];
+#pragma unroll
+    for (uint32_t u = 0; u < 4; ++u) {
+        const uint32_t g = 4u * tid + u;
+        if (g < a.ngroups) {
+            a.goff[g] = off;
+            a.gcur[g] = off;
+            a.gcnt[g] = 0u;   // zero for the next step
+        }
+        if (g == a.ngroups) a.goff[g] = off;
+        off += c[u];
+    }
+    if (tid == 1023u && a.ngroups == kXGroups) a.goff[kXGroups] = off;
+}
+
+__global__ __launch_bounds__(256) void k_xs_scatter(XArgs a)
+{
+    __shared__ uint32_t h[kXGroups];
+    __shared__ unsigned long long base[kXGroups];
+    uint64_t c0, c1;
+    const uint4* L;
+    x_chunk(a, c0, c1, L);
+    if (c0 >= c1) return;   // (uniform) an empty chunk
+    for (uint32_t i = threadIdx.x; i < a.ngroups; i += 256u) h[i] = 0u;
+    __syncthreads();
+    for (uint64_t e0 = c0 + threadIdx.x; e0 < c1; e0 += 4u * 256u) {
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t e = e0 + 256u * u;
+            x[u] = e < c1 ? L[e].x : ~0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+            if (x[u] < a.N) atomicAdd(&h[x[u] >> a.gbits], 1u);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < a.ngroups; i += 256u) {
+        base[i] = h[i] ? atomicAdd(a.gcur + i, (unsigned long long)h[i]) : 0ull;
+        h[i] = 0u;
+    }
+    __syncthreads();
     unsigned long long bad = 0;
-    // four entries per thread and round, each step's loads all in flight together
-    const uint64_t S = (uint64_t)gridDim.x * 256u;
-    for (uint64_t e0 = (uint64_t)blockIdx.x * 256u + threadIdx.x; e0 < n; e0 += 4u * S) {
-        uint4 v[4];   // {target, offset, charge, rank}
+    for (uint64_t e0 = c0 + threadIdx.x; e0 < c1; e0 += 4u * 256u) {
+        uint4 v[4];
 #pragma unroll
         for (uint32_t u = 0; u < 4; ++u) {
-            const uint64_t e = e0 + u * S;
-            v[u] = e < n ? L[e] : make_uint4(~0u, 0u, 0u, 0u);
-        }
-        uint64_t lo[4], hi[4];
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) {
-            const uint32_t x = v[u].x < a.N ? v[u].x : 0u;
-            lo[u] = a.qoff[x];
-            hi[u] = a.qoff[x + 1];
+            const uint64_t e = e0 + 256u * u;
+            v[u] = e < c1 ? L[e] : make_uint4(~0u, 0u, 0u, 0u);
         }
 #pragma unroll
         for (uint32_t u = 0; u < 4; ++u) {
-            if (e0 + u * S >= n) continue;
-            const uint64_t pos = lo[u] + (uint64_t)v[u].w;
-            // cannot happen while counts and lists agree
-            if (v[u].x >= a.N || pos >= hi[u] || pos >= a.qcap) {
+            if (e0 + 256u * u >= c1) continue;
+            if (v[u].x >= a.N) {   // cannot happen: delivery writes only targets < N
                 ++bad;
                 continue;
             }
-            a.qsorted[pos] = make_uint2(v[u].y, v[u].z);
+            const uint32_t g = v[u].x >> a.gbits;
+            a.qtmp[base[g] + atomicAdd(&h[g], 1u)] = v[u];
         }
     }
     if (bad) atomicAdd(a.dropped, bad);
+}
+
+__global__ __launch_bounds__(256) void k_xs_group(XArgs a)
+{
+    __shared__ uint32_t c[1u << kXGroupBitsMax];
+    __shared__ uint32_t wsum[4];
+    const uint32_t g = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t j0 = g << a.gbits;
+    const uint32_t gs = 1u << a.gbits;
+    const uint32_t nj = a.N - j0 < gs ? a.N - j0 : gs;
+    const uint64_t lo = a.goff[g], hi = a.goff[g + 1];
+    for (uint32_t i = tid; i < nj; i += 256u) c[i] = 0u;
+    __syncthreads();
+    for (uint64_t e0 = lo + tid; e0 < hi; e0 += 4u * 256u) {
+        uint32_t x[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t e = e0 + 256u * u;
+            x[u] = e < hi ? a.qtmp[e].x - j0 : ~0u;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u)
+            if (x[u] < nj) atomicAdd(&c[x[u]], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the nj <= 4096 counts: thread i holds 16 in a row
+    const uint32_t per = (nj + 255u) / 256u;
+    const uint32_t b0 = tid * per;
+    uint32_t sum = 0;
+    for (uint32_t i = 0; i < per; ++i)
+        if (b0 + i < nj) sum += c[b0 + i];
+    uint32_t inc = sum;
+#pragma unroll
+    for (uint32_t d = 1; d < 64u; d <<= 1) {
+        const uint32_t y = __shfl_up(inc, d);
+        if (lane >= d) inc += y;
+    }
+    if (lane == 63u) wsum[wv] = inc;
+    __syncthreads();
+    uint32_t off = inc - sum;
+    for (uint32_t w = 0; w < wv; ++w) off += wsum[w];
+    for (uint32_t i = 0; i < per; ++i) {
+        if (b0 + i >= nj) break;
+        const uint32_t k = c[b0 + i];
+        a.qoff[j0 + b0 + i] = lo + off;
+        c[b0 + i] = off;   // the neuron's fill cursor
+        off += k;
+    }
+    if (j0 + nj == a.N && tid == 255u) a.qoff[a.N] = hi;
+    __syncthreads();
+    for (uint64_t e0 = lo + tid; e0 < hi; e0 += 4u * 256u) {
+        uint4 v[4];
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint64_t e = e0 + 256u * u;
+            v[u] = e < hi ? a.qtmp[e] : make_uint4(~0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < 4; ++u) {
+            const uint32_t x = v[u].x - j0;
+            if (e0 + 256u * u < hi && x < nj) a.qsorted[lo + atomicAdd(&c[x], 1u)] = make_uint2(v[u].y, v[u].z);
+        }
+    }
 }
 
 // What one neuron's step takes besides its queued inputs.
@@ -820,6 +980,65 @@ __global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)
     }
     const uint64_t rb = a.row_ptr[gid];
     a.spk[p] = make_uint4(gid, f, (uint32_t)rb, (uint32_t)(rb >> 32));
+    // the row's bucket lengths, which k_x_offsets turns into the spike's places
+    uint32_t prev = 0;
+    for (uint32_t d = 0; d < a.D; ++d) {
+        const uint32_t e = a.bend[(size_t)gid * a.D + d];
+        a.xpref[p * a.D + d] = e - prev;
+        prev = e;
+    }
+}
+
+// Where each spike's inputs go in the arrival lists, with no atomics: for
+// delay bucket d (one workgroup each, d < D), an exclusive scan over the
+// step's spikes of their rows' bucket-d lengths (k_x_list left them in
+// xpref) gives each spike's place in the list of slot (t + d_min + d) mod R,
+// after what earlier steps appended; the slot's count grows by the total.
+// Each thread scans a contiguous run of spikes, eight loads in flight.
+__global__ __launch_bounds__(1024) void k_x_offsets(XArgs a)
+{
+    __shared__ unsigned long long wsum[16];
+    const uint32_t d = blockIdx.x, tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
+    const uint32_t D = a.D;
+    const uint32_t slot = (a.ctrl->t0 + a.d_min + d) % a.R;
+    const uint64_t n = a.blk_off[a.nblk];   // the step's spikes
+    const uint64_t per = (n + 1023u) / 1024u;
+    const uint64_t p0 = (uint64_t)tid * per < n ? (uint64_t)tid * per : n;
+    const uint64_t p1 = p0 + per < n ? p0 + per : n;
+    uint32_t* const x = a.xpref + d;        // x[p * D]: spike p's bucket-d length, then place
+    unsigned long long sum = 0;
+    for (uint64_t p = p0; p < p1; p += 8u) {
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) v[u] = p + u < p1 ? x[(p + u) * D] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) sum += v[u];
+    }
+    unsigned long long inc = sum;
+#pragma unroll
+    for (uint32_t o = 1; o < 64u; o <<= 1) {
+        const unsigned long long y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63u) wsum[wv] = inc;
+    __syncthreads();
+    unsigned long long off = inc - sum, tot = 0;
+    for (uint32_t w = 0; w < 16u; ++w) {
+        if (w < wv) off += wsum[w];
+        tot += wsum[w];
+    }
+    for (uint64_t p = p0; p < p1; p += 8u) {
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) v[u] = p + u < p1 ? x[(p + u) * D] : 0u;
+#pragma unroll
+        for (uint32_t u = 0; u < 8; ++u) {
+            // (a place past 2^32 - 1 is past any list's capacity: the inputs are dropped, counted)
+            if (p + u < p1) x[(p + u) * D] = off < 0xFFFFFFFFull ? (uint32_t)off : 0xFFFFFFFFu;
+            off += v[u];
+        }
+    }
+    if (tid == 0) a.qn[slot] = a.qn_prev[slot] + tot;
 }
 
 __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
@@ -847,13 +1066,11 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
         const uint32_t end = lane < a.D ? endv : len;
         const uint32_t prev = __shfl_up(end, 1u);
         const uint32_t start = lane == 0 ? 0u : prev;
-        // the part of bucket `lane` inside this segment, its slot and reservation
-        const uint32_t lo = start > s0 ? start : s0;
-        const uint32_t hi = end < s1 ? end : s1;
-        const uint32_t cnt = (lane < a.D && hi > lo) ? hi - lo : 0u;
+        // bucket `lane`: its slot and where this spike's inputs of it start in
+        // the slot's list (the place k_x_offsets gave the spike there)
         const uint32_t slot = (t + a.d_min + lane) % a.R;
-        unsigned long long base = 0;
-        if (cnt) base = atomicAdd(a.qn + slot, (unsigned long long)cnt);
+        const unsigned long long base =
+            lane < a.D ? a.qn_prev[slot] + a.xpref[p * a.D + lane] : 0ull;
         // this lane's records k = s0 + 64 u + lane, u < 4: every load issued before any use
         uint32_t tg[4], bk[4];
         int32_t wq[4];
@@ -884,8 +1101,7 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
                 wq[u] = __float2int_rn(r[u].w * 65536.0f);
             }
         }
-        // each record's bucket, that bucket's reservation and the record's
-        // place in it
+        // each record's bucket and its place in that bucket's slot list
         unsigned long long pos[4];
         uint32_t sl[4];
         bool ok[4];
@@ -899,24 +1115,17 @@ __global__ __launch_bounds__(256) void k_x_deliver(XArgs a)
                 for (uint32_t l = 0; l < a.D; ++l)
                     d += kk >= (uint32_t)__builtin_amdgcn_readlane((int)end, (int)l) ? 1u : 0u;
             }
-            const uint32_t bl = __shfl(lo, (int)d);
+            const uint32_t bs = __shfl(start, (int)d);
             sl[u] = __shfl(slot, (int)d);
-            pos[u] = __shfl(base, (int)d) + (kk - bl);
+            pos[u] = __shfl(base, (int)d) + (kk - bs);
             ok[u] = k < s1 && pos[u] < a.qcap && tg[u] < a.N;
             if (k < s1 && !ok[u]) ++drop;
         }
-        // every count increment goes out before any entry is written: the
-        // increment returns the input's rank among its target's inputs of the slot
-        uint32_t rk[4];
-#pragma unroll
-        for (uint32_t u = 0; u < 4; ++u) rk[u] = ok[u] ? atomicAdd(a.qcnt + (size_t)sl[u] * a.N + tg[u], 1u) : 0u;
-        // one wait for the four ranks (else each store waits for the stores before it)
-        __builtin_amdgcn_s_waitcnt(0);
 #pragma unroll
         for (uint32_t u = 0; u < 4; ++u)
             if (ok[u])
                 a.qlist[(size_t)sl[u] * a.qcap + pos[u]] =
-                    make_uint4(tg[u], f, (uint32_t)(a.record ? cb_s[wq[u]] : wq[u]), rk[u]);
+                    make_uint4(tg[u], f, (uint32_t)(a.record ? cb_s[wq[u]] : wq[u]), 0u);
     }
     drop = x_wave_sum<unsigned long long>(drop);
     if (lane == 0 && drop) atomicAdd(a.dropped, drop);
@@ -956,7 +1165,13 @@ constexpr uint32_t kXGrid = 1024;   // workgroups of the grid-stride kernels
 
 hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 {
-    SNN_X_LAUNCH(ev, k_x_place, dim3(kXGrid), dim3(256), s, a);
+    // timed from the first kernel's start to the last one's end
+    if (ev) hipExtLaunchKernelGGL(k_xs_count, dim3(kXGrid), dim3(256), 0, s, ev->start, nullptr, 0, a);
+    else hipLaunchKernelGGL(k_xs_count, dim3(kXGrid), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_xs_scan, dim3(1), dim3(1024), 0, s, a);
+    hipLaunchKernelGGL(k_xs_scatter, dim3(kXGrid), dim3(256), 0, s, a);
+    if (ev) hipExtLaunchKernelGGL(k_xs_group, dim3(a.ngroups), dim3(256), 0, s, nullptr, ev->stop, 0, a);
+    else hipLaunchKernelGGL(k_xs_group, dim3(a.ngroups), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -975,6 +1190,7 @@ hipError_t launch_x_list(const XArgs& a, hipStream_t s)
 
 hipError_t launch_x_deliver(const XArgs& a, hipStream_t s, const LaunchEv* ev)
 {
+    hipLaunchKernelGGL(k_x_offsets, dim3(a.D), dim3(1024), 0, s, a);
     SNN_X_LAUNCH(ev, k_x_deliver, dim3(kXGrid), dim3(256), s, a);
     return hipGetLastError();
 }

@@ -5,11 +5,10 @@
 // emitted at the instant of the input that takes V above V_th and reaches each
 // target an integer delay later, keeping its offset.  Per arrival slot the
 // queued inputs are held twice: as an unsorted list appended by delivery
-// (one 16-byte {target, offset, charge} entry per event, and a per-target
-// count), and, at the step they arrive, counting-sorted by target into
-// {offset, charge} pairs.  The update takes each neuron's inputs, with its
-// external ones, in time order and integrates Eq. (1)-(2) exactly between
-// them.
+// (one 16-byte {target, offset, charge} entry per event), and, at the step
+// they arrive, counting-sorted by target into {offset, charge} pairs.  The
+// update takes each neuron's inputs, with its external ones, in time order
+// and integrates Eq. (1)-(2) exactly between them.
 #pragma once
 #include "snn_dev.h"
 
@@ -21,6 +20,9 @@ constexpr uint32_t kXLocal = 16;           // inputs per neuron sorted in LDS (m
 constexpr uint32_t kXBusyPer = 8;          // a workgroup averaging more inputs per neuron is busy
 constexpr uint32_t kXBusyCap = 15 * 1024;  // inputs of a busy workgroup held in LDS
 constexpr uint32_t kXWaveSort = 1024;      // longest slice a busy workgroup's wave sorts together
+constexpr uint32_t kXGroups = 4096;        // most target groups of the arrival sort
+constexpr uint32_t kXGroupBitsMax = 12;    // neurons per target group: at most 2^12
+constexpr uint64_t kXChunkMin = 1024;      // fewest inputs per workgroup of the arrival sort's chunk passes
 
 struct XArgs {
     uint32_t N, M, n_exc, sfa_on_inh;
@@ -42,13 +44,19 @@ struct XArgs {
     float* W;
     uint64_t* rend;                        // [N] end of the refractory period
     uint32_t* fs;                          // [N] offset of the neuron's last spike
-    uint32_t* qcnt;                        // [R][N] queued inputs per target (zeroed when scanned)
-    uint4* qlist;                          // [R][qcap] {target, offset, charge, rank among the target's inputs}
+    uint4* qlist;                          // [R][qcap] {target, offset, charge, 0}, in delivery order
     unsigned long long* qn;                // [R] entries appended per slot (may exceed qcap)
+    uint32_t* xpref;                       // [N][D] each spike's bucket lengths, then its place in each bucket's slot
     unsigned long long* qn_prev;           // [R] the same before the step's delivery
     unsigned long long* dropped;           // inputs that found their slot full
-    uint64_t* qoff;                        // [N + 1] exclusive scan of this step's counts
+    uint64_t* qoff;                        // [N + 1] start of each target's inputs of this step in qsorted
     uint2* qsorted;                        // [qcap] {offset, charge} by target
+    // arrival sort: targets in groups of 2^gbits neurons (ngroups <= kXGroups)
+    uint32_t gbits, ngroups;
+    uint32_t* gcnt;                        // [ngroups] inputs per group (zero between steps)
+    uint64_t* goff;                        // [ngroups + 1] start of each group's inputs
+    unsigned long long* gcur;              // [ngroups] fill cursors
+    uint4* qtmp;                           // [qcap] the arriving inputs by group
     uint32_t* blk_cnt;                     // [nblk] spikers per update workgroup
     uint32_t* blk_ext;                     // [nblk] external Poisson events per update workgroup
     uint32_t* blk_list;                    // [nblk * kXBlock] their ids, ascending
@@ -67,10 +75,11 @@ struct XArgs {
 };
 
 // One step of the solver, the step index t read from ctrl->t0 on the device
-// (so that a captured sequence of steps can be replayed): after the caller
-// has scanned qcnt[t mod R] into qoff, place the slot's inputs by target,
-// update every neuron, list the spikes (with their history entries), deliver
-// them, and close the step (t0 + 1).
+// (so that a captured sequence of steps can be replayed): order the arriving
+// slot's inputs by target (a counting sort by target group, then by neuron
+// within each group, which also gives qoff), update every neuron, list the
+// spikes (with their history entries), deliver them, and close the step
+// (t0 + 1).
 hipError_t launch_x_place(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_x_update(const XArgs& a, hipStream_t s, const LaunchEv* ev = nullptr);
 hipError_t launch_x_list(const XArgs& a, hipStream_t s);
