@@ -509,7 +509,7 @@ struct XWaveOut {
 };
 
 // One neuron's step by a whole wave, in closed form (Eq. (1)-(2)).  Its n
-// queued inputs (seg, in LDS) and its external inputs are sorted together
+// queued inputs (seg) and its external inputs are sorted together
 // by offset (a bitonic network over {offset, charge} packed as 64-bit keys;
 // padding sorts last and is never taken).  From the start Ts (the step's
 // start, or the end of a refractory period inside the step; earlier inputs
@@ -814,39 +814,25 @@ __global__ __launch_bounds__(kXBlock) void k_x_update(XArgs a)
     x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
 }
 
-// Busy workgroups: the workgroup's queued inputs are read into LDS in
-// windows of up to kXBusyCap entries, coalesced.  Lane l takes neuron
-// (l mod 64) * 4 + l / 64 of the workgroup, so that the run of consecutive
-// neurons a window holds keeps every wave busy.  Each wave updates its own
-// neurons whose slices lie whole in the window one at a time with all its
-// lanes, in closed form (x_wave_neuron; at most kXWaveSort inputs with the
-// external ones); a neuron with more inputs is updated by its own lane, which
-// heap-sorts its slice, holds its external inputs sorted in its LDS slots,
-// merges the two and integrates input by input.  The next window starts at
-// the first neuron not yet done, so every pass finishes at least that
-// neuron; only a slice longer than a whole window is sorted where it lies,
-// in global memory.
+// Busy workgroups: each wave updates its own 64 neurons one at a time with
+// all its lanes, in closed form (x_wave_neuron, the slice read coalesced
+// straight from qsorted into registers; at most kXWaveSort inputs with the
+// external ones).  No LDS window, so two workgroups share a CU and one's
+// loads overlap the other's shuffles.  A neuron with more inputs is updated
+// by its own lane, which heap-sorts its slice where it lies, holds its
+// external inputs sorted in its LDS slots, merges the two and integrates
+// input by input.
 __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
 {
-    __shared__ uint2 in_s[kXBusyCap];            // one window of the workgroup's inputs, by target
     __shared__ uint2 ev_s[kXLocal * kXBlock];    // external inputs [input][thread]
     __shared__ uint32_t pois_s[kMaxPois];
     __shared__ uint32_t wcnt[kXBlock / 64];
     __shared__ unsigned long long wext[kXBlock / 64], wdis[kXBlock / 64];
-    __shared__ unsigned long long wlo[kXBlock / 64];
-    __shared__ uint32_t spk_s[kXBlock];
     if (!x_block_busy(a)) return;   // (uniform) the workgroup is k_x_update's
     const uint32_t t = a.ctrl->t0;
-    const uint32_t tid = threadIdx.x, lane = tid & 63u, wv = tid >> 6;
-    const uint32_t first = blockIdx.x * kXBlock;
-    // neighbouring neurons go to different waves: a window holds a run of
-    // consecutive neurons, which then keeps every wave busy
-    const uint32_t jl = lane * (kXBlock / 64u) + wv;
-    const uint32_t j = first + jl;
+    const uint32_t tid = threadIdx.x, lane = tid & 63u;
+    const uint32_t j = blockIdx.x * kXBlock + tid;
     const bool live = j < a.N;
-    uint64_t base = a.qoff[first];
-    base = base < a.qcap ? base : a.qcap;
-    const uint64_t end = base + x_block_inputs(a);
     uint64_t k0 = 0, k1 = 0, re0 = 0;
     float V0 = 0.f, W0 = 0.f;
     if (live) {
@@ -862,8 +848,6 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
     uint32_t spiked = 0, next = 0, dis = 0;
     k1 = k1 < a.qcap ? k1 : a.qcap;
     k0 = k0 < k1 ? k0 : k1;
-    k0 = k0 > base ? k0 : base;
-    k1 = k1 > k0 ? k1 : k0;
     const uint32_t nrec = (uint32_t)(k1 - k0);
     if (live) {
         if (a.ext_const) {
@@ -877,77 +861,46 @@ __global__ __launch_bounds__(kXBlock) void k_x_update_busy(XArgs a)
     const bool exc = (j % a.M) < a.n_exc;
     const bool fj = (live && a.forced) ? a.forced[j] != 0 : false;
     const uint32_t ff = (live && a.forced) ? a.forced_f[j] : 0u;
-    const XIn in{j, t, next, jext, exc, fj, ff, t0};
-    bool done = !live;
-    uint64_t lo = base;
-    for (;;) {
-        const uint64_t hi = (end - lo) < kXBusyCap ? end : lo + kXBusyCap;
-        for (uint64_t i = lo + tid; i < hi; i += kXBlock) in_s[i - lo] = a.qsorted[i];
-        __syncthreads();
-        const bool whole = k0 >= lo && k1 <= hi;          // the slice lies in this window
-        const bool huge = nrec > kXBusyCap;                 // no window holds it
-        const bool take = !done && (whole || huge);
-        const bool coop = take && whole && nrec + next <= kXWaveSort;
-        const uint32_t off = whole ? (uint32_t)(k0 - lo) : 0u;
-        // (uniform) this wave's neurons whose slices lie in the window, one at
-        // a time with every lane
-        for (uint64_t m = __ballot(coop); m; m &= m - 1ull) {
-            const int l = __builtin_ctzll(m);
-            const uint64_t re_l = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(re0 >> 32), l) << 32) |
-                                  (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)re0, l);
-            const XIn in_l{(uint32_t)__builtin_amdgcn_readlane((int)j, l), t,
-                           (uint32_t)__builtin_amdgcn_readlane((int)next, l), jext,
-                           __builtin_amdgcn_readlane((int)exc, l) != 0, __builtin_amdgcn_readlane((int)fj, l) != 0,
-                           (uint32_t)__builtin_amdgcn_readlane((int)ff, l), t0};
-            XWaveOut o;
-            x_wave_neuron_any(a, in_s + __builtin_amdgcn_readlane((int)off, l),
-                              (uint32_t)__builtin_amdgcn_readlane((int)nrec, l), in_l,
-                              __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, V0), l)),
-                              __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, W0), l)),
-                              re_l, lane, o);
-            if (lane == (uint32_t)l) {
-                a.V[j] = o.V;
-                a.W[j] = o.W;
-                a.rend[j] = o.re;
-                if (o.spiked) a.fs[j] = o.fsp;
-                spiked = o.spiked;
-                dis = o.dis;
-                done = true;
-            }
+    const bool coop = live && nrec + next <= kXWaveSort;
+    // (uniform) this wave's neurons, one at a time with every lane
+    for (uint64_t m = __ballot(coop); m; m &= m - 1ull) {
+        const int l = __builtin_ctzll(m);
+        const uint64_t k0_l = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(k0 >> 32), l) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k0, l);
+        const uint64_t re_l = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(re0 >> 32), l) << 32) |
+                              (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)re0, l);
+        const XIn in_l{(uint32_t)__builtin_amdgcn_readlane((int)j, l), t,
+                       (uint32_t)__builtin_amdgcn_readlane((int)next, l), jext,
+                       __builtin_amdgcn_readlane((int)exc, l) != 0, __builtin_amdgcn_readlane((int)fj, l) != 0,
+                       (uint32_t)__builtin_amdgcn_readlane((int)ff, l), t0};
+        XWaveOut o;
+        x_wave_neuron_any(a, a.qsorted + k0_l, (uint32_t)__builtin_amdgcn_readlane((int)nrec, l), in_l,
+                          __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, V0), l)),
+                          __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, W0), l)),
+                          re_l, lane, o);
+        if (lane == (uint32_t)l) {
+            a.V[j] = o.V;
+            a.W[j] = o.W;
+            a.rend[j] = o.re;
+            if (o.spiked) a.fs[j] = o.fsp;
+            spiked = o.spiked;
+            dis = o.dis;
         }
-        if (take && !coop) {
-            XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
-            uint2* seg = whole ? in_s + off : a.qsorted + k0;
-            if (next <= kXLocal) x_take_merged(a, s, in, seg, nrec, ev_s + tid, false);
-            else x_take_selected(a, s, in, seg, nrec);
-            x_advance(a, s, t1);
-            a.V[j] = s.V;
-            a.W[j] = s.W;
-            a.rend[j] = s.re;
-            if (s.spiked) a.fs[j] = s.fsp;
-            spiked = s.spiked;
-            dis = s.dis;
-            done = true;
-        }
-        // the next window starts at the slice of the first neuron not done
-        unsigned long long m = done ? ~0ull : (unsigned long long)k0;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long y = __shfl_xor(m, o);
-            m = y < m ? y : m;
-        }
-        if (lane == 0) wlo[wv] = m;
-        __syncthreads();   // also: every lane is done with this window's LDS copy
-        unsigned long long nlo = ~0ull;
-        for (uint32_t w = 0; w < kXBlock / 64; ++w) nlo = wlo[w] < nlo ? wlo[w] : nlo;
-        __syncthreads();   // wlo is rewritten by the next pass
-        if (nlo == ~0ull) break;
-        lo = nlo;
     }
-    // the spiker list is built in ascending id: lane tid closes neuron first + tid
-    spk_s[jl] = spiked;
-    __syncthreads();
-    x_close_block(a, first + tid, spk_s[tid], next, dis, wcnt, wext, wdis);
+    if (live && !coop) {
+        XNeuron s{V0, W0, re0, t0, 0u, 0u, 0u};
+        const XIn in{j, t, next, jext, exc, fj, ff, t0};
+        if (next <= kXLocal) x_take_merged(a, s, in, a.qsorted + k0, nrec, ev_s + tid, false);
+        else x_take_selected(a, s, in, a.qsorted + k0, nrec);
+        x_advance(a, s, t1);
+        a.V[j] = s.V;
+        a.W[j] = s.W;
+        a.rend[j] = s.re;
+        if (s.spiked) a.fs[j] = s.fsp;
+        spiked = s.spiked;
+        dis = s.dis;
+    }
+    x_close_block(a, j, spiked, next, dis, wcnt, wext, wdis);
 }
 
 __global__ __launch_bounds__(kXBlock) void k_x_list(XArgs a)

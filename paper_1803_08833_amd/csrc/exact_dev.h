@@ -18,8 +18,7 @@ constexpr uint32_t kStreamExtTime = 7u;   // offsets of the external inputs of a
 constexpr uint32_t kXBlock = 256;          // neurons per update workgroup
 constexpr uint32_t kXLocal = 16;           // inputs per neuron sorted in LDS (more: slow path)
 constexpr uint32_t kXBusyPer = 8;          // a workgroup averaging more inputs per neuron is busy
-constexpr uint32_t kXBusyCap = 15 * 1024;  // inputs of a busy workgroup held in LDS
-constexpr uint32_t kXWaveSort = 1024;      // longest slice a busy workgroup's wave sorts together
+constexpr uint32_t kXWaveSort = 1024;      // most inputs of a neuron a busy workgroup's wave takes together
 constexpr uint32_t kXGroups = 4096;        // most target groups of the arrival sort
 constexpr uint32_t kXGroupBitsMax = 12;    // neurons per target group: at most 2^12
 constexpr uint64_t kXChunkMin = 1024;      // fewest inputs per workgroup of the arrival sort's chunk passes

@@ -116,8 +116,9 @@ def test_lockstep_exact_busy_sorted_by_waves(snn, oracle_mod, case):
     """A 12 Hz drive bursts the network within a few steps, so that every
     update workgroup is busy and its neurons' slices, at hundreds of distinct
     offsets with ties, span each width the busy kernel's waves sort together
-    (2-64 ... 513-1024 inputs) and, past 1024, the single-lane heap sort, over
-    many LDS windows per workgroup.  Lock-step against the oracle's free run."""
+    (2-64 ... 513-1024 inputs) and, past 1024, the single-lane heap sort, with
+    hundreds of thousands of inputs per workgroup.  Lock-step against the
+    oracle's free run."""
     if case == "upto512":
         net = W.make(2, 1, W.GAUSS, 1.0, 1100, 71, n_exc=960, n_inh=240, solver=W.SOLVER_EXACT, d_max=2,
                      ext_rate_hz=12.0)
@@ -278,12 +279,12 @@ def test_solver_specific_calls(snn):
 
 
 def test_busy_workgroups_taken_in_windows(snn, oracle_mod):
-    """Workgroups whose queued inputs in one step exceed the busy kernel's LDS
-    window (15,360 inputs) are taken in several windows: a 1000-neuron module
-    with 300 synapses per neuron, all of delay 1, where every neuron is forced
-    to fire in step 0 (at its constant-drive input, offset 0), so that each
-    256-neuron workgroup receives ~77 K inputs in step 1 (six windows); then
-    some neurons fire again.  Lock-step against the oracle: history with offsets, every queued
+    """Workgroups with far more queued inputs in one step than LDS holds
+    (over 30,720): a 1000-neuron module with 300 synapses per neuron, all of
+    delay 1, where every neuron is forced to fire in step 0 (at its
+    constant-drive input, offset 0), so that each 256-neuron workgroup
+    receives ~77 K inputs in step 1, all at one instant; then some neurons
+    fire again.  Lock-step against the oracle: history with offsets, every queued
     input and the state after each step."""
     net = W.make(1, 1, W.GAUSS, 1.0, 300, 77, n_exc=800, n_inh=200, d_min=1, d_max=1, t_ref=1.0,
                  solver=W.SOLVER_EXACT, ext_mode=W.EXT_CONST, ext_const_q=round(0.3 * 65536))
