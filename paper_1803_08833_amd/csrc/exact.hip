@@ -1,22 +1,28 @@
 // exact.hip -- gfx950 kernels of the exact-time event-driven solver
 // (Sec. II.A, Sec. II.C).
 //
-//   k_x_place    the arriving slot's queued inputs, counting-sorted by target
-//                (position: the target's scanned offset plus the input's rank
-//                among the target's inputs, taken when it was delivered)
+//   k_xs_count, k_xs_scan, k_xs_scatter, k_xs_group
+//                the arriving slot's queued inputs, counting-sorted by target
+//                (per target group in chunk histograms, then per neuron inside
+//                each group), which also gives every neuron's offset
 //   k_x_update   one thread per neuron: this step's inputs (queued and
 //                external) in time order, Eq. (1)-(2) solved exactly between
 //                them, a spike at the input that crosses threshold; ordered
 //                spiker list per 256-neuron workgroup
+//   k_x_update_busy
+//                workgroups with many inputs: one wave per neuron in turn,
+//                the inputs sorted in registers and every instant evaluated
+//                at once in closed form
 //   k_x_list     dense spike list of the step (each workgroup's place from the
-//                counts of those before it) and its AER history entries
-//                (step, id, offset)
+//                counts of those before it), its AER history entries
+//                (step, id, offset) and each spike's row bucket lengths
+//   k_x_offsets  each spike's place in each delay bucket's arrival list (a
+//                scan of the bucket lengths over the step's spikes)
 //   k_x_deliver  one wave per (spike, 256-record row segment): fan-out into
-//                the arrival slots' lists, one reservation per delay bucket
-//                the segment touches
+//                the arrival slots' lists at those places, no atomics
 //   k_x_finish   step counters (external events totalled over the workgroups)
 //
-// Like the step kernels this is bound by memory traffic and atomics, not by
+// Like the step kernels this is bound by memory traffic and latency, not by
 // arithmetic: no MFMA.
 #include "exact_dev.h"
 
