@@ -278,7 +278,7 @@ def test_solver_specific_calls(snn):
             b.admit(exact_net, 10)
 
 
-def test_busy_workgroups_taken_in_windows(snn, oracle_mod):
+def test_busy_workgroups_with_many_inputs(snn, oracle_mod):
     """Workgroups with far more queued inputs in one step than LDS holds
     (over 30,720): a 1000-neuron module with 300 synapses per neuron, all of
     delay 1, where every neuron is forced to fire in step 0 (at its
