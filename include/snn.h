@@ -125,8 +125,9 @@ typedef struct {
  * one instant are summed before the threshold test; Eq. (1)-(2) are solved
  * exactly between inputs; a spike at s holds V at V_r over [s, s + t_ref),
  * discarding inputs there (t_ref >= 1 ms).  The exact solver delivers through
- * its own per-slot input queues (SNN_OPT_QUEUE_CAP), not the delay ring, and
- * is not available to batches. */
+ * its own per-slot input queues (SNN_OPT_QUEUE_CAP), not the delay ring, is
+ * not available to batches and takes at most 2^24 neurons (SNN_E_INVAL from
+ * snn_build_synapses above that). */
 typedef struct {
     uint32_t kernel;          /* SNN_GAUSS or SNN_EXP                           */
     uint32_t record;          /* SNN_REC_F32 (8 B) or SNN_REC_CODE8 (4 B)       */
@@ -330,8 +331,9 @@ snn_status snn_stats(snn_net* net, snn_stats_t* out);
 /* Run n_ms steps launching each kernel separately between HIP events on the
  * network's stream and report average kernel durations.  The steps are real
  * simulation steps (state advances).  Exact solver: update_ms is the neuron
- * update, scatter_ms the placing of the arriving inputs by target,
- * deliver_ms the fan-out into the input queues, step_ms a whole step. */
+ * update, scatter_ms the ordering of the arriving inputs by target (from the
+ * first of its kernels' start to the last one's end), deliver_ms the fan-out
+ * into the input queues, step_ms a whole step. */
 snn_status snn_time_kernels(snn_net* net, uint32_t n_ms, snn_kernel_times* out);
 
 /* Return the network to its initial state (as after snn_build_grid: V from the
